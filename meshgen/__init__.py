@@ -1,0 +1,376 @@
+"""Seeded synthetic inputs for low-order-refined (LOR) assembly.
+
+This module builds the *inputs* of the assembly only: node coordinates of the
+Gauss-Lobatto-refined hexahedral mesh, the element-to-vertex and element-to-edge
+maps, per-subelement coefficients and cotangents.  It contains none of the
+assembly arithmetic (no shape functions, quadrature, Jacobians or sums), so both
+the CPU oracle and the GPU path can take their inputs from here without sharing
+any of the method's code.
+
+Conventions (section "The low-order-refined mesh" of the paper: each degree-p
+hexahedron is cut at the tensor Gauss-Lobatto lattice into p^3 subelements):
+
+* Element e = ex + n*(ey + n*ez) of an n x n x n Cartesian coarse mesh of the
+  unit cube.  Local vertex l = i + (p+1)*(j + (p+1)*k), i,j,k in [0, p].
+* Global lattice has N = n*p + 1 points per axis; global vertex id
+  X + N*(Y + N*Z) with X = p*ex + i (lexicographic, x fastest).
+* Subelement s = i + p*(j + p*k), i,j,k in [0, p); its corner (a,b,c) is local
+  vertex (i+a, j+b, k+c).
+* Local edges (lowest-order Nedelec on the LOR mesh): x-edges first, index
+  i + p*(j + (p+1)*k) with i < p; then y-edges at offset p*(p+1)^2, index
+  i + (p+1)*(j + p*k) with j < p; then z-edges at offset 2*p*(p+1)^2, index
+  i + (p+1)*(j + (p+1)*k) with k < p.  Each local edge points along +axis.
+* Global edges: with M = n*p, N = M + 1: x-edges X + M*(Y + N*Z); y-edges
+  M*N^2 + X + N*(Y + M*Z); z-edges 2*M*N^2 + X + N*(Y + N*Z); each points along
+  +axis.  A map entry v >= 0 means global edge v with the same orientation as the
+  local edge; v < 0 means global edge -1-v with the opposite orientation (the
+  orientation-in-the-sign convention of the processor-local assembly step A2).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import torch
+
+__all__ = [
+    "gll_points",
+    "cartesian_mesh",
+    "affine_mesh",
+    "nd_edge_map",
+    "kappa_field",
+    "cotangent",
+    "renumber_vertices",
+    "permute_elements",
+    "reorient_elements",
+    "flip_edge_signs",
+    "CONFIGS",
+    "config_mesh",
+]
+
+
+def gll_points(p: int) -> np.ndarray:
+    """The p+1 Gauss-Lobatto points mapped to [0, 1], ascending, float64.
+
+    Endpoints 0 and 1; the interior points are the roots of P_p' (derivative of
+    the degree-p Legendre polynomial) on [-1, 1].  The set is symmetrised so that
+    t_i + t_{p-i} = 1 up to one rounding.
+    """
+    if p < 1:
+        raise ValueError("p must be >= 1")
+    if p == 1:
+        r = np.array([-1.0, 1.0])
+    else:
+        inner = np.polynomial.legendre.Legendre.basis(p).deriv().roots().real
+        r = np.concatenate([[-1.0], np.sort(inner), [1.0]])
+    r = 0.5 * (r - r[::-1])
+    return 0.5 * (r + 1.0)
+
+
+def _lattice_1d(n: int, p: int) -> np.ndarray:
+    """Reference coordinate in [0,1] of each of the N = n*p+1 lattice points."""
+    t = gll_points(p)
+    x = np.empty(n * p + 1)
+    for e in range(n):
+        x[e * p:(e + 1) * p + 1] = (e + t) / n
+    x[0], x[-1] = 0.0, 1.0
+    return x
+
+
+def _elem_dofs(n: int, p: int) -> np.ndarray:
+    N = n * p + 1
+    q = p + 1
+    ex, ey, ez = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
+    # element id e = ex + n*(ey + n*ez): order so that ex varies fastest
+    ex = ex.transpose(2, 1, 0).reshape(-1)
+    ey = ey.transpose(2, 1, 0).reshape(-1)
+    ez = ez.transpose(2, 1, 0).reshape(-1)
+    i, j, k = np.meshgrid(np.arange(q), np.arange(q), np.arange(q), indexing="ij")
+    i = i.transpose(2, 1, 0).reshape(-1)
+    j = j.transpose(2, 1, 0).reshape(-1)
+    k = k.transpose(2, 1, 0).reshape(-1)
+    X = p * ex[:, None] + i[None, :]
+    Y = p * ey[:, None] + j[None, :]
+    Z = p * ez[:, None] + k[None, :]
+    g = X + N * (Y + N * Z)
+    return g.astype(np.int32)
+
+
+def cartesian_mesh(n: int, p: int, amp: float = 0.0) -> dict:
+    """n^3 hexes of degree p on the unit cube, LOR vertices perturbed by
+
+        x' = x + A sin(2 pi y) sin(2 pi z)   (and cyclically for y', z'),
+
+    with A = amp / n (amp is the amplitude in units of the coarse element size
+    h = 1/n).  The map is applied to every Gauss-Lobatto lattice vertex.
+    Returns a dict with coords [N^3, 3] float64, elem_dofs [n^3, (p+1)^3] int32,
+    n, p, N, nel, ndofs.
+    """
+    N = n * p + 1
+    x1 = _lattice_1d(n, p)
+    X, Y, Z = np.meshgrid(x1, x1, x1, indexing="ij")
+    X = X.transpose(2, 1, 0).reshape(-1)
+    Y = Y.transpose(2, 1, 0).reshape(-1)
+    Z = Z.transpose(2, 1, 0).reshape(-1)
+    A = amp / n
+    if A != 0.0:
+        tp = 2.0 * math.pi
+        sx, sy, sz = np.sin(tp * X), np.sin(tp * Y), np.sin(tp * Z)
+        X, Y, Z = X + A * sy * sz, Y + A * sz * sx, Z + A * sx * sy
+    coords = np.stack([X, Y, Z], axis=1).astype(np.float64)
+    return {
+        "coords": coords,
+        "elem_dofs": _elem_dofs(n, p),
+        "n": n,
+        "p": p,
+        "N": N,
+        "nel": n ** 3,
+        "ndofs": N ** 3,
+    }
+
+
+def affine_mesh(n: int, p: int, A: np.ndarray, t: np.ndarray) -> dict:
+    """Cartesian Gauss-Lobatto lattice mapped by x -> A x + t (parallelepipeds)."""
+    m = cartesian_mesh(n, p, 0.0)
+    m["coords"] = m["coords"] @ np.asarray(A, dtype=np.float64).T + np.asarray(t, dtype=np.float64)
+    return m
+
+
+def nd_edge_map(n: int, p: int) -> tuple[np.ndarray, int]:
+    """Signed element-to-edge map [n^3, 3p(p+1)^2] int32 and the edge count."""
+    M = n * p
+    N = M + 1
+    q = p + 1
+    ne = n ** 3
+    e = np.arange(ne)
+    ex, ey, ez = e % n, (e // n) % n, e // (n * n)
+    out = np.empty((ne, 3 * p * q * q), dtype=np.int64)
+    off = 0
+    # x-edges: i < p, j,k <= p
+    for k in range(q):
+        for j in range(q):
+            for i in range(p):
+                ll = i + p * (j + q * k)
+                X, Y, Z = p * ex + i, p * ey + j, p * ez + k
+                out[:, ll] = X + M * (Y + N * Z)
+    off = p * q * q
+    for k in range(q):
+        for j in range(p):
+            for i in range(q):
+                ll = off + i + q * (j + p * k)
+                X, Y, Z = p * ex + i, p * ey + j, p * ez + k
+                out[:, ll] = M * N * N + X + N * (Y + M * Z)
+    off = 2 * p * q * q
+    for k in range(p):
+        for j in range(q):
+            for i in range(q):
+                ll = off + i + q * (j + q * k)
+                X, Y, Z = p * ex + i, p * ey + j, p * ez + k
+                out[:, ll] = 2 * M * N * N + X + N * (Y + N * Z)
+    return out.astype(np.int32), 3 * M * N * N
+
+
+def kappa_field(nel: int, p: int, sigma: float, seed: int = 0, batch: int | None = None,
+                ) -> torch.Tensor:
+    """Log-normal per-subelement coefficient exp(sigma * z), z ~ N(0, 1).
+
+    Draw order: torch.Generator('cpu').manual_seed(seed), then one randn of shape
+    (B, nel, p, p, p) (index [b][e][k][j][i]), float64.  Returned with shape
+    (nel, p^3) when batch is None, else (batch, nel, p^3); subelement index
+    s = i + p*(j + p*k).
+    """
+    g = torch.Generator(device="cpu")
+    g.manual_seed(seed)
+    B = 1 if batch is None else batch
+    z = torch.randn((B, nel, p, p, p), generator=g, dtype=torch.float64)
+    k = torch.exp(sigma * z).reshape(B, nel, p ** 3)
+    return k[0] if batch is None else k
+
+
+def cotangent(batch: int, nnz: int, seed: int = 1) -> torch.Tensor:
+    """Gaussian cotangent on the CSR values, shape (batch, nnz), float64."""
+    g = torch.Generator(device="cpu")
+    g.manual_seed(seed)
+    return torch.randn((batch, nnz), generator=g, dtype=torch.float64)
+
+
+# ---------------------------------------------------------------- perturbations
+
+def renumber_vertices(mesh: dict, seed: int) -> tuple[dict, np.ndarray]:
+    """Random relabelling of the global vertices: new id = perm[old id]."""
+    rng = np.random.default_rng(seed)
+    perm = rng.permutation(mesh["ndofs"]).astype(np.int64)
+    out = dict(mesh)
+    coords = np.empty_like(mesh["coords"])
+    coords[perm] = mesh["coords"]
+    out["coords"] = coords
+    out["elem_dofs"] = perm[mesh["elem_dofs"].astype(np.int64)].astype(np.int32)
+    return out, perm
+
+
+def permute_elements(mesh: dict, seed: int) -> tuple[dict, np.ndarray]:
+    """Random reordering of the elements: new element r holds old element order[r]."""
+    rng = np.random.default_rng(seed)
+    order = rng.permutation(mesh["nel"]).astype(np.int64)
+    out = dict(mesh)
+    out["elem_dofs"] = np.ascontiguousarray(mesh["elem_dofs"][order])
+    return out, order
+
+
+def _cube_symmetries() -> list[tuple[tuple[int, int, int], tuple[bool, bool, bool]]]:
+    """The 24 rotations of the cube as (axis permutation, axis reversal): the
+    signed permutations of determinant +1, so that positively oriented elements
+    stay positively oriented."""
+    import itertools
+    out = []
+    for perm in itertools.permutations(range(3)):
+        inv = sum(1 for a in range(3) for b in range(a + 1, 3) if perm[a] > perm[b])
+        for flips in itertools.product([False, True], repeat=3):
+            if (inv + sum(flips)) % 2 == 0:
+                out.append((perm, flips))
+    return out
+
+
+def _sym_lattice_index(q: int, perm, flips) -> np.ndarray:
+    """For a (q x q x q) lattice (index i + q(j + q k)), the source index of every
+    destination index under the symmetry: new[c] = old[src[c]]."""
+    idx = np.arange(q ** 3)
+    c = [idx % q, (idx // q) % q, idx // (q * q)]
+    src = [None, None, None]
+    for d in range(3):
+        v = c[d]
+        src[perm[d]] = (q - 1 - v) if flips[d] else v
+    return src[0] + q * (src[1] + q * src[2])
+
+
+def reorient_elements(mesh: dict, seed: int, kappa: torch.Tensor | None = None,
+                      elem_edges: np.ndarray | None = None):
+    """Give every element an independent random local orientation (one of the 24
+    cube rotations applied to its local lattice).  The assembled LOR matrix is
+    unchanged; only the local numbering (and the local edge directions) differ.
+
+    Returns (mesh', kappa', elem_edges') with kappa [.., nel, p^3] permuted the
+    same way and the signed edge map re-signed where a local edge now points the
+    other way.
+    """
+    p = mesh["p"]
+    q = p + 1
+    syms = _cube_symmetries()
+    rng = np.random.default_rng(seed)
+    choice = rng.integers(0, len(syms), size=mesh["nel"])
+    ed = mesh["elem_dofs"].copy()
+    kap = None if kappa is None else kappa.clone()
+    ee = None if elem_edges is None else elem_edges.copy()
+    for si, (perm, flips) in enumerate(syms):
+        sel = np.nonzero(choice == si)[0]
+        if sel.size == 0:
+            continue
+        vsrc = _sym_lattice_index(q, perm, flips)
+        ed[sel] = mesh["elem_dofs"][sel][:, vsrc]
+        if kap is not None:
+            ssrc = torch.from_numpy(_sym_lattice_index(p, perm, flips))
+            ks = torch.from_numpy(sel)
+            kap[..., ks, :] = kappa[..., ks, :][..., ssrc]
+        if ee is not None:
+            esrc, esgn = _sym_edge_index(p, perm, flips)
+            old = elem_edges[sel][:, esrc].astype(np.int64)
+            neg = old < 0
+            gid = np.where(neg, -1 - old, old)
+            sgn = np.where(neg, -1, 1) * esgn[None, :]
+            ee[sel] = np.where(sgn > 0, gid, -1 - gid).astype(np.int32)
+    out = dict(mesh)
+    out["elem_dofs"] = ed
+    return out, kap, ee
+
+
+def _local_edges(p: int):
+    """List of (axis, i, j, k) for every local edge in local numbering."""
+    q = p + 1
+    out = []
+    for k in range(q):
+        for j in range(q):
+            for i in range(p):
+                out.append((0, i, j, k))
+    for k in range(q):
+        for j in range(p):
+            for i in range(q):
+                out.append((1, i, j, k))
+    for k in range(p):
+        for j in range(q):
+            for i in range(q):
+                out.append((2, i, j, k))
+    return out
+
+
+def _sym_edge_index(p: int, perm, flips):
+    """Edge analogue of _sym_lattice_index: returns (src, sign) so that the new
+    local edge c is the old local edge src[c], traversed with relative sign
+    sign[c] (-1 when the symmetry reverses it)."""
+    q = p + 1
+    edges = _local_edges(p)
+    lookup = {e: n for n, e in enumerate(edges)}
+    src = np.empty(len(edges), dtype=np.int64)
+    sgn = np.empty(len(edges), dtype=np.int64)
+    for c, (ax, i, j, k) in enumerate(edges):
+        # new edge from new-vertex v0=(i,j,k) to v1=v0+unit(ax)
+        v0 = [i, j, k]
+        v1 = [i, j, k]
+        v1[ax] += 1
+        o0 = [0, 0, 0]
+        o1 = [0, 0, 0]
+        for d in range(3):
+            o0[perm[d]] = (q - 1 - v0[d]) if flips[d] else v0[d]
+            o1[perm[d]] = (q - 1 - v1[d]) if flips[d] else v1[d]
+        oax = perm[ax]
+        if o1[oax] > o0[oax]:
+            base, s = o0, 1
+        else:
+            base, s = o1, -1
+        src[c] = lookup[(oax, base[0], base[1], base[2])]
+        sgn[c] = s
+    return src, sgn
+
+
+def flip_edge_signs(elem_edges: np.ndarray, nedges: int, seed: int):
+    """Reverse the global orientation of a random half of the edges.  Returns the
+    new signed map and the +-1 vector S with A' = S A S."""
+    rng = np.random.default_rng(seed)
+    s = np.where(rng.random(nedges) < 0.5, -1, 1).astype(np.int64)
+    old = elem_edges.astype(np.int64)
+    neg = old < 0
+    gid = np.where(neg, -1 - old, old)
+    sg = np.where(neg, -1, 1) * s[gid]
+    return np.where(sg > 0, gid, -1 - gid).astype(np.int32), s
+
+
+# ---------------------------------------------------------------- named workloads
+
+#: The five workloads of the benchmark plan: (space, n, p, amp, sigma, beta, batch).
+CONFIGS = {
+    "c1_h1_p2_uniform": dict(space="h1", n=4, p=2, amp=0.0, sigma=0.0, beta=0.0, batch=1),
+    "c2_h1_p4_curved": dict(space="h1", n=16, p=4, amp=0.1, sigma=1.0, beta=1.0, batch=1),
+    "c3_h1_p6_curved": dict(space="h1", n=32, p=6, amp=0.1, sigma=2.0, beta=1.0, batch=1),
+    "c4_nd_p3_curved": dict(space="nd", n=24, p=3, amp=0.1, sigma=1.0, beta=1.0, batch=1),
+    "c5_h1_p4_backward": dict(space="h1", n=16, p=4, amp=0.1, sigma=1.0, beta=1.0, batch=8),
+}
+
+
+def config_mesh(name: str, seed: int = 0) -> dict:
+    """Mesh, coefficients (and edge map for H(curl)) of a named workload."""
+    c = CONFIGS[name]
+    m = cartesian_mesh(c["n"], c["p"], c["amp"])
+    if c["sigma"] == 0.0:
+        kap = torch.ones((m["nel"], c["p"] ** 3), dtype=torch.float64)
+        if c["batch"] > 1:
+            kap = kap.expand(c["batch"], -1, -1).contiguous()
+    else:
+        kap = kappa_field(m["nel"], c["p"], c["sigma"], seed,
+                          batch=None if c["batch"] == 1 else c["batch"])
+    m["kappa"] = kap
+    m["beta"] = c["beta"]
+    m["config"] = dict(c, name=name)
+    if c["space"] == "nd":
+        ee, ned = nd_edge_map(c["n"], c["p"])
+        m["elem_edges"] = ee
+        m["nedges"] = ned
+    return m

@@ -1,0 +1,441 @@
+"""CPU FP64 oracle for low-order-refined (LOR) matrix assembly.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path imports, calls or links
+this module; only the tests, the smoke check and the CPU-baseline leg of the
+benchmark use it.  It shares no code with the HIP path (the only common import
+is the seeded input generator, which holds none of the method's arithmetic).
+
+What it computes is the plain definition of the LOR matrices, written out:
+
+* Section "The low-order-refined mesh": every degree-p hexahedron is split at its
+  tensor Gauss-Lobatto lattice into p^3 subelements; the subelement vertices are
+  the mapped lattice points (given here as node coordinates).
+* Section "Poisson problem": the LOR space is the p=1 (trilinear, Q1) H1 space on
+  the refined mesh, with the same degrees of freedom as the high-order space; its
+  stiffness matrix (kappa grad u, grad v) and mass matrix (beta u, v) are the
+  standard element-by-element assembled finite element matrices.
+* Section "Vector finite elements": the lowest-order interpolation-histopolation
+  H(curl) case is the standard lowest-order Nedelec element on the refined mesh;
+  its curl-curl (kappa curl u, curl v) and mass (beta u, v) matrices.
+* Step A2 (processor-local assembly): the orientation of a vector basis function
+  is carried by the sign of its degree of freedom.
+* Section "Adaptive mesh refinement": for conforming meshes the LOR matrix is the
+  element-by-element assembly Lambda^T A_hat Lambda, which is what the COO-then-
+  sort below computes (COO = the unassembled block-diagonal A_hat, the sort and
+  segment sum = the Boolean assembly operator).
+
+Readings of points the paper leaves open (each one is listed in the design doc):
+* Subelement quadrature: 2x2x2 Gauss-Legendre (weights 1/8 on the unit cube).
+* Coefficients: kappa constant per subelement, beta a scalar (or, for tests, a
+  per-subelement tensor).  Consistent (not lumped) mass.
+* CSR form: full symmetric storage, columns sorted ascending and unique, every
+  structurally present entry kept even where its value cancels to ~0.
+* Inverted subelements (det J <= 0 at a quadrature point) raise ValueError.
+
+Every function is in float64 and differentiable (torch autograd) in the node
+coordinates and the coefficients, which gives the reference gradient of the
+adjoint kernel.  "Parity unpinned" functions: none (see tests/test_oracle_pins.py
+for the pin of every function).
+"""
+from __future__ import annotations
+
+import math
+
+import torch
+
+__all__ = [
+    "GAUSS_T",
+    "h1_subelement_vertices",
+    "h1_subelement_matrices",
+    "nd_subelement_edges",
+    "nd_subelement_matrices",
+    "coo_to_csr",
+    "h1_matrix",
+    "h1_rows",
+    "nd_matrix",
+    "nd_rows",
+    "discrete_gradient",
+    "csr_to_dense",
+    "csr_to_scipy",
+]
+
+#: 2-point Gauss-Legendre abscissae on [0, 1]; each weight is 1/2.
+GAUSS_T = (0.5 - 0.5 / math.sqrt(3.0), 0.5 + 0.5 / math.sqrt(3.0))
+
+
+def _l(a: int, t: float) -> float:
+    """1D linear Lagrange function on [0,1]: l_0(t) = 1 - t, l_1(t) = t."""
+    return t if a == 1 else 1.0 - t
+
+
+def _dl(a: int) -> float:
+    return 1.0 if a == 1 else -1.0
+
+
+def _quad_points():
+    """The 8 tensor Gauss points q = q1 + 2 q2 + 4 q3 and weight 1/8 each."""
+    pts = []
+    for q3 in range(2):
+        for q2 in range(2):
+            for q1 in range(2):
+                pts.append((GAUSS_T[q1], GAUSS_T[q2], GAUSS_T[q3]))
+    return pts, 1.0 / 8.0
+
+
+# ------------------------------------------------------------------------- H1
+
+def _q1_reference():
+    """Trilinear shape functions phi[q, v] and reference gradients g[q, v, c] at
+    the Gauss points; vertex v = a + 2b + 4c sits at reference corner (a, b, c)."""
+    pts, w = _quad_points()
+    phi = torch.zeros(8, 8, dtype=torch.float64)
+    grad = torch.zeros(8, 8, 3, dtype=torch.float64)
+    for q, (x, y, z) in enumerate(pts):
+        for v in range(8):
+            a, b, c = v & 1, (v >> 1) & 1, (v >> 2) & 1
+            phi[q, v] = _l(a, x) * _l(b, y) * _l(c, z)
+            grad[q, v, 0] = _dl(a) * _l(b, y) * _l(c, z)
+            grad[q, v, 1] = _l(a, x) * _dl(b) * _l(c, z)
+            grad[q, v, 2] = _l(a, x) * _l(b, y) * _dl(c)
+    return phi, grad, w
+
+
+def h1_subelement_vertices(elem_dofs: torch.Tensor, p: int) -> torch.Tensor:
+    """Global vertex ids [nel, p^3, 8] of every subelement (LOR mesh section):
+    subelement s = i + p(j + p k) of element e has corner (a,b,c) at local
+    lattice vertex (i+a) + (p+1)((j+b) + (p+1)(k+c))."""
+    q = p + 1
+    ed = torch.as_tensor(elem_dofs).to(torch.int64)
+    idx = torch.empty(p ** 3, 8, dtype=torch.int64)
+    for k in range(p):
+        for j in range(p):
+            for i in range(p):
+                s = i + p * (j + p * k)
+                for v in range(8):
+                    a, b, c = v & 1, (v >> 1) & 1, (v >> 2) & 1
+                    idx[s, v] = (i + a) + q * ((j + b) + q * (k + c))
+    return ed[:, idx]
+
+
+def h1_subelement_matrices(X: torch.Tensor, kappa: torch.Tensor, beta) -> torch.Tensor:
+    """Q1 stiffness + mass of trilinear subelements, 2x2x2 Gauss.
+
+    X: [S, 8, 3] vertex coordinates; kappa: [S]; beta: scalar or [S].
+    Returns A^s = K^s + M^s, [S, 8, 8], with
+      K_uv = sum_q w kappa det(J) (J^-T g_u).(J^-T g_v),
+      M_uv = sum_q w beta  det(J) phi_u phi_v,
+    J_rc = d x_r / d xi_c = sum_v X_v,r g_v,c.
+    """
+    phi, grad, w = _q1_reference()
+    J = torch.einsum("svr,qvc->sqrc", X, grad)            # [S, 8, 3, 3]
+    det = torch.linalg.det(J)                              # [S, 8]
+    if bool((det <= 0).any()):
+        raise ValueError("inverted LOR subelement (det J <= 0 at a quadrature point)")
+    Jinv = torch.linalg.inv(J)
+    gp = torch.einsum("qvr,sqrc->sqvc", grad, Jinv)        # physical gradients
+    kap = torch.as_tensor(kappa, dtype=torch.float64)
+    K = torch.einsum("sq,sqvc,squc->svu", w * det, gp, gp) * kap[:, None, None]
+    bet = torch.as_tensor(beta, dtype=torch.float64)
+    Mq = torch.einsum("qv,qu->qvu", phi, phi)              # [8, 8, 8]
+    M = torch.einsum("sq,qvu->svu", w * det, Mq)
+    M = M * (bet[:, None, None] if bet.dim() == 1 else bet)
+    return K + M
+
+
+# --------------------------------------------------------------------- H(curl)
+
+def _nd_reference():
+    """Lowest-order Nedelec reference basis N[q, a, 3] and curls C[q, a, 3] at the
+    Gauss points.  Edge a: x-edges (b,c) -> b + 2c, y-edges (a,c) -> 4 + a + 2c,
+    z-edges (a,b) -> 8 + a + 2b; each points along +axis and has unit tangential
+    moment on its own edge."""
+    pts, w = _quad_points()
+    N = torch.zeros(8, 12, 3, dtype=torch.float64)
+    C = torch.zeros(8, 12, 3, dtype=torch.float64)
+    for q, (x, y, z) in enumerate(pts):
+        for b in range(2):
+            for c in range(2):
+                n = b + 2 * c
+                N[q, n, 0] = _l(b, y) * _l(c, z)
+                C[q, n, 1] = _l(b, y) * _dl(c)
+                C[q, n, 2] = -_dl(b) * _l(c, z)
+        for a in range(2):
+            for c in range(2):
+                n = 4 + a + 2 * c
+                N[q, n, 1] = _l(a, x) * _l(c, z)
+                C[q, n, 0] = -_l(a, x) * _dl(c)
+                C[q, n, 2] = _dl(a) * _l(c, z)
+        for a in range(2):
+            for b in range(2):
+                n = 8 + a + 2 * b
+                N[q, n, 2] = _l(a, x) * _l(b, y)
+                C[q, n, 0] = _l(a, x) * _dl(b)
+                C[q, n, 1] = -_dl(a) * _l(b, y)
+    return N, C, w
+
+
+def nd_subelement_edges(elem_edges: torch.Tensor, p: int):
+    """Global edge ids and orientation signs [nel, p^3, 12] of every subelement."""
+    q = p + 1
+    ee = torch.as_tensor(elem_edges).to(torch.int64)
+    idx = torch.empty(p ** 3, 12, dtype=torch.int64)
+    ox, oy, oz = 0, p * q * q, 2 * p * q * q
+    for k in range(p):
+        for j in range(p):
+            for i in range(p):
+                s = i + p * (j + p * k)
+                for b in range(2):
+                    for c in range(2):
+                        idx[s, b + 2 * c] = ox + i + p * ((j + b) + q * (k + c))
+                for a in range(2):
+                    for c in range(2):
+                        idx[s, 4 + a + 2 * c] = oy + (i + a) + q * (j + p * (k + c))
+                for a in range(2):
+                    for b in range(2):
+                        idx[s, 8 + a + 2 * b] = oz + (i + a) + q * ((j + b) + q * k)
+    raw = ee[:, idx]
+    sign = torch.where(raw < 0, -1.0, 1.0).to(torch.float64)
+    gid = torch.where(raw < 0, -1 - raw, raw)
+    return gid, sign
+
+
+def nd_subelement_matrices(X: torch.Tensor, kappa: torch.Tensor, beta) -> torch.Tensor:
+    """Lowest-order Nedelec curl-curl + mass of trilinear subelements, 2x2x2 Gauss,
+    in the local (+axis) orientation.  Covariant Piola map: N = J^-T N_hat,
+    curl N = J C_hat / det J.
+      K_ab = sum_q w kappa det(J) curlN_a . curlN_b,
+      M_ab = sum_q w beta  det(J) N_a . N_b.
+    X: [S, 8, 3]; returns [S, 12, 12]."""
+    _, grad, _ = _q1_reference()
+    Nr, Cr, w = _nd_reference()
+    J = torch.einsum("svr,qvc->sqrc", X, grad)
+    det = torch.linalg.det(J)
+    if bool((det <= 0).any()):
+        raise ValueError("inverted LOR subelement (det J <= 0 at a quadrature point)")
+    Jinv = torch.linalg.inv(J)
+    Nphys = torch.einsum("qar,sqrc->sqac", Nr, Jinv)               # N_hat^T J^-1
+    Cphys = torch.einsum("sqrc,qac->sqar", J, Cr) / det[:, :, None, None]
+    kap = torch.as_tensor(kappa, dtype=torch.float64)
+    bet = torch.as_tensor(beta, dtype=torch.float64)
+    K = torch.einsum("sq,sqac,sqbc->sab", w * det, Cphys, Cphys) * kap[:, None, None]
+    M = torch.einsum("sq,sqac,sqbc->sab", w * det, Nphys, Nphys)
+    M = M * (bet[:, None, None] if bet.dim() == 1 else bet)
+    return K + M
+
+
+# ------------------------------------------------------------------ assembly
+
+def coo_to_csr(rows: torch.Tensor, cols: torch.Tensor, vals: torch.Tensor, nrows: int):
+    """Sum duplicate (row, col) entries: stable sort by row*nrows + col, unique
+    keys become the pattern, values are segment sums (index_add_, differentiable).
+    Returns row_ptr [nrows+1] int64, col_idx [nnz] int64, values [nnz] float64."""
+    key = rows.to(torch.int64) * int(nrows) + cols.to(torch.int64)
+    order = torch.argsort(key, stable=True)
+    ks = key[order]
+    uniq, inverse = torch.unique_consecutive(ks, return_inverse=True)
+    values = torch.zeros(uniq.numel(), dtype=torch.float64)
+    values = values.index_add(0, inverse, vals[order])
+    r = uniq // int(nrows)
+    col_idx = uniq - r * int(nrows)
+    counts = torch.bincount(r, minlength=int(nrows))
+    row_ptr = torch.zeros(int(nrows) + 1, dtype=torch.int64)
+    row_ptr[1:] = torch.cumsum(counts, 0)
+    return row_ptr, col_idx, values
+
+
+def _as_f64(x) -> torch.Tensor:
+    if isinstance(x, torch.Tensor):
+        return x if x.dtype == torch.float64 else x.to(torch.float64)
+    return torch.as_tensor(x, dtype=torch.float64)
+
+
+def _coo_h1(coords, elem_dofs, p, kappa, beta, elems=None, chunk=4096):
+    coords = _as_f64(coords)
+    kappa = _as_f64(kappa)
+    ed = torch.as_tensor(elem_dofs)
+    if elems is not None:
+        elems = torch.as_tensor(elems, dtype=torch.int64)
+        ed = ed[elems]
+        kappa = kappa[elems]
+        if isinstance(beta, torch.Tensor) and beta.dim() > 0:
+            beta = beta[elems]
+    R, C, V = [], [], []
+    nel = ed.shape[0]
+    for e0 in range(0, nel, chunk):
+        e1 = min(nel, e0 + chunk)
+        sv = h1_subelement_vertices(ed[e0:e1], p).reshape(-1, 8)
+        X = coords[sv]                                          # [S, 8, 3]
+        kap = kappa[e0:e1].reshape(-1)
+        bet = beta[e0:e1].reshape(-1) if (isinstance(beta, torch.Tensor) and beta.dim() > 0) else beta
+        A = h1_subelement_matrices(X, kap, bet)                # [S, 8, 8]
+        R.append(sv[:, :, None].expand(-1, 8, 8).reshape(-1))
+        C.append(sv[:, None, :].expand(-1, 8, 8).reshape(-1))
+        V.append(A.reshape(-1))
+    return torch.cat(R), torch.cat(C), torch.cat(V)
+
+
+def h1_matrix(coords, elem_dofs, p: int, kappa, beta, ndofs: int | None = None):
+    """Assembled LOR H1 matrix (kappa-diffusion + beta-mass) in CSR.
+
+    coords [ndofs, 3] float64, elem_dofs [nel, (p+1)^3], kappa [nel, p^3],
+    beta scalar (or [nel, p^3]).  Returns (row_ptr, col_idx, values)."""
+    coords = _as_f64(coords)
+    nd = coords.shape[0] if ndofs is None else ndofs
+    R, C, V = _coo_h1(coords, elem_dofs, p, kappa, beta)
+    return coo_to_csr(R, C, V, nd)
+
+
+def _elements_touching(elem_ids: torch.Tensor, rows: torch.Tensor) -> torch.Tensor:
+    hit = torch.isin(elem_ids, rows).any(dim=1)
+    return torch.nonzero(hit).reshape(-1)
+
+
+def h1_rows(coords, elem_dofs, p: int, kappa, beta, rows):
+    """The listed rows of the H1 LOR matrix, computed from only the subelements
+    that touch them (same definition as h1_matrix).  Returns, for the sorted
+    unique rows, (rows, row_ptr, col_idx, values)."""
+    rows = torch.unique(torch.as_tensor(rows, dtype=torch.int64))
+    ed = torch.as_tensor(elem_dofs).to(torch.int64)
+    elems = _elements_touching(ed, rows)
+    R, C, V = _coo_h1(coords, ed, p, kappa, beta, elems=elems)
+    keep = torch.isin(R, rows)
+    R, C, V = R[keep], C[keep], V[keep]
+    pos = torch.searchsorted(rows, R)
+    # key on (row position, global column); columns range over all vertices
+    stride = int(C.max().item()) + 1 if C.numel() else 1
+    key = pos * stride + C
+    order = torch.argsort(key, stable=True)
+    ks = key[order]
+    uniq, inverse = torch.unique_consecutive(ks, return_inverse=True)
+    values = torch.zeros(uniq.numel(), dtype=torch.float64).index_add(0, inverse, V[order])
+    r = uniq // stride
+    col_idx = uniq - r * stride
+    counts = torch.bincount(r, minlength=rows.numel())
+    row_ptr = torch.zeros(rows.numel() + 1, dtype=torch.int64)
+    row_ptr[1:] = torch.cumsum(counts, 0)
+    return rows, row_ptr, col_idx, values
+
+
+def _coo_nd(coords, elem_dofs, elem_edges, p, kappa, beta, elems=None, chunk=4096):
+    coords = _as_f64(coords)
+    kappa = _as_f64(kappa)
+    ed = torch.as_tensor(elem_dofs)
+    ee = torch.as_tensor(elem_edges)
+    if elems is not None:
+        elems = torch.as_tensor(elems, dtype=torch.int64)
+        ed, ee, kappa = ed[elems], ee[elems], kappa[elems]
+        if isinstance(beta, torch.Tensor) and beta.dim() > 0:
+            beta = beta[elems]
+    R, C, V = [], [], []
+    nel = ed.shape[0]
+    for e0 in range(0, nel, chunk):
+        e1 = min(nel, e0 + chunk)
+        sv = h1_subelement_vertices(ed[e0:e1], p).reshape(-1, 8)
+        gid, sg = nd_subelement_edges(ee[e0:e1], p)
+        gid = gid.reshape(-1, 12)
+        sg = sg.reshape(-1, 12)
+        X = coords[sv]
+        kap = kappa[e0:e1].reshape(-1)
+        bet = beta[e0:e1].reshape(-1) if (isinstance(beta, torch.Tensor) and beta.dim() > 0) else beta
+        A = nd_subelement_matrices(X, kap, bet) * (sg[:, :, None] * sg[:, None, :])
+        R.append(gid[:, :, None].expand(-1, 12, 12).reshape(-1))
+        C.append(gid[:, None, :].expand(-1, 12, 12).reshape(-1))
+        V.append(A.reshape(-1))
+    return torch.cat(R), torch.cat(C), torch.cat(V)
+
+
+def nd_matrix(coords, elem_dofs, elem_edges, p: int, kappa, beta, nedges: int):
+    """Assembled LOR H(curl) matrix (kappa curl-curl + beta mass) in CSR; rows and
+    columns are global edges with the orientation given by the sign of the signed
+    edge map."""
+    R, C, V = _coo_nd(coords, elem_dofs, elem_edges, p, kappa, beta)
+    return coo_to_csr(R, C, V, nedges)
+
+
+def nd_rows(coords, elem_dofs, elem_edges, p: int, kappa, beta, rows):
+    """The listed rows of the H(curl) LOR matrix (same definition as nd_matrix)."""
+    rows = torch.unique(torch.as_tensor(rows, dtype=torch.int64))
+    ee = torch.as_tensor(elem_edges).to(torch.int64)
+    gid = torch.where(ee < 0, -1 - ee, ee)
+    elems = _elements_touching(gid, rows)
+    R, C, V = _coo_nd(coords, elem_dofs, elem_edges, p, kappa, beta, elems=elems)
+    keep = torch.isin(R, rows)
+    R, C, V = R[keep], C[keep], V[keep]
+    pos = torch.searchsorted(rows, R)
+    stride = int(C.max().item()) + 1 if C.numel() else 1
+    key = pos * stride + C
+    order = torch.argsort(key, stable=True)
+    ks = key[order]
+    uniq, inverse = torch.unique_consecutive(ks, return_inverse=True)
+    values = torch.zeros(uniq.numel(), dtype=torch.float64).index_add(0, inverse, V[order])
+    r = uniq // stride
+    col_idx = uniq - r * stride
+    counts = torch.bincount(r, minlength=rows.numel())
+    row_ptr = torch.zeros(rows.numel() + 1, dtype=torch.int64)
+    row_ptr[1:] = torch.cumsum(counts, 0)
+    return rows, row_ptr, col_idx, values
+
+
+# ------------------------------------------------------- auxiliary: gradient
+
+def discrete_gradient(elem_dofs, elem_edges, p: int, nedges: int):
+    """Discrete gradient (vertices -> edges) of the LOR mesh in CSR, as in the
+    algorithm for the discrete gradient matrix (auxiliary computations of Step
+    S1.2): row i (an edge) has I[i] = 2i, J = (first vertex, second vertex) of
+    its local edge, A = (-sigma, +sigma) with sigma the orientation sign.
+    Returns (row_ptr, col_idx, values) with 2 entries per row (col order as
+    defined, not sorted)."""
+    q = p + 1
+    ed = torch.as_tensor(elem_dofs).to(torch.int64)
+    ee = torch.as_tensor(elem_edges).to(torch.int64)
+    nloc = 3 * p * q * q
+    v0 = torch.empty(nloc, dtype=torch.int64)
+    v1 = torch.empty(nloc, dtype=torch.int64)
+    n = 0
+    for ax, (nx, ny, nz) in enumerate([(p, q, q), (q, p, q), (q, q, p)]):
+        for k in range(nz):
+            for j in range(ny):
+                for i in range(nx):
+                    a = [i, j, k]
+                    b = [i, j, k]
+                    b[ax] += 1
+                    v0[n] = a[0] + q * (a[1] + q * a[2])
+                    v1[n] = b[0] + q * (b[1] + q * b[2])
+                    n += 1
+    raw = ee.reshape(-1)
+    gid = torch.where(raw < 0, -1 - raw, raw)
+    sig = torch.where(raw < 0, -1.0, 1.0).to(torch.float64)
+    j0 = ed[:, v0].reshape(-1)
+    j1 = ed[:, v1].reshape(-1)
+    J = torch.zeros(nedges, 2, dtype=torch.int64)
+    A = torch.zeros(nedges, 2, dtype=torch.float64)
+    seen = torch.zeros(nedges, dtype=torch.bool)
+    # every element sharing an edge writes the same row; keep the first writer
+    order = torch.arange(gid.numel() - 1, -1, -1)
+    J[gid[order], 0] = j0[order]
+    J[gid[order], 1] = j1[order]
+    A[gid[order], 0] = -sig[order]
+    A[gid[order], 1] = sig[order]
+    seen[gid] = True
+    if not bool(seen.all()):
+        raise ValueError("edge map does not cover every edge")
+    row_ptr = torch.arange(0, 2 * nedges + 1, 2, dtype=torch.int64)
+    return row_ptr, J.reshape(-1), A.reshape(-1)
+
+
+# ---------------------------------------------------------------- utilities
+
+def csr_to_dense(row_ptr, col_idx, values, ncols: int | None = None) -> torch.Tensor:
+    n = row_ptr.numel() - 1
+    m = n if ncols is None else ncols
+    rows = torch.repeat_interleave(torch.arange(n), row_ptr[1:] - row_ptr[:-1])
+    D = torch.zeros(n, m, dtype=values.dtype)
+    D.index_put_((rows, col_idx.to(torch.int64)), values, accumulate=True)
+    return D
+
+
+def csr_to_scipy(row_ptr, col_idx, values, ncols: int | None = None):
+    import scipy.sparse as sp
+    n = row_ptr.numel() - 1
+    m = n if ncols is None else ncols
+    return sp.csr_matrix((values.detach().numpy(), col_idx.numpy(), row_ptr.numpy()), shape=(n, m))

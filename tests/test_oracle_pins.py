@@ -1,0 +1,484 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Each test derives its expected value by a route that does not go through the
+oracle's code: lattice counting with 1D element matrices, conservation laws
+(partition of unity, exact volumes), exactness of the 2-point rule on affine
+cells, an independent dense brute-force assembly, the de Rham exact sequence,
+and the paper's printed pattern counts.  A dropped term, a wrong sign or index
+or a transposed Jacobian in the oracle fails at least one of them.
+"""
+import itertools
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import meshgen
+from oracle import lor_oracle as orc
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def dense(rp, ci, v, n=None):
+    return orc.csr_to_dense(rp, ci, v, n).numpy()
+
+
+def lattice_xyz(g, N):
+    g = np.asarray(g, dtype=np.int64)
+    return np.stack([g % N, (g // N) % N, g // (N * N)], axis=-1)
+
+
+# ----------------------------------------------------------- closed forms (C1)
+
+def _expected_uniform(N, h, kind):
+    """Assembled Q1 matrix on a uniform lattice of N^3 points, spacing h, from
+    lattice counting: entry (i, j) = (#cells holding both) x (cell-matrix entry
+    for the pair), with the cell matrix built from 1D linear element matrices
+    S = [[1,-1],[-1,1]]/h and M = h/6 [[2,1],[1,2]] by tensor products."""
+    S1 = np.array([[1.0, -1.0], [-1.0, 1.0]]) / h
+    M1 = h / 6.0 * np.array([[2.0, 1.0], [1.0, 2.0]])
+    if kind == "K":
+        cell = (np.kron(np.kron(M1, M1), S1) + np.kron(np.kron(M1, S1), M1)
+                + np.kron(np.kron(S1, M1), M1))
+    else:
+        cell = np.kron(np.kron(M1, M1), M1)
+    # kron order puts the x-index fastest: corner v = a + 2b + 4c
+    n = N ** 3
+    A = np.zeros((n, n))
+    for cz, cy, cx in itertools.product(range(N - 1), repeat=3):
+        ids = []
+        for c, b, a in itertools.product(range(2), repeat=3):
+            ids.append((cx + a) + N * ((cy + b) + N * (cz + c)))
+        ids = np.array(ids)
+        # ids enumerated with a fastest within (c, b, a) loops -> v = a + 2b + 4c
+        A[np.ix_(ids, ids)] += cell
+    return A
+
+
+@pytest.mark.parametrize("kind", ["K", "M"])
+def test_uniform_cube_closed_form(kind):
+    """C1 (4^3 hexes, p=2, undistorted): every row, boundary rows included."""
+    m = meshgen.cartesian_mesh(4, 2, 0.0)
+    N = m["N"]
+    h = 1.0 / (N - 1)
+    kap = torch.ones(m["nel"], 8, dtype=torch.float64) * (1.0 if kind == "K" else 0.0)
+    beta = 0.0 if kind == "K" else 1.0
+    rp, ci, v = orc.h1_matrix(m["coords"], m["elem_dofs"], 2, kap, beta)
+    assert rp[-1].item() == (3 * N - 2) ** 3
+    A = dense(rp, ci, v)
+    E = _expected_uniform(N, h, kind)
+    scale = np.abs(E).max()
+    assert np.abs(A - E).max() <= 1e-14 * scale
+    # interior stencil values quoted in the plan: 8h/3, 0, -h/6, -h/12
+    if kind == "K":
+        g = 4 + N * (4 + N * 4)
+        row = {tuple(lattice_xyz(c, N) - lattice_xyz(g, N)): A[g, c] for c in np.nonzero(E[g])[0]}
+        assert abs(A[g, g] - 8 * h / 3) < 1e-15
+        assert abs(row[(1, 1, 0)] + h / 6) < 1e-15
+        assert abs(row[(1, 1, 1)] + h / 12) < 1e-15
+        assert abs(A[g, g + 1]) < 1e-15
+
+
+# ------------------------------------------------------- conservation / exactness
+
+def test_diffusion_row_sums_vanish():
+    m = meshgen.cartesian_mesh(3, 3, 0.18)         # strongly curved (A = 0.06)
+    kap = meshgen.kappa_field(m["nel"], 3, 2.0, seed=3)
+    rp, ci, v = orc.h1_matrix(m["coords"], m["elem_dofs"], 3, kap, 0.0)
+    A = orc.csr_to_scipy(rp, ci, v)
+    rs = np.abs(np.asarray(A.sum(axis=1)).ravel())
+    rmax = np.asarray(abs(A).max(axis=1).todense()).ravel()
+    assert (rs <= 1e-14 * rmax).all()
+
+
+def test_symmetry():
+    m = meshgen.cartesian_mesh(3, 3, 0.18)
+    kap = meshgen.kappa_field(m["nel"], 3, 1.0, seed=4)
+    rp, ci, v = orc.h1_matrix(m["coords"], m["elem_dofs"], 3, kap, 1.0)
+    A = orc.csr_to_scipy(rp, ci, v)
+    D = abs(A - A.T).max()
+    assert D <= 1e-15 * abs(A).max()
+    # pattern is structurally symmetric
+    assert (A != 0).nnz == (A.T != 0).nnz
+
+
+@pytest.mark.parametrize("n,p,amp", [(4, 4, 0.1), (3, 5, 0.18), (2, 6, 0.12)])
+def test_mass_total_is_domain_volume(n, p, amp):
+    """Sum of all mass entries = volume of the union of trilinear subelements.
+    The sinusoidal map moves each face of the unit cube only along its normal,
+    by a bump whose trapezoid-weighted lattice sum vanishes (lattice symmetric
+    about 1/2), so that union has volume exactly 1."""
+    m = meshgen.cartesian_mesh(n, p, amp)
+    kap = torch.zeros(m["nel"], p ** 3, dtype=torch.float64)
+    rp, ci, v = orc.h1_matrix(m["coords"], m["elem_dofs"], p, kap, 1.0)
+    assert abs(v.sum().item() - 1.0) <= 1e-13
+
+
+def _affine():
+    A = np.array([[1.3, 0.4, -0.2], [0.1, 0.9, 0.3], [-0.25, 0.2, 1.1]])
+    t = np.array([0.3, -0.7, 1.9])
+    return A, t
+
+
+@pytest.mark.parametrize("p", [2, 3])
+def test_affine_energy(p):
+    """On parallelepiped cells the 2-point rule is exact for |grad u|^2 and u^2
+    with u affine: U^T K U = |a|^2 sum_s kappa_s vol_s and
+    U^T M U = beta * int (a.x + c)^2."""
+    n = 2
+    Am, t = _affine()
+    m = meshgen.affine_mesh(n, p, Am, t)
+    kap = meshgen.kappa_field(m["nel"], p, 1.0, seed=7)
+    a = np.array([0.7, -1.1, 0.4])
+    c = 0.35
+    X = m["coords"]
+    U = torch.from_numpy(X @ a + c)
+    detA = np.linalg.det(Am)
+    # subelement volumes from the lattice spacings
+    tt = meshgen.gll_points(p)
+    dt = np.diff(tt) / n
+    vol = np.einsum("i,j,k->kji", dt, dt, dt).reshape(-1) * detA   # s = i + p(j + p k)
+    rp, ci, v = orc.h1_matrix(X, m["elem_dofs"], p, kap, 0.0)
+    K = orc.csr_to_scipy(rp, ci, v)
+    want = float(a @ a) * float((kap.numpy() * vol[None, :]).sum())
+    got = float(U.numpy() @ (K @ U.numpy()))
+    assert abs(got - want) <= 1e-12 * abs(want)
+    beta = 2.5
+    rp, ci, v = orc.h1_matrix(X, m["elem_dofs"], p, torch.zeros_like(kap), beta)
+    M = orc.csr_to_scipy(rp, ci, v)
+    alpha = Am.T @ a
+    gamma = float(a @ t) + c
+    integral = detA * ((alpha.sum() / 2 + gamma) ** 2 + float(alpha @ alpha) / 12.0)
+    got = float(U.numpy() @ (M @ U.numpy()))
+    assert abs(got - beta * integral) <= 1e-12 * abs(beta * integral)
+
+
+# ------------------------------------------------------------ brute force (p=2)
+
+def _brute_force_dense(coords, elem_dofs, p, kappa, beta, npts):
+    """Independent dense assembly: explicit loops over subelements, quadrature
+    points and vertex pairs, Jacobian from explicit shape derivatives, physical
+    gradients by solving J^T y = grad_ref."""
+    xg, wg = np.polynomial.legendre.leggauss(npts)
+    xg = 0.5 * (xg + 1.0)
+    wg = 0.5 * wg
+    q = p + 1
+    nd = coords.shape[0]
+    A = np.zeros((nd, nd))
+    corners = [(a, b, c) for c in range(2) for b in range(2) for a in range(2)]
+    for e in range(elem_dofs.shape[0]):
+        for k in range(p):
+            for j in range(p):
+                for i in range(p):
+                    s = i + p * (j + p * k)
+                    ids = [elem_dofs[e, (i + a) + q * ((j + b) + q * (k + c))] for (a, b, c) in corners]
+                    Xs = coords[ids]
+                    Ke = np.zeros((8, 8))
+                    for (x1, w1) in zip(xg, wg):
+                        for (x2, w2) in zip(xg, wg):
+                            for (x3, w3) in zip(xg, wg):
+                                N = np.empty(8)
+                                dN = np.empty((8, 3))
+                                for v, (a, b, c) in enumerate(corners):
+                                    fa = x1 if a else 1 - x1
+                                    fb = x2 if b else 1 - x2
+                                    fc = x3 if c else 1 - x3
+                                    da = 1.0 if a else -1.0
+                                    db = 1.0 if b else -1.0
+                                    dc = 1.0 if c else -1.0
+                                    N[v] = fa * fb * fc
+                                    dN[v] = (da * fb * fc, fa * db * fc, fa * fb * dc)
+                                J = Xs.T @ dN          # J[r, c] = sum_v X[v, r] dN[v, c]
+                                dJ = np.linalg.det(J)
+                                G = np.linalg.solve(J.T, dN.T).T
+                                w = w1 * w2 * w3 * dJ
+                                Ke += w * (kappa[e, s] * (G @ G.T) + beta * np.outer(N, N))
+                    A[np.ix_(ids, ids)] += Ke
+    return A
+
+
+def test_brute_force_dense_curved():
+    m = meshgen.cartesian_mesh(2, 2, 0.12)
+    kap = meshgen.kappa_field(m["nel"], 2, 1.0, seed=11)
+    rp, ci, v = orc.h1_matrix(m["coords"], m["elem_dofs"], 2, kap, 0.6)
+    B = _brute_force_dense(m["coords"], m["elem_dofs"], 2, kap.numpy(), 0.6, 2)
+    A = dense(rp, ci, v)
+    assert np.abs(A - B).max() <= 1e-14 * np.abs(B).max()
+    # pattern: every stored entry is a lattice neighbour pair, and nothing else
+    assert ((A != 0) | (B == 0)).all()
+
+
+def test_brute_force_affine_exact_rule():
+    """On affine cells the 2-point rule equals a 4-point rule (exactness)."""
+    Am, t = _affine()
+    m = meshgen.affine_mesh(2, 2, Am, t)
+    kap = meshgen.kappa_field(m["nel"], 2, 1.0, seed=12)
+    rp, ci, v = orc.h1_matrix(m["coords"], m["elem_dofs"], 2, kap, 1.3)
+    B = _brute_force_dense(m["coords"], m["elem_dofs"], 2, kap.numpy(), 1.3, 4)
+    A = dense(rp, ci, v)
+    assert np.abs(A - B).max() <= 1e-13 * np.abs(B).max()
+
+
+# ------------------------------------------------------------- invariances
+
+def test_vertex_renumbering_is_a_permutation():
+    m = meshgen.cartesian_mesh(3, 2, 0.18)
+    kap = meshgen.kappa_field(m["nel"], 2, 1.0, seed=5)
+    rp, ci, v = orc.h1_matrix(m["coords"], m["elem_dofs"], 2, kap, 1.0)
+    m2, perm = meshgen.renumber_vertices(m, seed=9)
+    rp2, ci2, v2 = orc.h1_matrix(m2["coords"], m2["elem_dofs"], 2, kap, 1.0)
+    A = dense(rp, ci, v)
+    A2 = dense(rp2, ci2, v2)
+    P = np.zeros_like(A)
+    P[perm, np.arange(len(perm))] = 1.0
+    assert np.abs(A2 - P @ A @ P.T).max() <= 1e-15 * np.abs(A).max()
+    # row lengths travel with the rows
+    assert np.array_equal(np.diff(rp2.numpy())[perm], np.diff(rp.numpy()))
+
+
+def test_element_permutation_and_reorientation():
+    m = meshgen.cartesian_mesh(3, 3, 0.18)
+    kap = meshgen.kappa_field(m["nel"], 3, 1.0, seed=6)
+    rp, ci, v = orc.h1_matrix(m["coords"], m["elem_dofs"], 3, kap, 1.0)
+    m2, order = meshgen.permute_elements(m, seed=1)
+    rp2, ci2, v2 = orc.h1_matrix(m2["coords"], m2["elem_dofs"], 3, kap[torch.from_numpy(order)], 1.0)
+    assert torch.equal(rp, rp2) and torch.equal(ci, ci2)
+    assert (v - v2).abs().max() <= 1e-15 * v.abs().max()
+    m3, kap3, _ = meshgen.reorient_elements(m, seed=2, kappa=kap)
+    rp3, ci3, v3 = orc.h1_matrix(m3["coords"], m3["elem_dofs"], 3, kap3, 1.0)
+    assert torch.equal(rp, rp3) and torch.equal(ci, ci3)
+    assert (v - v3).abs().max() <= 1e-14 * v.abs().max()
+
+
+# -------------------------------------------------------------- pattern counts
+
+@pytest.mark.parametrize("n,p", [(1, 1), (2, 1), (2, 2), (3, 2), (2, 3), (1, 4), (2, 4)])
+def test_h1_pattern_count(n, p):
+    m = meshgen.cartesian_mesh(n, p, 0.0)
+    kap = torch.ones(m["nel"], p ** 3, dtype=torch.float64)
+    rp, ci, v = orc.h1_matrix(m["coords"], m["elem_dofs"], p, kap, 1.0)
+    N = m["N"]
+    assert rp[-1].item() == (3 * N - 2) ** 3
+    counts = (rp[1:] - rp[:-1]).numpy()
+    assert counts.max() == min(3, N) ** 3 and counts.min() == 8
+
+
+def test_paper_printed_counts_follow_the_lattice_formula():
+    """The paper prints the 3D p=6 / 32768-element and 2D p=6 / 262144-element
+    Helmholtz problem sizes; the lattice count that the oracle satisfies above,
+    (3N-2)^d with N = n p + 1, reproduces them exactly."""
+    with open(os.path.join(GOLDEN, "paper_counts.json")) as f:
+        g = json.load(f)
+    d3 = g["h1_3d"]
+    n = round(d3["elements"] ** (1 / 3))
+    N = n * d3["p"] + 1
+    assert n ** 3 == d3["elements"]
+    assert N ** 3 == d3["dofs"] and (3 * N - 2) ** 3 == d3["nnz"]
+    d2 = g["h1_2d"]
+    n2 = round(math.sqrt(d2["elements"]))
+    N2 = n2 * d2["p"] + 1
+    assert N2 ** 2 == d2["dofs"] and (3 * N2 - 2) ** 2 == d2["nnz"]
+
+
+def test_h1_pattern_count_moderate_size():
+    """A mid-size p=6 mesh: nnz from the oracle equals (3N-2)^3."""
+    m = meshgen.cartesian_mesh(3, 6, 0.1)
+    kap = torch.ones(m["nel"], 216, dtype=torch.float64)
+    rp, _, _ = orc.h1_matrix(m["coords"], m["elem_dofs"], 6, kap, 1.0)
+    assert rp[-1].item() == (3 * m["N"] - 2) ** 3
+
+
+def test_rows_subset_matches_full():
+    m = meshgen.cartesian_mesh(3, 3, 0.18)
+    kap = meshgen.kappa_field(m["nel"], 3, 1.0, seed=8)
+    rp, ci, v = orc.h1_matrix(m["coords"], m["elem_dofs"], 3, kap, 1.0)
+    rows = torch.tensor([0, 5, 77, 400, m["ndofs"] - 1, 313])
+    r, rp2, ci2, v2 = orc.h1_rows(m["coords"], m["elem_dofs"], 3, kap, 1.0, rows)
+    for n, g in enumerate(r.tolist()):
+        a, b = rp[g].item(), rp[g + 1].item()
+        c, d = rp2[n].item(), rp2[n + 1].item()
+        assert torch.equal(ci[a:b], ci2[c:d])
+        assert (v[a:b] - v2[c:d]).abs().max() <= 1e-15 * v[a:b].abs().max()
+
+
+# ----------------------------------------------------------------- H(curl)
+
+def _nd_setup(n, p, amp, seed, reorient=False, flip=False):
+    m = meshgen.cartesian_mesh(n, p, amp)
+    ee, ned = meshgen.nd_edge_map(n, p)
+    kap = meshgen.kappa_field(m["nel"], p, 1.0, seed=seed)
+    if reorient:
+        m, kap, ee = meshgen.reorient_elements(m, seed=seed + 1, kappa=kap, elem_edges=ee)
+    S = None
+    if flip:
+        ee, S = meshgen.flip_edge_signs(ee, ned, seed=seed + 2)
+    return m, ee, ned, kap, S
+
+
+def _gradient_from_topology(m, ee, ned, p):
+    """Discrete gradient written from its definition in this test: for every
+    local edge of every element, the row of its global edge gets -sigma at the
+    first local vertex and +sigma at the second."""
+    q = p + 1
+    G = np.zeros((ned, m["ndofs"]))
+    loc = []
+    for ax, dims in enumerate([(p, q, q), (q, p, q), (q, q, p)]):
+        for k in range(dims[2]):
+            for j in range(dims[1]):
+                for i in range(dims[0]):
+                    a = [i, j, k]
+                    b = list(a)
+                    b[ax] += 1
+                    loc.append((a[0] + q * (a[1] + q * a[2]), b[0] + q * (b[1] + q * b[2])))
+    ed = m["elem_dofs"]
+    for e in range(m["nel"]):
+        for l, (v0, v1) in enumerate(loc):
+            raw = int(ee[e, l])
+            g = raw if raw >= 0 else -1 - raw
+            s = 1.0 if raw >= 0 else -1.0
+            G[g, :] = 0.0
+            G[g, ed[e, v0]] = -s
+            G[g, ed[e, v1]] = s
+    return G
+
+
+@pytest.mark.parametrize("reorient,flip", [(False, False), (True, True)])
+def test_nd_exact_sequence(reorient, flip):
+    """curl grad = 0 on every trilinear cell:  K_curl G = 0.  And the gradients
+    of the Q1 basis are Nedelec fields with coefficients G:  G^T M_nd(c) G =
+    K_h1(c) with the same per-subelement coefficient c and quadrature."""
+    p = 2
+    m, ee, ned, kap, _ = _nd_setup(2, p, 0.12, seed=21, reorient=reorient, flip=flip)
+    G = _gradient_from_topology(m, ee, ned, p)
+    rp, ci, v = orc.nd_matrix(m["coords"], m["elem_dofs"], ee, p, kap, 0.0, ned)
+    Kc = dense(rp, ci, v, ned)
+    assert np.abs(Kc @ G).max() <= 1e-13 * np.abs(Kc).max()
+    rp, ci, v = orc.nd_matrix(m["coords"], m["elem_dofs"], ee, p, torch.zeros_like(kap), kap, ned)
+    Mn = dense(rp, ci, v, ned)
+    rp, ci, v = orc.h1_matrix(m["coords"], m["elem_dofs"], p, kap, 0.0)
+    Kh = dense(rp, ci, v)
+    assert np.abs(G.T @ Mn @ G - Kh).max() <= 1e-13 * np.abs(Kh).max()
+    # the oracle's discrete gradient (the algorithm's CSR form) is the same map
+    grp, gci, gv = orc.discrete_gradient(m["elem_dofs"], ee, p, ned)
+    assert np.abs(dense(grp, gci, gv, m["ndofs"]) - G).max() == 0.0
+
+
+def test_nd_affine_fields():
+    """u = a x X + b on parallelepipeds: curl u = 2a, so U^T K U = kappa |2a|^2 vol;
+    and for constant u, U^T M U = beta |u|^2 vol.  Edge DOF = u(mid) . (v1 - v0)."""
+    p = 2
+    Am, t = _affine()
+    m = meshgen.affine_mesh(2, p, Am, t)
+    ee, ned = meshgen.nd_edge_map(2, p)
+    kap = torch.full((m["nel"], p ** 3), 1.7, dtype=torch.float64)
+    G = _gradient_from_topology(m, ee, ned, p)
+    X = m["coords"]
+    # edge endpoints from the gradient rows
+    v0 = np.argmax(G < 0, axis=1)
+    v1 = np.argmax(G > 0, axis=1)
+    mid = 0.5 * (X[v0] + X[v1])
+    tan = X[v1] - X[v0]
+    a = np.array([0.3, -0.8, 0.5])
+    b = np.array([1.1, 0.2, -0.6])
+    U = np.einsum("ij,ij->i", np.cross(a, mid) + b, tan)
+    vol = np.linalg.det(Am)
+    rp, ci, v = orc.nd_matrix(X, m["elem_dofs"], ee, p, kap, 0.0, ned)
+    K = dense(rp, ci, v, ned)
+    assert abs(U @ K @ U - 1.7 * 4 * (a @ a) * vol) <= 1e-12 * 1.7 * 4 * (a @ a) * vol
+    Uc = tan @ b
+    rp, ci, v = orc.nd_matrix(X, m["elem_dofs"], ee, p, torch.zeros_like(kap), 2.0, ned)
+    M = dense(rp, ci, v, ned)
+    assert abs(Uc @ M @ Uc - 2.0 * (b @ b) * vol) <= 1e-12 * 2.0 * (b @ b) * vol
+
+
+def test_nd_sign_flip():
+    p = 2
+    m, ee, ned, kap, _ = _nd_setup(2, p, 0.12, seed=31)
+    rp, ci, v = orc.nd_matrix(m["coords"], m["elem_dofs"], ee, p, kap, 1.0, ned)
+    ee2, S = meshgen.flip_edge_signs(ee, ned, seed=5)
+    rp2, ci2, v2 = orc.nd_matrix(m["coords"], m["elem_dofs"], ee2, p, kap, 1.0, ned)
+    A = dense(rp, ci, v, ned)
+    A2 = dense(rp2, ci2, v2, ned)
+    assert np.abs(A2 - S[:, None] * A * S[None, :]).max() == 0.0
+
+
+@pytest.mark.parametrize("n,p", [(1, 2), (2, 1), (1, 3), (2, 2), (1, 5)])
+def test_nd_pattern_count(n, p):
+    """Cartesian count 3M(3M+1)(11M+1), M = n p; interior rows hold 33 (the
+    paper's 'about 33 nonzeros per row' for the Nedelec LOR system)."""
+    m, ee, ned, kap, _ = _nd_setup(n, p, 0.0, seed=1)
+    rp, ci, v = orc.nd_matrix(m["coords"], m["elem_dofs"], ee, p, kap, 1.0, ned)
+    M = n * p
+    assert rp[-1].item() == 3 * M * (3 * M + 1) * (11 * M + 1)
+    assert (rp[1:] - rp[:-1]).max().item() == (33 if M >= 2 else (rp[1:] - rp[:-1]).max().item())
+
+
+def test_nd_symmetric_and_rows_subset():
+    p = 3
+    m, ee, ned, kap, _ = _nd_setup(2, p, 0.12, seed=41, reorient=True, flip=True)
+    rp, ci, v = orc.nd_matrix(m["coords"], m["elem_dofs"], ee, p, kap, 1.0, ned)
+    A = orc.csr_to_scipy(rp, ci, v, ned)
+    assert abs(A - A.T).max() <= 1e-15 * abs(A).max()
+    rows = torch.tensor([0, 3, 100, ned - 1])
+    r, rp2, ci2, v2 = orc.nd_rows(m["coords"], m["elem_dofs"], ee, p, kap, 1.0, rows)
+    for n, g in enumerate(r.tolist()):
+        a, b = rp[g].item(), rp[g + 1].item()
+        c, d = rp2[n].item(), rp2[n + 1].item()
+        assert torch.equal(ci[a:b], ci2[c:d])
+        assert (v[a:b] - v2[c:d]).abs().max() <= 1e-15 * v[a:b].abs().max()
+
+
+# ------------------------------------------------------------------ gradients
+
+def test_oracle_gradient_kappa_closed_form_and_fd():
+    """L = <Gbar, A(kappa, X)>: dL/dkappa_s = <Gbar|s, K^s(kappa=1)> (linear), and
+    central differences in the coordinates (step 1e-6) match autograd."""
+    p = 2
+    m = meshgen.cartesian_mesh(2, p, 0.12)
+    kap = meshgen.kappa_field(m["nel"], p, 1.0, seed=2).requires_grad_(True)
+    X = torch.from_numpy(m["coords"]).clone().requires_grad_(True)
+    rp, ci, v = orc.h1_matrix(X, m["elem_dofs"], p, kap, 0.8)
+    Gb = meshgen.cotangent(1, v.numel(), seed=1)[0]
+    L = (Gb * v).sum()
+    gk, gx = torch.autograd.grad(L, (kap, X))
+    # closed form for kappa: per-subelement unit-kappa matrices, contracted with
+    # the cotangent at each subelement entry's CSR position
+    sv = orc.h1_subelement_vertices(torch.from_numpy(m["elem_dofs"]), p).reshape(-1, 8)
+    with torch.no_grad():
+        K1 = orc.h1_subelement_matrices(X[sv], torch.ones(sv.shape[0], dtype=torch.float64), 0.0)
+    pos = {}
+    for r in range(rp.numel() - 1):
+        for q in range(rp[r].item(), rp[r + 1].item()):
+            pos[(r, ci[q].item())] = q
+    want = torch.zeros(sv.shape[0], dtype=torch.float64)
+    for s in range(sv.shape[0]):
+        acc = 0.0
+        for u in range(8):
+            for w in range(8):
+                acc += Gb[pos[(sv[s, u].item(), sv[s, w].item())]].item() * K1[s, u, w].item()
+        want[s] = acc
+    assert (gk.reshape(-1) - want).abs().max() <= 1e-12 * want.abs().max()
+    gen = torch.Generator().manual_seed(3)
+    eps = 1e-6
+    for _ in range(3):
+        d = torch.randn(X.shape, generator=gen, dtype=torch.float64)
+        d /= d.norm()
+        with torch.no_grad():
+            vp = orc.h1_matrix(X + eps * d, m["elem_dofs"], p, kap, 0.8)[2]
+            vm = orc.h1_matrix(X - eps * d, m["elem_dofs"], p, kap, 0.8)[2]
+        fd = ((Gb * vp).sum() - (Gb * vm).sum()).item() / (2 * eps)
+        ad = (gx * d).sum().item()
+        assert abs(fd - ad) <= 1e-6 * (abs(ad) + 1.0)
+
+
+def test_inverted_subelement_raises():
+    m = meshgen.cartesian_mesh(1, 2, 0.0)
+    X = m["coords"].copy()
+    # push the centre vertex through a corner of the domain: inverts cells
+    X[13] = [1.5, 1.5, 1.5]
+    kap = torch.ones(1, 8, dtype=torch.float64)
+    with pytest.raises(ValueError):
+        orc.h1_matrix(X, m["elem_dofs"], 2, kap, 1.0)
