@@ -1,0 +1,236 @@
+"""Benchmark of the LOR assembly hot path on one MI355X.
+
+Workload (the headline configuration): H1 diffusion + mass LOR assembly at
+p = 6 on 32^3 curved hexahedra (sinusoidal node map, amplitude 0.1 h),
+log-normal kappa (sigma 2) per subelement, beta = 1: 7,189,057 rows,
+192,100,033 nonzeros.  Inputs are synthetic and already resident in HBM; the
+pattern and schedule are built once outside the timed region (they depend on
+the mesh only) and their time is reported separately.
+
+One step = one lor_assemble_h1 call in FP64 (every colour of the element
+colouring, i.e. all subelement integration, row sums and CSR stores).
+value = rows / step time in MDOF/s.  Extra fields report the FP32 form, the
+backward (adjoint) at p = 4 with a batch of 8 kappa fields, the H(curl)
+assembly at p = 3, the pattern time, the roofline of the dominant kernel and
+the CPU oracle timed on a bounded sample.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes_h1(nel, p, ndofs, nnz, vbytes, batch=1):
+    """Every input read once, every value written once (col_idx not read)."""
+    q = p + 1
+    return (batch * nnz * vbytes           # values
+            + ndofs * 3 * 8                # coords (FP64)
+            + nel * q ** 3 * 4             # elem_dofs
+            + batch * nel * p ** 3 * vbytes  # kappa
+            + (ndofs + 1) * 4)             # row_ptr
+
+
+def time_it(fn, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(steps):
+        fn()
+    t1.record()
+    torch.cuda.synchronize()
+    return t0.elapsed_time(t1) / steps
+
+
+def cpu_baseline(m, sample_elems):
+    """The oracle (unchanged) on the first `sample_elems` elements of the workload."""
+    import torch
+    from oracle import lor_oracle as orc
+    ne = min(sample_elems, m["nel"])
+    t = time.perf_counter()
+    R, C, V = orc._coo_h1(m["coords"], m["elem_dofs"][:ne], m["p"], m["kappa"][:ne], m["beta"])
+    orc.coo_to_csr(R, C, V, m["ndofs"])
+    dt = time.perf_counter() - t
+    t_full = dt * m["nel"] / ne
+    return {
+        "value": m["ndofs"] / t_full / 1e6,
+        "unit": "MDOF/s",
+        "cores": torch.get_num_threads(),
+        "kind": "oracle",
+        "sample": f"CPU FP64 oracle (COO + stable sort + segment sums) on {ne} of {m['nel']} elements "
+                  f"({ne * m['p'] ** 3} subelements) in {dt:.1f} s, scaled to the whole mesh",
+        "cpu": platform.processor() or platform.machine(),
+    }
+
+
+def load_traffic(name):
+    path = os.path.join(ROOT, "profiles", name)
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        return json.load(f)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--cpu-sample", type=int, default=4096, help="elements of the CPU oracle sample")
+    ap.add_argument("--skip-extras", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); multi-GPU sharding is "
+              f"described in DESIGN.md but not built", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import meshgen
+    import paper_2210_12253_amd as lor
+
+    dev = torch.device("cuda:0")
+    log("building C3 inputs")
+    m = meshgen.config_mesh("c3_h1_p6_curved")
+    p, nel, ndofs = m["p"], m["nel"], m["ndofs"]
+    ed = torch.from_numpy(m["elem_dofs"]).to(dev)
+    x = torch.from_numpy(m["coords"]).to(dev)
+    k64 = m["kappa"].to(dev)
+    k32 = k64.float()
+    torch.cuda.synchronize()
+
+    log("pattern")
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    pat = lor.lor_pattern(lor.LOR_H1, p, ed, ndofs)
+    torch.cuda.synchronize()
+    t_pattern = (time.perf_counter() - t) * 1e3
+    nnz = pat.nnz
+    v64 = torch.empty(nnz, dtype=torch.float64, device=dev)
+    v32 = torch.empty(nnz, dtype=torch.float32, device=dev)
+
+    log("timing fp64")
+    ms64 = time_it(lambda: lor.lor_assemble_h1(pat, ed, x, k64, 1.0, out=v64), args.steps, args.warmup)
+    log("timing fp32")
+    ms32 = time_it(lambda: lor.lor_assemble_h1(pat, ed, x, k32, 1.0, dtype=torch.float32, fp64_fallback=True,
+                                               out=v32), args.steps, args.warmup)
+
+    b64 = algorithmic_bytes_h1(nel, p, ndofs, nnz, 8)
+    b32 = algorithmic_bytes_h1(nel, p, ndofs, nnz, 4)
+    ach = b64 / (ms64 * 1e-3) / 1e9
+    traffic = load_traffic("h1_p6_c3_traffic.json")
+    out = {
+        "metric": "LOR assembly MDOF/s & %HBM roofline, H1 p=6: FP64 vs FP32; backward MDOF/s",
+        "value": ndofs / (ms64 * 1e-3) / 1e6,
+        "unit": "MDOF/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms64,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "H1 diffusion+mass LOR assembly, p=6, 32^3 curved hexes (amp 0.1h), "
+                        "log-normal kappa sigma=2, beta=1",
+            "rows": ndofs, "nnz": nnz, "elements": nel, "subelements": nel * p ** 3,
+            "launches_per_step": pat.ncolors,
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": ach,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": ach / HBM_PEAK_GBS,
+            "traffic": traffic,
+            "kernel": "k_h1_assemble<6,double,double> (one dispatch per element colour)",
+            "algorithmic_bytes_per_step": b64,
+        },
+        "fp32": {
+            "ms_per_step": ms32,
+            "value": ndofs / (ms32 * 1e-3) / 1e6,
+            "unit": "MDOF/s",
+            "achieved_GBs": b32 / (ms32 * 1e-3) / 1e9,
+            "frac": b32 / (ms32 * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "speedup_vs_fp64": ms64 / ms32,
+        },
+        "pattern": {"ms": t_pattern, "ms_cold_total": t_pattern + ms64, "ncolors": pat.ncolors},
+    }
+
+    if not args.skip_extras:
+        out["backward"] = bench_backward(lor, meshgen, args, dev)
+        out["nd"] = bench_nd(lor, meshgen, args, dev)
+        log("cpu baseline")
+        out["cpu_baseline"] = cpu_baseline(m, args.cpu_sample)
+    print(json.dumps(out))
+
+
+def bench_backward(lor, meshgen, args, dev):
+    import torch
+    try:
+        m = meshgen.config_mesh("c5_h1_p4_backward")
+        ed = torch.from_numpy(m["elem_dofs"]).to(dev)
+        x = torch.from_numpy(m["coords"]).to(dev)
+        pat = lor.lor_pattern(lor.LOR_H1, m["p"], ed, m["ndofs"])
+        res = {}
+        for name, dt in (("f64", torch.float64), ("f32", torch.float32)):
+            k = m["kappa"].to(dev, dt)
+            gv = meshgen.cotangent(8, pat.nnz, seed=1).to(dev, dt)
+            ws = torch.empty(lor.load_library().lor_backward_workspace(m["p"], m["nel"]), dtype=torch.uint8,
+                             device=dev)
+            ms = time_it(lambda: lor.lor_assemble_backward(pat, ed, x, k, 1.0, gv, dtype=dt, workspace=ws),
+                         args.steps, args.warmup)
+            fwd = time_it(lambda: lor.lor_assemble_h1(pat, ed, x, k, 1.0, dtype=dt), args.steps, args.warmup)
+            res[name] = {"ms": ms, "value": 8 * m["ndofs"] / (ms * 1e-3) / 1e6, "unit": "MDOF/s (batch*rows)",
+                         "forward_batch8_ms": fwd}
+        res["workload"] = "backward of H1 p=4, 16^3 curved hexes, batch 8 kappa fields"
+        res["speedup_f32_vs_f64"] = res["f64"]["ms"] / res["f32"]["ms"]
+        return res
+    except lor.LorError as e:
+        return {"error": str(e)}
+
+
+def bench_nd(lor, meshgen, args, dev):
+    import torch
+    try:
+        m = meshgen.config_mesh("c4_nd_p3_curved")
+        ed = torch.from_numpy(m["elem_dofs"]).to(dev)
+        ee = torch.from_numpy(m["elem_edges"]).to(dev)
+        x = torch.from_numpy(m["coords"]).to(dev)
+        pat = lor.lor_pattern(lor.LOR_ND, m["p"], ee, m["nedges"])
+        res = {}
+        for name, dt in (("f64", torch.float64), ("f32", torch.float32)):
+            k = m["kappa"].to(dev, dt)
+            out = torch.empty(pat.nnz, dtype=dt, device=dev)
+            ms = time_it(lambda: lor.lor_assemble_nd(pat, ed, ee, x, k, 1.0, m["ndofs"], dtype=dt, out=out),
+                         args.steps, args.warmup)
+            res[name] = {"ms": ms, "value": m["nedges"] / (ms * 1e-3) / 1e6, "unit": "MDOF/s"}
+        res["workload"] = "H(curl) LOR assembly, p=3, 24^3 curved hexes, kappa sigma=1, beta=1"
+        res["rows"], res["nnz"] = m["nedges"], pat.nnz
+        return res
+    except lor.LorError as e:
+        return {"error": str(e)}
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,222 @@
+/*
+ * lor.h -- C ABI of the MI355X (gfx950) low-order-refined (LOR) assembly library.
+ *
+ * What is assembled (Pazner, Kolev, Camier, "End-to-end GPU acceleration of
+ * low-order-refined preconditioning for high-order finite element
+ * discretizations"):
+ *   - Section 2.1 (the LOR mesh): each degree-p hexahedron is split at its tensor
+ *     Gauss-Lobatto lattice into p^3 trilinear subelements ("macro element").
+ *   - Section 2.2: the LOR H1 matrix is the Q1 (p = 1) finite element matrix on
+ *     that mesh, here kappa-diffusion + beta-mass, with the same degrees of
+ *     freedom as the high-order space.
+ *   - Section 2.3: the lowest-order interpolation-histopolation H(curl) case is
+ *     the lowest-order Nedelec element on the LOR mesh, here kappa curl-curl +
+ *     beta-mass.
+ *   - Section 3, Step S1.2 (steps A1 and A2): macro-element assembly followed by
+ *     the processor-local CSR matrix (row pointer I, columns J, values A), the
+ *     orientation of vector degrees of freedom carried by their sign.
+ *
+ * Readings of points the paper leaves open: 2x2x2 Gauss-Legendre quadrature per
+ * subelement; kappa constant per subelement, beta a scalar; consistent mass;
+ * CSR with columns sorted ascending and unique per row, both triangles stored,
+ * every structurally present entry kept even where its value cancels.
+ *
+ * Conventions shared by every call
+ *   - Every array argument is a DEVICE pointer (hipMalloc'd / torch CUDA memory)
+ *     owned by the caller, except where a parameter says "host".  The library
+ *     keeps no device memory between calls; lor_pattern allocates and frees its
+ *     own temporaries.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *     lor_pattern synchronises `stream` (it must read counts back); the
+ *     lor_assemble_* calls are asynchronous on `stream` and never synchronise.
+ *   - Status codes are <= 0 (lor_status).  Arguments are validated on the host
+ *     before any device work; on error nothing is launched and lor_last_error()
+ *     returns a message (thread-local).  No C++ exception crosses the ABI.
+ *   - Indices are int32; a mesh whose entry count or nnz reaches 2^31 is
+ *     rejected with LOR_EOVERFLOW.
+ *   - Results are deterministic: repeated calls give bitwise-identical values,
+ *     and A[i][j] and A[j][i] are bitwise equal.
+ */
+#ifndef LOR_H
+#define LOR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  LOR_OK = 0,
+  LOR_EINVAL = -1,        /* bad argument (null pointer, size, p out of range, ...) */
+  LOR_EOVERFLOW = -2,     /* an index or count does not fit int32 */
+  LOR_EDEVICE = -3,       /* a HIP runtime call failed (message has the HIP error) */
+  LOR_EUNSUPPORTED = -4   /* valid input outside what this build handles */
+} lor_status;
+
+typedef enum { LOR_H1 = 0, LOR_ND = 1 } lor_space;
+typedef enum { LOR_F64 = 0, LOR_F32 = 1 } lor_dtype;
+
+/* Highest polynomial degree handled (the whole macro element is staged in LDS). */
+#define LOR_MAX_P 6
+/* Most element colours a schedule may use (see lor_sched). */
+#define LOR_MAX_COLORS 64
+/* Most nonzeros in one row of the assembled matrix. */
+#define LOR_MAX_ROW_NNZ 127
+
+/* FP32 form: subelements whose corner-Jacobian ratio max/min exceeds
+ * det_ratio_thresh (or whose smallest corner Jacobian is <= 0) are integrated
+ * with FP64 geometry instead of FP32. */
+#define LOR_FP64_FALLBACK 0x1u
+
+/*
+ * Assembly schedule written by lor_pattern and read by the lor_assemble_* calls.
+ * The struct itself lives in host memory; `dev` is a caller-owned device
+ * buffer of `dev_bytes` bytes that holds the device part:
+ *   - the element order by colour (elements of one colour share no degree of
+ *     freedom, so one colour is assembled without write conflicts; colours run
+ *     in increasing order on the stream),
+ *   - per element, for each of its `nent` local stencil entries, the position
+ *     of the entry inside its CSR row and whether this element is the first
+ *     (lowest colour) contributor to that entry, stored once per distinct
+ *     element class (`nclass` classes),
+ *   - the vertex-to-element incidence lists used by the adjoint,
+ *   - the reference-element stencil tables (the shared column pattern of one
+ *     macro element, computed once, as in step A1).
+ * The host fields are descriptive except color_ptr (used to size launches).
+ */
+typedef struct lor_sched {
+  int32_t space;                 /* lor_space */
+  int32_t p;
+  int64_t nel;
+  int64_t nrows;
+  int64_t nnz;
+  int32_t nloc;                  /* local dofs per element */
+  int32_t nent;                  /* local stencil entries per element */
+  int32_t ncolors;
+  int32_t max_row_nnz;
+  int32_t color_ptr[LOR_MAX_COLORS + 1];  /* colour c = order[color_ptr[c] .. color_ptr[c+1]) */
+  int64_t nclass;
+  size_t dev_bytes;              /* written by phase 1: bytes to allocate for dev */
+  void* dev;                     /* set by the caller before phase 2 */
+  size_t off_order, off_color, off_class, off_tables;
+  size_t off_inc_ptr, off_inc_list;
+  size_t off_st_ptr, off_st_col, off_ent_row, off_recipe;
+  size_t reserved[8];
+} lor_sched;
+
+/*
+ * lor_pattern -- sparsity pattern (steps A1/A2: the shared local column pattern,
+ * row counts, scan, column fill) and the assembly schedule.
+ *
+ *   space     LOR_H1: rows are mesh vertices; LOR_ND: rows are mesh edges.
+ *   p         polynomial degree, 1 <= p <= LOR_MAX_P.
+ *   nel       number of (macro) elements, >= 0.
+ *   nrows     number of global dofs (vertices or edges).
+ *   elem_map  [nel][nloc] int32.  LOR_H1: nloc = (p+1)^3 global vertex ids,
+ *             local vertex i + (p+1)(j + (p+1)k).  LOR_ND: nloc = 3p(p+1)^2
+ *             signed global edge ids: x-edges i + p(j + (p+1)k) first, then
+ *             y-edges (offset p(p+1)^2, index i + (p+1)(j + p k)), then z-edges
+ *             (offset 2p(p+1)^2, index i + (p+1)(j + (p+1)k)); a local edge
+ *             points along its +axis; entry v >= 0 is edge v with that
+ *             orientation, v < 0 is edge -1-v with the opposite one.
+ *   row_ptr   [nrows+1] int32, written in phase 1.
+ *   nnz       HOST int64, written in phase 1.
+ *   col_idx   NULL selects phase 1.  Otherwise [nnz] int32, written in phase 2
+ *             (sorted ascending, unique per row).
+ *   sched     HOST struct.  Phase 1 writes sched->dev_bytes; the caller then
+ *             sets sched->dev to a device buffer of that size and calls again
+ *             with col_idx != NULL (phase 2), which fills the schedule.
+ * Phase 1 and phase 2 each synchronise `stream`.  Errors: LOR_EINVAL (bad
+ * arguments, a map entry out of [0, nrows), an element whose lattice is not
+ * conforming with its neighbours), LOR_EOVERFLOW (nnz or nel*nloc >= 2^31),
+ * LOR_EUNSUPPORTED (a row with more than LOR_MAX_ROW_NNZ nonzeros, or more than
+ * LOR_MAX_COLORS colours).
+ */
+int lor_pattern(int space, int p, int64_t nel, int64_t nrows, const int32_t* elem_map,
+                int32_t* row_ptr, int64_t* nnz, int32_t* col_idx, lor_sched* sched,
+                void* stream);
+
+/*
+ * lor_assemble_h1 -- values of the LOR H1 matrix (Section 2.2; Step S1.2 A1+A2):
+ *   A = sum over subelements s of  kappa_s K^s + beta M^s,
+ *   K^s_uv = sum_q w_q det J (J^-T g_u).(J^-T g_v),  M^s_uv = sum_q w_q det J phi_u phi_v,
+ * 2x2x2 Gauss points q on each trilinear subelement.
+ *
+ *   p, nel, ndofs  as for lor_pattern (space LOR_H1).
+ *   batch          number of independent coefficient fields (>= 1).
+ *   elem_dofs      [nel][(p+1)^3] int32, the map given to lor_pattern.
+ *   coords         [ndofs][3] float64 vertex coordinates (always FP64).
+ *   kappa          [batch][nel][p^3] in `dtype`; subelement i + p(j + p k).
+ *   beta           mass coefficient (scalar).
+ *   row_ptr, sched the pattern and schedule from lor_pattern(LOR_H1, ...).
+ *   values         [batch][nnz] in `dtype`, overwritten (every entry written).
+ *   dtype          LOR_F64: all arithmetic in FP64.  LOR_F32: edge vectors
+ *                  formed in FP64 then rounded; Jacobians, quadrature and
+ *                  subelement matrices in FP32 (FP64 on flagged subelements if
+ *                  flags has LOR_FP64_FALLBACK); sums within an element in FP64;
+ *                  stored as FP32.
+ *   flags          0 or LOR_FP64_FALLBACK (FP32 only).
+ *   det_ratio_thresh  threshold of the fallback (e.g. 10).
+ *   diag           NULL or device int32[2]: [0] += number of subelements that
+ *                  took the FP64 fallback, [1] += number of subelements with a
+ *                  non-positive Jacobian at a quadrature point (inverted; their
+ *                  values are still written).  The caller zeroes it.
+ */
+int lor_assemble_h1(int p, int64_t nel, int64_t ndofs, int batch, const int32_t* elem_dofs,
+                    const double* coords, const void* kappa, double beta, const int32_t* row_ptr,
+                    const lor_sched* sched, void* values, int dtype, unsigned flags,
+                    double det_ratio_thresh, int32_t* diag, void* stream);
+
+/*
+ * lor_assemble_nd -- values of the LOR H(curl) matrix (Section 2.3; Step S1.2
+ * with orientation signs, A2): lowest-order Nedelec on each subelement,
+ *   K_ab = sum_q w det J (J c_a / det J).(J c_b / det J),
+ *   M_ab = sum_q w det J (J^-T n_a).(J^-T n_b),
+ * times sigma_a sigma_b from the signed edge map; A = kappa_s K + beta M.
+ *   elem_dofs   [nel][(p+1)^3] vertex map (geometry).
+ *   elem_edges  [nel][3p(p+1)^2] signed edge map (the one given to lor_pattern).
+ *   nedges      number of rows.  Other arguments as for lor_assemble_h1.
+ */
+int lor_assemble_nd(int p, int64_t nel, int64_t ndofs_h1, int64_t nedges, int batch,
+                    const int32_t* elem_dofs, const int32_t* elem_edges, const double* coords,
+                    const void* kappa, double beta, const int32_t* row_ptr, const lor_sched* sched,
+                    void* values, int dtype, unsigned flags, double det_ratio_thresh,
+                    int32_t* diag, void* stream);
+
+/*
+ * lor_assemble_backward -- adjoint of lor_assemble_h1 with respect to kappa and
+ * the vertex coordinates, for the loss L = sum_b <grad_values[b], values[b]>:
+ *   grad_kappa[b][e][s] = dL/dkappa[b][e][s]                   (overwritten)
+ *   grad_coords[v][c]   = sum_b dL/dcoords[v][c]  (FP64, overwritten; coords are
+ *                         shared by the batch, so their gradient is summed)
+ *   grad_values  [batch][nnz] in dtype;  grad_kappa [batch][nel][p^3] in dtype.
+ *   workspace    device buffer of lor_backward_workspace(p, nel) bytes (holds
+ *                the per-element coordinate gradient before the vertex gather).
+ * Subelement geometry is recomputed, not stored.  Arithmetic in dtype; the
+ * vertex gather sums in FP64 in a fixed order (deterministic).
+ */
+int lor_assemble_backward(int p, int64_t nel, int64_t ndofs, int batch, const int32_t* elem_dofs,
+                          const double* coords, const void* kappa, double beta,
+                          const int32_t* row_ptr, const lor_sched* sched, const void* grad_values,
+                          void* grad_kappa, double* grad_coords, void* workspace, int dtype,
+                          void* stream);
+
+/* Bytes of the `workspace` argument of lor_assemble_backward. */
+size_t lor_backward_workspace(int p, int64_t nel);
+
+/* sizeof(lor_sched) as compiled into the library (for bindings to check their layout). */
+size_t lor_sched_bytes(void);
+
+/* Message for the last non-OK status returned on this thread ("" if none). */
+const char* lor_last_error(void);
+
+/* ABI version of this library (incremented on incompatible changes). */
+int lor_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LOR_H */

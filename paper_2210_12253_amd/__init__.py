@@ -1,0 +1,19 @@
+"""MI355X-native (gfx950) assembly of low-order-refined (LOR) matrices.
+
+The compute path is the HIP library liblor.so (C ABI in include/lor.h); this
+package is its Python binding.
+"""
+from .lor import (  # noqa: F401
+    LOR_F32,
+    LOR_F64,
+    LOR_H1,
+    LOR_ND,
+    LorError,
+    LorH1,
+    Pattern,
+    load_library,
+    lor_assemble_backward,
+    lor_assemble_h1,
+    lor_assemble_nd,
+    lor_pattern,
+)

@@ -1,0 +1,288 @@
+// Values of the LOR H1 matrix (Step S1.2, A1 + A2 fused), one workgroup per
+// batch of macro elements of one colour.
+//
+// The paper assembles each macro element's sparse block in global memory with
+// one thread per subelement and atomic additions, then scatters the blocks
+// into CSR.  Here the block never leaves the chip:
+//
+//   phase 0  gather the macro element's (p+1)^3 vertex coordinates and the row
+//            pointers of its vertices into LDS;
+//   phase 1  one lane per subelement integrates its 8x8 matrix (36 unique
+//            entries, sum-factorised 2x2x2 Gauss) into LDS;
+//   phase 2  one lane per local vertex (row) sums the rows of the <= 8
+//            subelements around it in a fixed order (atomic-free, FP64 sums,
+//            bitwise symmetric), then writes the finished local row into LDS
+//            in the compact local-stencil order;
+//   phase 3  lanes walk the compact entries and store them at
+//            row_ptr[row] + position-in-row (from the schedule): a plain store
+//            for the entry's first contributor, an add to the value already
+//            there for the others.  Colours run in order, so every entry's
+//            contributions are summed in the same order (deterministic).
+#include "lor_common.hpp"
+#include "lor_h1_math.hpp"
+
+namespace lor {
+
+template <int P>
+struct H1Cfg {
+  static constexpr int Q = P + 1;
+  static constexpr int NSUB = P * P * P;
+  static constexpr int NLOC = Q * Q * Q;
+  static constexpr int T1 = 3 * P + 1;            // stencil entries per axis
+  static constexpr int NENT = T1 * T1 * T1;       // local stencil entries per element
+  // elements per workgroup: 256 lanes cover the subelements and every lane owns
+  // at most two local rows
+  static constexpr int E = P == 1 ? 64 : P == 2 ? 16 : P == 3 ? 8 : P == 4 ? 4 : P == 5 ? 2 : 1;
+  static constexpr int THREADS = 256;
+  static_assert(E * NLOC <= 2 * THREADS, "two rows per lane");
+  static_assert(E * NSUB <= THREADS, "one subelement per lane");
+};
+
+// number of stencil offsets along one axis at lattice coordinate t, and the
+// prefix sum of that count over coordinates < t
+template <int P>
+__device__ __forceinline__ int cnt1(int t) {
+  return (t == 0 || t == P) ? 2 : 3;
+}
+template <int P>
+__device__ __forceinline__ int pre1(int t) {
+  return t == 0 ? 0 : 3 * t - 1;
+}
+
+template <int P, typename T, typename R>
+__global__ __launch_bounds__(256) void k_h1_assemble(
+    const int32_t* __restrict__ order, int32_t ncol, const int32_t* __restrict__ elem_dofs,
+    const double* __restrict__ coords, const T* __restrict__ kappa, T beta,
+    const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ class_id,
+    const uint8_t* __restrict__ tables, const int32_t* __restrict__ ent_row, int64_t nel,
+    int64_t nnz, T* __restrict__ values, unsigned flags, R det_thresh, int32_t* __restrict__ diag) {
+  using C = H1Cfg<P>;
+  constexpr int Q = C::Q, NSUB = C::NSUB, NLOC = C::NLOC, NENT = C::NENT, E = C::E;
+  constexpr int SUBW = E * NSUB * 36;        // subelement entries, layout [E][36][NSUB]
+  constexpr int STGW = E * NENT;             // finished local entries, [E][NENT]
+  constexpr int REGW = SUBW > STGW ? SUBW : STGW;
+  __shared__ double sX[E * NLOC * 3];
+  __shared__ int32_t sRp[E * NLOC];
+  __shared__ R sSub[REGW];
+  __shared__ int32_t sElem[E];
+  T* sStg = reinterpret_cast<T*>(sSub);
+  static_assert(sizeof(T) <= sizeof(R), "staging aliases the subelement region");
+
+  const int tid = threadIdx.x;
+  const int64_t b = blockIdx.y;
+  kappa += b * nel * NSUB;
+  values += b * nnz;
+  const int64_t first = static_cast<int64_t>(blockIdx.x) * E;
+  const int ne = static_cast<int>(ncol - first < E ? ncol - first : E);
+  if (tid < E) sElem[tid] = tid < ne ? order[first + tid] : 0;
+  __syncthreads();
+
+  // phase 0: coordinates and row pointers of the element vertices
+  for (int i = tid; i < ne * NLOC; i += C::THREADS) {
+    const int el = i / NLOC;
+    const int l = i - el * NLOC;
+    const int32_t g = elem_dofs[static_cast<int64_t>(sElem[el]) * NLOC + l];
+    sX[3 * i + 0] = coords[3 * static_cast<int64_t>(g) + 0];
+    sX[3 * i + 1] = coords[3 * static_cast<int64_t>(g) + 1];
+    sX[3 * i + 2] = coords[3 * static_cast<int64_t>(g) + 2];
+    sRp[i] = row_ptr[g];
+  }
+  __syncthreads();
+
+  // phase 1: subelement matrices
+  if (tid < ne * NSUB) {
+    const int el = tid / NSUB;
+    const int s = tid - el * NSUB;
+    const int si = s % P, sj = (s / P) % P, sk = s / (P * P);
+    double X[8][3];
+#pragma unroll
+    for (int v = 0; v < 8; ++v) {
+      const int lv = (si + (v & 1)) + Q * ((sj + ((v >> 1) & 1)) + Q * (sk + (v >> 2)));
+#pragma unroll
+      for (int d = 0; d < 3; ++d) X[v][d] = sX[3 * (el * NLOC + lv) + d];
+    }
+    const R kap = static_cast<R>(kappa[static_cast<int64_t>(sElem[el]) * NSUB + s]);
+    R* out = sSub + el * 36 * NSUB + s;
+    bool done = false;
+    if constexpr (!std::is_same<R, double>::value) {
+      if (flags & LOR_FP64_FALLBACK) {
+        R ex[2][2][3], ey[2][2][3], ez[2][2][3];
+        h1_edges<R>(X, ex, ey, ez);
+        R dmin, dmax;
+        h1_corner_det_range<R>(ex, ey, ez, dmin, dmax);
+        if (!(dmin > R(0)) || dmax > det_thresh * dmin) {
+          double dx[2][2][3], dy[2][2][3], dz[2][2][3];
+          h1_edges<double>(X, dx, dy, dz);
+          H1Factors<double> F;
+          const bool ok = h1_factors<double>(dx, dy, dz, static_cast<double>(kap), static_cast<double>(beta), F);
+#pragma unroll
+          for (int u = 0; u < 8; ++u)
+#pragma unroll
+            for (int v = u; v < 8; ++v) out[pair_index(u, v) * NSUB] = static_cast<R>(h1_entry<double>(F, u, v));
+          if (diag) {
+            atomicAdd(&diag[0], 1);
+            if (!ok) atomicAdd(&diag[1], 1);
+          }
+          done = true;
+        }
+      }
+    }
+    if (!done) {
+      R ex[2][2][3], ey[2][2][3], ez[2][2][3];
+      h1_edges<R>(X, ex, ey, ez);
+      H1Factors<R> F;
+      const bool ok = h1_factors<R>(ex, ey, ez, kap, static_cast<R>(beta), F);
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+#pragma unroll
+        for (int v = u; v < 8; ++v) out[pair_index(u, v) * NSUB] = h1_entry<R>(F, u, v);
+      if (!ok && diag) atomicAdd(&diag[1], 1);
+    }
+  }
+  __syncthreads();
+
+  // phase 2: local rows.  Lane owns rows tid and tid + 256.
+  double acc[2][27];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+#pragma unroll
+    for (int o = 0; o < 27; ++o) acc[h][o] = 0.0;
+    const int r = tid + h * C::THREADS;
+    if (r < ne * NLOC) {
+      const int el = r / NLOC;
+      const int l = r - el * NLOC;
+      const int x = l % Q, y = (l / Q) % Q, z = l / (Q * Q);
+      const R* base = sSub + el * 36 * NSUB;
+      // corner u of the subelement s = (x,y,z) - u; s decreases as u grows
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int a = u & 1, bb = (u >> 1) & 1, c = u >> 2;
+        const int sx = x - a, sy = y - bb, sz = z - c;
+        if (sx >= 0 && sx < P && sy >= 0 && sy < P && sz >= 0 && sz < P) {
+          const int s = sx + P * (sy + P * sz);
+#pragma unroll
+          for (int v = 0; v < 8; ++v) {
+            const int o = ((v & 1) - a + 1) + 3 * ((((v >> 1) & 1) - bb + 1) + 3 * ((v >> 2) - c + 1));
+            acc[h][o] += static_cast<double>(base[pair_index(u, v) * NSUB + s]);
+          }
+        }
+      }
+    }
+  }
+  __syncthreads();  // every lane has read sSub; now it becomes the staging area
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int r = tid + h * C::THREADS;
+    if (r < ne * NLOC) {
+      const int el = r / NLOC;
+      const int l = r - el * NLOC;
+      const int x = l % Q, y = (l / Q) % Q, z = l / (Q * Q);
+      const int nx = cnt1<P>(x), ny = cnt1<P>(y);
+      const int rbase = pre1<P>(z) * C::T1 * C::T1 + cnt1<P>(z) * pre1<P>(y) * C::T1 + cnt1<P>(z) * ny * pre1<P>(x);
+      T* dst = sStg + el * NENT + rbase;
+      const int x0 = x > 0 ? 1 : 0, y0 = y > 0 ? 1 : 0, z0 = z > 0 ? 1 : 0;
+#pragma unroll
+      for (int o = 0; o < 27; ++o) {
+        const int dx = o % 3 - 1, dy = (o / 3) % 3 - 1, dz = o / 9 - 1;
+        if (x + dx < 0 || x + dx > P || y + dy < 0 || y + dy > P || z + dz < 0 || z + dz > P) continue;
+        const int idx = ((dz + z0) * ny + (dy + y0)) * nx + (dx + x0);
+        dst[idx] = static_cast<T>(acc[h][o]);
+      }
+    }
+  }
+  __syncthreads();
+
+  // phase 3: store into the CSR values
+  for (int i = tid; i < ne * NENT; i += C::THREADS) {
+    const int el = i / NENT;
+    const int k = i - el * NENT;
+    const int32_t e = sElem[el];
+    const uint8_t t = tables[static_cast<int64_t>(class_id[e]) * NENT + k];
+    const int64_t pos = static_cast<int64_t>(sRp[el * NLOC + ent_row[k]]) + (t & kRankMask);
+    const T v = sStg[i];
+    if (t & kFirstBit)
+      values[pos] = v;
+    else
+      values[pos] = values[pos] + v;
+  }
+}
+
+template <int P, typename T, typename R>
+static int launch_h1(const lor_sched* sched, int batch, const int32_t* elem_dofs, const double* coords,
+                     const void* kappa, double beta, const int32_t* row_ptr, void* values, unsigned flags,
+                     double thr, int32_t* diag, hipStream_t st) {
+  using C = H1Cfg<P>;
+  const int32_t* order = dev_at<int32_t>(sched, sched->off_order);
+  const int32_t* cls = dev_at<int32_t>(sched, sched->off_class);
+  const uint8_t* tab = dev_at<uint8_t>(sched, sched->off_tables);
+  const int32_t* ent_row = dev_at<int32_t>(sched, sched->off_ent_row);
+  for (int c = 0; c < sched->ncolors; ++c) {
+    const int32_t n = sched->color_ptr[c + 1] - sched->color_ptr[c];
+    if (n <= 0) continue;
+    dim3 grid(static_cast<unsigned>(ceil_div(n, C::E)), static_cast<unsigned>(batch));
+    k_h1_assemble<P, T, R><<<grid, C::THREADS, 0, st>>>(
+        order + sched->color_ptr[c], n, elem_dofs, coords, static_cast<const T*>(kappa), static_cast<T>(beta),
+        row_ptr, cls, tab, ent_row, sched->nel, sched->nnz, static_cast<T*>(values), flags, static_cast<R>(thr),
+        diag);
+    LOR_LAUNCHED("k_h1_assemble");
+  }
+  return LOR_OK;
+}
+
+template <typename T, typename R>
+static int dispatch_h1(int p, const lor_sched* s, int batch, const int32_t* ed, const double* x, const void* k,
+                       double beta, const int32_t* rp, void* v, unsigned f, double thr, int32_t* diag,
+                       hipStream_t st) {
+  switch (p) {
+    case 1: return launch_h1<1, T, R>(s, batch, ed, x, k, beta, rp, v, f, thr, diag, st);
+    case 2: return launch_h1<2, T, R>(s, batch, ed, x, k, beta, rp, v, f, thr, diag, st);
+    case 3: return launch_h1<3, T, R>(s, batch, ed, x, k, beta, rp, v, f, thr, diag, st);
+    case 4: return launch_h1<4, T, R>(s, batch, ed, x, k, beta, rp, v, f, thr, diag, st);
+    case 5: return launch_h1<5, T, R>(s, batch, ed, x, k, beta, rp, v, f, thr, diag, st);
+    case 6: return launch_h1<6, T, R>(s, batch, ed, x, k, beta, rp, v, f, thr, diag, st);
+    default: LOR_FAIL(LOR_EUNSUPPORTED, "p = %d not compiled", p);
+  }
+}
+
+// Shared argument checks of the value calls.
+int check_sched(const lor_sched* s, int space, int p, int64_t nel, int64_t nrows) {
+  if (!s) LOR_FAIL(LOR_EINVAL, "sched is NULL");
+  if (!s->dev) LOR_FAIL(LOR_EINVAL, "sched->dev is NULL (run lor_pattern phase 2 first)");
+  if (s->space != space) LOR_FAIL(LOR_EINVAL, "sched was built for another space");
+  if (s->p != p || s->nel != nel || s->nrows != nrows)
+    LOR_FAIL(LOR_EINVAL, "sched (p=%d nel=%lld nrows=%lld) does not match the call (p=%d nel=%lld nrows=%lld)",
+             s->p, (long long)s->nel, (long long)s->nrows, p, (long long)nel, (long long)nrows);
+  if (s->ncolors < 0 || s->ncolors > LOR_MAX_COLORS) LOR_FAIL(LOR_EINVAL, "sched->ncolors out of range");
+  if (s->color_ptr[s->ncolors] != nel) LOR_FAIL(LOR_EINVAL, "sched colour table does not cover the elements");
+  return LOR_OK;
+}
+
+}  // namespace lor
+
+using namespace lor;
+
+extern "C" int lor_assemble_h1(int p, int64_t nel, int64_t ndofs, int batch, const int32_t* elem_dofs,
+                               const double* coords, const void* kappa, double beta, const int32_t* row_ptr,
+                               const lor_sched* sched, void* values, int dtype, unsigned flags,
+                               double det_ratio_thresh, int32_t* diag, void* stream) {
+  clear_error();
+  if (p < 1 || p > LOR_MAX_P) LOR_FAIL(LOR_EINVAL, "p = %d outside [1, %d]", p, LOR_MAX_P);
+  if (nel < 0 || ndofs < 1) LOR_FAIL(LOR_EINVAL, "nel < 0 or ndofs < 1");
+  if (batch < 1) LOR_FAIL(LOR_EINVAL, "batch < 1");
+  if (dtype != LOR_F64 && dtype != LOR_F32) LOR_FAIL(LOR_EINVAL, "dtype must be LOR_F64 or LOR_F32");
+  if (flags & ~LOR_FP64_FALLBACK) LOR_FAIL(LOR_EINVAL, "unknown flag bits 0x%x", flags);
+  if ((flags & LOR_FP64_FALLBACK) && !(det_ratio_thresh >= 1.0))
+    LOR_FAIL(LOR_EINVAL, "det_ratio_thresh must be >= 1");
+  if (nel > 0 && (!elem_dofs || !coords || !kappa || !row_ptr || !values))
+    LOR_FAIL(LOR_EINVAL, "a required pointer is NULL");
+  int rc = check_sched(sched, LOR_H1, p, nel, ndofs);
+  if (rc) return rc;
+  if (static_cast<int64_t>(batch) * sched->nnz >= (int64_t(1) << 40)) LOR_FAIL(LOR_EOVERFLOW, "batch * nnz too large");
+  if (nel == 0) return LOR_OK;
+  hipStream_t st = as_stream(stream);
+  if (dtype == LOR_F64)
+    return dispatch_h1<double, double>(p, sched, batch, elem_dofs, coords, kappa, beta, row_ptr, values, 0u,
+                                       det_ratio_thresh, diag, st);
+  return dispatch_h1<float, float>(p, sched, batch, elem_dofs, coords, kappa, beta, row_ptr, values, flags,
+                                   det_ratio_thresh, diag, st);
+}

@@ -1,0 +1,751 @@
+// Sparsity pattern and assembly schedule of the LOR matrices.
+//
+// Step S1.2 of the paper builds the processor-local CSR matrix of the LOR
+// discretisation in two stages: A1 fills per-macro-element sparse blocks that
+// share one local column pattern (computed once for the reference macro
+// element), A2 counts the nonzeros of every row without double-counting the
+// entries seen by several macro elements, scans the counts into the row
+// pointer, then fills the columns.  This file does the integer half of that:
+//
+//   * reference element: the local stencil (which local dofs a local dof
+//     couples to: the 27-point lattice neighbourhood for vertices, the edges of
+//     the shared subelements for Nedelec edges), computed once on the host and
+//     copied into the schedule -- the analogue of the shared column array J_hat;
+//   * vertex/edge -> (element, local dof) incidence lists (transpose of the
+//     element map, counting sort, each list sorted so the result is
+//     deterministic);
+//   * per row: the sorted union of the local stencils of every incident
+//     element gives the columns (deduplicated exactly, so no entry is counted
+//     twice whatever the number of elements sharing the row);
+//   * exclusive scan of the counts -> row pointer;
+//   * element colouring (greedy in element order, run as Jones-Plassmann
+//     rounds): elements of one colour share no dof, so the value kernels can
+//     add a colour's contributions without atomics and in a fixed order;
+//   * per element and local stencil entry, the position of the entry inside its
+//     CSR row and whether the element is the entry's first contributor.
+#include <algorithm>
+#include <climits>
+#include <vector>
+
+#include "lor_common.hpp"
+
+namespace lor {
+
+// ------------------------------------------------------------ device buffer
+
+struct DevBuf {
+  void* p = nullptr;
+  ~DevBuf() {
+    if (p) (void)hipFree(p);
+  }
+  int alloc(size_t bytes) {
+    if (bytes == 0) bytes = 16;
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
+      p = nullptr;
+      set_error("hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+      return LOR_EDEVICE;
+    }
+    return LOR_OK;
+  }
+  template <typename T>
+  T* as() const {
+    return static_cast<T*>(p);
+  }
+};
+
+// ---------------------------------------------------------- reference element
+
+struct RefElem {
+  int nloc = 0, nent = 0;
+  std::vector<int32_t> st_ptr, st_col, ent_row;
+  std::vector<int32_t> reps;    // local dofs whose incidences give element adjacency
+  std::vector<int32_t> recipe;  // Nedelec: per local edge, subelement contributions
+};
+
+static int nd_local(int p, int ax, int i, int j, int k) {
+  const int q = p + 1;
+  if (ax == 0) return i + p * (j + q * k);
+  if (ax == 1) return p * q * q + i + q * (j + p * k);
+  return 2 * p * q * q + i + q * (j + q * k);
+}
+
+// The 12 local edges of subelement (i,j,k): x-edges (b,c) -> b + 2c, y-edges
+// (a,c) -> 4 + a + 2c, z-edges (a,b) -> 8 + a + 2b.
+static void nd_sub_edges(int p, int i, int j, int k, int out[12]) {
+  for (int c = 0; c < 2; ++c)
+    for (int b = 0; b < 2; ++b) out[b + 2 * c] = nd_local(p, 0, i, j + b, k + c);
+  for (int c = 0; c < 2; ++c)
+    for (int a = 0; a < 2; ++a) out[4 + a + 2 * c] = nd_local(p, 1, i + a, j, k + c);
+  for (int b = 0; b < 2; ++b)
+    for (int a = 0; a < 2; ++a) out[8 + a + 2 * b] = nd_local(p, 2, i + a, j + b, k);
+}
+
+static RefElem build_ref_h1(int p) {
+  RefElem r;
+  const int q = p + 1;
+  r.nloc = q * q * q;
+  r.st_ptr.push_back(0);
+  for (int k = 0; k < q; ++k)
+    for (int j = 0; j < q; ++j)
+      for (int i = 0; i < q; ++i) {
+        const int l = i + q * (j + q * k);
+        for (int dz = -1; dz <= 1; ++dz)
+          for (int dy = -1; dy <= 1; ++dy)
+            for (int dx = -1; dx <= 1; ++dx) {
+              const int a = i + dx, b = j + dy, c = k + dz;
+              if (a < 0 || b < 0 || c < 0 || a > p || b > p || c > p) continue;
+              r.st_col.push_back(a + q * (b + q * c));
+              r.ent_row.push_back(l);
+            }
+        r.st_ptr.push_back(static_cast<int32_t>(r.st_col.size()));
+      }
+  r.nent = static_cast<int>(r.st_col.size());
+  for (int c = 0; c < 2; ++c)
+    for (int b = 0; b < 2; ++b)
+      for (int a = 0; a < 2; ++a) r.reps.push_back(a * p + q * (b * p + q * (c * p)));
+  return r;
+}
+
+static RefElem build_ref_nd(int p) {
+  RefElem r;
+  const int q = p + 1;
+  r.nloc = 3 * p * q * q;
+  std::vector<std::vector<int>> nbr(r.nloc);
+  // recipe: per local edge, 4 slots of (subelement << 4 | local index), -1 if
+  // absent, followed by 4 x 12 stencil positions of the subelement's edges.
+  const int RS = 4 + 48;
+  r.recipe.assign(static_cast<size_t>(r.nloc) * RS, -1);
+  std::vector<int> nsub(r.nloc, 0);
+  for (int k = 0; k < p; ++k)
+    for (int j = 0; j < p; ++j)
+      for (int i = 0; i < p; ++i) {
+        int ed[12];
+        nd_sub_edges(p, i, j, k, ed);
+        const int s = i + p * (j + p * k);
+        for (int u = 0; u < 12; ++u) {
+          const int l = ed[u];
+          r.recipe[static_cast<size_t>(l) * RS + nsub[l]] = (s << 4) | u;
+          ++nsub[l];
+          for (int v = 0; v < 12; ++v) nbr[l].push_back(ed[v]);
+        }
+      }
+  r.st_ptr.push_back(0);
+  for (int l = 0; l < r.nloc; ++l) {
+    auto& v = nbr[l];
+    std::sort(v.begin(), v.end());
+    v.erase(std::unique(v.begin(), v.end()), v.end());
+    for (int c : v) {
+      r.st_col.push_back(c);
+      r.ent_row.push_back(l);
+    }
+    r.st_ptr.push_back(static_cast<int32_t>(r.st_col.size()));
+    // stencil positions of each contributing subelement's edges
+    for (int m = 0; m < nsub[l]; ++m) {
+      const int code = r.recipe[static_cast<size_t>(l) * RS + m];
+      const int s = code >> 4;
+      const int si = s % p, sj = (s / p) % p, sk = s / (p * p);
+      int ed[12];
+      nd_sub_edges(p, si, sj, sk, ed);
+      for (int w = 0; w < 12; ++w) {
+        const int pos = static_cast<int>(std::lower_bound(v.begin(), v.end(), ed[w]) - v.begin());
+        r.recipe[static_cast<size_t>(l) * RS + 4 + m * 12 + w] = pos;
+      }
+    }
+  }
+  r.nent = static_cast<int>(r.st_col.size());
+  // both end edges of every coarse edge: elements sharing an edge dof share one
+  for (int c = 0; c < 2; ++c)
+    for (int b = 0; b < 2; ++b) {
+      r.reps.push_back(nd_local(p, 0, 0, b * p, c * p));
+      r.reps.push_back(nd_local(p, 0, p - 1, b * p, c * p));
+      r.reps.push_back(nd_local(p, 1, b * p, 0, c * p));
+      r.reps.push_back(nd_local(p, 1, b * p, p - 1, c * p));
+      r.reps.push_back(nd_local(p, 2, b * p, c * p, 0));
+      r.reps.push_back(nd_local(p, 2, b * p, c * p, p - 1));
+    }
+  std::sort(r.reps.begin(), r.reps.end());
+  r.reps.erase(std::unique(r.reps.begin(), r.reps.end()), r.reps.end());
+  return r;
+}
+
+static RefElem build_ref(int space, int p) { return space == LOR_H1 ? build_ref_h1(p) : build_ref_nd(p); }
+
+// ------------------------------------------------------------------- scan
+
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 8;
+constexpr int kScanTile = kScanThreads * kScanItems;
+
+template <typename TI>
+__global__ __launch_bounds__(kScanThreads) void k_scan_tiles(const TI* __restrict__ in, int64_t n,
+                                                             int64_t* __restrict__ out,
+                                                             int64_t* __restrict__ tile_sums) {
+  __shared__ int64_t sh[kScanThreads];
+  const int t = threadIdx.x;
+  const int64_t base = static_cast<int64_t>(blockIdx.x) * kScanTile + t * kScanItems;
+  int64_t v[kScanItems];
+  int64_t s = 0;
+#pragma unroll
+  for (int i = 0; i < kScanItems; ++i) {
+    v[i] = (base + i < n) ? static_cast<int64_t>(in[base + i]) : 0;
+    s += v[i];
+  }
+  sh[t] = s;
+  __syncthreads();
+  for (int off = 1; off < kScanThreads; off <<= 1) {
+    const int64_t x = (t >= off) ? sh[t - off] : 0;
+    __syncthreads();
+    sh[t] += x;
+    __syncthreads();
+  }
+  int64_t ex = sh[t] - s;
+#pragma unroll
+  for (int i = 0; i < kScanItems; ++i) {
+    if (base + i < n) out[base + i] = ex;
+    ex += v[i];
+  }
+  if (t == kScanThreads - 1) tile_sums[blockIdx.x] = sh[t];
+}
+
+__global__ void k_scan_add(int64_t* __restrict__ out, int64_t n, const int64_t* __restrict__ tile_off) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) out[i] += tile_off[i / kScanTile];
+}
+
+template <typename TI>
+__global__ void k_scan_total(const TI* __restrict__ in, int64_t n, int64_t* __restrict__ out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) out[n] = (n == 0) ? 0 : out[n - 1] + static_cast<int64_t>(in[n - 1]);
+}
+
+// Exclusive scan of n values into out[0..n], out[n] = total.
+template <typename TI>
+static int scan_exclusive(const TI* in, int64_t n, int64_t* out, hipStream_t st) {
+  if (n == 0) {
+    k_scan_total<TI><<<1, 1, 0, st>>>(in, 0, out);
+    LOR_LAUNCHED("k_scan_total");
+    return LOR_OK;
+  }
+  const int64_t ntiles = ceil_div(n, kScanTile);
+  DevBuf sums, offs;
+  int rc = sums.alloc(sizeof(int64_t) * (ntiles + 1));
+  if (rc) return rc;
+  rc = offs.alloc(sizeof(int64_t) * (ntiles + 1));
+  if (rc) return rc;
+  k_scan_tiles<TI><<<ntiles, kScanThreads, 0, st>>>(in, n, out, sums.as<int64_t>());
+  LOR_LAUNCHED("k_scan_tiles");
+  if (ntiles > 1) {
+    rc = scan_exclusive<int64_t>(sums.as<int64_t>(), ntiles, offs.as<int64_t>(), st);
+    if (rc) return rc;
+    k_scan_add<<<ceil_div(n, 256), 256, 0, st>>>(out, n, offs.as<int64_t>());
+    LOR_LAUNCHED("k_scan_add");
+  }
+  k_scan_total<TI><<<1, 1, 0, st>>>(in, n, out);
+  LOR_LAUNCHED("k_scan_total");
+  return LOR_OK;
+}
+
+// ------------------------------------------------------------ small kernels
+
+__device__ __forceinline__ int32_t dof_id(int32_t v, int is_signed) {
+  return (is_signed && v < 0) ? -1 - v : v;
+}
+
+__global__ void k_fill_i32(int32_t* __restrict__ a, int64_t n, int32_t v) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = v;
+}
+
+__global__ void k_iota_i32(int32_t* __restrict__ a, int64_t n) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = static_cast<int32_t>(i);
+}
+
+__global__ void k_i64_to_i32(const int64_t* __restrict__ a, int64_t n, int32_t* __restrict__ b) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = static_cast<int32_t>(a[i]);
+}
+
+// Error bits reported by the kernels below.
+enum : int32_t {
+  kErrMapRange = 1,
+  kErrRowTooLong = 2,
+  kErrRowCount = 4,
+  kErrTooManyColors = 8,
+  kErrColorConflict = 16,
+  kErrRankMissing = 32,
+};
+
+__global__ void k_count_inc(const int32_t* __restrict__ map, int64_t total, int64_t nrows, int is_signed,
+                            int32_t* __restrict__ cnt, int32_t* __restrict__ err) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= total) return;
+  const int32_t g = dof_id(map[i], is_signed);
+  if (g < 0 || g >= nrows) {
+    atomicOr(err, kErrMapRange);
+    return;
+  }
+  atomicAdd(&cnt[g], 1);
+}
+
+__global__ void k_fill_inc(const int32_t* __restrict__ map, int64_t total, int64_t nrows, int is_signed,
+                           const int32_t* __restrict__ inc_ptr, int32_t* __restrict__ fill,
+                           int32_t* __restrict__ inc_list) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= total) return;
+  const int32_t g = dof_id(map[i], is_signed);
+  if (g < 0 || g >= nrows) return;
+  const int32_t slot = atomicAdd(&fill[g], 1);
+  inc_list[inc_ptr[g] + slot] = static_cast<int32_t>(i);
+}
+
+// Sort each (short) incidence list so that later passes are order-independent.
+__global__ void k_sort_inc(const int32_t* __restrict__ inc_ptr, int32_t* __restrict__ inc_list, int64_t nrows) {
+  const int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (g >= nrows) return;
+  const int32_t a = inc_ptr[g], b = inc_ptr[g + 1];
+  for (int32_t i = a + 1; i < b; ++i) {
+    const int32_t x = inc_list[i];
+    int32_t j = i - 1;
+    while (j >= a && inc_list[j] > x) {
+      inc_list[j + 1] = inc_list[j];
+      --j;
+    }
+    inc_list[j + 1] = x;
+  }
+}
+
+// Columns of row g: sorted union of the local stencils of its incidences.
+// One lane per row; the per-lane working list lives in LDS (odd stride, so
+// lanes working on the same slot hit different banks).
+constexpr int kRowThreads = 64;
+constexpr int kRowStride = LOR_MAX_ROW_NNZ + 2;
+
+template <bool FILL>
+__global__ __launch_bounds__(kRowThreads) void k_row_cols(
+    const int32_t* __restrict__ map, int nloc, int is_signed, const int32_t* __restrict__ inc_ptr,
+    const int32_t* __restrict__ inc_list, const int32_t* __restrict__ st_ptr,
+    const int32_t* __restrict__ st_col, int64_t nrows, int32_t* __restrict__ cnt,
+    const int32_t* __restrict__ row_ptr, int32_t* __restrict__ col_idx, int32_t* __restrict__ err) {
+  __shared__ int32_t buf[kRowThreads * kRowStride];
+  const int64_t g = static_cast<int64_t>(blockIdx.x) * kRowThreads + threadIdx.x;
+  if (g >= nrows) return;
+  int32_t* b = buf + threadIdx.x * kRowStride;
+  int n = 0;
+  bool overflow = false;
+  for (int32_t ii = inc_ptr[g]; ii < inc_ptr[g + 1] && !overflow; ++ii) {
+    const int32_t inc = inc_list[ii];
+    const int32_t e = inc / nloc;
+    const int32_t l = inc - e * nloc;
+    const int32_t* me = map + static_cast<int64_t>(e) * nloc;
+    for (int32_t kk = st_ptr[l]; kk < st_ptr[l + 1]; ++kk) {
+      const int32_t c = dof_id(me[st_col[kk]], is_signed);
+      int pos = n;
+      while (pos > 0 && b[pos - 1] > c) --pos;
+      if (pos > 0 && b[pos - 1] == c) continue;
+      if (n >= LOR_MAX_ROW_NNZ) {
+        overflow = true;
+        break;
+      }
+      for (int m = n; m > pos; --m) b[m] = b[m - 1];
+      b[pos] = c;
+      ++n;
+    }
+  }
+  if (overflow) {
+    atomicOr(err, kErrRowTooLong);
+    if (!FILL) cnt[g] = 0;
+    return;
+  }
+  if (!FILL) {
+    cnt[g] = n;
+  } else {
+    const int32_t base = row_ptr[g];
+    if (row_ptr[g + 1] - base != n) {
+      atomicOr(err, kErrRowCount);
+      return;
+    }
+    for (int m = 0; m < n; ++m) col_idx[base + m] = b[m];
+  }
+}
+
+// One Jones-Plassmann round with priorities = element index: an uncoloured
+// element whose lower-index neighbours are all coloured takes the smallest
+// colour none of its coloured neighbours uses.  The fixed point equals the
+// sequential greedy colouring in element order (deterministic).
+__global__ void k_jp_round(const int32_t* __restrict__ map, int nloc, int is_signed,
+                           const int32_t* __restrict__ reps, int nreps,
+                           const int32_t* __restrict__ inc_ptr, const int32_t* __restrict__ inc_list,
+                           int64_t nel, int32_t* color, int32_t* __restrict__ ncolored,
+                           int32_t* __restrict__ err) {
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= nel) return;
+  if (__hip_atomic_load(&color[e], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= 0) return;
+  uint64_t used = 0;
+  const int32_t* me = map + e * nloc;
+  for (int r = 0; r < nreps; ++r) {
+    const int32_t g = dof_id(me[reps[r]], is_signed);
+    for (int32_t ii = inc_ptr[g]; ii < inc_ptr[g + 1]; ++ii) {
+      const int32_t e2 = inc_list[ii] / nloc;
+      if (e2 == e) continue;
+      const int32_t c2 = __hip_atomic_load(&color[e2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (c2 < 0) {
+        if (e2 < e) return;
+        continue;
+      }
+      used |= (1ull << c2);
+    }
+  }
+  if (~used == 0ull) {
+    atomicOr(err, kErrTooManyColors);
+    return;
+  }
+  const int c = __ffsll(static_cast<long long>(~used)) - 1;
+  if (c >= LOR_MAX_COLORS) {
+    atomicOr(err, kErrTooManyColors);
+    return;
+  }
+  __hip_atomic_store(&color[e], c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  atomicAdd(ncolored, 1);
+}
+
+// Every dof's incident elements must carry pairwise different colours.
+__global__ void k_check_colors(const int32_t* __restrict__ inc_ptr, const int32_t* __restrict__ inc_list,
+                               int nloc, int64_t nrows, const int32_t* __restrict__ color,
+                               int32_t* __restrict__ err) {
+  const int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (g >= nrows) return;
+  const int32_t a = inc_ptr[g], b = inc_ptr[g + 1];
+  for (int32_t i = a; i < b; ++i) {
+    const int32_t ei = inc_list[i] / nloc;
+    for (int32_t j = i + 1; j < b; ++j) {
+      const int32_t ej = inc_list[j] / nloc;
+      if (ei != ej && color[ei] == color[ej]) {
+        atomicOr(err, kErrColorConflict);
+        return;
+      }
+    }
+  }
+}
+
+__global__ void k_color_flags(const int32_t* __restrict__ color, int64_t nel, int c, int32_t* __restrict__ f) {
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e < nel) f[e] = (color[e] == c) ? 1 : 0;
+}
+
+__global__ void k_color_scatter(const int32_t* __restrict__ color, int64_t nel, int c,
+                                const int64_t* __restrict__ pos, int32_t base, int32_t* __restrict__ order) {
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e < nel && color[e] == c) order[base + pos[e]] = static_cast<int32_t>(e);
+}
+
+// Position of every local stencil entry inside its CSR row; lowest colour per nnz.
+__global__ void k_rank_pass0(const int32_t* __restrict__ map, int nloc, int is_signed, int nent,
+                             const int32_t* __restrict__ ent_row, const int32_t* __restrict__ ent_col,
+                             const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col_idx,
+                             const int32_t* __restrict__ color, int64_t total,
+                             int32_t* __restrict__ mincolor, uint8_t* __restrict__ tables,
+                             int32_t* __restrict__ err) {
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= total) return;
+  const int64_t e = idx / nent;
+  const int k = static_cast<int>(idx - e * nent);
+  const int32_t* me = map + e * nloc;
+  const int32_t g = dof_id(me[ent_row[k]], is_signed);
+  const int32_t c = dof_id(me[ent_col[k]], is_signed);
+  int32_t lo = row_ptr[g], hi = row_ptr[g + 1];
+  const int32_t start = lo;
+  while (lo < hi) {
+    const int32_t mid = (lo + hi) >> 1;
+    if (col_idx[mid] < c)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  if (lo >= row_ptr[g + 1] || col_idx[lo] != c) {
+    atomicOr(err, kErrRankMissing);
+    tables[idx] = 0;
+    return;
+  }
+  tables[idx] = static_cast<uint8_t>(lo - start);
+  atomicMin(&mincolor[lo], color[e]);
+}
+
+__global__ void k_rank_pass1(const int32_t* __restrict__ map, int nloc, int is_signed, int nent,
+                             const int32_t* __restrict__ ent_row, const int32_t* __restrict__ row_ptr,
+                             const int32_t* __restrict__ color, int64_t total,
+                             const int32_t* __restrict__ mincolor, uint8_t* __restrict__ tables) {
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= total) return;
+  const int64_t e = idx / nent;
+  const int k = static_cast<int>(idx - e * nent);
+  const int32_t g = dof_id(map[e * nloc + ent_row[k]], is_signed);
+  const uint8_t t = tables[idx];
+  if (mincolor[row_ptr[g] + (t & kRankMask)] == color[e]) tables[idx] = static_cast<uint8_t>(t | kFirstBit);
+}
+
+// --------------------------------------------------------------- host side
+
+static size_t align256(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
+
+static size_t layout(lor_sched* s, const RefElem& r) {
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = align256(off + bytes);
+    return o;
+  };
+  s->off_order = take(sizeof(int32_t) * s->nel);
+  s->off_color = take(sizeof(int32_t) * s->nel);
+  s->off_class = take(sizeof(int32_t) * s->nel);
+  s->off_tables = take(static_cast<size_t>(s->nel) * r.nent);
+  s->off_inc_ptr = take(sizeof(int32_t) * (s->nrows + 1));
+  s->off_inc_list = take(sizeof(int32_t) * s->nel * r.nloc);
+  s->off_st_ptr = take(sizeof(int32_t) * r.st_ptr.size());
+  s->off_st_col = take(sizeof(int32_t) * r.st_col.size());
+  s->off_ent_row = take(sizeof(int32_t) * r.ent_row.size());
+  s->off_recipe = take(sizeof(int32_t) * std::max<size_t>(1, r.recipe.size()));
+  return off;
+}
+
+static int read_err(const int32_t* d_err, hipStream_t st, int32_t* h) {
+  LOR_HIP(hipMemcpyAsync(h, d_err, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  LOR_HIP(hipStreamSynchronize(st));
+  return LOR_OK;
+}
+
+static int report_err(int32_t e) {
+  if (e & kErrMapRange) LOR_FAIL(LOR_EINVAL, "element map entry outside [0, nrows)");
+  if (e & kErrRowTooLong) LOR_FAIL(LOR_EUNSUPPORTED, "a row has more than %d nonzeros", LOR_MAX_ROW_NNZ);
+  if (e & kErrTooManyColors) LOR_FAIL(LOR_EUNSUPPORTED, "element colouring needs more than %d colours", LOR_MAX_COLORS);
+  if (e & kErrColorConflict)
+    LOR_FAIL(LOR_EINVAL, "elements sharing a dof got the same colour: the element lattices are not conforming");
+  if (e & (kErrRowCount | kErrRankMissing))
+    LOR_FAIL(LOR_EINVAL, "row_ptr does not match the element map (call phase 1 with the same map)");
+  return LOR_OK;
+}
+
+// Incidence lists (transpose of the element map) into inc_ptr / inc_list.
+static int build_incidence(const int32_t* map, int64_t nel, int nloc, int is_signed, int64_t nrows,
+                           int32_t* inc_ptr, int32_t* inc_list, int32_t* d_err, hipStream_t st) {
+  const int64_t total = nel * nloc;
+  DevBuf cnt, ptr64;
+  int rc = cnt.alloc(sizeof(int32_t) * (nrows + 1));
+  if (rc) return rc;
+  rc = ptr64.alloc(sizeof(int64_t) * (nrows + 1));
+  if (rc) return rc;
+  LOR_HIP(hipMemsetAsync(cnt.p, 0, sizeof(int32_t) * (nrows + 1), st));
+  if (total > 0) {
+    k_count_inc<<<ceil_div(total, 256), 256, 0, st>>>(map, total, nrows, is_signed, cnt.as<int32_t>(), d_err);
+    LOR_LAUNCHED("k_count_inc");
+  }
+  rc = scan_exclusive<int32_t>(cnt.as<int32_t>(), nrows, ptr64.as<int64_t>(), st);
+  if (rc) return rc;
+  k_i64_to_i32<<<ceil_div(nrows + 1, 256), 256, 0, st>>>(ptr64.as<int64_t>(), nrows + 1, inc_ptr);
+  LOR_LAUNCHED("k_i64_to_i32");
+  LOR_HIP(hipMemsetAsync(cnt.p, 0, sizeof(int32_t) * (nrows + 1), st));
+  if (total > 0) {
+    k_fill_inc<<<ceil_div(total, 256), 256, 0, st>>>(map, total, nrows, is_signed, inc_ptr,
+                                                     cnt.as<int32_t>(), inc_list);
+    LOR_LAUNCHED("k_fill_inc");
+  }
+  k_sort_inc<<<ceil_div(nrows, 256), 256, 0, st>>>(inc_ptr, inc_list, nrows);
+  LOR_LAUNCHED("k_sort_inc");
+  return LOR_OK;
+}
+
+template <typename T>
+static int upload(const std::vector<T>& v, void* dst, hipStream_t st) {
+  if (v.empty()) return LOR_OK;
+  LOR_HIP(hipMemcpyAsync(dst, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice, st));
+  return LOR_OK;
+}
+
+}  // namespace lor
+
+using namespace lor;
+
+extern "C" int lor_pattern(int space, int p, int64_t nel, int64_t nrows, const int32_t* elem_map,
+                           int32_t* row_ptr, int64_t* nnz, int32_t* col_idx, lor_sched* sched,
+                           void* stream) {
+  clear_error();
+  if (space != LOR_H1 && space != LOR_ND) LOR_FAIL(LOR_EINVAL, "space must be LOR_H1 or LOR_ND");
+  if (p < 1 || p > LOR_MAX_P) LOR_FAIL(LOR_EINVAL, "p = %d outside [1, %d]", p, LOR_MAX_P);
+  if (nel < 0) LOR_FAIL(LOR_EINVAL, "nel < 0");
+  if (nrows < 1) LOR_FAIL(LOR_EINVAL, "nrows < 1");
+  if (!row_ptr || !nnz || !sched) LOR_FAIL(LOR_EINVAL, "row_ptr, nnz and sched must not be NULL");
+  if (nel > 0 && !elem_map) LOR_FAIL(LOR_EINVAL, "elem_map is NULL");
+  const int nloc = space == LOR_H1 ? nloc_h1(p) : nloc_nd(p);
+  if (nel * static_cast<int64_t>(nloc) >= INT32_MAX) LOR_FAIL(LOR_EOVERFLOW, "nel * nloc >= 2^31");
+  if (nrows >= INT32_MAX) LOR_FAIL(LOR_EOVERFLOW, "nrows >= 2^31 - 1");
+  const int is_signed = space == LOR_ND;
+  hipStream_t st = as_stream(stream);
+  const RefElem ref = build_ref(space, p);
+  const int64_t total = nel * nloc;
+  int rc;
+  if (col_idx != nullptr) {
+    if (!sched->dev) LOR_FAIL(LOR_EINVAL, "sched->dev is NULL (allocate sched->dev_bytes after phase 1)");
+    if (sched->space != space || sched->p != p || sched->nel != nel || sched->nrows != nrows ||
+        sched->nnz != *nnz)
+      LOR_FAIL(LOR_EINVAL, "sched does not come from phase 1 of the same pattern");
+    lor_sched probe = *sched;
+    if (layout(&probe, ref) != sched->dev_bytes) LOR_FAIL(LOR_EINVAL, "sched->dev_bytes changed since phase 1");
+  }
+
+  DevBuf err, st_ptr, st_col;
+  if ((rc = err.alloc(sizeof(int32_t)))) return rc;
+  LOR_HIP(hipMemsetAsync(err.p, 0, sizeof(int32_t), st));
+  int32_t herr = 0;
+
+  if (col_idx == nullptr) {
+    // ---------------------------------------------------------------- phase 1
+    DevBuf inc_ptr, inc_list, cnt, ptr64;
+    if ((rc = inc_ptr.alloc(sizeof(int32_t) * (nrows + 1)))) return rc;
+    if ((rc = inc_list.alloc(sizeof(int32_t) * std::max<int64_t>(1, total)))) return rc;
+    if ((rc = cnt.alloc(sizeof(int32_t) * nrows))) return rc;
+    if ((rc = ptr64.alloc(sizeof(int64_t) * (nrows + 1)))) return rc;
+    if ((rc = st_ptr.alloc(sizeof(int32_t) * ref.st_ptr.size()))) return rc;
+    if ((rc = st_col.alloc(sizeof(int32_t) * ref.st_col.size()))) return rc;
+    if ((rc = upload(ref.st_ptr, st_ptr.p, st))) return rc;
+    if ((rc = upload(ref.st_col, st_col.p, st))) return rc;
+    if ((rc = build_incidence(elem_map, nel, nloc, is_signed, nrows, inc_ptr.as<int32_t>(),
+                              inc_list.as<int32_t>(), err.as<int32_t>(), st)))
+      return rc;
+    if ((rc = read_err(err.as<int32_t>(), st, &herr))) return rc;
+    if ((rc = report_err(herr))) return rc;
+    k_row_cols<false><<<ceil_div(nrows, kRowThreads), kRowThreads, 0, st>>>(
+        elem_map, nloc, is_signed, inc_ptr.as<int32_t>(), inc_list.as<int32_t>(), st_ptr.as<int32_t>(),
+        st_col.as<int32_t>(), nrows, cnt.as<int32_t>(), nullptr, nullptr, err.as<int32_t>());
+    LOR_LAUNCHED("k_row_cols<count>");
+    if ((rc = scan_exclusive<int32_t>(cnt.as<int32_t>(), nrows, ptr64.as<int64_t>(), st))) return rc;
+    int64_t total_nnz = 0;
+    LOR_HIP(hipMemcpyAsync(&total_nnz, ptr64.as<int64_t>() + nrows, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    if ((rc = read_err(err.as<int32_t>(), st, &herr))) return rc;
+    if ((rc = report_err(herr))) return rc;
+    if (total_nnz >= INT32_MAX) LOR_FAIL(LOR_EOVERFLOW, "nnz = %lld >= 2^31", (long long)total_nnz);
+    k_i64_to_i32<<<ceil_div(nrows + 1, 256), 256, 0, st>>>(ptr64.as<int64_t>(), nrows + 1, row_ptr);
+    LOR_LAUNCHED("k_i64_to_i32");
+    LOR_HIP(hipStreamSynchronize(st));
+    *nnz = total_nnz;
+    sched->space = space;
+    sched->p = p;
+    sched->nel = nel;
+    sched->nrows = nrows;
+    sched->nnz = total_nnz;
+    sched->nloc = nloc;
+    sched->nent = ref.nent;
+    sched->ncolors = 0;
+    sched->nclass = 0;
+    sched->dev = nullptr;
+    sched->dev_bytes = layout(sched, ref);
+    return LOR_OK;
+  }
+
+  // ------------------------------------------------------------------ phase 2
+  const int64_t nnzv = *nnz;
+  int32_t* d_order = dev_at<int32_t>(sched, sched->off_order);
+  int32_t* d_color = dev_at<int32_t>(sched, sched->off_color);
+  int32_t* d_class = dev_at<int32_t>(sched, sched->off_class);
+  uint8_t* d_tab = dev_at<uint8_t>(sched, sched->off_tables);
+  int32_t* d_inc_ptr = dev_at<int32_t>(sched, sched->off_inc_ptr);
+  int32_t* d_inc_list = dev_at<int32_t>(sched, sched->off_inc_list);
+  int32_t* d_st_ptr = dev_at<int32_t>(sched, sched->off_st_ptr);
+  int32_t* d_st_col = dev_at<int32_t>(sched, sched->off_st_col);
+  int32_t* d_ent_row = dev_at<int32_t>(sched, sched->off_ent_row);
+  int32_t* d_recipe = dev_at<int32_t>(sched, sched->off_recipe);
+  DevBuf reps;
+  if ((rc = reps.alloc(sizeof(int32_t) * ref.reps.size()))) return rc;
+  if ((rc = upload(ref.st_ptr, d_st_ptr, st))) return rc;
+  if ((rc = upload(ref.st_col, d_st_col, st))) return rc;
+  if ((rc = upload(ref.ent_row, d_ent_row, st))) return rc;
+  if ((rc = upload(ref.recipe, d_recipe, st))) return rc;
+  if ((rc = upload(ref.reps, reps.p, st))) return rc;
+
+  if ((rc = build_incidence(elem_map, nel, nloc, is_signed, nrows, d_inc_ptr, d_inc_list, err.as<int32_t>(), st)))
+    return rc;
+  k_row_cols<true><<<ceil_div(nrows, kRowThreads), kRowThreads, 0, st>>>(
+      elem_map, nloc, is_signed, d_inc_ptr, d_inc_list, d_st_ptr, d_st_col, nrows, nullptr, row_ptr, col_idx,
+      err.as<int32_t>());
+  LOR_LAUNCHED("k_row_cols<fill>");
+  if ((rc = read_err(err.as<int32_t>(), st, &herr))) return rc;
+  if ((rc = report_err(herr))) return rc;
+
+  // colouring
+  DevBuf ncol;
+  if ((rc = ncol.alloc(sizeof(int32_t)))) return rc;
+  LOR_HIP(hipMemsetAsync(ncol.p, 0, sizeof(int32_t), st));
+  if (nel > 0) {
+    k_fill_i32<<<ceil_div(nel, 256), 256, 0, st>>>(d_color, nel, -1);
+    LOR_LAUNCHED("k_fill_i32");
+  }
+  int32_t colored = 0;
+  for (int64_t round = 0; colored < nel; ++round) {
+    if (round > nel) LOR_FAIL(LOR_EDEVICE, "element colouring did not converge");
+    k_jp_round<<<ceil_div(nel, 256), 256, 0, st>>>(elem_map, nloc, is_signed, reps.as<int32_t>(),
+                                                   static_cast<int>(ref.reps.size()), d_inc_ptr, d_inc_list,
+                                                   nel, d_color, ncol.as<int32_t>(), err.as<int32_t>());
+    LOR_LAUNCHED("k_jp_round");
+    LOR_HIP(hipMemcpyAsync(&colored, ncol.p, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    if ((rc = read_err(err.as<int32_t>(), st, &herr))) return rc;
+    if ((rc = report_err(herr))) return rc;
+  }
+  k_check_colors<<<ceil_div(nrows, 256), 256, 0, st>>>(d_inc_ptr, d_inc_list, nloc, nrows, d_color,
+                                                       err.as<int32_t>());
+  LOR_LAUNCHED("k_check_colors");
+  if ((rc = read_err(err.as<int32_t>(), st, &herr))) return rc;
+  if ((rc = report_err(herr))) return rc;
+
+  // element order by colour (stable)
+  {
+    DevBuf flags, pos;
+    if ((rc = flags.alloc(sizeof(int32_t) * std::max<int64_t>(1, nel)))) return rc;
+    if ((rc = pos.alloc(sizeof(int64_t) * (nel + 1)))) return rc;
+    int32_t base = 0;
+    int nc = 0;
+    sched->color_ptr[0] = 0;
+    for (int c = 0; c < LOR_MAX_COLORS && base < nel; ++c) {
+      k_color_flags<<<ceil_div(nel, 256), 256, 0, st>>>(d_color, nel, c, flags.as<int32_t>());
+      LOR_LAUNCHED("k_color_flags");
+      if ((rc = scan_exclusive<int32_t>(flags.as<int32_t>(), nel, pos.as<int64_t>(), st))) return rc;
+      k_color_scatter<<<ceil_div(nel, 256), 256, 0, st>>>(d_color, nel, c, pos.as<int64_t>(), base, d_order);
+      LOR_LAUNCHED("k_color_scatter");
+      int64_t cnt = 0;
+      LOR_HIP(hipMemcpyAsync(&cnt, pos.as<int64_t>() + nel, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+      LOR_HIP(hipStreamSynchronize(st));
+      base += static_cast<int32_t>(cnt);
+      sched->color_ptr[c + 1] = base;
+      nc = c + 1;
+    }
+    if (base != nel) LOR_FAIL(LOR_EDEVICE, "colour order incomplete");
+    sched->ncolors = nc;
+    for (int c = nc + 1; c <= LOR_MAX_COLORS; ++c) sched->color_ptr[c] = base;
+  }
+
+  // rank tables
+  {
+    DevBuf mincol;
+    if ((rc = mincol.alloc(sizeof(int32_t) * std::max<int64_t>(1, nnzv)))) return rc;
+    const int64_t tot = nel * ref.nent;
+    k_fill_i32<<<ceil_div(std::max<int64_t>(1, nnzv), 256), 256, 0, st>>>(mincol.as<int32_t>(), nnzv, INT32_MAX);
+    LOR_LAUNCHED("k_fill_i32");
+    if (tot > 0) {
+      k_rank_pass0<<<ceil_div(tot, 256), 256, 0, st>>>(elem_map, nloc, is_signed, ref.nent, d_ent_row, d_st_col,
+                                                        row_ptr, col_idx, d_color, tot, mincol.as<int32_t>(), d_tab,
+                                                        err.as<int32_t>());
+      LOR_LAUNCHED("k_rank_pass0");
+      k_rank_pass1<<<ceil_div(tot, 256), 256, 0, st>>>(elem_map, nloc, is_signed, ref.nent, d_ent_row, row_ptr,
+                                                        d_color, tot, mincol.as<int32_t>(), d_tab);
+      LOR_LAUNCHED("k_rank_pass1");
+    }
+    if (nel > 0) {
+      k_iota_i32<<<ceil_div(nel, 256), 256, 0, st>>>(d_class, nel);
+      LOR_LAUNCHED("k_iota_i32");
+    }
+    if ((rc = read_err(err.as<int32_t>(), st, &herr))) return rc;
+    if ((rc = report_err(herr))) return rc;
+  }
+  sched->nclass = nel;
+  sched->max_row_nnz = 0;
+  LOR_HIP(hipStreamSynchronize(st));
+  return LOR_OK;
+}

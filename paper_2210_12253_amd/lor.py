@@ -1,0 +1,263 @@
+"""Python binding of the LOR assembly C ABI (include/lor.h).
+
+Argument marshalling only: every step of the assembly runs in the HIP kernels
+of liblor.so.  PyTorch provides device memory and the current stream.  If the
+library has not been built the import fails loudly -- there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblor.so")
+
+LOR_OK, LOR_EINVAL, LOR_EOVERFLOW, LOR_EDEVICE, LOR_EUNSUPPORTED = 0, -1, -2, -3, -4
+LOR_H1, LOR_ND = 0, 1
+LOR_F64, LOR_F32 = 0, 1
+LOR_MAX_P = 6
+LOR_MAX_COLORS = 64
+LOR_FP64_FALLBACK = 0x1
+
+ABI_SYMBOLS = (
+    "lor_pattern",
+    "lor_assemble_h1",
+    "lor_assemble_nd",
+    "lor_assemble_backward",
+    "lor_backward_workspace",
+    "lor_sched_bytes",
+    "lor_last_error",
+    "lor_abi_version",
+)
+
+
+class LorError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"[{code}] {msg}")
+        self.code = code
+
+
+class LorSched(ctypes.Structure):
+    _fields_ = [
+        ("space", ctypes.c_int32),
+        ("p", ctypes.c_int32),
+        ("nel", ctypes.c_int64),
+        ("nrows", ctypes.c_int64),
+        ("nnz", ctypes.c_int64),
+        ("nloc", ctypes.c_int32),
+        ("nent", ctypes.c_int32),
+        ("ncolors", ctypes.c_int32),
+        ("max_row_nnz", ctypes.c_int32),
+        ("color_ptr", ctypes.c_int32 * (LOR_MAX_COLORS + 1)),
+        ("nclass", ctypes.c_int64),
+        ("dev_bytes", ctypes.c_size_t),
+        ("dev", ctypes.c_void_p),
+        ("off_order", ctypes.c_size_t),
+        ("off_color", ctypes.c_size_t),
+        ("off_class", ctypes.c_size_t),
+        ("off_tables", ctypes.c_size_t),
+        ("off_inc_ptr", ctypes.c_size_t),
+        ("off_inc_list", ctypes.c_size_t),
+        ("off_st_ptr", ctypes.c_size_t),
+        ("off_st_col", ctypes.c_size_t),
+        ("off_ent_row", ctypes.c_size_t),
+        ("off_recipe", ctypes.c_size_t),
+        ("reserved", ctypes.c_size_t * 8),
+    ]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load liblor.so (raises if it is missing: build it with __graft_entry__.build())."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"HIP library {path} not built; run `python -c 'import __graft_entry__ as g; g.build()'`")
+    lib = ctypes.CDLL(path)
+    vp, i32, i64, u32, f64, sz = (ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_uint, ctypes.c_double,
+                                  ctypes.c_size_t)
+    lib.lor_pattern.argtypes = [i32, i32, i64, i64, vp, vp, ctypes.POINTER(ctypes.c_int64), vp,
+                                ctypes.POINTER(LorSched), vp]
+    lib.lor_pattern.restype = i32
+    lib.lor_assemble_h1.argtypes = [i32, i64, i64, i32, vp, vp, vp, f64, vp, ctypes.POINTER(LorSched), vp, i32, u32,
+                                    f64, vp, vp]
+    lib.lor_assemble_h1.restype = i32
+    lib.lor_assemble_nd.argtypes = [i32, i64, i64, i64, i32, vp, vp, vp, vp, f64, vp, ctypes.POINTER(LorSched), vp,
+                                    i32, u32, f64, vp, vp]
+    lib.lor_assemble_nd.restype = i32
+    lib.lor_assemble_backward.argtypes = [i32, i64, i64, i32, vp, vp, vp, f64, vp, ctypes.POINTER(LorSched), vp, vp,
+                                          vp, vp, i32, vp]
+    lib.lor_assemble_backward.restype = i32
+    lib.lor_backward_workspace.argtypes = [i32, i64]
+    lib.lor_backward_workspace.restype = sz
+    lib.lor_sched_bytes.argtypes = []
+    lib.lor_sched_bytes.restype = sz
+    lib.lor_last_error.argtypes = []
+    lib.lor_last_error.restype = ctypes.c_char_p
+    lib.lor_abi_version.argtypes = []
+    lib.lor_abi_version.restype = i32
+    if lib.lor_sched_bytes() != ctypes.sizeof(LorSched):
+        raise ImportError("lor_sched layout mismatch between liblor.so and the binding")
+    _lib = lib
+    return lib
+
+
+def _check(rc: int) -> None:
+    if rc != LOR_OK:
+        msg = _lib.lor_last_error().decode() if _lib is not None else ""
+        raise LorError(rc, msg)
+
+
+def _ptr(t: torch.Tensor | None) -> int | None:
+    return None if t is None else t.data_ptr()
+
+
+def _stream() -> int:
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _dev_tensor(t, dtype, name, device) -> torch.Tensor:
+    t = torch.as_tensor(t)
+    if t.dtype != dtype:
+        t = t.to(dtype)
+    if t.device != device:
+        t = t.to(device)
+    if not t.is_contiguous():
+        t = t.contiguous()
+    return t
+
+
+def _dtype_code(dtype) -> int:
+    if dtype == torch.float64:
+        return LOR_F64
+    if dtype == torch.float32:
+        return LOR_F32
+    raise ValueError("dtype must be torch.float64 or torch.float32")
+
+
+@dataclass
+class Pattern:
+    """CSR pattern + assembly schedule of one mesh (built once, reused)."""
+    space: int
+    p: int
+    nel: int
+    nrows: int
+    nnz: int
+    row_ptr: torch.Tensor
+    col_idx: torch.Tensor
+    sched: LorSched
+    sched_dev: torch.Tensor
+
+    @property
+    def ncolors(self) -> int:
+        return int(self.sched.ncolors)
+
+
+def lor_pattern(space: int, p: int, elem_map: torch.Tensor, nrows: int, device=None) -> Pattern:
+    """Pattern and schedule (lor_pattern phases 1 and 2) on the current CUDA device."""
+    lib = load_library()
+    device = torch.device("cuda") if device is None else torch.device(device)
+    em = _dev_tensor(elem_map, torch.int32, "elem_map", device)
+    nel = em.shape[0]
+    row_ptr = torch.empty(nrows + 1, dtype=torch.int32, device=device)
+    nnz = ctypes.c_int64(0)
+    sched = LorSched()
+    st = _stream()
+    _check(lib.lor_pattern(space, p, nel, nrows, _ptr(em), _ptr(row_ptr), ctypes.byref(nnz), None,
+                           ctypes.byref(sched), st))
+    col_idx = torch.empty(max(1, nnz.value), dtype=torch.int32, device=device)[: nnz.value]
+    sched_dev = torch.empty(int(sched.dev_bytes), dtype=torch.uint8, device=device)
+    sched.dev = sched_dev.data_ptr()
+    cptr = col_idx.data_ptr() if nnz.value > 0 else torch.empty(1, dtype=torch.int32, device=device).data_ptr()
+    _check(lib.lor_pattern(space, p, nel, nrows, _ptr(em), _ptr(row_ptr), ctypes.byref(nnz), cptr,
+                           ctypes.byref(sched), st))
+    return Pattern(space, p, nel, nrows, nnz.value, row_ptr, col_idx, sched, sched_dev)
+
+
+def lor_assemble_h1(pat: Pattern, elem_dofs, coords, kappa, beta: float, dtype=torch.float64,
+                    fp64_fallback: bool = False, det_ratio_thresh: float = 10.0,
+                    diag: torch.Tensor | None = None, out: torch.Tensor | None = None) -> torch.Tensor:
+    """Values of the H1 LOR matrix, [nnz] (or [batch, nnz] for kappa [batch, nel, p^3])."""
+    lib = load_library()
+    dev = pat.row_ptr.device
+    ed = _dev_tensor(elem_dofs, torch.int32, "elem_dofs", dev)
+    x = _dev_tensor(coords, torch.float64, "coords", dev)
+    k = _dev_tensor(kappa, dtype, "kappa", dev)
+    batched = k.dim() == 3
+    batch = k.shape[0] if batched else 1
+    if out is None:
+        out = torch.empty((batch, pat.nnz) if batched else (pat.nnz,), dtype=dtype, device=dev)
+    flags = LOR_FP64_FALLBACK if fp64_fallback else 0
+    _check(lib.lor_assemble_h1(pat.p, pat.nel, pat.nrows, batch, _ptr(ed), _ptr(x), _ptr(k), float(beta),
+                               _ptr(pat.row_ptr), ctypes.byref(pat.sched), _ptr(out), _dtype_code(dtype), flags,
+                               float(det_ratio_thresh), _ptr(diag), _stream()))
+    return out
+
+
+def lor_assemble_nd(pat: Pattern, elem_dofs, elem_edges, coords, kappa, beta: float, ndofs_h1: int,
+                    dtype=torch.float64, fp64_fallback: bool = False, det_ratio_thresh: float = 10.0,
+                    diag: torch.Tensor | None = None, out: torch.Tensor | None = None) -> torch.Tensor:
+    """Values of the H(curl) LOR matrix, [nnz] (or [batch, nnz])."""
+    lib = load_library()
+    dev = pat.row_ptr.device
+    ed = _dev_tensor(elem_dofs, torch.int32, "elem_dofs", dev)
+    ee = _dev_tensor(elem_edges, torch.int32, "elem_edges", dev)
+    x = _dev_tensor(coords, torch.float64, "coords", dev)
+    k = _dev_tensor(kappa, dtype, "kappa", dev)
+    batched = k.dim() == 3
+    batch = k.shape[0] if batched else 1
+    if out is None:
+        out = torch.empty((batch, pat.nnz) if batched else (pat.nnz,), dtype=dtype, device=dev)
+    flags = LOR_FP64_FALLBACK if fp64_fallback else 0
+    _check(lib.lor_assemble_nd(pat.p, pat.nel, ndofs_h1, pat.nrows, batch, _ptr(ed), _ptr(ee), _ptr(x), _ptr(k),
+                               float(beta), _ptr(pat.row_ptr), ctypes.byref(pat.sched), _ptr(out),
+                               _dtype_code(dtype), flags, float(det_ratio_thresh), _ptr(diag), _stream()))
+    return out
+
+
+def lor_assemble_backward(pat: Pattern, elem_dofs, coords, kappa, beta: float, grad_values,
+                          dtype=torch.float64, workspace: torch.Tensor | None = None):
+    """Adjoint of lor_assemble_h1: returns (grad_kappa like kappa, grad_coords [ndofs, 3] FP64)."""
+    lib = load_library()
+    dev = pat.row_ptr.device
+    ed = _dev_tensor(elem_dofs, torch.int32, "elem_dofs", dev)
+    x = _dev_tensor(coords, torch.float64, "coords", dev)
+    k = _dev_tensor(kappa, dtype, "kappa", dev)
+    gv = _dev_tensor(grad_values, dtype, "grad_values", dev)
+    batched = k.dim() == 3
+    batch = k.shape[0] if batched else 1
+    gk = torch.empty_like(k)
+    gx = torch.empty((pat.nrows, 3), dtype=torch.float64, device=dev)
+    if workspace is None:
+        workspace = torch.empty(max(1, int(lib.lor_backward_workspace(pat.p, pat.nel))), dtype=torch.uint8,
+                                device=dev)
+    _check(lib.lor_assemble_backward(pat.p, pat.nel, pat.nrows, batch, _ptr(ed), _ptr(x), _ptr(k), float(beta),
+                                     _ptr(pat.row_ptr), ctypes.byref(pat.sched), _ptr(gv), _ptr(gk), _ptr(gx),
+                                     _ptr(workspace), _dtype_code(dtype), _stream()))
+    return gk, gx
+
+
+class LorH1(torch.autograd.Function):
+    """values = assemble_h1(coords, kappa); backward through the hand-written adjoint
+    kernel (geometry recomputed, not stored).  beta gets no gradient."""
+
+    @staticmethod
+    def forward(ctx, coords, kappa, beta, pat, elem_dofs):
+        dtype = kappa.dtype
+        vals = lor_assemble_h1(pat, elem_dofs, coords, kappa, beta, dtype=dtype)
+        ctx.save_for_backward(coords, kappa)
+        ctx.pat, ctx.elem_dofs, ctx.beta = pat, elem_dofs, beta
+        return vals
+
+    @staticmethod
+    def backward(ctx, grad_values):
+        coords, kappa = ctx.saved_tensors
+        gk, gx = lor_assemble_backward(ctx.pat, ctx.elem_dofs, coords, kappa, ctx.beta,
+                                       grad_values.contiguous(), dtype=kappa.dtype)
+        return gx.to(coords.dtype), gk, None, None, None

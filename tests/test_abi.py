@@ -1,0 +1,92 @@
+"""The C ABI library loads, exports every symbol include/lor.h declares, and
+rejects bad arguments on the host before touching the GPU (no compute calls)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2210_12253_amd as pkg
+from paper_2210_12253_amd import lor as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    src = open(os.path.join(ROOT, "include", "lor.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(lor_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_exports_every_declared_symbol():
+    lib = pkg.load_library()
+    declared = header_functions()
+    assert "lor_pattern" in declared and "lor_assemble_backward" in declared
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert set(declared) == set(L.ABI_SYMBOLS)
+    assert lib.lor_abi_version() == 1
+    assert lib.lor_sched_bytes() == ctypes.sizeof(L.LorSched)
+
+
+def _err(lib):
+    return lib.lor_last_error().decode()
+
+
+FAKE = 0x1000  # never dereferenced: validation fails first
+
+
+def test_pattern_argument_errors():
+    lib = pkg.load_library()
+    s = L.LorSched()
+    nnz = ctypes.c_int64(0)
+    rc = lib.lor_pattern(0, 0, 1, 8, FAKE, FAKE, ctypes.byref(nnz), None, ctypes.byref(s), None)
+    assert rc == L.LOR_EINVAL and "p = 0" in _err(lib)
+    assert lib.lor_pattern(0, 7, 1, 8, FAKE, FAKE, ctypes.byref(nnz), None, ctypes.byref(s), None) == L.LOR_EINVAL
+    assert lib.lor_pattern(5, 2, 1, 8, FAKE, FAKE, ctypes.byref(nnz), None, ctypes.byref(s), None) == L.LOR_EINVAL
+    assert lib.lor_pattern(0, 2, 1, 8, FAKE, None, ctypes.byref(nnz), None, ctypes.byref(s), None) == L.LOR_EINVAL
+    assert lib.lor_pattern(0, 2, 1, 8, None, FAKE, ctypes.byref(nnz), None, ctypes.byref(s), None) == L.LOR_EINVAL
+    assert lib.lor_pattern(0, 2, -1, 8, FAKE, FAKE, ctypes.byref(nnz), None, ctypes.byref(s), None) == L.LOR_EINVAL
+    # nel * (p+1)^3 >= 2^31
+    rc = lib.lor_pattern(0, 6, 1 << 30, 8, FAKE, FAKE, ctypes.byref(nnz), None, ctypes.byref(s), None)
+    assert rc == L.LOR_EOVERFLOW and "2^31" in _err(lib)
+    # phase 2 without a device buffer
+    s.dev = None
+    rc = lib.lor_pattern(0, 2, 1, 27, FAKE, FAKE, ctypes.byref(nnz), FAKE, ctypes.byref(s), None)
+    assert rc == L.LOR_EINVAL and "dev" in _err(lib)
+
+
+def test_assemble_argument_errors():
+    lib = pkg.load_library()
+    s = L.LorSched()
+    h1 = lib.lor_assemble_h1
+    args = lambda **kw: dict(dict(p=2, nel=1, ndofs=27, batch=1, ed=FAKE, x=FAKE, k=FAKE, beta=1.0, rp=FAKE,
+                                  sched=ctypes.byref(s), v=FAKE, dtype=0, flags=0, thr=10.0, diag=None, st=None),
+                             **kw)
+    call = lambda a: h1(a["p"], a["nel"], a["ndofs"], a["batch"], a["ed"], a["x"], a["k"], a["beta"], a["rp"],
+                        a["sched"], a["v"], a["dtype"], a["flags"], a["thr"], a["diag"], a["st"])
+    assert call(args(p=0)) == L.LOR_EINVAL
+    assert call(args(batch=0)) == L.LOR_EINVAL
+    assert call(args(dtype=7)) == L.LOR_EINVAL
+    assert call(args(flags=0x10)) == L.LOR_EINVAL
+    assert call(args(dtype=1, flags=1, thr=0.5)) == L.LOR_EINVAL
+    assert call(args(v=None)) == L.LOR_EINVAL
+    # schedule not built / built for another mesh
+    assert call(args()) == L.LOR_EINVAL and "sched" in _err(lib)
+    s.dev = FAKE
+    s.space, s.p, s.nel, s.nrows = 1, 2, 1, 27
+    assert call(args()) == L.LOR_EINVAL and "space" in _err(lib)
+    s.space, s.p = 0, 3
+    assert call(args()) == L.LOR_EINVAL and "does not match" in _err(lib)
+    nd = lib.lor_assemble_nd(2, 1, 27, 54, 1, FAKE, FAKE, FAKE, FAKE, 1.0, FAKE, ctypes.byref(s), FAKE, 0, 0, 10.0,
+                             None, None)
+    assert nd in (L.LOR_EINVAL, L.LOR_EUNSUPPORTED)
+    bw = lib.lor_assemble_backward(0, 1, 27, 1, FAKE, FAKE, FAKE, 1.0, FAKE, ctypes.byref(s), FAKE, FAKE, FAKE, FAKE,
+                                   0, None)
+    assert bw in (L.LOR_EINVAL, L.LOR_EUNSUPPORTED)
+
+
+def test_backward_workspace_size():
+    lib = pkg.load_library()
+    assert lib.lor_backward_workspace(4, 4096) == 8 * 3 * 4096 * 125
+    assert lib.lor_backward_workspace(0, 10) == 0

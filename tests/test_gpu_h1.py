@@ -1,0 +1,198 @@
+"""GPU parity of the LOR H1 path (pattern + values, FP64 and FP32) against the
+CPU oracle, through the C ABI (Python binding)."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import meshgen
+import paper_2210_12253_amd as lor
+from oracle import lor_oracle as orc
+from tests.gpu_helpers import row_rel_err, transpose_perm
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda:0")
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _pattern(m):
+    return lor.lor_pattern(lor.LOR_H1, m["p"], torch.from_numpy(m["elem_dofs"]).to(DEV), m["ndofs"])
+
+
+def _check_pattern(pat, rp, ci):
+    assert pat.nnz == rp[-1].item()
+    assert torch.equal(pat.row_ptr.cpu().to(torch.int64), rp)
+    assert torch.equal(pat.col_idx.cpu().to(torch.int64), ci)
+
+
+def _assemble(pat, m, kap, beta, dtype=torch.float64, **kw):
+    v = lor.lor_assemble_h1(pat, torch.from_numpy(m["elem_dofs"]), torch.from_numpy(m["coords"]), kap, beta,
+                            dtype=dtype, **kw)
+    torch.cuda.synchronize()
+    return v.cpu()
+
+
+# --------------------------------------------------------------- small meshes
+
+CASES = [
+    # (n, p, amp, sigma, beta, perturbation)
+    (4, 2, 0.0, 0.0, 0.0, None),       # the closed-form workload
+    (2, 1, 0.1, 1.0, 1.0, None),
+    (3, 2, 0.15, 1.0, 1.0, "renumber"),
+    (2, 3, 0.15, 2.0, 0.5, "reorient"),
+    (3, 3, 0.1, 1.0, 1.0, "permute"),
+    (2, 4, 0.12, 1.0, 1.0, "reorient"),
+    (2, 5, 0.12, 1.0, 1.0, None),
+    (2, 6, 0.12, 2.0, 1.0, "renumber"),
+    (1, 6, 0.1, 1.0, 1.0, None),
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=[f"n{c[0]}p{c[1]}-{c[5]}" for c in CASES])
+def test_h1_small_parity(case):
+    n, p, amp, sigma, beta, pert = case
+    _say("case", case)
+    m = meshgen.cartesian_mesh(n, p, amp)
+    kap = (torch.ones(m["nel"], p ** 3, dtype=torch.float64) if sigma == 0.0
+           else meshgen.kappa_field(m["nel"], p, sigma, seed=0))
+    if pert == "renumber":
+        m, _ = meshgen.renumber_vertices(m, seed=3)
+    elif pert == "permute":
+        m, order = meshgen.permute_elements(m, seed=4)
+        kap = kap[torch.from_numpy(order)]
+    elif pert == "reorient":
+        m, kap, _ = meshgen.reorient_elements(m, seed=5, kappa=kap)
+    rp, ci, v = orc.h1_matrix(m["coords"], m["elem_dofs"], p, kap, beta)
+    pat = _pattern(m)
+    _check_pattern(pat, rp, ci)
+    v64 = _assemble(pat, m, kap, beta)
+    assert row_rel_err(rp, ci, v64, ci, v) <= 1e-12
+    v32 = _assemble(pat, m, kap.float(), beta, dtype=torch.float32)
+    assert row_rel_err(rp, ci, v32, ci, v) <= 1e-6
+    # determinism and bitwise symmetry
+    v64b = _assemble(pat, m, kap, beta)
+    assert torch.equal(v64, v64b)
+    t = transpose_perm(rp, ci)
+    assert torch.equal(v64, v64[torch.from_numpy(t)])
+    assert torch.equal(v32, v32[torch.from_numpy(t)])
+
+
+def test_h1_closed_form_uniform_cube():
+    """C1 values reproduce the 27-point stencil of the uniform cube exactly
+    enough: interior diagonal 8h/3, edge -h/6, corner -h/12, face 0."""
+    m = meshgen.cartesian_mesh(4, 2, 0.0)
+    N = m["N"]
+    h = 1.0 / (N - 1)
+    kap = torch.ones(m["nel"], 8, dtype=torch.float64)
+    pat = _pattern(m)
+    v = _assemble(pat, m, kap, 0.0)
+    rp = pat.row_ptr.cpu().to(torch.int64)
+    ci = pat.col_idx.cpu().to(torch.int64)
+    g = 4 + N * (4 + N * 4)
+    cols = ci[rp[g]:rp[g + 1]].numpy()
+    vals = v[rp[g]:rp[g + 1]].numpy()
+    ref = {0: 8 * h / 3, 1: 0.0, 2: -h / 6, 3: -h / 12}
+    for c, x in zip(cols, vals):
+        d = sum(int(a != b) for a, b in zip(np.unravel_index(c, (N, N, N)), np.unravel_index(g, (N, N, N))))
+        assert abs(x - ref[d]) <= 1e-15
+    assert rp[-1].item() == (3 * N - 2) ** 3
+
+
+def test_h1_batch_matches_single():
+    m = meshgen.cartesian_mesh(2, 3, 0.1)
+    kb = meshgen.kappa_field(m["nel"], 3, 1.0, seed=2, batch=3)
+    pat = _pattern(m)
+    vb = _assemble(pat, m, kb, 0.7)
+    for b in range(3):
+        vs = _assemble(pat, m, kb[b], 0.7)
+        assert torch.equal(vb[b], vs)
+
+
+def test_h1_empty_mesh():
+    pat = lor.lor_pattern(lor.LOR_H1, 2, torch.zeros((0, 27), dtype=torch.int32, device=DEV), 5)
+    assert pat.nnz == 0 and torch.equal(pat.row_ptr.cpu(), torch.zeros(6, dtype=torch.int32))
+    v = lor.lor_assemble_h1(pat, torch.zeros((0, 27), dtype=torch.int32), torch.zeros((5, 3), dtype=torch.float64),
+                            torch.zeros((0, 8), dtype=torch.float64), 1.0)
+    torch.cuda.synchronize()
+    assert v.numel() == 0
+
+
+def test_h1_map_out_of_range_is_rejected():
+    m = meshgen.cartesian_mesh(1, 2, 0.0)
+    ed = torch.from_numpy(m["elem_dofs"]).clone()
+    ed[0, 5] = m["ndofs"] + 3
+    with pytest.raises(lor.LorError, match="outside"):
+        lor.lor_pattern(lor.LOR_H1, 2, ed.to(DEV), m["ndofs"])
+
+
+def test_h1_fp32_fallback_branch():
+    """A pinched vertex makes a few subelements strongly non-affine (corner
+    Jacobian ratio > 10): with the fallback they are integrated with FP64
+    geometry, counted in diag[0]."""
+    m = meshgen.cartesian_mesh(1, 2, 0.0)
+    X = m["coords"].copy()
+    X[13] = [0.96, 0.5, 0.5]   # centre vertex pushed towards a face: corner-Jacobian ratio 24
+    m["coords"] = X
+    kap = torch.ones(1, 8, dtype=torch.float64)
+    rp, ci, v = orc.h1_matrix(X, m["elem_dofs"], 2, kap, 1.0)
+    pat = _pattern(m)
+    diag = torch.zeros(2, dtype=torch.int32, device=DEV)
+    v32 = _assemble(pat, m, kap.float(), 1.0, dtype=torch.float32, fp64_fallback=True, det_ratio_thresh=10.0,
+                    diag=diag)
+    d = diag.cpu().tolist()
+    assert d[0] > 0 and d[1] == 0
+    assert row_rel_err(rp, ci, v32, ci, v) <= 1e-6
+
+
+# ------------------------------------------------------------- benchmark sizes
+
+def test_h1_c2_full_parity():
+    """C2: p=4, 16^3 curved hexes, log-normal kappa (sigma 1), beta 1: every
+    entry against the oracle, FP64 and FP32."""
+    m = meshgen.config_mesh("c2_h1_p4_curved")
+    _say("c2 oracle")
+    rp, ci, v = orc.h1_matrix(m["coords"], m["elem_dofs"], 4, m["kappa"], 1.0)
+    pat = _pattern(m)
+    _check_pattern(pat, rp, ci)
+    v64 = _assemble(pat, m, m["kappa"], 1.0)
+    e64 = row_rel_err(rp, ci, v64, ci, v)
+    v32 = _assemble(pat, m, m["kappa"].float(), 1.0, dtype=torch.float32, fp64_fallback=True)
+    e32 = row_rel_err(rp, ci, v32, ci, v)
+    _say(f"c2 row-rel err fp64 {e64:.3e} fp32 {e32:.3e}")
+    assert e64 <= 1e-12 and e32 <= 1e-6
+
+
+def test_h1_c3_paper_counts_and_sampled_rows():
+    """C3 (p=6, 32^3 curved hexes): the pattern has the paper's 7,189,057 rows and
+    192,100,033 nonzeros; sampled rows (corners, faces, edges, random interior)
+    match the oracle in FP64 and FP32, in the launch configuration the benchmark
+    times."""
+    m = meshgen.config_mesh("c3_h1_p6_curved")
+    pat = _pattern(m)
+    assert pat.nrows == 7189057 and pat.nnz == 192100033
+    v64 = lor.lor_assemble_h1(pat, torch.from_numpy(m["elem_dofs"]), torch.from_numpy(m["coords"]), m["kappa"], 1.0)
+    v32 = lor.lor_assemble_h1(pat, torch.from_numpy(m["elem_dofs"]), torch.from_numpy(m["coords"]),
+                              m["kappa"].float(), 1.0, dtype=torch.float32, fp64_fallback=True)
+    torch.cuda.synchronize()
+    N = m["N"]
+    rng = np.random.default_rng(0)
+    pick = [0, N - 1, N * N - 1, N ** 3 - 1, (N // 2) * (1 + N + N * N), 6 + N * (6 + N * 6), 7 + N * 12]
+    pick += list(rng.integers(0, N ** 3, size=400))
+    rows, rp, ci, v = orc.h1_rows(m["coords"], m["elem_dofs"], 6, m["kappa"], 1.0, torch.tensor(pick))
+    grp = pat.row_ptr.cpu().to(torch.int64)
+    gci = pat.col_idx.cpu().to(torch.int64)
+    idx = torch.cat([torch.arange(grp[r], grp[r + 1]) for r in rows.tolist()])
+    assert torch.equal(gci[idx], ci)
+    assert torch.equal(grp[rows + 1] - grp[rows], rp[1:] - rp[:-1])
+    e64 = row_rel_err(rp, ci, v64.cpu()[idx], ci, v)
+    e32 = row_rel_err(rp, ci, v32.cpu()[idx], ci, v)
+    _say(f"c3 sampled row-rel err fp64 {e64:.3e} fp32 {e32:.3e}")
+    assert e64 <= 1e-12 and e32 <= 1e-6
+    # structural: every row of the Cartesian p=6 mesh has 8, 12, 18 or 27 entries
+    cnt = (grp[1:] - grp[:-1])
+    assert int(cnt.max()) == 27 and int(cnt.min()) == 8
