@@ -98,6 +98,7 @@ typedef struct lor_sched {
   int32_t max_row_nnz;
   int32_t color_ptr[LOR_MAX_COLORS + 1];  /* colour c = order[color_ptr[c] .. color_ptr[c+1]) */
   int64_t nclass;
+  int64_t tab_stride;            /* bytes between two element tables (nent rounded up to 16) */
   size_t dev_bytes;              /* written by phase 1: bytes to allocate for dev */
   void* dev;                     /* set by the caller before phase 2 */
   size_t off_order, off_color, off_class, off_tables;

@@ -65,6 +65,19 @@ inline int nloc_nd(int p) { return 3 * p * (p + 1) * (p + 1); }
 constexpr uint8_t kFirstBit = 0x80u;
 constexpr uint8_t kRankMask = 0x7fu;
 
+// Workgroup barrier for LDS traffic only.  __syncthreads() is also a
+// workgroup-scope memory fence, which makes every wave wait for all of its
+// outstanding global loads and stores first; the assembly kernels keep global
+// prefetches and stores in flight across phases, so they synchronise LDS with
+// this barrier instead (wait for the wave's LDS operations, then s_barrier).
+__device__ __forceinline__ void lds_barrier() {
+  __asm__ volatile("" ::: "memory");
+  // s_waitcnt lgkmcnt(0) with vmcnt and expcnt left at their maxima
+  __builtin_amdgcn_s_waitcnt(0xC07F);
+  __builtin_amdgcn_s_barrier();
+  __asm__ volatile("" ::: "memory");
+}
+
 template <typename T>
 inline T* dev_at(const lor_sched* s, size_t off) {
   return reinterpret_cast<T*>(static_cast<char*>(s->dev) + off);

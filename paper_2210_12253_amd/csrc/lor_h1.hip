@@ -1,23 +1,28 @@
-// Values of the LOR H1 matrix (Step S1.2, A1 + A2 fused), one workgroup per
-// batch of macro elements of one colour.
+// Values of the LOR H1 matrix (Step S1.2, A1 + A2 fused).
 //
 // The paper assembles each macro element's sparse block in global memory with
 // one thread per subelement and atomic additions, then scatters the blocks
-// into CSR.  Here the block never leaves the chip:
+// into CSR.  Here the block never leaves the chip.  A workgroup walks a chunk
+// of macro elements of one colour (E elements at a time, "group"), and for
+// every group:
 //
-//   phase 0  gather the macro element's (p+1)^3 vertex coordinates and the row
-//            pointers of its vertices into LDS;
+//   stage    the vertex coordinates, row pointers and rank table of the group,
+//            prefetched into registers while the previous group was computed,
+//            are written to LDS; the loads for the next group are issued
+//            (software pipelining: the gather latency hides behind the
+//            arithmetic);
 //   phase 1  one lane per subelement integrates its 8x8 matrix (36 unique
 //            entries, sum-factorised 2x2x2 Gauss) into LDS;
 //   phase 2  one lane per local vertex (row) sums the rows of the <= 8
 //            subelements around it in a fixed order (atomic-free, FP64 sums,
-//            bitwise symmetric), then writes the finished local row into LDS
-//            in the compact local-stencil order;
+//            bitwise symmetric) and writes the finished row into LDS in the
+//            compact local-stencil order;
 //   phase 3  lanes walk the compact entries and store them at
-//            row_ptr[row] + position-in-row (from the schedule): a plain store
-//            for the entry's first contributor, an add to the value already
-//            there for the others.  Colours run in order, so every entry's
-//            contributions are summed in the same order (deterministic).
+//            row_ptr[row] + position-in-row: a plain store for the entry's
+//            first contributor, an add to the stored value for the others.
+//            All loads of the phase are issued before any store.
+// Colours run as separate launches in increasing order, so every entry's
+// contributions are summed in the same order (deterministic).
 #include "lor_common.hpp"
 #include "lor_h1_math.hpp"
 
@@ -28,14 +33,21 @@ struct H1Cfg {
   static constexpr int Q = P + 1;
   static constexpr int NSUB = P * P * P;
   static constexpr int NLOC = Q * Q * Q;
-  static constexpr int T1 = 3 * P + 1;            // stencil entries per axis
-  static constexpr int NENT = T1 * T1 * T1;       // local stencil entries per element
-  // elements per workgroup: 256 lanes cover the subelements and every lane owns
+  static constexpr int T1 = 3 * P + 1;             // stencil entries per axis
+  static constexpr int NENT = T1 * T1 * T1;        // local stencil entries per element
+  static constexpr int NENTP = (NENT + 15) / 16 * 16;  // table stride in bytes
+  // elements per group: 256 lanes cover the subelements and every lane owns
   // at most two local rows
   static constexpr int E = P == 1 ? 64 : P == 2 ? 16 : P == 3 ? 8 : P == 4 ? 4 : P == 5 ? 2 : 1;
   static constexpr int THREADS = 256;
-  static_assert(E * NLOC <= 2 * THREADS, "two rows per lane");
+  static constexpr int RV = (E * NLOC + THREADS - 1) / THREADS;         // vertex slots per lane
+  static constexpr int TW = E * NENTP / 4;                             // table words per group
+  static constexpr int RW = (TW + THREADS - 1) / THREADS;              // table words per lane
+  static constexpr int NJ = (E * NENT + THREADS - 1) / THREADS;        // phase-3 entries per lane
+  static constexpr int MAXCHUNK = 256;                                 // elements per workgroup
+  static_assert(RV <= 2, "two rows per lane");
   static_assert(E * NSUB <= THREADS, "one subelement per lane");
+  static_assert(NJ <= 64, "phase-3 mask");
 };
 
 // number of stencil offsets along one axis at lattice coordinate t, and the
@@ -49,162 +61,285 @@ __device__ __forceinline__ int pre1(int t) {
   return t == 0 ? 0 : 3 * t - 1;
 }
 
+// FP32 form, strongly curved subelement: FP64 geometry and quadrature, entries
+// rounded to FP32.
+template <int NSUB>
+__device__ __forceinline__ bool h1_fp64_fallback(const double (&X)[8][3], double kap, double bet, float* out) {
+  double dx[2][2][3], dy[2][2][3], dz[2][2][3];
+  h1_edges<double>(X, dx, dy, dz);
+  H1Factors<double> F;
+  const bool ok = h1_factors<double>(dx, dy, dz, kap, bet, F);
+#pragma unroll
+  for (int u = 0; u < 8; ++u)
+#pragma unroll
+    for (int v = u; v < 8; ++v) out[pair_index(u, v) * NSUB] = static_cast<float>(h1_entry<double>(F, u, v));
+  return ok;
+}
+
 template <int P, typename T, typename R>
-__global__ __launch_bounds__(256) void k_h1_assemble(
-    const int32_t* __restrict__ order, int32_t ncol, const int32_t* __restrict__ elem_dofs,
-    const double* __restrict__ coords, const T* __restrict__ kappa, T beta,
-    const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ class_id,
-    const uint8_t* __restrict__ tables, const int32_t* __restrict__ ent_row, int64_t nel,
+__global__ __launch_bounds__(256, 2) void k_h1_assemble(
+    const int32_t* __restrict__ order, int32_t ncol, int32_t chunk, const int32_t* __restrict__ elem_dofs,
+    const double* __restrict__ coords, const T* __restrict__ kappa, T beta, const int32_t* __restrict__ row_ptr,
+    const uint8_t* __restrict__ tables, int64_t tab_stride, const uint16_t* __restrict__ ent_row, int64_t nel,
     int64_t nnz, T* __restrict__ values, unsigned flags, R det_thresh, int32_t* __restrict__ diag) {
   using C = H1Cfg<P>;
-  constexpr int Q = C::Q, NSUB = C::NSUB, NLOC = C::NLOC, NENT = C::NENT, E = C::E;
-  constexpr int SUBW = E * NSUB * 36;        // subelement entries, layout [E][36][NSUB]
-  constexpr int STGW = E * NENT;             // finished local entries, [E][NENT]
+  constexpr int Q = C::Q, NSUB = C::NSUB, NLOC = C::NLOC, NENT = C::NENT, NENTP = C::NENTP, E = C::E;
+  constexpr int TH = C::THREADS, RV = C::RV, RW = C::RW, NJ = C::NJ, TWE = NENTP / 4;
+  constexpr int SUBW = E * NSUB * 36;  // subelement entries, layout [E][36][NSUB]
+  constexpr int STGW = E * NENT;       // finished local entries, [E][NENT]
   constexpr int REGW = SUBW > STGW ? SUBW : STGW;
   __shared__ double sX[E * NLOC * 3];
   __shared__ int32_t sRp[E * NLOC];
+  __shared__ uint32_t sTabW[E * TWE];
   __shared__ R sSub[REGW];
-  __shared__ int32_t sElem[E];
+  __shared__ int32_t sOrd[C::MAXCHUNK];
   T* sStg = reinterpret_cast<T*>(sSub);
+  const uint8_t* sTab = reinterpret_cast<const uint8_t*>(sTabW);
   static_assert(sizeof(T) <= sizeof(R), "staging aliases the subelement region");
 
   const int tid = threadIdx.x;
-  const int64_t b = blockIdx.y;
-  kappa += b * nel * NSUB;
-  values += b * nnz;
-  const int64_t first = static_cast<int64_t>(blockIdx.x) * E;
-  const int ne = static_cast<int>(ncol - first < E ? ncol - first : E);
-  if (tid < E) sElem[tid] = tid < ne ? order[first + tid] : 0;
+  kappa += static_cast<int64_t>(blockIdx.y) * nel * NSUB;
+  values += static_cast<int64_t>(blockIdx.y) * nnz;
+  const int64_t cbeg = static_cast<int64_t>(blockIdx.x) * chunk;
+  const int nce = static_cast<int>(ncol - cbeg < chunk ? ncol - cbeg : chunk);
+  const int ngr = (nce + E - 1) / E;
+  if (tid < nce) sOrd[tid] = order[cbeg + tid];
   __syncthreads();
 
-  // phase 0: coordinates and row pointers of the element vertices
-  for (int i = tid; i < ne * NLOC; i += C::THREADS) {
-    const int el = i / NLOC;
-    const int l = i - el * NLOC;
-    const int32_t g = elem_dofs[static_cast<int64_t>(sElem[el]) * NLOC + l];
-    sX[3 * i + 0] = coords[3 * static_cast<int64_t>(g) + 0];
-    sX[3 * i + 1] = coords[3 * static_cast<int64_t>(g) + 1];
-    sX[3 * i + 2] = coords[3 * static_cast<int64_t>(g) + 2];
-    sRp[i] = row_ptr[g];
-  }
-  __syncthreads();
-
-  // phase 1: subelement matrices
-  if (tid < ne * NSUB) {
-    const int el = tid / NSUB;
-    const int s = tid - el * NSUB;
-    const int si = s % P, sj = (s / P) % P, sk = s / (P * P);
-    double X[8][3];
+  auto group_size = [&](int g) { return nce - g * E < E ? nce - g * E : E; };
+  // --- prefetch helpers (registers) ----------------------------------------
+  auto load_dofs = [&](int g, int32_t (&d)[RV]) {
 #pragma unroll
-    for (int v = 0; v < 8; ++v) {
-      const int lv = (si + (v & 1)) + Q * ((sj + ((v >> 1) & 1)) + Q * (sk + (v >> 2)));
-#pragma unroll
-      for (int d = 0; d < 3; ++d) X[v][d] = sX[3 * (el * NLOC + lv) + d];
+    for (int j = 0; j < RV; ++j) {
+      const int i = tid + j * TH;
+      d[j] = -1;
+      if (g < ngr && i < group_size(g) * NLOC) {
+        const int el = i / NLOC;
+        d[j] = elem_dofs[static_cast<int64_t>(sOrd[g * E + el]) * NLOC + (i - el * NLOC)];
+      }
     }
-    const R kap = static_cast<R>(kappa[static_cast<int64_t>(sElem[el]) * NSUB + s]);
-    R* out = sSub + el * 36 * NSUB + s;
-    bool done = false;
-    if constexpr (!std::is_same<R, double>::value) {
-      if (flags & LOR_FP64_FALLBACK) {
+  };
+  auto load_geo = [&](const int32_t (&d)[RV], double (&x)[RV][3], int32_t (&rp)[RV]) {
+#pragma unroll
+    for (int j = 0; j < RV; ++j) {
+      if (d[j] >= 0) {
+        const int64_t g3 = 3 * static_cast<int64_t>(d[j]);
+        x[j][0] = coords[g3 + 0];
+        x[j][1] = coords[g3 + 1];
+        x[j][2] = coords[g3 + 2];
+        rp[j] = row_ptr[d[j]];
+      }
+    }
+  };
+  auto load_kap = [&](int g, T& k) {
+    if (g < ngr && tid < group_size(g) * NSUB) {
+      const int el = tid / NSUB;
+      k = kappa[static_cast<int64_t>(sOrd[g * E + el]) * NSUB + (tid - el * NSUB)];
+    }
+  };
+  auto load_tab = [&](int g, uint32_t (&w)[RW]) {
+#pragma unroll
+    for (int j = 0; j < RW; ++j) {
+      const int i = tid + j * TH;
+      if (g < ngr && i < group_size(g) * TWE) {
+        const int el = i / TWE;
+        const uint32_t* row = reinterpret_cast<const uint32_t*>(tables + sOrd[g * E + el] * tab_stride);
+        w[j] = row[i - el * TWE];
+      }
+    }
+  };
+
+  int32_t dnext[RV];
+  double xq[RV][3] = {};
+  int32_t rq[RV] = {};
+  T kq = T(0);
+  {
+    int32_t d0[RV];
+    load_dofs(0, d0);
+    load_geo(d0, xq, rq);
+    load_dofs(1, dnext);
+    load_kap(0, kq);
+  }
+
+  for (int g = 0; g < ngr; ++g) {
+    const int ne = group_size(g);
+    // Index arithmetic below is cheap; an opaque copy of the lane id keeps the
+    // compiler from hoisting it out of the loop into long-lived registers.
+    int tid = threadIdx.x;
+    __asm__ volatile("" : "+v"(tid));
+    lds_barrier();  // the previous group is done with every LDS buffer
+#pragma unroll
+    for (int j = 0; j < RV; ++j) {
+      const int i = tid + j * TH;
+      if (i < ne * NLOC) {
+        sX[3 * i + 0] = xq[j][0];
+        sX[3 * i + 1] = xq[j][1];
+        sX[3 * i + 2] = xq[j][2];
+        sRp[i] = rq[j];
+      }
+    }
+    const T kcur = kq;
+    // prefetch the next group; the loads complete while this group is computed
+    load_geo(dnext, xq, rq);
+    load_dofs(g + 2, dnext);
+    load_kap(g + 1, kq);
+    lds_barrier();
+
+    // phase 1: subelement matrices
+    if (tid < ne * NSUB) {
+      const int el = tid / NSUB;
+      const int s = tid - el * NSUB;
+      const int si = s % P, sj = (s / P) % P, sk = s / (P * P);
+      auto load_X = [&](double (&X)[8][3]) {
+#pragma unroll
+        for (int v = 0; v < 8; ++v) {
+          const int lv = (si + (v & 1)) + Q * ((sj + ((v >> 1) & 1)) + Q * (sk + (v >> 2)));
+#pragma unroll
+          for (int d = 0; d < 3; ++d) X[v][d] = sX[3 * (el * NLOC + lv) + d];
+        }
+      };
+      const R kap = static_cast<R>(kcur);
+      R* out = sSub + el * 36 * NSUB + s;
+      bool fallback = false;
+      if constexpr (!std::is_same<R, double>::value) {
+        if (flags & LOR_FP64_FALLBACK) {
+          // corner-Jacobian test; the edge vectors are formed again below so
+          // that they are not kept alive across the FP64 branch
+          R ex[2][2][3], ey[2][2][3], ez[2][2][3];
+          double X[8][3];
+          load_X(X);
+          h1_edges<R>(X, ex, ey, ez);
+          R dmin, dmax;
+          h1_corner_det_range<R>(ex, ey, ez, dmin, dmax);
+          fallback = !(dmin > R(0)) || dmax > det_thresh * dmin;
+        }
+      }
+      if (!fallback) {
         R ex[2][2][3], ey[2][2][3], ez[2][2][3];
-        h1_edges<R>(X, ex, ey, ez);
-        R dmin, dmax;
-        h1_corner_det_range<R>(ex, ey, ez, dmin, dmax);
-        if (!(dmin > R(0)) || dmax > det_thresh * dmin) {
-          double dx[2][2][3], dy[2][2][3], dz[2][2][3];
-          h1_edges<double>(X, dx, dy, dz);
-          H1Factors<double> F;
-          const bool ok = h1_factors<double>(dx, dy, dz, static_cast<double>(kap), static_cast<double>(beta), F);
+        {
+          double X[8][3];
+          load_X(X);
+          h1_edges<R>(X, ex, ey, ez);
+        }
+        H1Factors<R> F;
+        const bool ok = h1_factors<R>(ex, ey, ez, kap, static_cast<R>(beta), F);
 #pragma unroll
-          for (int u = 0; u < 8; ++u)
+        for (int u = 0; u < 8; ++u)
 #pragma unroll
-            for (int v = u; v < 8; ++v) out[pair_index(u, v) * NSUB] = static_cast<R>(h1_entry<double>(F, u, v));
-          if (diag) {
-            atomicAdd(&diag[0], 1);
-            if (!ok) atomicAdd(&diag[1], 1);
-          }
-          done = true;
+          for (int v = u; v < 8; ++v) out[pair_index(u, v) * NSUB] = h1_entry<R>(F, u, v);
+        if (!ok && diag) atomicAdd(&diag[1], 1);
+      }
+      if (fallback) {
+        // FP32 form on a strongly curved subelement: FP64 geometry and
+        // quadrature from the FP64 coordinates, entries rounded to FP32
+        double X[8][3];
+        load_X(X);
+        const bool ok = h1_fp64_fallback<NSUB>(X, static_cast<double>(kap), static_cast<double>(beta),
+                                               reinterpret_cast<float*>(out));
+        if (diag) {
+          atomicAdd(&diag[0], 1);
+          if (!ok) atomicAdd(&diag[1], 1);
         }
       }
     }
-    if (!done) {
-      R ex[2][2][3], ey[2][2][3], ez[2][2][3];
-      h1_edges<R>(X, ex, ey, ez);
-      H1Factors<R> F;
-      const bool ok = h1_factors<R>(ex, ey, ez, kap, static_cast<R>(beta), F);
-#pragma unroll
-      for (int u = 0; u < 8; ++u)
-#pragma unroll
-        for (int v = u; v < 8; ++v) out[pair_index(u, v) * NSUB] = h1_entry<R>(F, u, v);
-      if (!ok && diag) atomicAdd(&diag[1], 1);
-    }
-  }
-  __syncthreads();
+    lds_barrier();
 
-  // phase 2: local rows.  Lane owns rows tid and tid + 256.
-  double acc[2][27];
+    // phase 2: local rows.  Lane owns rows tid and tid + 256.  The rank table
+    // of the group is fetched meanwhile (needed in phase 3 only).
+    uint32_t twq[RW];
+    load_tab(g, twq);
+    double acc[2][27];
 #pragma unroll
-  for (int h = 0; h < 2; ++h) {
+    for (int h = 0; h < 2; ++h) {
 #pragma unroll
-    for (int o = 0; o < 27; ++o) acc[h][o] = 0.0;
-    const int r = tid + h * C::THREADS;
-    if (r < ne * NLOC) {
-      const int el = r / NLOC;
-      const int l = r - el * NLOC;
-      const int x = l % Q, y = (l / Q) % Q, z = l / (Q * Q);
-      const R* base = sSub + el * 36 * NSUB;
-      // corner u of the subelement s = (x,y,z) - u; s decreases as u grows
+      for (int o = 0; o < 27; ++o) acc[h][o] = 0.0;
+      const int r = tid + h * TH;
+      if (r < ne * NLOC) {
+        const int el = r / NLOC;
+        const int l = r - el * NLOC;
+        const int x = l % Q, y = (l / Q) % Q, z = l / (Q * Q);
+        const R* base = sSub + el * 36 * NSUB;
+        // corner u of the subelement s = (x,y,z) - u; s decreases as u grows
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int a = u & 1, bb = (u >> 1) & 1, c = u >> 2;
-        const int sx = x - a, sy = y - bb, sz = z - c;
-        if (sx >= 0 && sx < P && sy >= 0 && sy < P && sz >= 0 && sz < P) {
-          const int s = sx + P * (sy + P * sz);
+        for (int u = 0; u < 8; ++u) {
+          const int a = u & 1, bb = (u >> 1) & 1, c = u >> 2;
+          const int sx = x - a, sy = y - bb, sz = z - c;
+          if (sx >= 0 && sx < P && sy >= 0 && sy < P && sz >= 0 && sz < P) {
+            const int s = sx + P * (sy + P * sz);
 #pragma unroll
-          for (int v = 0; v < 8; ++v) {
-            const int o = ((v & 1) - a + 1) + 3 * ((((v >> 1) & 1) - bb + 1) + 3 * ((v >> 2) - c + 1));
-            acc[h][o] += static_cast<double>(base[pair_index(u, v) * NSUB + s]);
+            for (int v = 0; v < 8; ++v) {
+              const int o = ((v & 1) - a + 1) + 3 * ((((v >> 1) & 1) - bb + 1) + 3 * ((v >> 2) - c + 1));
+              acc[h][o] += static_cast<double>(base[pair_index(u, v) * NSUB + s]);
+            }
           }
         }
       }
     }
-  }
-  __syncthreads();  // every lane has read sSub; now it becomes the staging area
+    lds_barrier();  // every lane has read sSub; now it becomes the staging area
 #pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    const int r = tid + h * C::THREADS;
-    if (r < ne * NLOC) {
-      const int el = r / NLOC;
-      const int l = r - el * NLOC;
-      const int x = l % Q, y = (l / Q) % Q, z = l / (Q * Q);
-      const int nx = cnt1<P>(x), ny = cnt1<P>(y);
-      const int rbase = pre1<P>(z) * C::T1 * C::T1 + cnt1<P>(z) * pre1<P>(y) * C::T1 + cnt1<P>(z) * ny * pre1<P>(x);
-      T* dst = sStg + el * NENT + rbase;
-      const int x0 = x > 0 ? 1 : 0, y0 = y > 0 ? 1 : 0, z0 = z > 0 ? 1 : 0;
+    for (int h = 0; h < 2; ++h) {
+      const int r = tid + h * TH;
+      if (r < ne * NLOC) {
+        const int el = r / NLOC;
+        const int l = r - el * NLOC;
+        const int x = l % Q, y = (l / Q) % Q, z = l / (Q * Q);
+        const int nx = cnt1<P>(x), ny = cnt1<P>(y);
+        const int rbase = pre1<P>(z) * C::T1 * C::T1 + cnt1<P>(z) * pre1<P>(y) * C::T1 + cnt1<P>(z) * ny * pre1<P>(x);
+        T* dst = sStg + el * NENT + rbase;
+        const int x0 = x > 0 ? 1 : 0, y0 = y > 0 ? 1 : 0, z0 = z > 0 ? 1 : 0;
 #pragma unroll
-      for (int o = 0; o < 27; ++o) {
-        const int dx = o % 3 - 1, dy = (o / 3) % 3 - 1, dz = o / 9 - 1;
-        if (x + dx < 0 || x + dx > P || y + dy < 0 || y + dy > P || z + dz < 0 || z + dz > P) continue;
-        const int idx = ((dz + z0) * ny + (dy + y0)) * nx + (dx + x0);
-        dst[idx] = static_cast<T>(acc[h][o]);
+        for (int o = 0; o < 27; ++o) {
+          const int dx = o % 3 - 1, dy = (o / 3) % 3 - 1, dz = o / 9 - 1;
+          if (x + dx < 0 || x + dx > P || y + dy < 0 || y + dy > P || z + dz < 0 || z + dz > P) continue;
+          dst[((dz + z0) * ny + (dy + y0)) * nx + (dx + x0)] = static_cast<T>(acc[h][o]);
+        }
       }
     }
-  }
-  __syncthreads();
+#pragma unroll
+    for (int j = 0; j < RW; ++j) {
+      const int i = tid + j * TH;
+      if (i < ne * TWE) sTabW[i] = twq[j];
+    }
+    lds_barrier();
 
-  // phase 3: store into the CSR values
-  for (int i = tid; i < ne * NENT; i += C::THREADS) {
-    const int el = i / NENT;
-    const int k = i - el * NENT;
-    const int32_t e = sElem[el];
-    const uint8_t t = tables[static_cast<int64_t>(class_id[e]) * NENT + k];
-    const int64_t pos = static_cast<int64_t>(sRp[el * NLOC + ent_row[k]]) + (t & kRankMask);
-    const T v = sStg[i];
-    if (t & kFirstBit)
-      values[pos] = v;
-    else
-      values[pos] = values[pos] + v;
+    // phase 3: store into the CSR values; every load is issued before any store
+    int32_t pos[NJ];
+    T old[NJ];
+    uint64_t rmw = 0;
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+      const int i = tid + j * TH;
+      pos[j] = -1;
+      if (i < ne * NENT) {
+        const int el = i / NENT;
+        const int k = i - el * NENT;
+        const uint8_t t = sTab[el * NENTP + k];
+        pos[j] = sRp[el * NLOC + ent_row[k]] + (t & kRankMask);
+        if (!(t & kFirstBit)) rmw |= (1ull << j);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+      old[j] = T(0);
+      if ((rmw >> j) & 1ull) old[j] = values[pos[j]];
+    }
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+      if (pos[j] >= 0) values[pos[j]] = sStg[tid + j * TH] + old[j];
+    }
   }
+}
+
+static int num_cus() {
+  static int cached[64] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  if (cached[dev] == 0) {
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) n = 256;
+    cached[dev] = n;
+  }
+  return cached[dev];
 }
 
 template <int P, typename T, typename R>
@@ -212,18 +347,24 @@ static int launch_h1(const lor_sched* sched, int batch, const int32_t* elem_dofs
                      const void* kappa, double beta, const int32_t* row_ptr, void* values, unsigned flags,
                      double thr, int32_t* diag, hipStream_t st) {
   using C = H1Cfg<P>;
+  if (sched->tab_stride != C::NENTP || sched->nent != C::NENT)
+    LOR_FAIL(LOR_EINVAL, "schedule tables do not match p = %d", P);
   const int32_t* order = dev_at<int32_t>(sched, sched->off_order);
-  const int32_t* cls = dev_at<int32_t>(sched, sched->off_class);
   const uint8_t* tab = dev_at<uint8_t>(sched, sched->off_tables);
-  const int32_t* ent_row = dev_at<int32_t>(sched, sched->off_ent_row);
+  const uint16_t* ent_row = dev_at<uint16_t>(sched, sched->off_ent_row);
+  const int wgs = 2 * num_cus();  // two resident workgroups per CU
   for (int c = 0; c < sched->ncolors; ++c) {
     const int32_t n = sched->color_ptr[c + 1] - sched->color_ptr[c];
     if (n <= 0) continue;
-    dim3 grid(static_cast<unsigned>(ceil_div(n, C::E)), static_cast<unsigned>(batch));
+    const int64_t groups = ceil_div(n, C::E);
+    int64_t gpw = ceil_div(groups, wgs);  // groups per workgroup
+    if (gpw * C::E > C::MAXCHUNK) gpw = C::MAXCHUNK / C::E;
+    const int32_t chunk = static_cast<int32_t>(gpw * C::E);
+    dim3 grid(static_cast<unsigned>(ceil_div(n, chunk)), static_cast<unsigned>(batch));
     k_h1_assemble<P, T, R><<<grid, C::THREADS, 0, st>>>(
-        order + sched->color_ptr[c], n, elem_dofs, coords, static_cast<const T*>(kappa), static_cast<T>(beta),
-        row_ptr, cls, tab, ent_row, sched->nel, sched->nnz, static_cast<T*>(values), flags, static_cast<R>(thr),
-        diag);
+        order + sched->color_ptr[c], n, chunk, elem_dofs, coords, static_cast<const T*>(kappa), static_cast<T>(beta),
+        row_ptr, tab, sched->tab_stride, ent_row, sched->nel, sched->nnz, static_cast<T*>(values), flags,
+        static_cast<R>(thr), diag);
     LOR_LAUNCHED("k_h1_assemble");
   }
   return LOR_OK;
@@ -268,7 +409,7 @@ extern "C" int lor_assemble_h1(int p, int64_t nel, int64_t ndofs, int batch, con
   clear_error();
   if (p < 1 || p > LOR_MAX_P) LOR_FAIL(LOR_EINVAL, "p = %d outside [1, %d]", p, LOR_MAX_P);
   if (nel < 0 || ndofs < 1) LOR_FAIL(LOR_EINVAL, "nel < 0 or ndofs < 1");
-  if (batch < 1) LOR_FAIL(LOR_EINVAL, "batch < 1");
+  if (batch < 1 || batch > 65535) LOR_FAIL(LOR_EINVAL, "batch outside [1, 65535]");
   if (dtype != LOR_F64 && dtype != LOR_F32) LOR_FAIL(LOR_EINVAL, "dtype must be LOR_F64 or LOR_F32");
   if (flags & ~LOR_FP64_FALLBACK) LOR_FAIL(LOR_EINVAL, "unknown flag bits 0x%x", flags);
   if ((flags & LOR_FP64_FALLBACK) && !(det_ratio_thresh >= 1.0))

@@ -136,7 +136,8 @@ __device__ __forceinline__ bool h1_factors(const R (&ex)[2][2][3], const R (&ey)
     }
 
   R H00[2][2] = {}, H11[2][2] = {}, H22[2][2] = {};
-  R Z01[2][2][2] = {}, Z02[2][2][2] = {}, Z12[3][2][2] = {}, U[3][2][2] = {};
+  R Z01[2][2][2] = {}, Z02[2][2][2] = {};
+  R G12q[2][2][2], Dq[2][2][2];  // per Gauss point (q1, q2, q3): G_12 and beta det J / 8
   bool ok = true;
   const R wk = R(0.125) * kap;
   const R wb = R(0.125) * bet;
@@ -177,11 +178,8 @@ __device__ __forceinline__ bool h1_factors(const R (&ex)[2][2][3], const R (&ey)
           Z01[x][q2][q3] += R(L1(x, q1)) * g01;
           Z02[x][q2][q3] += R(L1(x, q1)) * g02;
         }
-#pragma unroll
-        for (int al = 0; al < 3; ++al) {
-          Z12[al][q2][q3] += R(LL(al, q1)) * g12;
-          U[al][q2][q3] += R(LL(al, q1)) * dm;
-        }
+        G12q[q1][q2][q3] = g12;
+        Dq[q1][q2][q3] = dm;
       }
 
   // diagonal families: contract the two remaining axes with LL
@@ -221,6 +219,17 @@ __device__ __forceinline__ bool h1_factors(const R (&ex)[2][2][3], const R (&ey)
       for (int B = 0; B < 3; ++B) F.T02[x][z][B] = R(LL(B, 0)) * t0 + R(LL(B, 1)) * t1;
     }
   }
+  // contract xi of the raw per-point values with LL_A
+  R Z12[3][2][2], U[3][2][2];
+#pragma unroll
+  for (int al = 0; al < 3; ++al)
+#pragma unroll
+    for (int t2 = 0; t2 < 2; ++t2)
+#pragma unroll
+      for (int t3 = 0; t3 < 2; ++t3) {
+        Z12[al][t2][t3] = R(LL(al, 0)) * G12q[0][t2][t3] + R(LL(al, 1)) * G12q[1][t2][t3];
+        U[al][t2][t3] = R(LL(al, 0)) * Dq[0][t2][t3] + R(LL(al, 1)) * Dq[1][t2][t3];
+      }
 #pragma unroll
   for (int al = 0; al < 3; ++al) {
 #pragma unroll

@@ -58,7 +58,8 @@ struct DevBuf {
 
 struct RefElem {
   int nloc = 0, nent = 0;
-  std::vector<int32_t> st_ptr, st_col, ent_row;
+  std::vector<int32_t> st_ptr, st_col;
+  std::vector<uint16_t> ent_row;  // local row of every compact stencil entry
   std::vector<int32_t> reps;    // local dofs whose incidences give element adjacency
   std::vector<int32_t> recipe;  // Nedelec: per local edge, subelement contributions
 };
@@ -96,7 +97,7 @@ static RefElem build_ref_h1(int p) {
               const int a = i + dx, b = j + dy, c = k + dz;
               if (a < 0 || b < 0 || c < 0 || a > p || b > p || c > p) continue;
               r.st_col.push_back(a + q * (b + q * c));
-              r.ent_row.push_back(l);
+              r.ent_row.push_back(static_cast<uint16_t>(l));
             }
         r.st_ptr.push_back(static_cast<int32_t>(r.st_col.size()));
       }
@@ -137,7 +138,7 @@ static RefElem build_ref_nd(int p) {
     v.erase(std::unique(v.begin(), v.end()), v.end());
     for (int c : v) {
       r.st_col.push_back(c);
-      r.ent_row.push_back(l);
+      r.ent_row.push_back(static_cast<uint16_t>(l));
     }
     r.st_ptr.push_back(static_cast<int32_t>(r.st_col.size()));
     // stencil positions of each contributing subelement's edges
@@ -440,8 +441,8 @@ __global__ void k_color_scatter(const int32_t* __restrict__ color, int64_t nel, 
 }
 
 // Position of every local stencil entry inside its CSR row; lowest colour per nnz.
-__global__ void k_rank_pass0(const int32_t* __restrict__ map, int nloc, int is_signed, int nent,
-                             const int32_t* __restrict__ ent_row, const int32_t* __restrict__ ent_col,
+__global__ void k_rank_pass0(const int32_t* __restrict__ map, int nloc, int is_signed, int nent, int64_t stride,
+                             const uint16_t* __restrict__ ent_row, const int32_t* __restrict__ ent_col,
                              const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col_idx,
                              const int32_t* __restrict__ color, int64_t total,
                              int32_t* __restrict__ mincolor, uint8_t* __restrict__ tables,
@@ -462,17 +463,18 @@ __global__ void k_rank_pass0(const int32_t* __restrict__ map, int nloc, int is_s
     else
       hi = mid;
   }
+  uint8_t* tab = tables + e * stride + k;
   if (lo >= row_ptr[g + 1] || col_idx[lo] != c) {
     atomicOr(err, kErrRankMissing);
-    tables[idx] = 0;
+    *tab = 0;
     return;
   }
-  tables[idx] = static_cast<uint8_t>(lo - start);
+  *tab = static_cast<uint8_t>(lo - start);
   atomicMin(&mincolor[lo], color[e]);
 }
 
-__global__ void k_rank_pass1(const int32_t* __restrict__ map, int nloc, int is_signed, int nent,
-                             const int32_t* __restrict__ ent_row, const int32_t* __restrict__ row_ptr,
+__global__ void k_rank_pass1(const int32_t* __restrict__ map, int nloc, int is_signed, int nent, int64_t stride,
+                             const uint16_t* __restrict__ ent_row, const int32_t* __restrict__ row_ptr,
                              const int32_t* __restrict__ color, int64_t total,
                              const int32_t* __restrict__ mincolor, uint8_t* __restrict__ tables) {
   const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -480,8 +482,9 @@ __global__ void k_rank_pass1(const int32_t* __restrict__ map, int nloc, int is_s
   const int64_t e = idx / nent;
   const int k = static_cast<int>(idx - e * nent);
   const int32_t g = dof_id(map[e * nloc + ent_row[k]], is_signed);
-  const uint8_t t = tables[idx];
-  if (mincolor[row_ptr[g] + (t & kRankMask)] == color[e]) tables[idx] = static_cast<uint8_t>(t | kFirstBit);
+  uint8_t* tab = tables + e * stride + k;
+  const uint8_t t = *tab;
+  if (mincolor[row_ptr[g] + (t & kRankMask)] == color[e]) *tab = static_cast<uint8_t>(t | kFirstBit);
 }
 
 // --------------------------------------------------------------- host side
@@ -498,12 +501,13 @@ static size_t layout(lor_sched* s, const RefElem& r) {
   s->off_order = take(sizeof(int32_t) * s->nel);
   s->off_color = take(sizeof(int32_t) * s->nel);
   s->off_class = take(sizeof(int32_t) * s->nel);
-  s->off_tables = take(static_cast<size_t>(s->nel) * r.nent);
+  s->tab_stride = (r.nent + 15) / 16 * 16;
+  s->off_tables = take(static_cast<size_t>(s->nel) * s->tab_stride);
   s->off_inc_ptr = take(sizeof(int32_t) * (s->nrows + 1));
   s->off_inc_list = take(sizeof(int32_t) * s->nel * r.nloc);
   s->off_st_ptr = take(sizeof(int32_t) * r.st_ptr.size());
   s->off_st_col = take(sizeof(int32_t) * r.st_col.size());
-  s->off_ent_row = take(sizeof(int32_t) * r.ent_row.size());
+  s->off_ent_row = take(sizeof(uint16_t) * r.ent_row.size());
   s->off_recipe = take(sizeof(int32_t) * std::max<size_t>(1, r.recipe.size()));
   return off;
 }
@@ -651,7 +655,7 @@ extern "C" int lor_pattern(int space, int p, int64_t nel, int64_t nrows, const i
   int32_t* d_inc_list = dev_at<int32_t>(sched, sched->off_inc_list);
   int32_t* d_st_ptr = dev_at<int32_t>(sched, sched->off_st_ptr);
   int32_t* d_st_col = dev_at<int32_t>(sched, sched->off_st_col);
-  int32_t* d_ent_row = dev_at<int32_t>(sched, sched->off_ent_row);
+  uint16_t* d_ent_row = dev_at<uint16_t>(sched, sched->off_ent_row);
   int32_t* d_recipe = dev_at<int32_t>(sched, sched->off_recipe);
   DevBuf reps;
   if ((rc = reps.alloc(sizeof(int32_t) * ref.reps.size()))) return rc;
@@ -729,11 +733,14 @@ extern "C" int lor_pattern(int space, int p, int64_t nel, int64_t nrows, const i
     k_fill_i32<<<ceil_div(std::max<int64_t>(1, nnzv), 256), 256, 0, st>>>(mincol.as<int32_t>(), nnzv, INT32_MAX);
     LOR_LAUNCHED("k_fill_i32");
     if (tot > 0) {
-      k_rank_pass0<<<ceil_div(tot, 256), 256, 0, st>>>(elem_map, nloc, is_signed, ref.nent, d_ent_row, d_st_col,
+      LOR_HIP(hipMemsetAsync(d_tab, 0, static_cast<size_t>(nel) * sched->tab_stride, st));
+      k_rank_pass0<<<ceil_div(tot, 256), 256, 0, st>>>(elem_map, nloc, is_signed, ref.nent, sched->tab_stride,
+                                                        d_ent_row, d_st_col,
                                                         row_ptr, col_idx, d_color, tot, mincol.as<int32_t>(), d_tab,
                                                         err.as<int32_t>());
       LOR_LAUNCHED("k_rank_pass0");
-      k_rank_pass1<<<ceil_div(tot, 256), 256, 0, st>>>(elem_map, nloc, is_signed, ref.nent, d_ent_row, row_ptr,
+      k_rank_pass1<<<ceil_div(tot, 256), 256, 0, st>>>(elem_map, nloc, is_signed, ref.nent, sched->tab_stride,
+                                                        d_ent_row, row_ptr,
                                                         d_color, tot, mincol.as<int32_t>(), d_tab);
       LOR_LAUNCHED("k_rank_pass1");
     }

@@ -53,6 +53,7 @@ class LorSched(ctypes.Structure):
         ("max_row_nnz", ctypes.c_int32),
         ("color_ptr", ctypes.c_int32 * (LOR_MAX_COLORS + 1)),
         ("nclass", ctypes.c_int64),
+        ("tab_stride", ctypes.c_int64),
         ("dev_bytes", ctypes.c_size_t),
         ("dev", ctypes.c_void_p),
         ("off_order", ctypes.c_size_t),
