@@ -1,15 +1,285 @@
 // Adjoint of the LOR H1 assembly with respect to kappa and the coordinates.
+//
+// L = sum_b <Gbar_b, A_b>,  A_b = sum_s kappa_{b,s} K^s + beta M^s  (K^s at kappa = 1).
+//   dL/dkappa_{b,s} = sum_{u,v} Gbar_b[pos(s,u,v)] K^s_uv,
+//   dL/dX = sum_s <sum_b kappa_{b,s} Gbar_b|s, dK^s/dX> + <sum_b Gbar_b|s, dM^s/dX>.
+// One lane per subelement recomputes the geometry and K^s (nothing is stored
+// by the forward pass), gathers the cotangent at the 64 CSR positions of its
+// 8x8 block for every batch entry, writes dL/dkappa, and runs the reverse of
+// the sum-factorised integration to get the adjoint of its 8 corner
+// coordinates.  The corners are summed per element vertex in LDS in a fixed
+// order (element E-vector), then per global vertex over its sorted
+// incidences (deterministic; coordinates are shared by the batch, so their
+// gradient is the sum over the batch).
 #include "lor_common.hpp"
+#include "lor_h1_adjoint.hpp"
+
+namespace lor {
+
+int check_sched(const lor_sched* s, int space, int p, int64_t nel, int64_t nrows);
+
+template <int P>
+struct BwCfg {
+  static constexpr int Q = P + 1;
+  static constexpr int NSUB = P * P * P;
+  static constexpr int NLOC = Q * Q * Q;
+  static constexpr int T1 = 3 * P + 1;
+  static constexpr int NENT = T1 * T1 * T1;
+  static constexpr int NENTP = (NENT + 15) / 16 * 16;
+  static constexpr int E = P == 1 ? 64 : P == 2 ? 16 : P == 3 ? 8 : P == 4 ? 4 : P == 5 ? 2 : 1;
+  static constexpr int THREADS = 256;
+  static constexpr int TWE = NENTP / 4;
+};
+
+// Compact index of stencil entry (vertex (x,y,z), offset (dx,dy,dz)) inside
+// the element table: rows in lexicographic order, each row's valid offsets in
+// (dz, dy, dx) lexicographic order.
+template <int P>
+__device__ __forceinline__ int compact_index(int x, int y, int z, int dx, int dy, int dz) {
+  constexpr int T1 = 3 * P + 1;
+  auto cnt = [](int t) { return (t == 0 || t == P) ? 2 : 3; };
+  auto pre = [](int t) { return t == 0 ? 0 : 3 * t - 1; };
+  const int nx = cnt(x), ny = cnt(y);
+  const int rbase = pre(z) * T1 * T1 + cnt(z) * pre(y) * T1 + cnt(z) * ny * pre(x);
+  return rbase + ((dz + (z > 0 ? 1 : 0)) * ny + (dy + (y > 0 ? 1 : 0))) * nx + (dx + (x > 0 ? 1 : 0));
+}
+
+template <int P, typename T, typename R>
+__global__ __launch_bounds__(256, 1) void k_h1_backward(
+    int64_t nel, int32_t chunk, const int32_t* __restrict__ elem_dofs, const double* __restrict__ coords,
+    const T* __restrict__ kappa, T beta, const int32_t* __restrict__ row_ptr, const uint8_t* __restrict__ tables,
+    int64_t tab_stride, int batch, int64_t nnz, const T* __restrict__ gvals, T* __restrict__ gkappa,
+    double* __restrict__ ework) {
+  using C = BwCfg<P>;
+  constexpr int Q = C::Q, NSUB = C::NSUB, NLOC = C::NLOC, NENTP = C::NENTP, E = C::E, TH = C::THREADS;
+  constexpr int TWE = C::TWE;
+  __shared__ double sX[E * NLOC * 3];
+  __shared__ int32_t sRp[E * NLOC];
+  __shared__ uint32_t sTabW[E * TWE];
+  __shared__ double sXb[E * 24 * NSUB];
+  const uint8_t* sTab = reinterpret_cast<const uint8_t*>(sTabW);
+
+  const int64_t cbeg = static_cast<int64_t>(blockIdx.x) * chunk;
+  const int nce = static_cast<int>(nel - cbeg < chunk ? nel - cbeg : chunk);
+  const int ngr = (nce + E - 1) / E;
+  for (int g = 0; g < ngr; ++g) {
+    int tid = threadIdx.x;
+    __asm__ volatile("" : "+v"(tid));
+    const int ne = nce - g * E < E ? nce - g * E : E;
+    const int64_t e0 = cbeg + static_cast<int64_t>(g) * E;  // elements e0 .. e0+ne-1
+    lds_barrier();
+    for (int i = tid; i < ne * NLOC; i += TH) {
+      const int el = i / NLOC;
+      const int32_t v = elem_dofs[(e0 + el) * NLOC + (i - el * NLOC)];
+      sX[3 * i + 0] = coords[3 * static_cast<int64_t>(v) + 0];
+      sX[3 * i + 1] = coords[3 * static_cast<int64_t>(v) + 1];
+      sX[3 * i + 2] = coords[3 * static_cast<int64_t>(v) + 2];
+      sRp[i] = row_ptr[v];
+    }
+    for (int i = tid; i < ne * TWE; i += TH) {
+      const int el = i / TWE;
+      const uint32_t* row = reinterpret_cast<const uint32_t*>(tables + (e0 + el) * tab_stride);
+      sTabW[i] = row[i - el * TWE];
+    }
+    lds_barrier();
+
+    if (tid < ne * NSUB) {
+      const int el = tid / NSUB;
+      const int s = tid - el * NSUB;
+      const int64_t e = e0 + el;
+      const int si = s % P, sj = (s / P) % P, sk = s / (P * P);
+      R ex[2][2][3], ey[2][2][3], ez[2][2][3];
+      {
+        double X[8][3];
+#pragma unroll
+        for (int v = 0; v < 8; ++v) {
+          const int lv = (si + (v & 1)) + Q * ((sj + ((v >> 1) & 1)) + Q * (sk + (v >> 2)));
+#pragma unroll
+          for (int d = 0; d < 3; ++d) X[v][d] = sX[3 * (el * NLOC + lv) + d];
+        }
+        h1_edges<R>(X, ex, ey, ez);
+      }
+      R Kt[36];
+      {
+        H1Factors<R> F;
+        (void)h1_factors<R>(ex, ey, ez, R(1), R(0), F);
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+#pragma unroll
+          for (int v = u; v < 8; ++v) Kt[pair_index(u, v)] = h1_entry<R>(F, u, v);
+      }
+      // CSR positions of the 64 ordered corner pairs
+      int32_t pos[64];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int x = si + (u & 1), y = sj + ((u >> 1) & 1), z = sk + (u >> 2);
+        const int lu = x + Q * (y + Q * z);
+        const int32_t rb = sRp[el * NLOC + lu];
+#pragma unroll
+        for (int v = 0; v < 8; ++v) {
+          const int k = compact_index<P>(x, y, z, (v & 1) - (u & 1), ((v >> 1) & 1) - ((u >> 1) & 1),
+                                         (v >> 2) - (u >> 2));
+          pos[u * 8 + v] = rb + (sTab[el * NENTP + k] & kRankMask);
+        }
+      }
+      R Wk[36], Wm[36];
+#pragma unroll
+      for (int i = 0; i < 36; ++i) Wk[i] = Wm[i] = R(0);
+      for (int b = 0; b < batch; ++b) {
+        const T* gb = gvals + static_cast<int64_t>(b) * nnz;
+        const R kb = static_cast<R>(kappa[(static_cast<int64_t>(b) * nel + e) * NSUB + s]);
+        R gk = R(0);
+        // ordered pairs (u, v) and (v, u) both feed the unique entry {u, v}
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+#pragma unroll
+          for (int v = 0; v < 8; ++v) {
+            const R w = static_cast<R>(gb[pos[u * 8 + v]]);
+            gk += Kt[pair_index(u, v)] * w;
+            Wk[pair_index(u, v)] += kb * w;
+            Wm[pair_index(u, v)] += w;
+          }
+        gkappa[(static_cast<int64_t>(b) * nel + e) * NSUB + s] = static_cast<T>(gk);
+      }
+      R gx[2][2][3], gy[2][2][3], gz[2][2][3];
+      h1_adjoint<R>(ex, ey, ez, Wk, Wm, static_cast<R>(beta), gx, gy, gz);
+      // corner adjoints from the edge adjoints: e = X(hi) - X(lo)
+      double* xb = sXb + el * 24 * NSUB + s;
+#pragma unroll
+      for (int v = 0; v < 8; ++v) {
+        const int a = v & 1, b2 = (v >> 1) & 1, c = v >> 2;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          const R val = (a ? gx[b2][c][d] : -gx[b2][c][d]) + (b2 ? gy[a][c][d] : -gy[a][c][d]) +
+                        (c ? gz[a][b2][d] : -gz[a][b2][d]);
+          xb[(v * 3 + d) * NSUB] = static_cast<double>(val);
+        }
+      }
+    }
+    lds_barrier();
+    // per element vertex: sum its <= 8 subelement corners in a fixed order
+    for (int i = tid; i < ne * NLOC; i += TH) {
+      const int el = i / NLOC;
+      const int l = i - el * NLOC;
+      const int x = l % Q, y = (l / Q) % Q, z = l / (Q * Q);
+      double acc[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int sx = x - (u & 1), sy = y - ((u >> 1) & 1), sz = z - (u >> 2);
+        if (sx >= 0 && sx < P && sy >= 0 && sy < P && sz >= 0 && sz < P) {
+          const int s = sx + P * (sy + P * sz);
+#pragma unroll
+          for (int d = 0; d < 3; ++d) acc[d] += sXb[el * 24 * NSUB + (u * 3 + d) * NSUB + s];
+        }
+      }
+      double* w = ework + ((e0 + el) * NLOC + l) * 3;
+      w[0] = acc[0];
+      w[1] = acc[1];
+      w[2] = acc[2];
+    }
+  }
+}
+
+// grad_coords[g] = sum over the sorted incidences (e, l) of g of the element
+// E-vector adjoint.
+__global__ void k_gather_vertices(const int32_t* __restrict__ inc_ptr, const int32_t* __restrict__ inc_list,
+                                  int64_t nrows, const double* __restrict__ ework, double* __restrict__ gcoords) {
+  const int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (g >= nrows) return;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+  for (int32_t i = inc_ptr[g]; i < inc_ptr[g + 1]; ++i) {
+    const double* w = ework + 3 * static_cast<int64_t>(inc_list[i]);
+    a0 += w[0];
+    a1 += w[1];
+    a2 += w[2];
+  }
+  gcoords[3 * g + 0] = a0;
+  gcoords[3 * g + 1] = a1;
+  gcoords[3 * g + 2] = a2;
+}
+
+static int num_cus_bw() {
+  static int cached[64] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  if (cached[dev] == 0) {
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) n = 256;
+    cached[dev] = n;
+  }
+  return cached[dev];
+}
+
+template <int P, typename T, typename R>
+static int launch_bw(const lor_sched* sched, int batch, const int32_t* elem_dofs, const double* coords,
+                     const void* kappa, double beta, const int32_t* row_ptr, const void* gvals, void* gkappa,
+                     double* gcoords, void* workspace, hipStream_t st) {
+  using C = BwCfg<P>;
+  if (sched->tab_stride != C::NENTP || sched->nent != C::NENT)
+    LOR_FAIL(LOR_EINVAL, "schedule tables do not match p = %d", P);
+  const uint8_t* tab = dev_at<uint8_t>(sched, sched->off_tables);
+  const int64_t nel = sched->nel;
+  const int64_t groups = ceil_div(nel, C::E);
+  const int64_t gpw = ceil_div(groups, num_cus_bw());
+  const int32_t chunk = static_cast<int32_t>(gpw * C::E);
+  double* ework = static_cast<double*>(workspace);
+  k_h1_backward<P, T, R><<<static_cast<unsigned>(ceil_div(nel, chunk)), C::THREADS, 0, st>>>(
+      nel, chunk, elem_dofs, coords, static_cast<const T*>(kappa), static_cast<T>(beta), row_ptr, tab,
+      sched->tab_stride, batch, sched->nnz, static_cast<const T*>(gvals), static_cast<T*>(gkappa), ework);
+  LOR_LAUNCHED("k_h1_backward");
+  k_gather_vertices<<<static_cast<unsigned>(ceil_div(sched->nrows, 256)), 256, 0, st>>>(
+      dev_at<int32_t>(sched, sched->off_inc_ptr), dev_at<int32_t>(sched, sched->off_inc_list), sched->nrows, ework,
+      gcoords);
+  LOR_LAUNCHED("k_gather_vertices");
+  return LOR_OK;
+}
+
+template <typename T, typename R>
+static int dispatch_bw(int p, const lor_sched* s, int batch, const int32_t* ed, const double* x, const void* k,
+                       double beta, const int32_t* rp, const void* gv, void* gk, double* gx, void* ws,
+                       hipStream_t st) {
+  switch (p) {
+    case 1: return launch_bw<1, T, R>(s, batch, ed, x, k, beta, rp, gv, gk, gx, ws, st);
+    case 2: return launch_bw<2, T, R>(s, batch, ed, x, k, beta, rp, gv, gk, gx, ws, st);
+    case 3: return launch_bw<3, T, R>(s, batch, ed, x, k, beta, rp, gv, gk, gx, ws, st);
+    case 4: return launch_bw<4, T, R>(s, batch, ed, x, k, beta, rp, gv, gk, gx, ws, st);
+    case 5: return launch_bw<5, T, R>(s, batch, ed, x, k, beta, rp, gv, gk, gx, ws, st);
+    case 6: return launch_bw<6, T, R>(s, batch, ed, x, k, beta, rp, gv, gk, gx, ws, st);
+    default: LOR_FAIL(LOR_EUNSUPPORTED, "p = %d not compiled", p);
+  }
+}
+
+}  // namespace lor
+
+using namespace lor;
 
 extern "C" size_t lor_backward_workspace(int p, int64_t nel) {
   if (p < 1 || p > LOR_MAX_P || nel < 0) return 0;
-  return sizeof(double) * 3 * static_cast<size_t>(nel) * lor::nloc_h1(p);
+  return sizeof(double) * 3 * static_cast<size_t>(nel) * nloc_h1(p);
 }
 
 extern "C" int lor_assemble_backward(int p, int64_t nel, int64_t ndofs, int batch, const int32_t* elem_dofs,
                                      const double* coords, const void* kappa, double beta, const int32_t* row_ptr,
                                      const lor_sched* sched, const void* grad_values, void* grad_kappa,
                                      double* grad_coords, void* workspace, int dtype, void* stream) {
-  lor::clear_error();
-  LOR_FAIL(LOR_EUNSUPPORTED, "lor_assemble_backward is not built yet");
+  clear_error();
+  if (p < 1 || p > LOR_MAX_P) LOR_FAIL(LOR_EINVAL, "p = %d outside [1, %d]", p, LOR_MAX_P);
+  if (nel < 0 || ndofs < 1) LOR_FAIL(LOR_EINVAL, "nel < 0 or ndofs < 1");
+  if (batch < 1) LOR_FAIL(LOR_EINVAL, "batch < 1");
+  if (dtype != LOR_F64 && dtype != LOR_F32) LOR_FAIL(LOR_EINVAL, "dtype must be LOR_F64 or LOR_F32");
+  if (!grad_coords) LOR_FAIL(LOR_EINVAL, "grad_coords is NULL");
+  if (nel > 0 && (!elem_dofs || !coords || !kappa || !row_ptr || !grad_values || !grad_kappa || !workspace))
+    LOR_FAIL(LOR_EINVAL, "a required pointer is NULL");
+  int rc = check_sched(sched, LOR_H1, p, nel, ndofs);
+  if (rc) return rc;
+  hipStream_t st = as_stream(stream);
+  if (nel == 0) {
+    LOR_HIP(hipMemsetAsync(grad_coords, 0, sizeof(double) * 3 * ndofs, st));
+    return LOR_OK;
+  }
+  if (dtype == LOR_F64)
+    return dispatch_bw<double, double>(p, sched, batch, elem_dofs, coords, kappa, beta, row_ptr, grad_values,
+                                       grad_kappa, grad_coords, workspace, st);
+  return dispatch_bw<float, float>(p, sched, batch, elem_dofs, coords, kappa, beta, row_ptr, grad_values,
+                                   grad_kappa, grad_coords, workspace, st);
 }

@@ -110,17 +110,16 @@ __device__ __forceinline__ void h1_corner_det_range(const R (&ex)[2][2][3], cons
       }
 }
 
-// Factor tables of one subelement; returns false if det J <= 0 at a Gauss point.
+// Jacobian columns at the Gauss points: J_0 = dx/dxi depends on (eta, zeta)
+// only and is the bilinear interpolant of the four x-edge vectors, etc.
+// c0[q2][q3], c1[q1][q3], c2[q1][q2].
 template <typename R>
-__device__ __forceinline__ bool h1_factors(const R (&ex)[2][2][3], const R (&ey)[2][2][3],
-                                           const R (&ez)[2][2][3], R kap, R bet, H1Factors<R>& F) {
-  // Jacobian columns at the Gauss points: J_0 depends on (eta, zeta) only, etc.
-  R c0[2][2][3], c1[2][2][3], c2[2][2][3];
+__device__ __forceinline__ void jac_columns(const R (&ex)[2][2][3], const R (&ey)[2][2][3], const R (&ez)[2][2][3],
+                                            R (&c0)[2][2][3], R (&c1)[2][2][3], R (&c2)[2][2][3]) {
 #pragma unroll
   for (int d = 0; d < 3; ++d)
 #pragma unroll
     for (int qs = 0; qs < 2; ++qs) {
-      // interpolate along the first free axis
       const R m0x = R(L1(0, qs)) * ex[0][0][d] + R(L1(1, qs)) * ex[1][0][d];
       const R m1x = R(L1(0, qs)) * ex[0][1][d] + R(L1(1, qs)) * ex[1][1][d];
       const R m0y = R(L1(0, qs)) * ey[0][0][d] + R(L1(1, qs)) * ey[1][0][d];
@@ -129,12 +128,82 @@ __device__ __forceinline__ bool h1_factors(const R (&ex)[2][2][3], const R (&ey)
       const R m1z = R(L1(0, qs)) * ez[0][1][d] + R(L1(1, qs)) * ez[1][1][d];
 #pragma unroll
       for (int qt = 0; qt < 2; ++qt) {
-        c0[qs][qt][d] = R(L1(0, qt)) * m0x + R(L1(1, qt)) * m1x;  // (q2 = qs, q3 = qt)
-        c1[qs][qt][d] = R(L1(0, qt)) * m0y + R(L1(1, qt)) * m1y;  // (q1 = qs, q3 = qt)
-        c2[qs][qt][d] = R(L1(0, qt)) * m0z + R(L1(1, qt)) * m1z;  // (q1 = qs, q2 = qt)
+        c0[qs][qt][d] = R(L1(0, qt)) * m0x + R(L1(1, qt)) * m1x;
+        c1[qs][qt][d] = R(L1(0, qt)) * m0y + R(L1(1, qt)) * m1y;
+        c2[qs][qt][d] = R(L1(0, qt)) * m0z + R(L1(1, qt)) * m1z;
       }
     }
+}
 
+// Contract the per-point metric values into the S and T factor tables.
+//   H00[q2][q3] = sum_q1 G00,  H11[q1][q3] = sum_q2 G11,  H22[q1][q2] = sum_q3 G22,
+//   Z01[x][q2][q3] = sum_q1 l_x(xi) G01,  Z02[x][q2][q3] = sum_q1 l_x(xi) G02,
+//   G12q[q1][q2][q3] = G12 at every point.
+template <typename R>
+__device__ __forceinline__ void h1_contract_stiffness(const R (&H00)[2][2], const R (&H11)[2][2],
+                                                      const R (&H22)[2][2], const R (&Z01)[2][2][2],
+                                                      const R (&Z02)[2][2][2], const R (&G12q)[2][2][2],
+                                                      H1Factors<R>& F) {
+#pragma unroll
+  for (int B = 0; B < 3; ++B) {
+    R y0[2], y1[2], y2[2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      y0[t] = R(LL(B, 0)) * H00[0][t] + R(LL(B, 1)) * H00[1][t];  // S0: eta -> B
+      y1[t] = R(LL(B, 0)) * H11[0][t] + R(LL(B, 1)) * H11[1][t];  // S1: xi  -> B
+      y2[t] = R(LL(B, 0)) * H22[0][t] + R(LL(B, 1)) * H22[1][t];  // S2: xi  -> B
+    }
+#pragma unroll
+    for (int Cc = 0; Cc < 3; ++Cc) {
+      F.S0[B][Cc] = R(LL(Cc, 0)) * y0[0] + R(LL(Cc, 1)) * y0[1];
+      F.S1[B][Cc] = R(LL(Cc, 0)) * y1[0] + R(LL(Cc, 1)) * y1[1];
+      F.S2[B][Cc] = R(LL(Cc, 0)) * y2[0] + R(LL(Cc, 1)) * y2[1];
+    }
+  }
+#pragma unroll
+  for (int x = 0; x < 2; ++x) {
+#pragma unroll
+    for (int y = 0; y < 2; ++y) {
+      // T01[x][y][C]: eta -> l_y, zeta -> LL_C
+      const R t0 = R(L1(y, 0)) * Z01[x][0][0] + R(L1(y, 1)) * Z01[x][1][0];
+      const R t1 = R(L1(y, 0)) * Z01[x][0][1] + R(L1(y, 1)) * Z01[x][1][1];
+#pragma unroll
+      for (int Cc = 0; Cc < 3; ++Cc) F.T01[x][y][Cc] = R(LL(Cc, 0)) * t0 + R(LL(Cc, 1)) * t1;
+    }
+#pragma unroll
+    for (int z = 0; z < 2; ++z) {
+      // T02[x][z][B]: zeta -> l_z, eta -> LL_B
+      const R t0 = R(L1(z, 0)) * Z02[x][0][0] + R(L1(z, 1)) * Z02[x][0][1];
+      const R t1 = R(L1(z, 0)) * Z02[x][1][0] + R(L1(z, 1)) * Z02[x][1][1];
+#pragma unroll
+      for (int B = 0; B < 3; ++B) F.T02[x][z][B] = R(LL(B, 0)) * t0 + R(LL(B, 1)) * t1;
+    }
+  }
+#pragma unroll
+  for (int al = 0; al < 3; ++al) {
+    R Z12[2][2];
+#pragma unroll
+    for (int t2 = 0; t2 < 2; ++t2)
+#pragma unroll
+      for (int t3 = 0; t3 < 2; ++t3)
+        Z12[t2][t3] = R(LL(al, 0)) * G12q[0][t2][t3] + R(LL(al, 1)) * G12q[1][t2][t3];
+#pragma unroll
+    for (int y = 0; y < 2; ++y) {
+      // T12[y][z][A]: xi -> LL_A, eta -> l_y, zeta -> l_z
+      const R t0 = R(L1(y, 0)) * Z12[0][0] + R(L1(y, 1)) * Z12[1][0];
+      const R t1 = R(L1(y, 0)) * Z12[0][1] + R(L1(y, 1)) * Z12[1][1];
+#pragma unroll
+      for (int z = 0; z < 2; ++z) F.T12[y][z][al] = R(L1(z, 0)) * t0 + R(L1(z, 1)) * t1;
+    }
+  }
+}
+
+// Factor tables of one subelement; returns false if det J <= 0 at a Gauss point.
+template <typename R>
+__device__ __forceinline__ bool h1_factors(const R (&ex)[2][2][3], const R (&ey)[2][2][3],
+                                           const R (&ez)[2][2][3], R kap, R bet, H1Factors<R>& F) {
+  R c0[2][2][3], c1[2][2][3], c2[2][2][3];
+  jac_columns<R>(ex, ey, ez, c0, c1, c2);
   R H00[2][2] = {}, H11[2][2] = {}, H22[2][2] = {};
   R Z01[2][2][2] = {}, Z02[2][2][2] = {};
   R G12q[2][2][2], Dq[2][2][2];  // per Gauss point (q1, q2, q3): G_12 and beta det J / 8
@@ -163,87 +232,32 @@ __device__ __forceinline__ bool h1_factors(const R (&ex)[2][2][3], const R (&ey)
         const R det = A[0] * r0[0] + A[1] * r0[1] + A[2] * r0[2];
         ok = ok && (det > R(0));
         const R f = wk * rcp_refined(det);
-        const R g00 = f * (r0[0] * r0[0] + r0[1] * r0[1] + r0[2] * r0[2]);
-        const R g11 = f * (r1[0] * r1[0] + r1[1] * r1[1] + r1[2] * r1[2]);
-        const R g22 = f * (r2[0] * r2[0] + r2[1] * r2[1] + r2[2] * r2[2]);
+        H00[q2][q3] += f * (r0[0] * r0[0] + r0[1] * r0[1] + r0[2] * r0[2]);
+        H11[q1][q3] += f * (r1[0] * r1[0] + r1[1] * r1[1] + r1[2] * r1[2]);
+        H22[q1][q2] += f * (r2[0] * r2[0] + r2[1] * r2[1] + r2[2] * r2[2]);
         const R g01 = f * (r0[0] * r1[0] + r0[1] * r1[1] + r0[2] * r1[2]);
         const R g02 = f * (r0[0] * r2[0] + r0[1] * r2[1] + r0[2] * r2[2]);
-        const R g12 = f * (r1[0] * r2[0] + r1[1] * r2[1] + r1[2] * r2[2]);
-        const R dm = wb * det;
-        H00[q2][q3] += g00;
-        H11[q1][q3] += g11;
-        H22[q1][q2] += g22;
+        G12q[q1][q2][q3] = f * (r1[0] * r2[0] + r1[1] * r2[1] + r1[2] * r2[2]);
+        Dq[q1][q2][q3] = wb * det;
 #pragma unroll
         for (int x = 0; x < 2; ++x) {
           Z01[x][q2][q3] += R(L1(x, q1)) * g01;
           Z02[x][q2][q3] += R(L1(x, q1)) * g02;
         }
-        G12q[q1][q2][q3] = g12;
-        Dq[q1][q2][q3] = dm;
       }
-
-  // diagonal families: contract the two remaining axes with LL
+  h1_contract_stiffness<R>(H00, H11, H22, Z01, Z02, G12q, F);
+  // mass: TM[A][B][C] = sum_q D(q) LL_A(xi) LL_B(eta) LL_C(zeta)
 #pragma unroll
-  for (int B = 0; B < 3; ++B) {
-    R y0[2], y1[2], y2[2];
-#pragma unroll
-    for (int t = 0; t < 2; ++t) {
-      y0[t] = R(LL(B, 0)) * H00[0][t] + R(LL(B, 1)) * H00[1][t];  // S0: axis eta -> B
-      y1[t] = R(LL(B, 0)) * H11[0][t] + R(LL(B, 1)) * H11[1][t];  // S1: axis xi  -> B
-      y2[t] = R(LL(B, 0)) * H22[0][t] + R(LL(B, 1)) * H22[1][t];  // S2: axis xi  -> B
-    }
-#pragma unroll
-    for (int Cc = 0; Cc < 3; ++Cc) {
-      F.S0[B][Cc] = R(LL(Cc, 0)) * y0[0] + R(LL(Cc, 1)) * y0[1];
-      F.S1[B][Cc] = R(LL(Cc, 0)) * y1[0] + R(LL(Cc, 1)) * y1[1];
-      F.S2[B][Cc] = R(LL(Cc, 0)) * y2[0] + R(LL(Cc, 1)) * y2[1];
-    }
-  }
-  // off-diagonal families
-#pragma unroll
-  for (int x = 0; x < 2; ++x) {
-#pragma unroll
-    for (int y = 0; y < 2; ++y) {
-      // T01[x][y][C]: eta -> l_y, zeta -> LL_C
-      R t0 = R(L1(y, 0)) * Z01[x][0][0] + R(L1(y, 1)) * Z01[x][1][0];
-      R t1 = R(L1(y, 0)) * Z01[x][0][1] + R(L1(y, 1)) * Z01[x][1][1];
-#pragma unroll
-      for (int Cc = 0; Cc < 3; ++Cc) F.T01[x][y][Cc] = R(LL(Cc, 0)) * t0 + R(LL(Cc, 1)) * t1;
-    }
-#pragma unroll
-    for (int z = 0; z < 2; ++z) {
-      // T02[x][z][B]: zeta -> l_z, eta -> LL_B
-      R t0 = R(L1(z, 0)) * Z02[x][0][0] + R(L1(z, 1)) * Z02[x][0][1];
-      R t1 = R(L1(z, 0)) * Z02[x][1][0] + R(L1(z, 1)) * Z02[x][1][1];
-#pragma unroll
-      for (int B = 0; B < 3; ++B) F.T02[x][z][B] = R(LL(B, 0)) * t0 + R(LL(B, 1)) * t1;
-    }
-  }
-  // contract xi of the raw per-point values with LL_A
-  R Z12[3][2][2], U[3][2][2];
-#pragma unroll
-  for (int al = 0; al < 3; ++al)
+  for (int al = 0; al < 3; ++al) {
+    R U[2][2];
 #pragma unroll
     for (int t2 = 0; t2 < 2; ++t2)
 #pragma unroll
-      for (int t3 = 0; t3 < 2; ++t3) {
-        Z12[al][t2][t3] = R(LL(al, 0)) * G12q[0][t2][t3] + R(LL(al, 1)) * G12q[1][t2][t3];
-        U[al][t2][t3] = R(LL(al, 0)) * Dq[0][t2][t3] + R(LL(al, 1)) * Dq[1][t2][t3];
-      }
-#pragma unroll
-  for (int al = 0; al < 3; ++al) {
-#pragma unroll
-    for (int y = 0; y < 2; ++y) {
-      // T12[y][z][A]: eta -> l_y, zeta -> l_z
-      const R t0 = R(L1(y, 0)) * Z12[al][0][0] + R(L1(y, 1)) * Z12[al][1][0];
-      const R t1 = R(L1(y, 0)) * Z12[al][0][1] + R(L1(y, 1)) * Z12[al][1][1];
-#pragma unroll
-      for (int z = 0; z < 2; ++z) F.T12[y][z][al] = R(L1(z, 0)) * t0 + R(L1(z, 1)) * t1;
-    }
+      for (int t3 = 0; t3 < 2; ++t3) U[t2][t3] = R(LL(al, 0)) * Dq[0][t2][t3] + R(LL(al, 1)) * Dq[1][t2][t3];
 #pragma unroll
     for (int B = 0; B < 3; ++B) {
-      const R t0 = R(LL(B, 0)) * U[al][0][0] + R(LL(B, 1)) * U[al][1][0];
-      const R t1 = R(LL(B, 0)) * U[al][0][1] + R(LL(B, 1)) * U[al][1][1];
+      const R t0 = R(LL(B, 0)) * U[0][0] + R(LL(B, 1)) * U[1][0];
+      const R t1 = R(LL(B, 0)) * U[0][1] + R(LL(B, 1)) * U[1][1];
 #pragma unroll
       for (int Cc = 0; Cc < 3; ++Cc) F.TM[al][B][Cc] = R(LL(Cc, 0)) * t0 + R(LL(Cc, 1)) * t1;
     }

@@ -61,7 +61,7 @@ struct RefElem {
   std::vector<int32_t> st_ptr, st_col;
   std::vector<uint16_t> ent_row;  // local row of every compact stencil entry
   std::vector<int32_t> reps;    // local dofs whose incidences give element adjacency
-  std::vector<int32_t> recipe;  // Nedelec: per local edge, subelement contributions
+  std::vector<uint64_t> recipe64;  // Nedelec: per compact entry, subelement contributions
 };
 
 static int nd_local(int p, int ax, int i, int j, int k) {
@@ -108,16 +108,17 @@ static RefElem build_ref_h1(int p) {
   return r;
 }
 
+static int pair12(int u, int v) {
+  if (u > v) std::swap(u, v);
+  return 12 * u - (u * (u - 1)) / 2 + (v - u);
+}
+
 static RefElem build_ref_nd(int p) {
   RefElem r;
   const int q = p + 1;
   r.nloc = 3 * p * q * q;
   std::vector<std::vector<int>> nbr(r.nloc);
-  // recipe: per local edge, 4 slots of (subelement << 4 | local index), -1 if
-  // absent, followed by 4 x 12 stencil positions of the subelement's edges.
-  const int RS = 4 + 48;
-  r.recipe.assign(static_cast<size_t>(r.nloc) * RS, -1);
-  std::vector<int> nsub(r.nloc, 0);
+  std::vector<std::vector<int>> subs(r.nloc);  // subelements holding each local edge
   for (int k = 0; k < p; ++k)
     for (int j = 0; j < p; ++j)
       for (int i = 0; i < p; ++i) {
@@ -125,34 +126,43 @@ static RefElem build_ref_nd(int p) {
         nd_sub_edges(p, i, j, k, ed);
         const int s = i + p * (j + p * k);
         for (int u = 0; u < 12; ++u) {
-          const int l = ed[u];
-          r.recipe[static_cast<size_t>(l) * RS + nsub[l]] = (s << 4) | u;
-          ++nsub[l];
-          for (int v = 0; v < 12; ++v) nbr[l].push_back(ed[v]);
+          subs[ed[u]].push_back(s);
+          for (int v = 0; v < 12; ++v) nbr[ed[u]].push_back(ed[v]);
         }
       }
+  // recipe: per compact entry (l, l'), the contributions (subelement s, edge
+  // pair index) of every subelement holding both edges, in increasing s, as
+  // 16-bit codes (s << 7 | pair) packed into 64 bits, 0xffff = none
   r.st_ptr.push_back(0);
   for (int l = 0; l < r.nloc; ++l) {
     auto& v = nbr[l];
     std::sort(v.begin(), v.end());
     v.erase(std::unique(v.begin(), v.end()), v.end());
+    std::vector<int>& sl = subs[l];
+    std::sort(sl.begin(), sl.end());
     for (int c : v) {
       r.st_col.push_back(c);
       r.ent_row.push_back(static_cast<uint16_t>(l));
+      uint64_t rec = ~0ull;
+      int m = 0;
+      for (int s : sl) {
+        const int si = s % p, sj = (s / p) % p, sk = s / (p * p);
+        int ed[12];
+        nd_sub_edges(p, si, sj, sk, ed);
+        int u = -1, w = -1;
+        for (int t = 0; t < 12; ++t) {
+          if (ed[t] == l) u = t;
+          if (ed[t] == c) w = t;
+        }
+        if (u < 0 || w < 0) continue;
+        const uint64_t code = static_cast<uint64_t>((s << 7) | pair12(u, w));
+        rec &= ~(0xffffull << (16 * m));
+        rec |= code << (16 * m);
+        ++m;
+      }
+      r.recipe64.push_back(rec);
     }
     r.st_ptr.push_back(static_cast<int32_t>(r.st_col.size()));
-    // stencil positions of each contributing subelement's edges
-    for (int m = 0; m < nsub[l]; ++m) {
-      const int code = r.recipe[static_cast<size_t>(l) * RS + m];
-      const int s = code >> 4;
-      const int si = s % p, sj = (s / p) % p, sk = s / (p * p);
-      int ed[12];
-      nd_sub_edges(p, si, sj, sk, ed);
-      for (int w = 0; w < 12; ++w) {
-        const int pos = static_cast<int>(std::lower_bound(v.begin(), v.end(), ed[w]) - v.begin());
-        r.recipe[static_cast<size_t>(l) * RS + 4 + m * 12 + w] = pos;
-      }
-    }
   }
   r.nent = static_cast<int>(r.st_col.size());
   // both end edges of every coarse edge: elements sharing an edge dof share one
@@ -508,7 +518,7 @@ static size_t layout(lor_sched* s, const RefElem& r) {
   s->off_st_ptr = take(sizeof(int32_t) * r.st_ptr.size());
   s->off_st_col = take(sizeof(int32_t) * r.st_col.size());
   s->off_ent_row = take(sizeof(uint16_t) * r.ent_row.size());
-  s->off_recipe = take(sizeof(int32_t) * std::max<size_t>(1, r.recipe.size()));
+  s->off_recipe = take(sizeof(uint64_t) * std::max<size_t>(1, r.recipe64.size()));
   return off;
 }
 
@@ -656,13 +666,13 @@ extern "C" int lor_pattern(int space, int p, int64_t nel, int64_t nrows, const i
   int32_t* d_st_ptr = dev_at<int32_t>(sched, sched->off_st_ptr);
   int32_t* d_st_col = dev_at<int32_t>(sched, sched->off_st_col);
   uint16_t* d_ent_row = dev_at<uint16_t>(sched, sched->off_ent_row);
-  int32_t* d_recipe = dev_at<int32_t>(sched, sched->off_recipe);
+  uint64_t* d_recipe = dev_at<uint64_t>(sched, sched->off_recipe);
   DevBuf reps;
   if ((rc = reps.alloc(sizeof(int32_t) * ref.reps.size()))) return rc;
   if ((rc = upload(ref.st_ptr, d_st_ptr, st))) return rc;
   if ((rc = upload(ref.st_col, d_st_col, st))) return rc;
   if ((rc = upload(ref.ent_row, d_ent_row, st))) return rc;
-  if ((rc = upload(ref.recipe, d_recipe, st))) return rc;
+  if ((rc = upload(ref.recipe64, d_recipe, st))) return rc;
   if ((rc = upload(ref.reps, reps.p, st))) return rc;
 
   if ((rc = build_incidence(elem_map, nel, nloc, is_signed, nrows, d_inc_ptr, d_inc_list, err.as<int32_t>(), st)))
