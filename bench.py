@@ -81,12 +81,117 @@ def cpu_baseline(m, sample_elems):
     }
 
 
-def load_traffic(name):
-    path = os.path.join(ROOT, "profiles", name)
+KERNEL_SOURCES = ("lor_h1.hip", "lor_h1_math.hpp", "lor_common.hpp")
+TRAFFIC_FILE = "h1_p6_32cubed_traffic.json"
+
+
+def kernel_source_hash():
+    """Hash of the sources of the dominant kernel: counters taken on other code are stale."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2210_12253_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic():
+    """HBM bytes per launch from the committed FETCH_SIZE / WRITE_SIZE summary,
+    or None when it is missing or was taken on other kernel sources."""
+    path = os.path.join(ROOT, "profiles", TRAFFIC_FILE)
     if not os.path.exists(path):
-        return None
+        return None, None
     with open(path) as f:
-        return json.load(f)
+        t = json.load(f)
+    if t.get("kernel_source_hash") != kernel_source_hash():
+        return None, {"stale": True, "file": TRAFFIC_FILE}
+    return t["bytes_per_launch"], t
+
+
+def copy_calibration(torch, dev, nbytes=1 << 30, reps=5):
+    """A plain 1 GiB device-to-device copy (torch's copy kernel): the achievable
+    bandwidth reference and the known-size kernel the HBM counters are scaled by."""
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    t1.record()
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / reps
+    del src, dst
+    torch.cuda.empty_cache()
+    return {"bytes_read": nbytes, "bytes_written": nbytes, "ms": ms,
+            "GBs": 2 * nbytes / (ms * 1e-3) / 1e9}
+
+
+def _read_csvs(d, suffix):
+    import glob
+    import csv
+    rows = []
+    for path in sorted(glob.glob(os.path.join(d, "**", f"*{suffix}"), recursive=True)):
+        with open(path, newline="") as f:
+            rows.extend(csv.DictReader(f))
+    return rows
+
+
+def summarize_profiles(stats_dir, fetch_dir, write_dir, command):
+    """Turn rocprofv3 CSV output into the short text summary and the traffic
+    record that bench.py reads.  stats_dir: --kernel-trace --stats run;
+    fetch_dir / write_dir: --pmc FETCH_SIZE and --pmc WRITE_SIZE runs of the
+    same command (counters in KiB per dispatch)."""
+    lines = [f"command: {command}", ""]
+    stats = _read_csvs(stats_dir, "kernel_stats.csv")
+    lines.append(f"{'kernel':70s} {'calls':>6s} {'avg_us':>10s} {'min_us':>10s} {'max_us':>10s} {'pct':>6s}")
+    for r in sorted(stats, key=lambda r: -float(r["TotalDurationNs"])):
+        lines.append(f"{r['Name'][:70]:70s} {int(r['Calls']):6d} {float(r['AverageNs']) / 1e3:10.2f} "
+                     f"{float(r['MinNs']) / 1e3:10.2f} {float(r['MaxNs']) / 1e3:10.2f} "
+                     f"{float(r['Percentage']):6.2f}")
+    res = {}
+    for key, d, counter in (("fetch", fetch_dir, "FETCH_SIZE"), ("write", write_dir, "WRITE_SIZE")):
+        per = {}
+        for r in _read_csvs(d, "counter_collection.csv"):
+            if r["Counter_Name"] != counter:
+                continue
+            per.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]) * 1024.0)
+        res[key] = per
+    def pick(per, needle):
+        vals = [v for k, vs in per.items() if needle in k for v in vs]
+        return sum(vals) / len(vals) if vals else None
+    def pick_copy(per):
+        # the calibration copy moves exactly 1 GiB each way; take the dispatch closest to it
+        best = None
+        for k, vs in per.items():
+            if "copy" in k.lower() or "elementwise" in k.lower():
+                for v in vs:
+                    if best is None or abs(v - (1 << 30)) < abs(best - (1 << 30)):
+                        best = v
+        return best
+    fk, wk = pick(res["fetch"], "k_h1_assemble<6, double"), pick(res["write"], "k_h1_assemble<6, double")
+    fc, wc = pick_copy(res["fetch"]), pick_copy(res["write"])
+    lines.append("")
+    lines.append(f"FETCH_SIZE per dispatch: k_h1_assemble<6,double> {fk}, calibration copy {fc} (1 GiB moved)")
+    lines.append(f"WRITE_SIZE per dispatch: k_h1_assemble<6,double> {wk}, calibration copy {wc} (1 GiB moved)")
+    out = None
+    if None not in (fk, wk, fc, wc):
+        sf, sw = (1 << 30) / fc, (1 << 30) / wc
+        out = {
+            "kernel": "k_h1_assemble<6,double,double>",
+            "kernel_source_hash": kernel_source_hash(),
+            "fetch_bytes_per_launch": fk * sf,
+            "write_bytes_per_launch": wk * sw,
+            "bytes_per_launch": fk * sf + wk * sw,
+            "fetch_scale": sf, "write_scale": sw,
+            "command": command,
+        }
+        lines.append(f"scaled: fetch {out['fetch_bytes_per_launch'] / 1e6:.2f} MB + write "
+                     f"{out['write_bytes_per_launch'] / 1e6:.2f} MB = {out['bytes_per_launch'] / 1e6:.2f} MB per launch "
+                     f"(scale fetch {sf:.4f}, write {sw:.4f})")
+    return "\n".join(lines) + "\n", out
 
 
 def main():
@@ -96,7 +201,21 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--cpu-sample", type=int, default=4096, help="elements of the CPU oracle sample")
     ap.add_argument("--skip-extras", action="store_true")
+    ap.add_argument("--summarize-profiles", nargs=3, metavar=("STATS_DIR", "FETCH_DIR", "WRITE_DIR"),
+                    help="summarise rocprofv3 CSV output of this script (no GPU use)")
+    ap.add_argument("--profile-command", default="", help="command recorded in the summary")
+    ap.add_argument("--profile-name", default="h1_p6_32cubed_fp64")
     args = ap.parse_args()
+    if args.summarize_profiles:
+        text, traffic = summarize_profiles(*args.summarize_profiles, args.profile_command)
+        os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
+        with open(os.path.join(ROOT, "profiles", args.profile_name + ".txt"), "w") as f:
+            f.write(text)
+        if traffic is not None:
+            with open(os.path.join(ROOT, "profiles", TRAFFIC_FILE), "w") as f:
+                json.dump(traffic, f, indent=1)
+        print(text)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); multi-GPU sharding is "
               f"described in DESIGN.md but not built", file=sys.stderr)
@@ -117,6 +236,9 @@ def main():
     k32 = k64.float()
     torch.cuda.synchronize()
 
+    log("copy calibration")
+    calib = copy_calibration(torch, dev)
+
     log("pattern")
     torch.cuda.synchronize()
     t = time.perf_counter()
@@ -135,8 +257,10 @@ def main():
 
     b64 = algorithmic_bytes_h1(nel, p, ndofs, nnz, 8)
     b32 = algorithmic_bytes_h1(nel, p, ndofs, nnz, 4)
-    ach = b64 / (ms64 * 1e-3) / 1e9
-    traffic = load_traffic("h1_p6_c3_traffic.json")
+    launches = pat.ncolors
+    avg_launch_us = ms64 * 1e3 / launches     # HIP events on the launch stream, whole timed region
+    ach = (b64 / launches) / (avg_launch_us * 1e-6) / 1e9
+    traffic, traffic_detail = load_traffic()
     out = {
         "metric": "LOR assembly MDOF/s & %HBM roofline, H1 p=6: FP64 vs FP32; backward MDOF/s",
         "value": ndofs / (ms64 * 1e-3) / 1e6,
@@ -164,7 +288,12 @@ def main():
             "frac": ach / HBM_PEAK_GBS,
             "traffic": traffic,
             "kernel": "k_h1_assemble<6,double,double> (one dispatch per element colour)",
-            "algorithmic_bytes_per_step": b64,
+            "algorithmic_bytes_per_launch": b64 / launches,
+            "avg_launch_us": avg_launch_us,
+            "launches_per_step": launches,
+            "traffic_detail": traffic_detail,
+            "copy_calibration": calib,
+            "frac_of_measured_copy": ach / calib["GBs"],
         },
         "fp32": {
             "ms_per_step": ms32,

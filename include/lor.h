@@ -104,7 +104,8 @@ typedef struct lor_sched {
   size_t off_order, off_color, off_class, off_tables;
   size_t off_inc_ptr, off_inc_list;
   size_t off_st_ptr, off_st_col, off_ent_row, off_recipe;
-  size_t reserved[8];
+  size_t off_zero;               /* 256 zero bytes (read in place of an old value that is absent) */
+  size_t reserved[7];
 } lor_sched;
 
 /*

@@ -81,7 +81,8 @@ __global__ __launch_bounds__(256, 2) void k_h1_assemble(
     const int32_t* __restrict__ order, int32_t ncol, int32_t chunk, const int32_t* __restrict__ elem_dofs,
     const double* __restrict__ coords, const T* __restrict__ kappa, T beta, const int32_t* __restrict__ row_ptr,
     const uint8_t* __restrict__ tables, int64_t tab_stride, const uint16_t* __restrict__ ent_row, int64_t nel,
-    int64_t nnz, T* __restrict__ values, unsigned flags, R det_thresh, int32_t* __restrict__ diag) {
+    int64_t nnz, T* __restrict__ values, const T* __restrict__ zero, unsigned flags, R det_thresh,
+    int32_t* __restrict__ diag) {
   using C = H1Cfg<P>;
   constexpr int Q = C::Q, NSUB = C::NSUB, NLOC = C::NLOC, NENT = C::NENT, NENTP = C::NENTP, E = C::E;
   constexpr int TH = C::THREADS, RV = C::RV, RW = C::RW, NJ = C::NJ, TWE = NENTP / 4;
@@ -138,13 +139,22 @@ __global__ __launch_bounds__(256, 2) void k_h1_assemble(
     }
   };
   auto load_tab = [&](int g, uint32_t (&w)[RW]) {
+    if constexpr (E == 1) {
+      const uint32_t* row = reinterpret_cast<const uint32_t*>(tables + sOrd[g] * tab_stride);
 #pragma unroll
-    for (int j = 0; j < RW; ++j) {
-      const int i = tid + j * TH;
-      if (g < ngr && i < group_size(g) * TWE) {
-        const int el = i / TWE;
-        const uint32_t* row = reinterpret_cast<const uint32_t*>(tables + sOrd[g * E + el] * tab_stride);
-        w[j] = row[i - el * TWE];
+      for (int j = 0; j < RW; ++j) {
+        const uint32_t i = static_cast<uint32_t>(threadIdx.x) + j * TH;
+        if (i < static_cast<uint32_t>(TWE)) w[j] = row[i];
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < RW; ++j) {
+        const int i = tid + j * TH;
+        if (g < ngr && i < group_size(g) * TWE) {
+          const int el = i / TWE;
+          const uint32_t* row = reinterpret_cast<const uint32_t*>(tables + sOrd[g * E + el] * tab_stride);
+          w[j] = row[i - el * TWE];
+        }
       }
     }
   };
@@ -162,11 +172,12 @@ __global__ __launch_bounds__(256, 2) void k_h1_assemble(
   }
 
   for (int g = 0; g < ngr; ++g) {
-    const int ne = group_size(g);
+    const int ne = E == 1 ? 1 : group_size(g);
     // Index arithmetic below is cheap; an opaque copy of the lane id keeps the
     // compiler from hoisting it out of the loop into long-lived registers.
     int tid = threadIdx.x;
     __asm__ volatile("" : "+v"(tid));
+    __builtin_assume(tid >= 0 && tid < TH);
     lds_barrier();  // the previous group is done with every LDS buffer
 #pragma unroll
     for (int j = 0; j < RV; ++j) {
@@ -283,16 +294,22 @@ __global__ __launch_bounds__(256, 2) void k_h1_assemble(
         const int el = r / NLOC;
         const int l = r - el * NLOC;
         const int x = l % Q, y = (l / Q) % Q, z = l / (Q * Q);
-        const int nx = cnt1<P>(x), ny = cnt1<P>(y);
-        const int rbase = pre1<P>(z) * C::T1 * C::T1 + cnt1<P>(z) * pre1<P>(y) * C::T1 + cnt1<P>(z) * ny * pre1<P>(x);
-        T* dst = sStg + el * NENT + rbase;
+        const int nx = cnt1<P>(x), ny = cnt1<P>(y), nxy = nx * ny;
+        const int rbase = pre1<P>(z) * C::T1 * C::T1 + cnt1<P>(z) * pre1<P>(y) * C::T1 + nxy * pre1<P>(x);
         const int x0 = x > 0 ? 1 : 0, y0 = y > 0 ? 1 : 0, z0 = z > 0 ? 1 : 0;
+        // entry (dx, dy, dz) of the row sits at c + dz * nxy + dy * nx + dx
+        T* c = sStg + el * NENT + rbase + z0 * nxy + y0 * nx + x0;
+        const bool vx[3] = {x > 0, true, x < P}, vy[3] = {y > 0, true, y < P}, vz[3] = {z > 0, true, z < P};
 #pragma unroll
-        for (int o = 0; o < 27; ++o) {
-          const int dx = o % 3 - 1, dy = (o / 3) % 3 - 1, dz = o / 9 - 1;
-          if (x + dx < 0 || x + dx > P || y + dy < 0 || y + dy > P || z + dz < 0 || z + dz > P) continue;
-          dst[((dz + z0) * ny + (dy + y0)) * nx + (dx + x0)] = static_cast<T>(acc[h][o]);
-        }
+        for (int dz = -1; dz <= 1; ++dz)
+#pragma unroll
+          for (int dy = -1; dy <= 1; ++dy) {
+            T* line = c + dz * nxy + dy * nx;
+            const bool vzy = vz[dz + 1] && vy[dy + 1];
+#pragma unroll
+            for (int dx = -1; dx <= 1; ++dx)
+              if (vzy && vx[dx + 1]) line[dx] = static_cast<T>(acc[h][(dx + 1) + 3 * (dy + 1) + 9 * (dz + 1)]);
+          }
       }
     }
 #pragma unroll
@@ -302,30 +319,43 @@ __global__ __launch_bounds__(256, 2) void k_h1_assemble(
     }
     lds_barrier();
 
-    // phase 3: store into the CSR values; every load is issued before any store
-    int32_t pos[NJ];
-    T old[NJ];
-    uint64_t rmw = 0;
+    // phase 3: store into the CSR values.  Every load is issued before any
+    // store and the memory instructions sit in straight-line code (no branch
+    // per entry), so each store waits only for its own operand.  A first
+    // contributor reads its "old value" from a zero slot (one shared cache
+    // line) instead of taking a branch; lanes past the end of the group
+    // repeat their first store.
+    if (tid < ne * NENT) {
+      const uint32_t ut = static_cast<uint32_t>(tid);
+      uint32_t erow[NJ];
 #pragma unroll
-    for (int j = 0; j < NJ; ++j) {
-      const int i = tid + j * TH;
-      pos[j] = -1;
-      if (i < ne * NENT) {
-        const int el = i / NENT;
-        const int k = i - el * NENT;
-        const uint8_t t = sTab[el * NENTP + k];
-        pos[j] = sRp[el * NLOC + ent_row[k]] + (t & kRankMask);
-        if (!(t & kFirstBit)) rmw |= (1ull << j);
+      for (int j = 0; j < NJ; ++j) {
+        const uint32_t i = ut + j * TH;
+        const bool ok = i < static_cast<uint32_t>(ne * NENT);
+        const uint32_t el = E == 1 ? 0u : i / NENT;
+        erow[j] = ent_row[ok ? i - el * NENT : 0u];
       }
-    }
+      uint32_t pos[NJ];
+      T old[NJ];
 #pragma unroll
-    for (int j = 0; j < NJ; ++j) {
-      old[j] = T(0);
-      if ((rmw >> j) & 1ull) old[j] = values[pos[j]];
-    }
+      for (int j = 0; j < NJ; ++j) {
+        const uint32_t i = ut + j * TH;
+        const bool ok = i < static_cast<uint32_t>(ne * NENT);
+        const uint32_t el = ok ? (E == 1 ? 0u : i / NENT) : 0u;
+        const uint32_t k = ok ? i - el * NENT : 0u;
+        const uint32_t t = sTab[el * NENTP + k];
+        pos[j] = static_cast<uint32_t>(sRp[el * NLOC + erow[j]]) + (t & kRankMask);
+        old[j] = *((t & kFirstBit) ? zero : values + pos[j]);
+      }
+      const T v0 = sStg[ut] + old[0];
+      values[pos[0]] = v0;
 #pragma unroll
-    for (int j = 0; j < NJ; ++j) {
-      if (pos[j] >= 0) values[pos[j]] = sStg[tid + j * TH] + old[j];
+      for (int j = 1; j < NJ; ++j) {
+        const uint32_t i = ut + j * TH;
+        const bool ok = i < static_cast<uint32_t>(ne * NENT);
+        const T v = sStg[ok ? i : ut] + old[j];
+        values[ok ? pos[j] : pos[0]] = ok ? v : v0;
+      }
     }
   }
 }
@@ -363,8 +393,8 @@ static int launch_h1(const lor_sched* sched, int batch, const int32_t* elem_dofs
     dim3 grid(static_cast<unsigned>(ceil_div(n, chunk)), static_cast<unsigned>(batch));
     k_h1_assemble<P, T, R><<<grid, C::THREADS, 0, st>>>(
         order + sched->color_ptr[c], n, chunk, elem_dofs, coords, static_cast<const T*>(kappa), static_cast<T>(beta),
-        row_ptr, tab, sched->tab_stride, ent_row, sched->nel, sched->nnz, static_cast<T*>(values), flags,
-        static_cast<R>(thr), diag);
+        row_ptr, tab, sched->tab_stride, ent_row, sched->nel, sched->nnz, static_cast<T*>(values),
+        dev_at<T>(sched, sched->off_zero), flags, static_cast<R>(thr), diag);
     LOR_LAUNCHED("k_h1_assemble");
   }
   return LOR_OK;

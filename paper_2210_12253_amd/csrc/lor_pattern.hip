@@ -519,6 +519,7 @@ static size_t layout(lor_sched* s, const RefElem& r) {
   s->off_st_col = take(sizeof(int32_t) * r.st_col.size());
   s->off_ent_row = take(sizeof(uint16_t) * r.ent_row.size());
   s->off_recipe = take(sizeof(uint64_t) * std::max<size_t>(1, r.recipe64.size()));
+  s->off_zero = take(256);
   return off;
 }
 
@@ -674,6 +675,7 @@ extern "C" int lor_pattern(int space, int p, int64_t nel, int64_t nrows, const i
   if ((rc = upload(ref.ent_row, d_ent_row, st))) return rc;
   if ((rc = upload(ref.recipe64, d_recipe, st))) return rc;
   if ((rc = upload(ref.reps, reps.p, st))) return rc;
+  LOR_HIP(hipMemsetAsync(dev_at<uint8_t>(sched, sched->off_zero), 0, 256, st));
 
   if ((rc = build_incidence(elem_map, nel, nloc, is_signed, nrows, d_inc_ptr, d_inc_list, err.as<int32_t>(), st)))
     return rc;

@@ -66,7 +66,8 @@ class LorSched(ctypes.Structure):
         ("off_st_col", ctypes.c_size_t),
         ("off_ent_row", ctypes.c_size_t),
         ("off_recipe", ctypes.c_size_t),
-        ("reserved", ctypes.c_size_t * 8),
+        ("off_zero", ctypes.c_size_t),
+        ("reserved", ctypes.c_size_t * 7),
     ]
 
 
