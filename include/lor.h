@@ -80,7 +80,8 @@ typedef enum { LOR_F64 = 0, LOR_F32 = 1 } lor_dtype;
  *   - per element, for each of its `nent` local stencil entries, the position
  *     of the entry inside its CSR row and whether this element is the first
  *     (lowest colour) contributor to that entry, stored once per distinct
- *     element class (`nclass` classes),
+ *     element class (`nclass` classes; on a structured mesh a few hundred, so
+ *     the tables the assembly reads stay cache resident),
  *   - the vertex-to-element incidence lists used by the adjoint,
  *   - the reference-element stencil tables (the shared column pattern of one
  *     macro element, computed once, as in step A1).
@@ -105,7 +106,8 @@ typedef struct lor_sched {
   size_t off_inc_ptr, off_inc_list;
   size_t off_st_ptr, off_st_col, off_ent_row, off_recipe;
   size_t off_zero;               /* 256 zero bytes (read in place of an old value that is absent) */
-  size_t reserved[7];
+  size_t off_order_class;        /* class of order[i] (int32 per element, in colour order) */
+  size_t reserved[6];
 } lor_sched;
 
 /*

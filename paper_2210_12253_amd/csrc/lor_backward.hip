@@ -48,7 +48,7 @@ template <int P, typename T, typename R>
 __global__ __launch_bounds__(256, 1) void k_h1_backward(
     int64_t nel, int32_t chunk, const int32_t* __restrict__ elem_dofs, const double* __restrict__ coords,
     const T* __restrict__ kappa, T beta, const int32_t* __restrict__ row_ptr, const uint8_t* __restrict__ tables,
-    int64_t tab_stride, int batch, int64_t nnz, const T* __restrict__ gvals, T* __restrict__ gkappa,
+    const int32_t* __restrict__ elem_class, int64_t tab_stride, int batch, int64_t nnz, const T* __restrict__ gvals, T* __restrict__ gkappa,
     double* __restrict__ ework) {
   using C = BwCfg<P>;
   constexpr int Q = C::Q, NSUB = C::NSUB, NLOC = C::NLOC, NENTP = C::NENTP, E = C::E, TH = C::THREADS;
@@ -78,7 +78,7 @@ __global__ __launch_bounds__(256, 1) void k_h1_backward(
     }
     for (int i = tid; i < ne * TWE; i += TH) {
       const int el = i / TWE;
-      const uint32_t* row = reinterpret_cast<const uint32_t*>(tables + (e0 + el) * tab_stride);
+      const uint32_t* row = reinterpret_cast<const uint32_t*>(tables + elem_class[e0 + el] * tab_stride);
       sTabW[i] = row[i - el * TWE];
     }
     lds_barrier();
@@ -225,7 +225,7 @@ static int launch_bw(const lor_sched* sched, int batch, const int32_t* elem_dofs
   double* ework = static_cast<double*>(workspace);
   k_h1_backward<P, T, R><<<static_cast<unsigned>(ceil_div(nel, chunk)), C::THREADS, 0, st>>>(
       nel, chunk, elem_dofs, coords, static_cast<const T*>(kappa), static_cast<T>(beta), row_ptr, tab,
-      sched->tab_stride, batch, sched->nnz, static_cast<const T*>(gvals), static_cast<T*>(gkappa), ework);
+      dev_at<int32_t>(sched, sched->off_class), sched->tab_stride, batch, sched->nnz, static_cast<const T*>(gvals), static_cast<T*>(gkappa), ework);
   LOR_LAUNCHED("k_h1_backward");
   k_gather_vertices<<<static_cast<unsigned>(ceil_div(sched->nrows, 256)), 256, 0, st>>>(
       dev_at<int32_t>(sched, sched->off_inc_ptr), dev_at<int32_t>(sched, sched->off_inc_list), sched->nrows, ework,

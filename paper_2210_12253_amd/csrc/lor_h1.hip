@@ -78,7 +78,8 @@ __device__ __forceinline__ bool h1_fp64_fallback(const double (&X)[8][3], double
 
 template <int P, typename T, typename R>
 __global__ __launch_bounds__(256, 2) void k_h1_assemble(
-    const int32_t* __restrict__ order, int32_t ncol, int32_t chunk, const int32_t* __restrict__ elem_dofs,
+    const int32_t* __restrict__ order, const int32_t* __restrict__ order_class, int32_t ncol, int32_t chunk,
+    const int32_t* __restrict__ elem_dofs,
     const double* __restrict__ coords, const T* __restrict__ kappa, T beta, const int32_t* __restrict__ row_ptr,
     const uint8_t* __restrict__ tables, int64_t tab_stride, const uint16_t* __restrict__ ent_row, int64_t nel,
     int64_t nnz, T* __restrict__ values, const T* __restrict__ zero, unsigned flags, R det_thresh,
@@ -94,6 +95,7 @@ __global__ __launch_bounds__(256, 2) void k_h1_assemble(
   __shared__ uint32_t sTabW[E * TWE];
   __shared__ R sSub[REGW];
   __shared__ int32_t sOrd[C::MAXCHUNK];
+  __shared__ int32_t sCls[C::MAXCHUNK];
   T* sStg = reinterpret_cast<T*>(sSub);
   const uint8_t* sTab = reinterpret_cast<const uint8_t*>(sTabW);
   static_assert(sizeof(T) <= sizeof(R), "staging aliases the subelement region");
@@ -104,7 +106,10 @@ __global__ __launch_bounds__(256, 2) void k_h1_assemble(
   const int64_t cbeg = static_cast<int64_t>(blockIdx.x) * chunk;
   const int nce = static_cast<int>(ncol - cbeg < chunk ? ncol - cbeg : chunk);
   const int ngr = (nce + E - 1) / E;
-  if (tid < nce) sOrd[tid] = order[cbeg + tid];
+  if (tid < nce) {
+    sOrd[tid] = order[cbeg + tid];
+    sCls[tid] = order_class[cbeg + tid];
+  }
   __syncthreads();
 
   auto group_size = [&](int g) { return nce - g * E < E ? nce - g * E : E; };
@@ -140,7 +145,7 @@ __global__ __launch_bounds__(256, 2) void k_h1_assemble(
   };
   auto load_tab = [&](int g, uint32_t (&w)[RW]) {
     if constexpr (E == 1) {
-      const uint32_t* row = reinterpret_cast<const uint32_t*>(tables + sOrd[g] * tab_stride);
+      const uint32_t* row = reinterpret_cast<const uint32_t*>(tables + sCls[g] * tab_stride);
 #pragma unroll
       for (int j = 0; j < RW; ++j) {
         const uint32_t i = static_cast<uint32_t>(threadIdx.x) + j * TH;
@@ -152,7 +157,7 @@ __global__ __launch_bounds__(256, 2) void k_h1_assemble(
         const int i = tid + j * TH;
         if (g < ngr && i < group_size(g) * TWE) {
           const int el = i / TWE;
-          const uint32_t* row = reinterpret_cast<const uint32_t*>(tables + sOrd[g * E + el] * tab_stride);
+          const uint32_t* row = reinterpret_cast<const uint32_t*>(tables + sCls[g * E + el] * tab_stride);
           w[j] = row[i - el * TWE];
         }
       }
@@ -295,7 +300,7 @@ __global__ __launch_bounds__(256, 2) void k_h1_assemble(
         const int l = r - el * NLOC;
         const int x = l % Q, y = (l / Q) % Q, z = l / (Q * Q);
         const int nx = cnt1<P>(x), ny = cnt1<P>(y), nxy = nx * ny;
-        const int rbase = pre1<P>(z) * C::T1 * C::T1 + cnt1<P>(z) * pre1<P>(y) * C::T1 + nxy * pre1<P>(x);
+        const int rbase = pre1<P>(z) * C::T1 * C::T1 + cnt1<P>(z) * pre1<P>(y) * C::T1 + cnt1<P>(z) * ny * pre1<P>(x);
         const int x0 = x > 0 ? 1 : 0, y0 = y > 0 ? 1 : 0, z0 = z > 0 ? 1 : 0;
         // entry (dx, dy, dz) of the row sits at c + dz * nxy + dy * nx + dx
         T* c = sStg + el * NENT + rbase + z0 * nxy + y0 * nx + x0;
@@ -380,6 +385,7 @@ static int launch_h1(const lor_sched* sched, int batch, const int32_t* elem_dofs
   if (sched->tab_stride != C::NENTP || sched->nent != C::NENT)
     LOR_FAIL(LOR_EINVAL, "schedule tables do not match p = %d", P);
   const int32_t* order = dev_at<int32_t>(sched, sched->off_order);
+  const int32_t* ocls = dev_at<int32_t>(sched, sched->off_order_class);
   const uint8_t* tab = dev_at<uint8_t>(sched, sched->off_tables);
   const uint16_t* ent_row = dev_at<uint16_t>(sched, sched->off_ent_row);
   const int wgs = 2 * num_cus();  // two resident workgroups per CU
@@ -392,7 +398,7 @@ static int launch_h1(const lor_sched* sched, int batch, const int32_t* elem_dofs
     const int32_t chunk = static_cast<int32_t>(gpw * C::E);
     dim3 grid(static_cast<unsigned>(ceil_div(n, chunk)), static_cast<unsigned>(batch));
     k_h1_assemble<P, T, R><<<grid, C::THREADS, 0, st>>>(
-        order + sched->color_ptr[c], n, chunk, elem_dofs, coords, static_cast<const T*>(kappa), static_cast<T>(beta),
+        order + sched->color_ptr[c], ocls + sched->color_ptr[c], n, chunk, elem_dofs, coords, static_cast<const T*>(kappa), static_cast<T>(beta),
         row_ptr, tab, sched->tab_stride, ent_row, sched->nel, sched->nnz, static_cast<T*>(values),
         dev_at<T>(sched, sched->off_zero), flags, static_cast<R>(thr), diag);
     LOR_LAUNCHED("k_h1_assemble");

@@ -44,11 +44,13 @@ struct NDCfg {
 
 template <int P, typename T, typename R>
 __global__ __launch_bounds__(256) void k_nd_assemble(
-    const int32_t* __restrict__ order, int32_t ncol, int32_t chunk, const int32_t* __restrict__ elem_dofs,
+    const int32_t* __restrict__ order, const int32_t* __restrict__ order_class, int32_t ncol, int32_t chunk,
+    const int32_t* __restrict__ elem_dofs,
     const int32_t* __restrict__ elem_edges, const double* __restrict__ coords, const T* __restrict__ kappa, T beta,
     const int32_t* __restrict__ row_ptr, const uint8_t* __restrict__ tables, int64_t tab_stride,
     const uint16_t* __restrict__ ent_row, const int32_t* __restrict__ ent_col, const uint64_t* __restrict__ recipe,
-    int64_t nel, int64_t nnz, T* __restrict__ values, unsigned flags, R det_thresh, int32_t* __restrict__ diag) {
+    int64_t nel, int64_t nnz, T* __restrict__ values, const T* __restrict__ zero, unsigned flags, R det_thresh,
+    int32_t* __restrict__ diag) {
   using C = NDCfg<P, R>;
   constexpr int Q = C::Q, NSUB = C::NSUB, NLOCV = C::NLOCV, NLOCE = C::NLOCE, NENT = C::NENT;
   constexpr int NENTP = C::NENTP, E = C::E, TH = C::THREADS, TWE = C::TWE, CH = C::CH;
@@ -58,6 +60,7 @@ __global__ __launch_bounds__(256) void k_nd_assemble(
   __shared__ uint32_t sTabW[E * TWE];
   __shared__ R sSub[E * 78 * NSUB];
   __shared__ int32_t sOrd[C::MAXCHUNK];
+  __shared__ int32_t sCls[C::MAXCHUNK];
   const uint8_t* sTab = reinterpret_cast<const uint8_t*>(sTabW);
 
   kappa += static_cast<int64_t>(blockIdx.y) * nel * NSUB;
@@ -65,12 +68,16 @@ __global__ __launch_bounds__(256) void k_nd_assemble(
   const int64_t cbeg = static_cast<int64_t>(blockIdx.x) * chunk;
   const int nce = static_cast<int>(ncol - cbeg < chunk ? ncol - cbeg : chunk);
   const int ngr = (nce + E - 1) / E;
-  if (static_cast<int>(threadIdx.x) < nce) sOrd[threadIdx.x] = order[cbeg + threadIdx.x];
+  if (static_cast<int>(threadIdx.x) < nce) {
+    sOrd[threadIdx.x] = order[cbeg + threadIdx.x];
+    sCls[threadIdx.x] = order_class[cbeg + threadIdx.x];
+  }
   __syncthreads();
 
   for (int g = 0; g < ngr; ++g) {
     int tid = threadIdx.x;
     __asm__ volatile("" : "+v"(tid));
+    __builtin_assume(tid >= 0 && tid < TH);
     const int ne = nce - g * E < E ? nce - g * E : E;
     lds_barrier();  // the previous group is done with every LDS buffer
     // phase 0
@@ -90,7 +97,7 @@ __global__ __launch_bounds__(256) void k_nd_assemble(
     }
     for (int i = tid; i < ne * TWE; i += TH) {
       const int el = i / TWE;
-      const uint32_t* row = reinterpret_cast<const uint32_t*>(tables + sOrd[g * E + el] * tab_stride);
+      const uint32_t* row = reinterpret_cast<const uint32_t*>(tables + sCls[g * E + el] * tab_stride);
       sTabW[i] = row[i - el * TWE];
     }
     lds_barrier();
@@ -161,46 +168,49 @@ __global__ __launch_bounds__(256) void k_nd_assemble(
     lds_barrier();
 
     // phase 2: entry sums and CSR stores, CH entries per lane at a time with
-    // every load issued before the stores
+    // every load issued before the stores and no branch around a memory
+    // instruction (a first contributor reads its old value from the zero
+    // slot; a lane past the end repeats its first store of the chunk)
     for (int base = 0; base < ne * NENT; base += CH * TH) {
-      int32_t pos[CH];
+      if (base + tid >= ne * NENT) break;
+      uint32_t pos[CH];
       T val[CH];
       T old[CH];
-      uint32_t rmw = 0;
+      uint64_t recs[CH];
+      int32_t ls[CH], cs[CH];
+#pragma unroll
+      for (int j = 0; j < CH; ++j) {  // reference-element tables (cache resident), all in flight
+        const int i0 = base + tid + j * TH;
+        const int i = i0 < ne * NENT ? i0 : base + tid;
+        const int k = i - (i / NENT) * NENT;
+        recs[j] = recipe[k];
+        ls[j] = ent_row[k];
+        cs[j] = ent_col[k];
+      }
 #pragma unroll
       for (int j = 0; j < CH; ++j) {
-        const int i = base + tid + j * TH;
-        pos[j] = -1;
-        val[j] = T(0);
-        if (i < ne * NENT) {
-          const int el = i / NENT;
-          const int k = i - el * NENT;
-          const int l = ent_row[k];
-          const int c = ent_col[k];
-          const uint64_t rec = recipe[k];
-          double acc = 0.0;
+        const int i0 = base + tid + j * TH;
+        const int i = i0 < ne * NENT ? i0 : base + tid;
+        const int el = i / NENT;
+        const int k = i - el * NENT;
+        const int l = ls[j];
+        const int c = cs[j];
+        const uint64_t rec = recs[j];
+        double acc = 0.0;
 #pragma unroll
-          for (int m = 0; m < 4; ++m) {
-            const uint32_t code = static_cast<uint32_t>((rec >> (16 * m)) & 0xffffu);
-            if (code != 0xffffu)
-              acc += static_cast<double>(sSub[(el * 78 + static_cast<int>(code & 127u)) * NSUB + (code >> 7)]);
-          }
-          if (sSg[el * NLOCE + l] ^ sSg[el * NLOCE + c]) acc = -acc;
-          const uint8_t t = sTab[el * NENTP + k];
-          pos[j] = sRp[el * NLOCE + l] + (t & kRankMask);
-          val[j] = static_cast<T>(acc);
-          if (!(t & kFirstBit)) rmw |= (1u << j);
+        for (int m = 0; m < 4; ++m) {
+          const uint32_t code = static_cast<uint32_t>((rec >> (16 * m)) & 0xffffu);
+          if (code != 0xffffu)
+            acc += static_cast<double>(sSub[(el * 78 + static_cast<int>(code & 127u)) * NSUB + (code >> 7)]);
         }
+        if (sSg[el * NLOCE + l] ^ sSg[el * NLOCE + c]) acc = -acc;
+        const uint32_t t = sTab[el * NENTP + k];
+        pos[j] = static_cast<uint32_t>(sRp[el * NLOCE + l]) + (t & kRankMask);
+        val[j] = static_cast<T>(acc);
+        old[j] = *((t & kFirstBit) ? zero : values + pos[j]);
       }
 #pragma unroll
-      for (int j = 0; j < CH; ++j) {
-        old[j] = T(0);
-        if ((rmw >> j) & 1u) old[j] = values[pos[j]];
-      }
-#pragma unroll
-      for (int j = 0; j < CH; ++j) {
-        if (pos[j] >= 0) values[pos[j]] = val[j] + old[j];
-      }
+      for (int j = 0; j < CH; ++j) values[pos[j]] = val[j] + old[j];
     }
   }
 }
@@ -225,6 +235,7 @@ static int launch_nd(const lor_sched* sched, int batch, const int32_t* elem_dofs
   if (sched->tab_stride != C::NENTP || sched->nent != C::NENT)
     LOR_FAIL(LOR_EINVAL, "schedule tables do not match p = %d", P);
   const int32_t* order = dev_at<int32_t>(sched, sched->off_order);
+  const int32_t* ocls = dev_at<int32_t>(sched, sched->off_order_class);
   const uint8_t* tab = dev_at<uint8_t>(sched, sched->off_tables);
   const uint16_t* ent_row = dev_at<uint16_t>(sched, sched->off_ent_row);
   const int32_t* ent_col = dev_at<int32_t>(sched, sched->off_st_col);
@@ -239,9 +250,9 @@ static int launch_nd(const lor_sched* sched, int batch, const int32_t* elem_dofs
     const int32_t chunk = static_cast<int32_t>(gpw * C::E);
     dim3 grid(static_cast<unsigned>(ceil_div(n, chunk)), static_cast<unsigned>(batch));
     k_nd_assemble<P, T, R><<<grid, C::THREADS, 0, st>>>(
-        order + sched->color_ptr[c], n, chunk, elem_dofs, elem_edges, coords, static_cast<const T*>(kappa),
+        order + sched->color_ptr[c], ocls + sched->color_ptr[c], n, chunk, elem_dofs, elem_edges, coords, static_cast<const T*>(kappa),
         static_cast<T>(beta), row_ptr, tab, sched->tab_stride, ent_row, ent_col, recipe, sched->nel, sched->nnz,
-        static_cast<T*>(values), flags, static_cast<R>(thr), diag);
+        static_cast<T*>(values), dev_at<T>(sched, sched->off_zero), flags, static_cast<R>(thr), diag);
     LOR_LAUNCHED("k_nd_assemble");
   }
   return LOR_OK;

@@ -25,6 +25,7 @@
 //     CSR row and whether the element is the entry's first contributor.
 #include <algorithm>
 #include <climits>
+#include <unordered_map>
 #include <vector>
 
 #include "lor_common.hpp"
@@ -497,6 +498,48 @@ __global__ void k_rank_pass1(const int32_t* __restrict__ map, int nloc, int is_s
   if (mincolor[row_ptr[g] + (t & kRankMask)] == color[e]) *tab = static_cast<uint8_t>(t | kFirstBit);
 }
 
+// Table deduplication: elements whose rank tables are byte-identical share one
+// class.  64-bit FNV-1a of every element table; the host numbers classes by
+// first appearance; equality with the class representative is then verified
+// word by word, so a hash collision can only cost the deduplication, never
+// correctness.
+__global__ void k_table_hash(const uint32_t* __restrict__ tables, int64_t words, int64_t nel,
+                             uint64_t* __restrict__ hash) {
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= nel) return;
+  const uint32_t* t = tables + e * words;
+  uint64_t h = 1469598103934665603ull;
+  for (int64_t w = 0; w < words; ++w) {
+    h ^= t[w];
+    h *= 1099511628211ull;
+  }
+  hash[e] = h;
+}
+
+__global__ void k_table_verify(const uint32_t* __restrict__ tables, int64_t words, int64_t nel,
+                               const int32_t* __restrict__ cls, const int32_t* __restrict__ rep,
+                               int32_t* __restrict__ mismatch) {
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= nel * words) return;
+  const int64_t e = idx / words;
+  const int64_t w = idx - e * words;
+  if (tables[e * words + w] != tables[static_cast<int64_t>(rep[cls[e]]) * words + w]) atomicOr(mismatch, 1);
+}
+
+__global__ void k_table_gather(const uint32_t* __restrict__ tables, int64_t words, int64_t nclass,
+                               const int32_t* __restrict__ rep, uint32_t* __restrict__ out) {
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= nclass * words) return;
+  const int64_t c = idx / words;
+  out[idx] = tables[static_cast<int64_t>(rep[c]) * words + (idx - c * words)];
+}
+
+__global__ void k_gather_i32(const int32_t* __restrict__ src, const int32_t* __restrict__ idx, int64_t n,
+                             int32_t* __restrict__ dst) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = src[idx[i]];
+}
+
 // --------------------------------------------------------------- host side
 
 static size_t align256(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
@@ -520,6 +563,7 @@ static size_t layout(lor_sched* s, const RefElem& r) {
   s->off_ent_row = take(sizeof(uint16_t) * r.ent_row.size());
   s->off_recipe = take(sizeof(uint64_t) * std::max<size_t>(1, r.recipe64.size()));
   s->off_zero = take(256);
+  s->off_order_class = take(sizeof(int32_t) * s->nel);
   return off;
 }
 
@@ -756,14 +800,62 @@ extern "C" int lor_pattern(int space, int p, int64_t nel, int64_t nrows, const i
                                                         d_color, tot, mincol.as<int32_t>(), d_tab);
       LOR_LAUNCHED("k_rank_pass1");
     }
-    if (nel > 0) {
-      k_iota_i32<<<ceil_div(nel, 256), 256, 0, st>>>(d_class, nel);
-      LOR_LAUNCHED("k_iota_i32");
-    }
     if ((rc = read_err(err.as<int32_t>(), st, &herr))) return rc;
     if ((rc = report_err(herr))) return rc;
   }
+  // element classes (identical rank tables share one stored table)
   sched->nclass = nel;
+  if (nel > 0) {
+    const int64_t words = sched->tab_stride / 4;
+    uint32_t* tabw = dev_at<uint32_t>(sched, sched->off_tables);
+    DevBuf hash;
+    if ((rc = hash.alloc(sizeof(uint64_t) * nel))) return rc;
+    k_table_hash<<<ceil_div(nel, 256), 256, 0, st>>>(tabw, words, nel, hash.as<uint64_t>());
+    LOR_LAUNCHED("k_table_hash");
+    std::vector<uint64_t> h(static_cast<size_t>(nel));
+    LOR_HIP(hipMemcpyAsync(h.data(), hash.p, sizeof(uint64_t) * nel, hipMemcpyDeviceToHost, st));
+    LOR_HIP(hipStreamSynchronize(st));
+    std::unordered_map<uint64_t, int32_t> first;
+    std::vector<int32_t> cls(static_cast<size_t>(nel)), rep;
+    for (int64_t e = 0; e < nel; ++e) {
+      auto it = first.find(h[e]);
+      if (it == first.end()) {
+        it = first.emplace(h[e], static_cast<int32_t>(rep.size())).first;
+        rep.push_back(static_cast<int32_t>(e));
+      }
+      cls[e] = it->second;
+    }
+    const int64_t ncls = static_cast<int64_t>(rep.size());
+    DevBuf drep, mism;
+    if ((rc = drep.alloc(sizeof(int32_t) * ncls))) return rc;
+    if ((rc = mism.alloc(sizeof(int32_t)))) return rc;
+    if ((rc = upload(cls, d_class, st))) return rc;
+    if ((rc = upload(rep, drep.p, st))) return rc;
+    LOR_HIP(hipMemsetAsync(mism.p, 0, sizeof(int32_t), st));
+    k_table_verify<<<ceil_div(nel * words, 256), 256, 0, st>>>(tabw, words, nel, d_class, drep.as<int32_t>(),
+                                                              mism.as<int32_t>());
+    LOR_LAUNCHED("k_table_verify");
+    int32_t hm = 0;
+    if ((rc = read_err(mism.as<int32_t>(), st, &hm))) return rc;
+    if (hm == 0 && ncls < nel) {
+      DevBuf tmp;
+      if ((rc = tmp.alloc(static_cast<size_t>(ncls) * sched->tab_stride))) return rc;
+      k_table_gather<<<ceil_div(ncls * words, 256), 256, 0, st>>>(tabw, words, ncls, drep.as<int32_t>(),
+                                                                  tmp.as<uint32_t>());
+      LOR_LAUNCHED("k_table_gather");
+      LOR_HIP(hipMemcpyAsync(tabw, tmp.p, static_cast<size_t>(ncls) * sched->tab_stride, hipMemcpyDeviceToDevice,
+                             st));
+      LOR_HIP(hipStreamSynchronize(st));
+      sched->nclass = ncls;
+    } else {
+      // a hash collision (or nothing to share): every element keeps its own table
+      k_iota_i32<<<ceil_div(nel, 256), 256, 0, st>>>(d_class, nel);
+      LOR_LAUNCHED("k_iota_i32");
+    }
+    k_gather_i32<<<ceil_div(nel, 256), 256, 0, st>>>(d_class, d_order, nel,
+                                                    dev_at<int32_t>(sched, sched->off_order_class));
+    LOR_LAUNCHED("k_gather_i32");
+  }
   sched->max_row_nnz = 0;
   LOR_HIP(hipStreamSynchronize(st));
   return LOR_OK;

@@ -67,7 +67,8 @@ class LorSched(ctypes.Structure):
         ("off_ent_row", ctypes.c_size_t),
         ("off_recipe", ctypes.c_size_t),
         ("off_zero", ctypes.c_size_t),
-        ("reserved", ctypes.c_size_t * 7),
+        ("off_order_class", ctypes.c_size_t),
+        ("reserved", ctypes.c_size_t * 6),
     ]
 
 
