@@ -147,7 +147,11 @@ def summarize_profiles(stats_dir, fetch_dir, write_dir, command):
     lines = [f"command: {command}", ""]
     stats = _read_csvs(stats_dir, "kernel_stats.csv")
     lines.append(f"{'kernel':70s} {'calls':>6s} {'avg_us':>10s} {'min_us':>10s} {'max_us':>10s} {'pct':>6s}")
+    def ours(name):
+        return "lor::" in name or name == "__amd_rocclr_copyBuffer"
     for r in sorted(stats, key=lambda r: -float(r["TotalDurationNs"])):
+        if not ours(r["Name"]):
+            continue
         lines.append(f"{r['Name'][:70]:70s} {int(r['Calls']):6d} {float(r['AverageNs']) / 1e3:10.2f} "
                      f"{float(r['MinNs']) / 1e3:10.2f} {float(r['MaxNs']) / 1e3:10.2f} "
                      f"{float(r['Percentage']):6.2f}")
@@ -199,8 +203,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--cpu-sample", type=int, default=4096, help="elements of the CPU oracle sample")
+    ap.add_argument("--cpu-sample", type=int, default=16384, help="elements of the CPU oracle sample")
     ap.add_argument("--skip-extras", action="store_true")
+    ap.add_argument("--pencil-full", action="store_true",
+                    help="FP32 pencil eigenvalues on the 274,625-row mesh instead of the 35,937-row one")
     ap.add_argument("--summarize-profiles", nargs=3, metavar=("STATS_DIR", "FETCH_DIR", "WRITE_DIR"),
                     help="summarise rocprofv3 CSV output of this script (no GPU use)")
     ap.add_argument("--profile-command", default="", help="command recorded in the summary")
@@ -309,9 +315,63 @@ def main():
     if not args.skip_extras:
         out["backward"] = bench_backward(lor, meshgen, args, dev)
         out["nd"] = bench_nd(lor, meshgen, args, dev)
+        log("fp32 pencil eigenvalues")
+        out["fp32"]["pencil_eigs"] = bench_fp32_pencil(lor, meshgen, dev, full=args.pencil_full)
         log("cpu baseline")
         out["cpu_baseline"] = cpu_baseline(m, args.cpu_sample)
     print(json.dumps(out))
+
+
+def pencil_extreme_eigs(row_ptr, col_idx, v64, v32, n, niter=400):
+    """Extreme eigenvalues of the pencil A64 x = lambda A32 x (the FP64 LOR
+    matrix preconditioned by its FP32 form, both on the same pattern), by
+    LOBPCG on the device: lambda - 1 are the extreme eigenvalues of
+    (A64 - A32) x = mu A32 x, which needs products with the two matrices only
+    (no factorisation of A32).  The difference is scaled by 2^24 so the
+    solver's tolerance is relative to the FP32 rounding level."""
+    import torch
+    rp = row_ptr.to(torch.int64)
+    ci = col_idx.to(torch.int64)
+    a32 = v32.to(torch.float64)
+    scale = 2.0 ** 24
+    E = torch.sparse_csr_tensor(rp, ci, (v64 - a32) * scale, (n, n)).to_sparse_coo()
+    B = torch.sparse_csr_tensor(rp, ci, a32, (n, n)).to_sparse_coo()
+    rows = torch.repeat_interleave(torch.arange(n, device=rp.device), rp[1:] - rp[:-1])
+    diag = torch.zeros(n, dtype=torch.float64, device=rp.device)
+    diag.index_add_(0, rows, torch.where(rows == ci, a32, torch.zeros_like(a32)))
+    iK = torch.sparse_coo_tensor(torch.arange(n, device=rp.device).repeat(2, 1), 1.0 / diag, (n, n))
+    out = {}
+    for name, largest in (("max", True), ("min", False)):
+        torch.manual_seed(0)
+        w, _ = torch.lobpcg(E, k=2, B=B, iK=iK, niter=niter, tol=1e-7, largest=largest)
+        out[name] = float(w[0]) / scale
+    return {"lambda_max_minus_1": out["max"], "one_minus_lambda_min": -out["min"]}
+
+
+def bench_fp32_pencil(lor, meshgen, dev, full=False):
+    """FP32-form quality: the p=4, 8^3 curved mesh by default (35,937 rows);
+    full=True takes the p=4, 16^3 mesh (274,625 rows, about a minute)."""
+    import torch
+    if full:
+        m = meshgen.config_mesh("c2_h1_p4_curved")
+        k = m["kappa"].to(dev)
+        n_el, beta = 16, m["beta"]
+    else:
+        m = meshgen.cartesian_mesh(8, 4, 0.1 / 8)
+        k = meshgen.kappa_field(m["nel"], 4, 1.0, seed=0).to(dev)
+        n_el, beta = 8, 1.0
+    ed = torch.from_numpy(m["elem_dofs"]).to(dev)
+    x = torch.from_numpy(m["coords"]).to(dev)
+    pat = lor.lor_pattern(lor.LOR_H1, 4, ed, m["ndofs"])
+    v64 = lor.lor_assemble_h1(pat, ed, x, k, beta)
+    v32 = lor.lor_assemble_h1(pat, ed, x, k.float(), beta, dtype=torch.float32, fp64_fallback=True)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    res = pencil_extreme_eigs(pat.row_ptr, pat.col_idx, v64, v32, m["ndofs"])
+    res["seconds"] = time.perf_counter() - t
+    res["workload"] = (f"H1 p=4, {n_el}^3 curved hexes, kappa sigma=1, beta=1 ({m['ndofs']} rows); "
+                       f"LOBPCG on the device")
+    return res
 
 
 def bench_backward(lor, meshgen, args, dev):
