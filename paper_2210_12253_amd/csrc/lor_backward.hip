@@ -57,6 +57,7 @@ __global__ __launch_bounds__(256, 1) void k_h1_backward(
   __shared__ int32_t sRp[E * NLOC];
   __shared__ uint32_t sTabW[E * TWE];
   __shared__ double sXb[E * 24 * NSUB];
+  __shared__ int32_t sPos[64 * TH];  // CSR positions of each lane's 64 corner pairs, [pair][lane]
   const uint8_t* sTab = reinterpret_cast<const uint8_t*>(sTabW);
 
   const int64_t cbeg = static_cast<int64_t>(blockIdx.x) * chunk;
@@ -88,8 +89,7 @@ __global__ __launch_bounds__(256, 1) void k_h1_backward(
       const int s = tid - el * NSUB;
       const int64_t e = e0 + el;
       const int si = s % P, sj = (s / P) % P, sk = s / (P * P);
-      R ex[2][2][3], ey[2][2][3], ez[2][2][3];
-      {
+      auto edges = [&](R (&ex)[2][2][3], R (&ey)[2][2][3], R (&ez)[2][2][3]) {
         double X[8][3];
 #pragma unroll
         for (int v = 0; v < 8; ++v) {
@@ -98,9 +98,11 @@ __global__ __launch_bounds__(256, 1) void k_h1_backward(
           for (int d = 0; d < 3; ++d) X[v][d] = sX[3 * (el * NLOC + lv) + d];
         }
         h1_edges<R>(X, ex, ey, ez);
-      }
+      };
       R Kt[36];
       {
+        R ex[2][2][3], ey[2][2][3], ez[2][2][3];
+        edges(ex, ey, ez);
         H1Factors<R> F;
         (void)h1_factors<R>(ex, ey, ez, R(1), R(0), F);
 #pragma unroll
@@ -108,8 +110,7 @@ __global__ __launch_bounds__(256, 1) void k_h1_backward(
 #pragma unroll
           for (int v = u; v < 8; ++v) Kt[pair_index(u, v)] = h1_entry<R>(F, u, v);
       }
-      // CSR positions of the 64 ordered corner pairs
-      int32_t pos[64];
+      // CSR positions of the 64 ordered corner pairs, kept in LDS (lane-major)
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         const int x = si + (u & 1), y = sj + ((u >> 1) & 1), z = sk + (u >> 2);
@@ -119,7 +120,7 @@ __global__ __launch_bounds__(256, 1) void k_h1_backward(
         for (int v = 0; v < 8; ++v) {
           const int k = compact_index<P>(x, y, z, (v & 1) - (u & 1), ((v >> 1) & 1) - ((u >> 1) & 1),
                                          (v >> 2) - (u >> 2));
-          pos[u * 8 + v] = rb + (sTab[el * NENTP + k] & kRankMask);
+          sPos[(u * 8 + v) * TH + tid] = rb + (sTab[el * NENTP + k] & kRankMask);
         }
       }
       R Wk[36], Wm[36];
@@ -134,13 +135,15 @@ __global__ __launch_bounds__(256, 1) void k_h1_backward(
         for (int u = 0; u < 8; ++u)
 #pragma unroll
           for (int v = 0; v < 8; ++v) {
-            const R w = static_cast<R>(gb[pos[u * 8 + v]]);
+            const R w = static_cast<R>(gb[sPos[(u * 8 + v) * TH + tid]]);
             gk += Kt[pair_index(u, v)] * w;
             Wk[pair_index(u, v)] += kb * w;
             Wm[pair_index(u, v)] += w;
           }
         gkappa[(static_cast<int64_t>(b) * nel + e) * NSUB + s] = static_cast<T>(gk);
       }
+      R ex[2][2][3], ey[2][2][3], ez[2][2][3];
+      edges(ex, ey, ez);
       R gx[2][2][3], gy[2][2][3], gz[2][2][3];
       h1_adjoint<R>(ex, ey, ez, Wk, Wm, static_cast<R>(beta), gx, gy, gz);
       // corner adjoints from the edge adjoints: e = X(hi) - X(lo)
