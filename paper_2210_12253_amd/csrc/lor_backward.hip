@@ -48,17 +48,21 @@ template <int P, typename T, typename R>
 __global__ __launch_bounds__(256, 1) void k_h1_backward(
     int64_t nel, int32_t chunk, const int32_t* __restrict__ elem_dofs, const double* __restrict__ coords,
     const T* __restrict__ kappa, T beta, const int32_t* __restrict__ row_ptr, const uint8_t* __restrict__ tables,
-    const int32_t* __restrict__ elem_class, int64_t tab_stride, int batch, int64_t nnz, const T* __restrict__ gvals, T* __restrict__ gkappa,
-    double* __restrict__ ework) {
+    const int32_t* __restrict__ elem_class, int64_t tab_stride, const uint16_t* __restrict__ ent_row, int batch,
+    int64_t nnz, const T* __restrict__ gvals, T* __restrict__ gkappa, double* __restrict__ ework) {
   using C = BwCfg<P>;
-  constexpr int Q = C::Q, NSUB = C::NSUB, NLOC = C::NLOC, NENTP = C::NENTP, E = C::E, TH = C::THREADS;
-  constexpr int TWE = C::TWE;
+  constexpr int Q = C::Q, NSUB = C::NSUB, NLOC = C::NLOC, NENT = C::NENT, NENTP = C::NENTP, E = C::E;
+  constexpr int TH = C::THREADS, TWE = C::TWE;
+  constexpr int NJ = (E * NENT + TH - 1) / TH;            // gathered entries per lane
+  constexpr int GW = E * NENT > 3 * E * 8 * NSUB ? E * NENT : 3 * E * 8 * NSUB;
   __shared__ double sX[E * NLOC * 3];
   __shared__ int32_t sRp[E * NLOC];
   __shared__ uint32_t sTabW[E * TWE];
-  __shared__ double sXb[E * 24 * NSUB];
-  __shared__ int32_t sPos[64 * TH];  // CSR positions of each lane's 64 corner pairs, [pair][lane]
+  __shared__ double sGX[GW];            // cotangent entries in compact order, later the corner adjoints
+  __shared__ uint16_t sK[64 * TH];      // compact index of each lane's 64 corner pairs, [pair][lane]
   const uint8_t* sTab = reinterpret_cast<const uint8_t*>(sTabW);
+  double* sG = sGX;
+  double* sXb = sGX;
 
   const int64_t cbeg = static_cast<int64_t>(blockIdx.x) * chunk;
   const int nce = static_cast<int>(nel - cbeg < chunk ? nel - cbeg : chunk);
@@ -66,9 +70,10 @@ __global__ __launch_bounds__(256, 1) void k_h1_backward(
   for (int g = 0; g < ngr; ++g) {
     int tid = threadIdx.x;
     __asm__ volatile("" : "+v"(tid));
+    __builtin_assume(tid >= 0 && tid < TH);
     const int ne = nce - g * E < E ? nce - g * E : E;
     const int64_t e0 = cbeg + static_cast<int64_t>(g) * E;  // elements e0 .. e0+ne-1
-    lds_barrier();
+    __syncthreads();
     for (int i = tid; i < ne * NLOC; i += TH) {
       const int el = i / NLOC;
       const int32_t v = elem_dofs[(e0 + el) * NLOC + (i - el * NLOC)];
@@ -82,66 +87,93 @@ __global__ __launch_bounds__(256, 1) void k_h1_backward(
       const uint32_t* row = reinterpret_cast<const uint32_t*>(tables + elem_class[e0 + el] * tab_stride);
       sTabW[i] = row[i - el * TWE];
     }
-    lds_barrier();
+    // CSR position of every compact entry of the group (row pointer + rank)
+    int32_t gpos[NJ];
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+      const int i = tid + j * TH;
+      const int i2 = i < ne * NENT ? i : 0;
+      const int el = i2 / NENT;
+      gpos[j] = static_cast<int32_t>(ent_row[i2 - el * NENT]);  // local row, completed below
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+      const int i = tid + j * TH;
+      const int i2 = i < ne * NENT ? i : 0;
+      const int el = i2 / NENT;
+      gpos[j] = sRp[el * NLOC + gpos[j]] + (sTab[el * NENTP + (i2 - el * NENT)] & kRankMask);
+    }
 
-    if (tid < ne * NSUB) {
-      const int el = tid / NSUB;
-      const int s = tid - el * NSUB;
-      const int64_t e = e0 + el;
-      const int si = s % P, sj = (s / P) % P, sk = s / (P * P);
-      auto edges = [&](R (&ex)[2][2][3], R (&ey)[2][2][3], R (&ez)[2][2][3]) {
-        double X[8][3];
+    const bool act = tid < ne * NSUB;
+    const int el = act ? tid / NSUB : 0;
+    const int s = act ? tid - el * NSUB : 0;
+    const int64_t e = e0 + el;
+    const int si = s % P, sj = (s / P) % P, sk = s / (P * P);
+    auto edges = [&](R (&ex)[2][2][3], R (&ey)[2][2][3], R (&ez)[2][2][3]) {
+      double X[8][3];
 #pragma unroll
-        for (int v = 0; v < 8; ++v) {
-          const int lv = (si + (v & 1)) + Q * ((sj + ((v >> 1) & 1)) + Q * (sk + (v >> 2)));
+      for (int v = 0; v < 8; ++v) {
+        const int lv = (si + (v & 1)) + Q * ((sj + ((v >> 1) & 1)) + Q * (sk + (v >> 2)));
 #pragma unroll
-          for (int d = 0; d < 3; ++d) X[v][d] = sX[3 * (el * NLOC + lv) + d];
-        }
-        h1_edges<R>(X, ex, ey, ez);
-      };
-      R Kt[36];
-      {
-        R ex[2][2][3], ey[2][2][3], ez[2][2][3];
-        edges(ex, ey, ez);
-        H1Factors<R> F;
-        (void)h1_factors<R>(ex, ey, ez, R(1), R(0), F);
-#pragma unroll
-        for (int u = 0; u < 8; ++u)
-#pragma unroll
-          for (int v = u; v < 8; ++v) Kt[pair_index(u, v)] = h1_entry<R>(F, u, v);
+        for (int d = 0; d < 3; ++d) X[v][d] = sX[3 * (el * NLOC + lv) + d];
       }
-      // CSR positions of the 64 ordered corner pairs, kept in LDS (lane-major)
+      h1_edges<R>(X, ex, ey, ez);
+    };
+    R Kt[36], Wk[36], Wm[36];
+#pragma unroll
+    for (int i = 0; i < 36; ++i) Kt[i] = Wk[i] = Wm[i] = R(0);
+    if (act) {
+      R ex[2][2][3], ey[2][2][3], ez[2][2][3];
+      edges(ex, ey, ez);
+      H1Factors<R> F;
+      (void)h1_factors<R>(ex, ey, ez, R(1), R(0), F);
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+#pragma unroll
+        for (int v = u; v < 8; ++v) Kt[pair_index(u, v)] = h1_entry<R>(F, u, v);
+      // compact index of the 64 ordered corner pairs inside the element's table
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         const int x = si + (u & 1), y = sj + ((u >> 1) & 1), z = sk + (u >> 2);
-        const int lu = x + Q * (y + Q * z);
-        const int32_t rb = sRp[el * NLOC + lu];
 #pragma unroll
-        for (int v = 0; v < 8; ++v) {
-          const int k = compact_index<P>(x, y, z, (v & 1) - (u & 1), ((v >> 1) & 1) - ((u >> 1) & 1),
-                                         (v >> 2) - (u >> 2));
-          sPos[(u * 8 + v) * TH + tid] = rb + (sTab[el * NENTP + k] & kRankMask);
-        }
+        for (int v = 0; v < 8; ++v)
+          sK[(u * 8 + v) * TH + tid] = static_cast<uint16_t>(compact_index<P>(
+              x, y, z, (v & 1) - (u & 1), ((v >> 1) & 1) - ((u >> 1) & 1), (v >> 2) - (u >> 2)));
       }
-      R Wk[36], Wm[36];
+    }
+    for (int b = 0; b < batch; ++b) {
+      const T* gb = gvals + static_cast<int64_t>(b) * nnz;
+      // the group's cotangent entries in compact (row-contiguous) order
+      T gv[NJ];
 #pragma unroll
-      for (int i = 0; i < 36; ++i) Wk[i] = Wm[i] = R(0);
-      for (int b = 0; b < batch; ++b) {
-        const T* gb = gvals + static_cast<int64_t>(b) * nnz;
+      for (int j = 0; j < NJ; ++j) gv[j] = gb[gpos[j]];
+      __syncthreads();  // the previous entry of the batch has been consumed
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) {
+        const int i = tid + j * TH;
+        if (i < ne * NENT) sG[i] = static_cast<double>(gv[j]);
+      }
+      __syncthreads();
+      if (act) {
         const R kb = static_cast<R>(kappa[(static_cast<int64_t>(b) * nel + e) * NSUB + s]);
+        const double* ge = sG + el * NENT;
         R gk = R(0);
         // ordered pairs (u, v) and (v, u) both feed the unique entry {u, v}
 #pragma unroll
         for (int u = 0; u < 8; ++u)
 #pragma unroll
           for (int v = 0; v < 8; ++v) {
-            const R w = static_cast<R>(gb[sPos[(u * 8 + v) * TH + tid]]);
+            const R w = static_cast<R>(ge[sK[(u * 8 + v) * TH + tid]]);
             gk += Kt[pair_index(u, v)] * w;
             Wk[pair_index(u, v)] += kb * w;
             Wm[pair_index(u, v)] += w;
           }
         gkappa[(static_cast<int64_t>(b) * nel + e) * NSUB + s] = static_cast<T>(gk);
       }
+    }
+    __syncthreads();  // sG is reused for the corner adjoints
+    if (act) {
       R ex[2][2][3], ey[2][2][3], ez[2][2][3];
       edges(ex, ey, ez);
       R gx[2][2][3], gy[2][2][3], gz[2][2][3];
@@ -159,23 +191,23 @@ __global__ __launch_bounds__(256, 1) void k_h1_backward(
         }
       }
     }
-    lds_barrier();
+    __syncthreads();
     // per element vertex: sum its <= 8 subelement corners in a fixed order
     for (int i = tid; i < ne * NLOC; i += TH) {
-      const int el = i / NLOC;
-      const int l = i - el * NLOC;
+      const int el2 = i / NLOC;
+      const int l = i - el2 * NLOC;
       const int x = l % Q, y = (l / Q) % Q, z = l / (Q * Q);
       double acc[3] = {0.0, 0.0, 0.0};
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         const int sx = x - (u & 1), sy = y - ((u >> 1) & 1), sz = z - (u >> 2);
         if (sx >= 0 && sx < P && sy >= 0 && sy < P && sz >= 0 && sz < P) {
-          const int s = sx + P * (sy + P * sz);
+          const int s2 = sx + P * (sy + P * sz);
 #pragma unroll
-          for (int d = 0; d < 3; ++d) acc[d] += sXb[el * 24 * NSUB + (u * 3 + d) * NSUB + s];
+          for (int d = 0; d < 3; ++d) acc[d] += sXb[el2 * 24 * NSUB + (u * 3 + d) * NSUB + s2];
         }
       }
-      double* w = ework + ((e0 + el) * NLOC + l) * 3;
+      double* w = ework + ((e0 + el2) * NLOC + l) * 3;
       w[0] = acc[0];
       w[1] = acc[1];
       w[2] = acc[2];
@@ -228,7 +260,8 @@ static int launch_bw(const lor_sched* sched, int batch, const int32_t* elem_dofs
   double* ework = static_cast<double*>(workspace);
   k_h1_backward<P, T, R><<<static_cast<unsigned>(ceil_div(nel, chunk)), C::THREADS, 0, st>>>(
       nel, chunk, elem_dofs, coords, static_cast<const T*>(kappa), static_cast<T>(beta), row_ptr, tab,
-      dev_at<int32_t>(sched, sched->off_class), sched->tab_stride, batch, sched->nnz, static_cast<const T*>(gvals), static_cast<T*>(gkappa), ework);
+      dev_at<int32_t>(sched, sched->off_class), sched->tab_stride, dev_at<uint16_t>(sched, sched->off_ent_row),
+      batch, sched->nnz, static_cast<const T*>(gvals), static_cast<T*>(gkappa), ework);
   LOR_LAUNCHED("k_h1_backward");
   k_gather_vertices<<<static_cast<unsigned>(ceil_div(sched->nrows, 256)), 256, 0, st>>>(
       dev_at<int32_t>(sched, sched->off_inc_ptr), dev_at<int32_t>(sched, sched->off_inc_list), sched->nrows, ework,
