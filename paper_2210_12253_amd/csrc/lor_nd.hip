@@ -32,18 +32,28 @@ struct NDCfg {
   static constexpr int NENTP = (NENT + 15) / 16 * 16;
   static constexpr int THREADS = 256;
   static constexpr int PER_EL = NSUB * 78 * static_cast<int>(sizeof(R)) + NENTP + NLOCV * 24 + NLOCE * 5;
-  static constexpr int BUDGET = 140 * 1024;
+  // The kernel is latency bound (few elements per colour, short phases
+  // between barriers), so small groups and several resident workgroups per
+  // CU beat one large group per CU.  FP64 keeps 256 VGPRs per lane (two
+  // workgroups per CU) because the subelement integration spills below
+  // that; FP32 runs four workgroups per CU.
+  static constexpr bool F64 = sizeof(R) == 8;
+  static constexpr int BUDGET = F64 ? 50 * 1024 : 30 * 1024;  // LDS for the per-element buffers
   static constexpr int E0 = THREADS / NSUB < 64 ? THREADS / NSUB : 64;
   static constexpr int E1 = BUDGET / PER_EL;
   static constexpr int E = (E0 < E1 ? E0 : E1) > 0 ? (E0 < E1 ? E0 : E1) : 1;
   static constexpr int TWE = NENTP / 4;
-  static constexpr int CH = 16;  // phase-2 entries per lane handled together
+  static constexpr int CH = 8;  // phase-2 entries per lane handled together
   static constexpr int MAXCHUNK = 256;
+  static constexpr int LDS = E * PER_EL + 2 * MAXCHUNK * 4 + 256;
+  static constexpr int WPC0 = F64 ? 2 : 4;
+  static constexpr int WPC1 = 160 * 1024 / LDS;
+  static constexpr int WPC = (WPC0 < WPC1 ? WPC0 : WPC1) > 0 ? (WPC0 < WPC1 ? WPC0 : WPC1) : 1;  // workgroups per CU
   static_assert(E * NSUB <= THREADS, "one subelement per lane");
 };
 
 template <int P, typename T, typename R>
-__global__ __launch_bounds__(256) void k_nd_assemble(
+__global__ __launch_bounds__(256, (NDCfg<P, R>::WPC)) void k_nd_assemble(
     const int32_t* __restrict__ order, const int32_t* __restrict__ order_class, int32_t ncol, int32_t chunk,
     const int32_t* __restrict__ elem_dofs,
     const int32_t* __restrict__ elem_edges, const double* __restrict__ coords, const T* __restrict__ kappa, T beta,
@@ -240,7 +250,7 @@ static int launch_nd(const lor_sched* sched, int batch, const int32_t* elem_dofs
   const uint16_t* ent_row = dev_at<uint16_t>(sched, sched->off_ent_row);
   const int32_t* ent_col = dev_at<int32_t>(sched, sched->off_st_col);
   const uint64_t* recipe = dev_at<uint64_t>(sched, sched->off_recipe);
-  const int wgs = num_cus_nd();
+  const int wgs = C::WPC * num_cus_nd();
   for (int c = 0; c < sched->ncolors; ++c) {
     const int32_t n = sched->color_ptr[c + 1] - sched->color_ptr[c];
     if (n <= 0) continue;
