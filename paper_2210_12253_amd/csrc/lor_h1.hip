@@ -50,6 +50,22 @@ struct H1Cfg {
   static_assert(NJ <= 64, "phase-3 mask");
 };
 
+// Resident workgroups per CU: as many as the LDS of one workgroup allows, up
+// to two in FP64 (the integration needs ~250 VGPRs per lane) and three in
+// FP32 (168 VGPRs per lane; the spills this costs are cheaper than the
+// latency a third workgroup hides).
+template <int P, typename R>
+struct H1Occ {
+  using C = H1Cfg<P>;
+  static constexpr int SUBW = C::E * C::NSUB * 36;
+  static constexpr int STGW = C::E * C::NENT;
+  static constexpr int LDS = C::E * C::NLOC * 28 + C::E * C::NENTP +
+                             (SUBW > STGW ? SUBW : STGW) * static_cast<int>(sizeof(R)) + 2 * C::MAXCHUNK * 4;
+  static constexpr int WANT = sizeof(R) == 8 ? 2 : 3;
+  static constexpr int FIT = 160 * 1024 / LDS;
+  static constexpr int WPC = WANT < FIT ? WANT : (FIT > 0 ? FIT : 1);
+};
+
 // number of stencil offsets along one axis at lattice coordinate t, and the
 // prefix sum of that count over coordinates < t
 template <int P>
@@ -77,7 +93,7 @@ __device__ __forceinline__ bool h1_fp64_fallback(const double (&X)[8][3], double
 }
 
 template <int P, typename T, typename R>
-__global__ __launch_bounds__(256, 2) void k_h1_assemble(
+__global__ __launch_bounds__(256, (H1Occ<P, R>::WPC)) void k_h1_assemble(
     const int32_t* __restrict__ order, const int32_t* __restrict__ order_class, int32_t ncol, int32_t chunk,
     const int32_t* __restrict__ elem_dofs,
     const double* __restrict__ coords, const T* __restrict__ kappa, T beta, const int32_t* __restrict__ row_ptr,
@@ -388,7 +404,7 @@ static int launch_h1(const lor_sched* sched, int batch, const int32_t* elem_dofs
   const int32_t* ocls = dev_at<int32_t>(sched, sched->off_order_class);
   const uint8_t* tab = dev_at<uint8_t>(sched, sched->off_tables);
   const uint16_t* ent_row = dev_at<uint16_t>(sched, sched->off_ent_row);
-  const int wgs = 2 * num_cus();  // two resident workgroups per CU
+  const int wgs = H1Occ<P, R>::WPC * num_cus();  // resident workgroups
   for (int c = 0; c < sched->ncolors; ++c) {
     const int32_t n = sched->color_ptr[c + 1] - sched->color_ptr[c];
     if (n <= 0) continue;
