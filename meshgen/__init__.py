@@ -44,6 +44,9 @@ __all__ = [
     "permute_elements",
     "reorient_elements",
     "flip_edge_signs",
+    "boundary_vertices",
+    "boundary_edges",
+    "random_dofs",
     "CONFIGS",
     "config_mesh",
 ]
@@ -341,6 +344,48 @@ def flip_edge_signs(elem_edges: np.ndarray, nedges: int, seed: int):
     gid = np.where(neg, -1 - old, old)
     sg = np.where(neg, -1, 1) * s[gid]
     return np.where(sg > 0, gid, -1 - gid).astype(np.int32), s
+
+
+# ---------------------------------------------------------------- essential dofs
+
+def boundary_vertices(n: int, p: int) -> np.ndarray:
+    """Ids (ascending, int32) of the lattice vertices on the boundary of the
+    cube: X, Y or Z equal to 0 or M = n*p."""
+    N = n * p + 1
+    g = np.arange(N ** 3, dtype=np.int64)
+    X, Y, Z = g % N, (g // N) % N, g // (N * N)
+    on = (X == 0) | (X == N - 1) | (Y == 0) | (Y == N - 1) | (Z == 0) | (Z == N - 1)
+    return g[on].astype(np.int32)
+
+
+def boundary_edges(n: int, p: int) -> np.ndarray:
+    """Ids (ascending, int32) of the edges lying in the boundary of the cube
+    (tangential edges, the essential dofs of H(curl)): an x-edge at (X, Y, Z)
+    lies in the boundary iff Y or Z is 0 or M, and cyclically."""
+    M = n * p
+    N = M + 1
+    out = []
+    a = np.arange(M * N * N, dtype=np.int64)
+    # x-edges X + M*(Y + N*Z)
+    Y, Z = (a // M) % N, a // (M * N)
+    out.append(a[(Y == 0) | (Y == M) | (Z == 0) | (Z == M)])
+    # y-edges M*N^2 + X + N*(Y + M*Z)
+    X, Z = a % N, a // (N * M)
+    out.append(M * N * N + a[(X == 0) | (X == M) | (Z == 0) | (Z == M)])
+    # z-edges 2*M*N^2 + X + N*(Y + N*Z)
+    X, Y = a % N, (a // N) % N
+    out.append(2 * M * N * N + a[(X == 0) | (X == M) | (Y == 0) | (Y == M)])
+    return np.concatenate(out).astype(np.int32)
+
+
+def random_dofs(ndofs: int, count: int, seed: int, duplicates: bool = True) -> np.ndarray:
+    """`count` random dof ids in [0, ndofs) (with repeats if duplicates), in
+    random order, int32.  Draw order: numpy default_rng(seed), then integers or
+    a permutation."""
+    rng = np.random.default_rng(seed)
+    if duplicates:
+        return rng.integers(0, ndofs, size=count).astype(np.int32)
+    return rng.permutation(ndofs)[:count].astype(np.int32)
 
 
 # ---------------------------------------------------------------- named workloads

@@ -55,6 +55,7 @@ __all__ = [
     "nd_matrix",
     "nd_rows",
     "discrete_gradient",
+    "eliminate_bc",
     "csr_to_dense",
     "csr_to_scipy",
 ]
@@ -421,6 +422,56 @@ def discrete_gradient(elem_dofs, elem_edges, p: int, nedges: int):
         raise ValueError("edge map does not cover every edge")
     row_ptr = torch.arange(0, 2 * nedges + 1, 2, dtype=torch.int64)
     return row_ptr, J.reshape(-1), A.reshape(-1)
+
+
+# ------------------------------------------------- boundary-condition elimination
+
+DIAG_POLICIES = ("one", "keep", "zero")
+
+
+def eliminate_bc(row_ptr, col_idx, values, ess, diag_policy: str = "one", rows=None):
+    """Step A4 of the processor-local assembly (Section 3, Step S1.2), one
+    process: the rows and the columns of the essential degrees of freedom are
+    eliminated, i.e. every entry (r, c) with r or c essential becomes 0, except
+    the diagonal entry (i, i) of an essential i, which becomes 1 ("one", the
+    usual choice the paper names), keeps its value ("keep") or becomes 0
+    ("zero").  The essential set is held as a Boolean marker over the
+    degrees of freedom, as in the paper.
+
+    row_ptr, col_idx: CSR arrays; values [nnz] or [batch, nnz]; ess: indices of
+    the essential dofs (duplicates allowed, each must lie in [0, n)); rows: the
+    global row id of each CSR row, for a block of sampled rows (default
+    0..n-1).  The marker has n = len(row_ptr) - 1 entries, or, with rows given,
+    one more than the largest row, column or essential index.
+    Returns (eliminated values, marker)."""
+    row_ptr = torch.as_tensor(row_ptr).to(torch.int64)
+    col_idx = torch.as_tensor(col_idx).to(torch.int64)
+    values = torch.as_tensor(values)
+    ess = torch.as_tensor(ess).to(torch.int64).reshape(-1)
+    if diag_policy not in DIAG_POLICIES:
+        raise ValueError(f"diag_policy must be one of {DIAG_POLICIES}")
+    nloc = row_ptr.numel() - 1
+    if rows is None:
+        rows = torch.arange(nloc)
+        n = nloc
+    else:
+        rows = torch.as_tensor(rows).to(torch.int64)
+        n = int(max(rows.max().item() if rows.numel() else -1, col_idx.max().item() if col_idx.numel() else -1,
+                    ess.max().item() if ess.numel() else -1)) + 1
+    if ess.numel() and (int(ess.min()) < 0 or int(ess.max()) >= n):
+        raise IndexError("essential dof outside [0, n)")
+    marker = torch.zeros(n, dtype=torch.bool)
+    marker[ess] = True
+    r = torch.repeat_interleave(rows, row_ptr[1:] - row_ptr[:-1])
+    hit = marker[r] | marker[col_idx]
+    on_diag = r == col_idx
+    out = values.clone()
+    out[..., hit & ~on_diag] = 0
+    if diag_policy == "one":
+        out[..., hit & on_diag] = 1
+    elif diag_policy == "zero":
+        out[..., hit & on_diag] = 0
+    return out, marker
 
 
 # ---------------------------------------------------------------- utilities

@@ -482,3 +482,85 @@ def test_inverted_subelement_raises():
     kap = torch.ones(1, 8, dtype=torch.float64)
     with pytest.raises(ValueError):
         orc.h1_matrix(X, m["elem_dofs"], 2, kap, 1.0)
+
+
+# -------------------------------------------- boundary-condition elimination (A4)
+
+def _elim_case(space):
+    if space == "h1":
+        m = meshgen.cartesian_mesh(2, 2, 0.1)
+        kap = meshgen.kappa_field(m["nel"], 2, 1.0, seed=3)
+        rp, ci, v = orc.h1_matrix(m["coords"], m["elem_dofs"], 2, kap, 1.0)
+        return rp, ci, v, m["ndofs"]
+    m = meshgen.cartesian_mesh(2, 2, 0.1)
+    ee, ned = meshgen.nd_edge_map(2, 2)
+    kap = meshgen.kappa_field(m["nel"], 2, 1.0, seed=4)
+    rp, ci, v = orc.nd_matrix(m["coords"], m["elem_dofs"], ee, 2, kap, 0.7, ned)
+    return rp, ci, v, ned
+
+
+@pytest.mark.parametrize("space", ["h1", "nd"])
+@pytest.mark.parametrize("policy", ["one", "keep", "zero"])
+def test_elimination_is_a_projection(space, policy):
+    """With P = diag(1 - marker), eliminating rows and columns is
+    P A P + (I - P) D, D = I ("one"), diag(A) ("keep") or 0 ("zero"): checked
+    with dense matrix products instead of the oracle's entrywise rule, on a
+    random essential set with repeats."""
+    rp, ci, v, n = _elim_case(space)
+    ess = meshgen.random_dofs(n, n // 3, seed=5)
+    out, marker = orc.eliminate_bc(rp, ci, v, ess, policy)
+    mk = np.zeros(n)
+    mk[ess] = 1.0
+    assert np.array_equal(marker.numpy(), mk > 0)
+    A = dense(rp, ci, v)
+    P = np.diag(1.0 - mk)
+    D = {"one": np.eye(n), "keep": np.diag(np.diag(A)), "zero": np.zeros((n, n))}[policy]
+    assert np.array_equal(dense(rp, ci, out), P @ A @ P + (np.eye(n) - P) @ D)
+    # symmetric in, symmetric out (to the rounding asymmetry of A itself);
+    # the pattern itself is kept (zeros stay stored)
+    E = dense(rp, ci, out)
+    assert np.all(np.abs(E - E.T) <= np.abs(A - A.T))
+    assert out.shape == v.shape
+
+
+def test_elimination_dirichlet_solve():
+    """The eliminated system with right-hand side [f - A g on free rows; g on
+    essential rows] has the solution of the reduced problem A_ff u_f =
+    f_f - A_fe g_e, u_e = g_e (textbook Dirichlet elimination)."""
+    rp, ci, v, n = _elim_case("h1")
+    bnd = meshgen.boundary_vertices(2, 2)
+    out, _ = orc.eliminate_bc(rp, ci, v, bnd, "one")
+    A = dense(rp, ci, v)
+    rng = np.random.default_rng(7)
+    f = rng.standard_normal(n)
+    g = np.zeros(n)
+    g[bnd] = rng.standard_normal(bnd.size)
+    free = np.setdiff1d(np.arange(n), bnd)
+    b = f - A @ g
+    b[bnd] = g[bnd]
+    u = np.linalg.solve(dense(rp, ci, out), b)
+    uf = np.linalg.solve(A[np.ix_(free, free)], f[free] - A[np.ix_(free, bnd)] @ g[bnd])
+    assert np.abs(u[bnd] - g[bnd]).max() <= 1e-13
+    assert np.abs(u[free] - uf).max() <= 1e-10 * np.abs(uf).max()
+
+
+def test_elimination_edge_cases():
+    rp, ci, v, n = _elim_case("h1")
+    out, marker = orc.eliminate_bc(rp, ci, v, np.zeros(0, np.int32))
+    assert torch.equal(out, v) and not bool(marker.any())
+    out, _ = orc.eliminate_bc(rp, ci, v, np.arange(n))
+    assert np.array_equal(dense(rp, ci, out), np.eye(n))
+    vb = torch.stack([v, 2 * v, -v])  # batched values: each batch entry on its own
+    ess = meshgen.random_dofs(n, 20, seed=9)
+    ob, _ = orc.eliminate_bc(rp, ci, vb, ess, "keep")
+    for b in range(3):
+        assert torch.equal(ob[b], orc.eliminate_bc(rp, ci, vb[b], ess, "keep")[0])
+    # a block of sampled rows gives the rows of the whole result
+    rows = torch.tensor([3, 11, 20])
+    sub_rp = torch.cat([torch.zeros(1, dtype=torch.int64), torch.cumsum(rp[rows + 1] - rp[rows], 0)])
+    idx = torch.cat([torch.arange(rp[r], rp[r + 1]) for r in rows.tolist()])
+    full, _ = orc.eliminate_bc(rp, ci, v, ess, "one")
+    part, _ = orc.eliminate_bc(sub_rp, ci[idx], v[idx], ess, "one", rows=rows)
+    assert torch.equal(part, full[idx])
+    with pytest.raises(IndexError):
+        orc.eliminate_bc(rp, ci, v, [n])
