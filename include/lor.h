@@ -57,6 +57,8 @@ typedef enum {
 
 typedef enum { LOR_H1 = 0, LOR_ND = 1 } lor_space;
 typedef enum { LOR_F64 = 0, LOR_F32 = 1 } lor_dtype;
+/* Diagonal entry of an eliminated row (lor_eliminate_bc). */
+typedef enum { LOR_DIAG_ONE = 0, LOR_DIAG_KEEP = 1, LOR_DIAG_ZERO = 2 } lor_diag_policy;
 
 /* Highest polynomial degree handled (the whole macro element is staged in LDS). */
 #define LOR_MAX_P 6
@@ -206,6 +208,34 @@ int lor_assemble_backward(int p, int64_t nel, int64_t ndofs, int batch, const in
                           const int32_t* row_ptr, const lor_sched* sched, const void* grad_values,
                           void* grad_kappa, double* grad_coords, void* workspace, int dtype,
                           void* stream);
+
+/*
+ * lor_eliminate_bc -- elimination of essential boundary conditions from an
+ * assembled matrix (Section 3, Step S1.2, step A4), on one device: every entry
+ * in the row or the column of an essential dof becomes 0, except the diagonal
+ * entry of an essential dof, which becomes 1 (LOR_DIAG_ONE, the usual choice),
+ * keeps its value (LOR_DIAG_KEEP) or becomes 0 (LOR_DIAG_ZERO).  In place.
+ *
+ *   nrows, nnz  matrix size; row_ptr [nrows+1], col_idx [nnz] int32: a CSR
+ *               pattern with columns sorted ascending within each row and
+ *               structurally symmetric (every (i, j) has a (j, i)), as
+ *               lor_pattern writes it.  Column i is found through row i.
+ *   values      [batch][nnz] in `dtype` (LOR_F64 or LOR_F32), modified in place.
+ *   ess_dofs    [ness] int32 essential dofs, any order, repeats allowed.
+ *   marker      [nrows] uint8, written: 1 for an essential dof, else 0 (the
+ *               marker array of the paper, e.g. for a right-hand side).
+ *   diag        NULL or device int32[2]: [0] += essential entries outside
+ *               [0, nrows) (ignored); [1] += column entries (c, i) not found
+ *               because the pattern is not structurally symmetric or a column
+ *               index is out of range.  The caller zeroes it.
+ * Asynchronous on `stream`; writes are deterministic (each entry has one
+ * writer).  Errors: LOR_EINVAL (bad sizes, NULL pointers, unknown policy),
+ * LOR_EOVERFLOW (nrows, nnz or ness >= 2^31).
+ */
+int lor_eliminate_bc(int64_t nrows, int64_t nnz, int batch, const int32_t* row_ptr,
+                     const int32_t* col_idx, void* values, int dtype, int64_t ness,
+                     const int32_t* ess_dofs, uint8_t* marker, int diag_policy, int32_t* diag,
+                     void* stream);
 
 /* Bytes of the `workspace` argument of lor_assemble_backward. */
 size_t lor_backward_workspace(int p, int64_t nel);

@@ -4,6 +4,9 @@ The compute path is the HIP library liblor.so (C ABI in include/lor.h); this
 package is its Python binding.
 """
 from .lor import (  # noqa: F401
+    LOR_DIAG_KEEP,
+    LOR_DIAG_ONE,
+    LOR_DIAG_ZERO,
     LOR_F32,
     LOR_F64,
     LOR_H1,
@@ -15,5 +18,6 @@ from .lor import (  # noqa: F401
     lor_assemble_backward,
     lor_assemble_h1,
     lor_assemble_nd,
+    lor_eliminate_bc,
     lor_pattern,
 )

@@ -21,6 +21,8 @@ LOR_F64, LOR_F32 = 0, 1
 LOR_MAX_P = 6
 LOR_MAX_COLORS = 64
 LOR_FP64_FALLBACK = 0x1
+LOR_DIAG_ONE, LOR_DIAG_KEEP, LOR_DIAG_ZERO = 0, 1, 2
+_DIAG_POLICY = {"one": LOR_DIAG_ONE, "keep": LOR_DIAG_KEEP, "zero": LOR_DIAG_ZERO}
 
 ABI_SYMBOLS = (
     "lor_pattern",
@@ -28,6 +30,7 @@ ABI_SYMBOLS = (
     "lor_assemble_nd",
     "lor_assemble_backward",
     "lor_backward_workspace",
+    "lor_eliminate_bc",
     "lor_sched_bytes",
     "lor_last_error",
     "lor_abi_version",
@@ -97,6 +100,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.lor_assemble_backward.argtypes = [i32, i64, i64, i32, vp, vp, vp, f64, vp, ctypes.POINTER(LorSched), vp, vp,
                                           vp, vp, i32, vp]
     lib.lor_assemble_backward.restype = i32
+    lib.lor_eliminate_bc.argtypes = [i64, i64, i32, vp, vp, vp, i32, i64, vp, vp, i32, vp, vp]
+    lib.lor_eliminate_bc.restype = i32
     lib.lor_backward_workspace.argtypes = [i32, i64]
     lib.lor_backward_workspace.restype = sz
     lib.lor_sched_bytes.argtypes = []
@@ -244,6 +249,29 @@ def lor_assemble_backward(pat: Pattern, elem_dofs, coords, kappa, beta: float, g
                                      _ptr(pat.row_ptr), ctypes.byref(pat.sched), _ptr(gv), _ptr(gk), _ptr(gx),
                                      _ptr(workspace), _dtype_code(dtype), _stream()))
     return gk, gx
+
+
+def lor_eliminate_bc(pat: Pattern, values: torch.Tensor, ess_dofs, diag_policy: str = "one",
+                     marker: torch.Tensor | None = None, diag: torch.Tensor | None = None) -> torch.Tensor:
+    """Eliminate the rows and columns of the essential dofs from `values`
+    ([nnz] or [batch, nnz], FP64 or FP32, on the pattern's device) in place;
+    returns the uint8 marker [nrows]."""
+    lib = load_library()
+    dev = pat.row_ptr.device
+    if values.device != dev or not values.is_contiguous():
+        raise ValueError("values must be a contiguous tensor on the pattern's device (modified in place)")
+    if values.shape[-1] != pat.nnz or values.dim() not in (1, 2):
+        raise ValueError("values must have shape [nnz] or [batch, nnz]")
+    if diag_policy not in _DIAG_POLICY:
+        raise ValueError(f"diag_policy must be one of {tuple(_DIAG_POLICY)}")
+    ess = _dev_tensor(ess_dofs, torch.int32, "ess_dofs", dev).reshape(-1)
+    batch = values.shape[0] if values.dim() == 2 else 1
+    if marker is None:
+        marker = torch.empty(pat.nrows, dtype=torch.uint8, device=dev)
+    _check(lib.lor_eliminate_bc(pat.nrows, pat.nnz, batch, _ptr(pat.row_ptr), _ptr(pat.col_idx), _ptr(values),
+                                _dtype_code(values.dtype), ess.numel(), _ptr(ess), _ptr(marker),
+                                _DIAG_POLICY[diag_policy], _ptr(diag), _stream()))
+    return marker
 
 
 class LorH1(torch.autograd.Function):

@@ -90,3 +90,25 @@ def test_backward_workspace_size():
     lib = pkg.load_library()
     assert lib.lor_backward_workspace(4, 4096) == 8 * 3 * 4096 * 125
     assert lib.lor_backward_workspace(0, 10) == 0
+
+
+def test_eliminate_argument_errors():
+    lib = pkg.load_library()
+    ok = (100, 500, 1, FAKE, FAKE, FAKE, L.LOR_F64, 10, FAKE, FAKE, L.LOR_DIAG_ONE, None, None)
+
+    def call(**kw):
+        names = ("nrows", "nnz", "batch", "rp", "ci", "v", "dtype", "ness", "ess", "marker", "policy", "diag", "st")
+        a = dict(zip(names, ok))
+        a.update(kw)
+        return lib.lor_eliminate_bc(*a.values())
+
+    assert call(nrows=-1) == L.LOR_EINVAL
+    assert call(nnz=1 << 31) == L.LOR_EOVERFLOW
+    assert call(batch=0) == L.LOR_EINVAL
+    assert call(dtype=7) == L.LOR_EINVAL
+    assert call(policy=3) == L.LOR_EINVAL and "diag_policy" in _err(lib)
+    assert call(marker=None) == L.LOR_EINVAL
+    assert call(ess=None) == L.LOR_EINVAL
+    assert call(v=None) == L.LOR_EINVAL
+    # nothing to do: no launch, OK
+    assert call(nrows=0, nnz=0, ness=0) == L.LOR_OK
