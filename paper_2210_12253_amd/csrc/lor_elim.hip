@@ -2,16 +2,16 @@
 // (Section 3, Step S1.2, step A4), on one device.
 //
 // The essential set is first written as a byte marker over the degrees of
-// freedom (the paper's marker array).  Then one half-wave per essential dof i
-// walks row i: every entry becomes 0 except the diagonal (1, kept, or 0), and
+// freedom (the paper's marker array).  Then a group of 16 lanes per essential
+// dof i walks row i (LOR rows have at most 33 entries): every entry becomes 0 except the diagonal (1, kept, or 0), and
 // for every column c != i that is not itself essential, the transposed entry
 // (c, i) is located by binary search in row c (columns are sorted) and set to
 // 0.  The LOR pattern is structurally symmetric, so column i is reached
 // through row i and the elimination is threaded over the essential dofs only,
 // as the paper does for the rows and columns of the diagonal block.  Entries
-// of a row that is itself essential are left to that row's own half-wave, so
-// every entry is written by one half-wave (two only if the essential list
-// repeats a dof, and then with the same value): the result is deterministic.
+// of a row that is itself essential are left to that row's own lane group, so
+// every entry is written by one group (two only if the essential list repeats
+// a dof, and then with the same value): the result is deterministic.
 #include <algorithm>
 
 #include "lor_common.hpp"
@@ -19,7 +19,7 @@
 namespace lor {
 
 constexpr int kElimThreads = 256;
-constexpr int kElimGroup = 32;  // lanes per essential row
+constexpr int kElimGroup = 16;  // lanes per essential row
 
 __global__ __launch_bounds__(kElimThreads) void k_elim_clear(uint8_t* __restrict__ marker, int64_t n) {
   const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
@@ -66,7 +66,7 @@ __global__ __launch_bounds__(kElimThreads) void k_elim_rows(
       if (diag) atomicAdd(&diag[1], 1);
       continue;
     }
-    if (marker[c]) continue;  // row c is essential: its own half-wave clears (c, i)
+    if (marker[c]) continue;  // row c is essential: its own lane group clears (c, i)
     const int64_t cb = min(max(static_cast<int64_t>(row_ptr[c]), int64_t(0)), nnz);
     const int64_t ce = min(max(static_cast<int64_t>(row_ptr[c + 1]), cb), nnz);
     int64_t lo = cb, hi = ce;  // first position in row c with column >= i
