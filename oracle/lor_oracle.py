@@ -385,7 +385,11 @@ def discrete_gradient(elem_dofs, elem_edges, p: int, nedges: int):
     S1.2): row i (an edge) has I[i] = 2i, J = (first vertex, second vertex) of
     its local edge, A = (-sigma, +sigma) with sigma the orientation sign.
     Returns (row_ptr, col_idx, values) with 2 entries per row (col order as
-    defined, not sorted)."""
+    defined, not sorted).  The algorithm takes each edge from one element (its
+    element map and local index); here that is the edge's first incidence, the
+    lowest element and then the lowest local edge.  The row is the same sparse
+    vector whichever element supplies it; only the order of its two entries
+    can differ where elements are reoriented."""
     q = p + 1
     ed = torch.as_tensor(elem_dofs).to(torch.int64)
     ee = torch.as_tensor(elem_edges).to(torch.int64)
@@ -405,21 +409,15 @@ def discrete_gradient(elem_dofs, elem_edges, p: int, nedges: int):
                     n += 1
     raw = ee.reshape(-1)
     gid = torch.where(raw < 0, -1 - raw, raw)
-    sig = torch.where(raw < 0, -1.0, 1.0).to(torch.float64)
-    j0 = ed[:, v0].reshape(-1)
-    j1 = ed[:, v1].reshape(-1)
-    J = torch.zeros(nedges, 2, dtype=torch.int64)
-    A = torch.zeros(nedges, 2, dtype=torch.float64)
-    seen = torch.zeros(nedges, dtype=torch.bool)
-    # every element sharing an edge writes the same row; keep the first writer
-    order = torch.arange(gid.numel() - 1, -1, -1)
-    J[gid[order], 0] = j0[order]
-    J[gid[order], 1] = j1[order]
-    A[gid[order], 0] = -sig[order]
-    A[gid[order], 1] = sig[order]
-    seen[gid] = True
-    if not bool(seen.all()):
+    flat = torch.arange(gid.numel())
+    none = gid.numel()
+    first = torch.full((nedges,), none, dtype=torch.int64).scatter_reduce(0, gid, flat, reduce="amin")
+    if bool((first == none).any()):
         raise ValueError("edge map does not cover every edge")
+    e, l = first // nloc, first % nloc
+    sig = torch.where(raw[first] < 0, -1.0, 1.0).to(torch.float64)
+    J = torch.stack([ed[e, v0[l]], ed[e, v1[l]]], dim=1)
+    A = torch.stack([-sig, sig], dim=1)
     row_ptr = torch.arange(0, 2 * nedges + 1, 2, dtype=torch.int64)
     return row_ptr, J.reshape(-1), A.reshape(-1)
 

@@ -564,3 +564,40 @@ def test_elimination_edge_cases():
     assert torch.equal(part, full[idx])
     with pytest.raises(IndexError):
         orc.eliminate_bc(rp, ci, v, [n])
+
+
+def test_discrete_gradient_first_incidence_order():
+    """On reoriented elements with flipped edge signs, each row of the
+    discrete gradient comes from the edge's first incidence (lowest element,
+    then lowest local edge), found here by a plain loop; the row is the same
+    sparse vector as the topological definition."""
+    p = 2
+    m = meshgen.cartesian_mesh(2, p, 0.0)
+    ee, ned = meshgen.nd_edge_map(2, p)
+    m, _, ee = meshgen.reorient_elements(m, seed=3, kappa=None, elem_edges=ee)
+    ee, _ = meshgen.flip_edge_signs(ee, ned, seed=4)
+    rp, ci, v = orc.discrete_gradient(m["elem_dofs"], ee, p, ned)
+    q = p + 1
+    loc = []
+    for ax, dims in enumerate([(p, q, q), (q, p, q), (q, q, p)]):
+        for k in range(dims[2]):
+            for j in range(dims[1]):
+                for i in range(dims[0]):
+                    a = [i, j, k]
+                    b = list(a)
+                    b[ax] += 1
+                    loc.append((a[0] + q * (a[1] + q * a[2]), b[0] + q * (b[1] + q * b[2])))
+    done = set()
+    for e in range(m["nel"]):
+        for l, (v0, v1) in enumerate(loc):
+            raw = int(ee[e, l])
+            g = raw if raw >= 0 else -1 - raw
+            if g in done:
+                continue
+            done.add(g)
+            s = 1.0 if raw >= 0 else -1.0
+            assert ci[2 * g].item() == m["elem_dofs"][e, v0] and ci[2 * g + 1].item() == m["elem_dofs"][e, v1]
+            assert v[2 * g].item() == -s and v[2 * g + 1].item() == s
+    assert len(done) == ned and torch.equal(rp, torch.arange(0, 2 * ned + 1, 2))
+    G = _gradient_from_topology(m, ee, ned, p)
+    assert np.array_equal(dense(rp, ci, v, m["ndofs"]), G)
