@@ -47,6 +47,7 @@ __all__ = [
     "boundary_vertices",
     "boundary_edges",
     "random_dofs",
+    "ho_nodes",
     "CONFIGS",
     "config_mesh",
 ]
@@ -344,6 +345,15 @@ def flip_edge_signs(elem_edges: np.ndarray, nedges: int, seed: int):
     gid = np.where(neg, -1 - old, old)
     sg = np.where(neg, -1, 1) * s[gid]
     return np.where(sg > 0, gid, -1 - gid).astype(np.int32), s
+
+
+def ho_nodes(n: int, q: int, amp: float = 0.0) -> np.ndarray:
+    """Nodes of a degree-q high-order mesh of the n^3 cube as an E-vector
+    [n^3][(q+1)^3][3]: the same curved map as cartesian_mesh, evaluated at
+    each element's tensor Gauss-Lobatto points of degree q (local node
+    i + (q+1)(j + (q+1)k))."""
+    m = cartesian_mesh(n, q, amp)
+    return np.ascontiguousarray(m["coords"][m["elem_dofs"]])
 
 
 # ---------------------------------------------------------------- essential dofs

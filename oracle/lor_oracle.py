@@ -56,6 +56,9 @@ __all__ = [
     "nd_rows",
     "discrete_gradient",
     "eliminate_bc",
+    "lagrange_matrix",
+    "interp_nodes",
+    "evec_to_tvec",
     "csr_to_dense",
     "csr_to_scipy",
 ]
@@ -420,6 +423,57 @@ def discrete_gradient(elem_dofs, elem_edges, p: int, nedges: int):
     A = torch.stack([-sig, sig], dim=1)
     row_ptr = torch.arange(0, 2 * nedges + 1, 2, dtype=torch.int64)
     return row_ptr, J.reshape(-1), A.reshape(-1)
+
+
+# ------------------------------------------ auxiliary: LOR coordinate vector
+
+def lagrange_matrix(src, dst) -> torch.Tensor:
+    """B[a][i] = l_i(dst[a]), l_i the Lagrange polynomial of the points `src`
+    (l_i(src[m]) = delta_im), written as the product formula."""
+    src = [float(t) for t in src]
+    dst = [float(t) for t in dst]
+    B = torch.empty(len(dst), len(src), dtype=torch.float64)
+    for a, x in enumerate(dst):
+        for i, xi in enumerate(src):
+            v = 1.0
+            for m, xm in enumerate(src):
+                if m != i:
+                    v *= (x - xm) / (xi - xm)
+            B[a, i] = v
+    return B
+
+
+def interp_nodes(nodes, p: int, q: int) -> torch.Tensor:
+    """Coordinates of the LOR vertices of every element as an E-vector
+    (auxiliary computations of Step S1.2 and the coordinate-vector results of
+    Section 4): the high-order mesh of degree q, given by its nodes at the
+    tensor Gauss-Lobatto points of degree q, is evaluated at the tensor
+    Gauss-Lobatto lattice of degree p with the tensor-product Lagrange basis,
+    X_out[e][a + (p+1)(b + (p+1)c)] = sum_ijk l_i(x_a) l_j(x_b) l_k(x_c) X[e][i + (q+1)(j + (q+1)k)].
+    nodes [nel][(q+1)^3][ncomp] -> [nel][(p+1)^3][ncomp], float64."""
+    import meshgen  # the point sets are those that define the inputs
+    X = torch.as_tensor(nodes, dtype=torch.float64)
+    nel, _, nc = X.shape
+    B = lagrange_matrix(meshgen.gll_points(q), meshgen.gll_points(p))
+    X = X.reshape(nel, q + 1, q + 1, q + 1, nc)  # [e][k][j][i][comp]
+    out = torch.einsum("ai,bj,ck,ekjid->ecbad", B, B, B, X)
+    return out.reshape(nel, (p + 1) ** 3, nc)
+
+
+def evec_to_tvec(evec, elem_map, ndofs: int) -> torch.Tensor:
+    """E-vector -> T-vector (deduplication with the element restriction map,
+    one value per degree of freedom): every dof takes the value of its first
+    incidence, the lowest element and then the lowest local index.
+    evec [nel][nloc][ncomp], elem_map [nel][nloc] -> [ndofs][ncomp]."""
+    E = torch.as_tensor(evec, dtype=torch.float64)
+    nc = E.shape[-1]
+    g = torch.as_tensor(elem_map).to(torch.int64).reshape(-1)
+    flat = torch.arange(g.numel())
+    none = g.numel()
+    first = torch.full((ndofs,), none, dtype=torch.int64).scatter_reduce(0, g, flat, reduce="amin")
+    if bool((first == none).any()):
+        raise ValueError("element map does not cover every dof")
+    return E.reshape(-1, nc)[first]
 
 
 # ------------------------------------------------- boundary-condition elimination

@@ -601,3 +601,65 @@ def test_discrete_gradient_first_incidence_order():
     assert len(done) == ned and torch.equal(rp, torch.arange(0, 2 * ned + 1, 2))
     G = _gradient_from_topology(m, ee, ned, p)
     assert np.array_equal(dense(rp, ci, v, m["ndofs"]), G)
+
+
+# ------------------------------------------------ LOR coordinate vector (aux)
+
+def test_interp_nodes_identity_when_degrees_match():
+    """q = p: the Lagrange basis at its own nodes is the identity, exactly."""
+    X = meshgen.ho_nodes(2, 3, 0.1)
+    assert np.array_equal(orc.interp_nodes(X, 3, 3).numpy(), X)
+
+
+@pytest.mark.parametrize("q,p", [(1, 6), (2, 4), (3, 5), (2, 2)])
+def test_interp_nodes_reproduces_polynomial_maps(q, p):
+    """A map whose components are polynomials of degree <= q in each variable
+    is reproduced exactly (to rounding) at the degree-p lattice: the nodes are
+    the map at the degree-q lattice, the expected values the map at the
+    degree-p lattice, both evaluated here directly."""
+    def f(P):
+        x, y, z = P[..., 0], P[..., 1], P[..., 2]
+        d = min(q, 2)
+        return np.stack([x + 0.3 * y ** d - 0.2 * x * z, y - 0.1 * (x * y) ** (d - 1) * z + 0.05,
+                         z + 0.2 * x ** d * y - 0.1], axis=-1)
+    mq = meshgen.cartesian_mesh(2, q, 0.0)
+    mp = meshgen.cartesian_mesh(2, p, 0.0)
+    nodes = f(mq["coords"])[mq["elem_dofs"]]
+    want = f(mp["coords"])[mp["elem_dofs"]]
+    got = orc.interp_nodes(nodes, p, q).numpy()
+    assert np.abs(got - want).max() <= 1e-14
+
+
+def test_interp_nodes_trilinear_gives_the_lattice():
+    """q = 1 from the 8 corners of each element of an affine mesh gives the
+    Gauss-Lobatto lattice of the same affine mesh (the input generator's own
+    lattice), as an E-vector; deduplicated it is the vertex coordinate array."""
+    A = np.array([[1.0, 0.2, 0.0], [0.1, 0.9, 0.3], [0.0, -0.2, 1.1]])
+    t = np.array([0.3, -0.1, 2.0])
+    m1 = meshgen.affine_mesh(3, 1, A, t)
+    m6 = meshgen.affine_mesh(3, 6, A, t)
+    E = orc.interp_nodes(m1["coords"][m1["elem_dofs"]], 6, 1)
+    assert np.abs(E.numpy() - m6["coords"][m6["elem_dofs"]]).max() <= 1e-14
+    T = orc.evec_to_tvec(E, m6["elem_dofs"], m6["ndofs"])
+    assert np.abs(T.numpy() - m6["coords"]).max() <= 1e-14
+
+
+def test_evec_to_tvec_first_incidence():
+    """Every dof takes the value of its first incidence (lowest element, then
+    lowest local index), found here by a plain loop over a renumbered mesh
+    whose E-vector differs per element."""
+    m, _ = meshgen.renumber_vertices(meshgen.cartesian_mesh(2, 2, 0.0), seed=1)
+    ed = m["elem_dofs"]
+    E = np.zeros(ed.shape + (2,))
+    E[..., 0] = np.arange(ed.size).reshape(ed.shape)
+    E[..., 1] = -ed
+    T = orc.evec_to_tvec(E, ed, m["ndofs"]).numpy()
+    seen = {}
+    for e in range(ed.shape[0]):
+        for l in range(ed.shape[1]):
+            seen.setdefault(int(ed[e, l]), (e, l))
+    assert len(seen) == m["ndofs"]
+    for g, (e, l) in seen.items():
+        assert T[g, 0] == e * ed.shape[1] + l and T[g, 1] == -g
+    with pytest.raises(ValueError):
+        orc.evec_to_tvec(E, ed, m["ndofs"] + 1)
