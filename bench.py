@@ -314,6 +314,7 @@ def main():
 
     if not args.skip_extras:
         out["elimination"] = bench_elim(lor, meshgen, m, pat, v64, args, dev)
+        out["aux"] = bench_aux(lor, meshgen, pat, args, dev)
         out["backward"] = bench_backward(lor, meshgen, args, dev)
         out["nd"] = bench_nd(lor, meshgen, args, dev)
         log("fp32 pencil eigenvalues")
@@ -442,6 +443,56 @@ def bench_elim(lor, meshgen, m, pat, v64, args, dev):
         }
     except lor.LorError as e:
         return {"error": str(e)}
+
+
+def bench_aux(lor, meshgen, pat_h1, args, dev):
+    """The auxiliary data of Step S1.2: the discrete gradient of the H(curl)
+    p=3 24^3 mesh, and the LOR coordinate vector of the headline mesh (32^3,
+    p=6) from degree-2 curved mesh nodes (interpolation to an E-vector, then
+    E-vector to T-vector).  Algorithmic bytes per dof: gradient 4 (row
+    pointer of the schedule) + 4 (first incidence) + 4 (edge map) + 8 (two
+    vertex ids) + 4 + 8 + 16 (row pointer, columns, FP64 values written) =
+    48 B per edge; interpolation reads the nodes and writes the E-vector once;
+    E->T reads 4 + 4 (row pointer, first incidence) + 24 (E-vector entry) and
+    writes 24 B per dof."""
+    import torch
+
+    def rl(bytes_, ms):
+        ach = bytes_ / (ms * 1e-3) / 1e9
+        return {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+                "algorithmic_bytes": bytes_}
+    res = {}
+    try:
+        m = meshgen.config_mesh("c4_nd_p3_curved")
+        ee = torch.from_numpy(m["elem_edges"]).to(dev)
+        ed = torch.from_numpy(m["elem_dofs"]).to(dev)
+        pat = lor.lor_pattern(lor.LOR_ND, 3, ee, m["nedges"])
+        ned = m["nedges"]
+        rp = torch.empty(ned + 1, dtype=torch.int32, device=dev)
+        ci = torch.empty(2 * ned, dtype=torch.int32, device=dev)
+        v = torch.empty(2 * ned, dtype=torch.float64, device=dev)
+        ms = time_it(lambda: lor.lor_discrete_gradient(pat, ed, ee, m["ndofs"], out=(rp, ci, v)),
+                     args.steps, args.warmup)
+        res["gradient"] = {"ms": ms, "value": ned / (ms * 1e-3) / 1e9, "unit": "GDOF/s (edges)",
+                           "workload": "discrete gradient, H(curl) p=3 24^3 (1,151,064 edges), FP64",
+                           "roofline": rl(48 * ned, ms)}
+        del pat, rp, ci, v, ee, ed
+        n, p, q = 32, 6, 2
+        X = torch.from_numpy(meshgen.ho_nodes(n, q, 0.1)).to(dev)
+        E = torch.empty((n ** 3, (p + 1) ** 3, 3), dtype=torch.float64, device=dev)
+        T = torch.empty((pat_h1.nrows, 3), dtype=torch.float64, device=dev)
+        ms_i = time_it(lambda: lor.lor_interp_nodes(X, p, q, out=E), args.steps, args.warmup)
+        ms_t = time_it(lambda: lor.lor_evec_to_tvec(pat_h1, E, out=T), args.steps, args.warmup)
+        res["interp_nodes"] = {"ms": ms_i, "value": E.shape[0] * E.shape[1] / (ms_i * 1e-3) / 1e9,
+                               "unit": "GDOF/s (E-vector points)",
+                               "workload": "degree-2 curved nodes -> p=6 Gauss-Lobatto lattice, 32^3 elements",
+                               "roofline": rl(X.numel() * 8 + E.numel() * 8, ms_i)}
+        res["evec_to_tvec"] = {"ms": ms_t, "value": pat_h1.nrows / (ms_t * 1e-3) / 1e9, "unit": "GDOF/s (vertices)",
+                               "workload": "E-vector of 32^3 p=6 elements -> 7,189,057 vertex coordinates",
+                               "roofline": rl(56 * pat_h1.nrows, ms_t)}
+    except lor.LorError as e:
+        res["error"] = str(e)
+    return res
 
 
 def bench_nd(lor, meshgen, args, dev):

@@ -237,6 +237,59 @@ int lor_eliminate_bc(int64_t nrows, int64_t nnz, int batch, const int32_t* row_p
                      const int32_t* ess_dofs, uint8_t* marker, int diag_policy, int32_t* diag,
                      void* stream);
 
+/*
+ * lor_discrete_gradient -- the discrete gradient matrix G (LOR vertices ->
+ * LOR edges) that the auxiliary-space Maxwell solver needs (Section 3, Step
+ * S1.2, auxiliary computations, and its algorithm for G in CSR form): row i
+ * (edge i) has the two entries I[i] = 2i, J = (first, second) vertex of the
+ * edge's local edge in the element that supplies it, A = (-sigma, +sigma) with
+ * sigma its orientation sign.  The supplying element is the edge's first
+ * incidence (lowest element, then lowest local edge) from the schedule, so
+ * the two entries of a row are in that local edge's order, not sorted.
+ *
+ *   p, nel      as for lor_assemble_nd; ndofs_h1 vertices, nedges edges.
+ *   elem_dofs   [nel][(p+1)^3] vertex map; elem_edges the signed edge map.
+ *   sched       the schedule lor_pattern(LOR_ND, p, elem_edges) wrote.
+ *   row_ptr     [nedges+1] int32, col_idx [2*nedges] int32, values
+ *               [2*nedges] in dtype (LOR_F64 / LOR_F32): written.
+ *   diag        NULL or device int32[2]: [0] += edges in no element (their row
+ *               is two zeros at column 0); [1] += rows with a vertex outside
+ *               [0, ndofs_h1).  The caller zeroes it.
+ * Asynchronous on `stream`.  Errors: LOR_EINVAL, LOR_EOVERFLOW (2*nedges >= 2^31).
+ */
+int lor_discrete_gradient(int p, int64_t nel, int64_t ndofs_h1, int64_t nedges, const int32_t* elem_dofs,
+                          const int32_t* elem_edges, const lor_sched* sched, int32_t* row_ptr,
+                          int32_t* col_idx, void* values, int dtype, int32_t* diag, void* stream);
+
+/*
+ * lor_interp_nodes -- LOR vertex coordinates as an E-vector (Section 3,
+ * auxiliary computations; the coordinate-vector kernels of Section 4): the
+ * degree-q high-order mesh, given by its nodes at the tensor Gauss-Lobatto
+ * points of degree q, evaluated at the tensor Gauss-Lobatto lattice of degree
+ * p with the tensor-product Lagrange basis (sum-factorised, FP64).
+ *
+ *   nodes  [nel][(q+1)^3][ncomp] float64, local node i + (q+1)(j + (q+1)k).
+ *   out    [nel][(p+1)^3][ncomp] float64, written.
+ *   1 <= p <= LOR_MAX_P, 1 <= q <= 8, 1 <= ncomp <= 3.
+ * Asynchronous on `stream`.  Errors: LOR_EINVAL, LOR_EOVERFLOW (nel >= 2^31).
+ */
+int lor_interp_nodes(int p, int q, int64_t nel, int ncomp, const double* nodes, double* out, void* stream);
+
+/*
+ * lor_evec_to_tvec -- E-vector to T-vector (the deduplication of the
+ * coordinate E-vector with the element restriction map, one thread per dof,
+ * Section 3 auxiliary computations): tvec[g] = evec at the first incidence of
+ * dof g (lowest element, then lowest local index).
+ *
+ *   sched  the schedule lor_pattern(LOR_H1, p, elem_dofs) wrote (its incidence
+ *          lists give the first incidences).
+ *   evec   [nel][(p+1)^3][ncomp] float64; tvec [ndofs][ncomp] float64, written.
+ *   diag   NULL or device int32[1]: [0] += dofs in no element (left as 0).
+ * Asynchronous on `stream`.  Errors: LOR_EINVAL.
+ */
+int lor_evec_to_tvec(int p, int64_t nel, int64_t ndofs, const lor_sched* sched, int ncomp, const double* evec,
+                     double* tvec, int32_t* diag, void* stream);
+
 /* Bytes of the `workspace` argument of lor_assemble_backward. */
 size_t lor_backward_workspace(int p, int64_t nel);
 

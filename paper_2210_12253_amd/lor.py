@@ -31,6 +31,9 @@ ABI_SYMBOLS = (
     "lor_assemble_backward",
     "lor_backward_workspace",
     "lor_eliminate_bc",
+    "lor_discrete_gradient",
+    "lor_interp_nodes",
+    "lor_evec_to_tvec",
     "lor_sched_bytes",
     "lor_last_error",
     "lor_abi_version",
@@ -102,6 +105,13 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.lor_assemble_backward.restype = i32
     lib.lor_eliminate_bc.argtypes = [i64, i64, i32, vp, vp, vp, i32, i64, vp, vp, i32, vp, vp]
     lib.lor_eliminate_bc.restype = i32
+    lib.lor_discrete_gradient.argtypes = [i32, i64, i64, i64, vp, vp, ctypes.POINTER(LorSched), vp, vp, vp, i32,
+                                          vp, vp]
+    lib.lor_discrete_gradient.restype = i32
+    lib.lor_interp_nodes.argtypes = [i32, i32, i64, i32, vp, vp, vp]
+    lib.lor_interp_nodes.restype = i32
+    lib.lor_evec_to_tvec.argtypes = [i32, i64, i64, ctypes.POINTER(LorSched), i32, vp, vp, vp, vp]
+    lib.lor_evec_to_tvec.restype = i32
     lib.lor_backward_workspace.argtypes = [i32, i64]
     lib.lor_backward_workspace.restype = sz
     lib.lor_sched_bytes.argtypes = []
@@ -272,6 +282,61 @@ def lor_eliminate_bc(pat: Pattern, values: torch.Tensor, ess_dofs, diag_policy: 
                                 _dtype_code(values.dtype), ess.numel(), _ptr(ess), _ptr(marker),
                                 _DIAG_POLICY[diag_policy], _ptr(diag), _stream()))
     return marker
+
+
+def lor_discrete_gradient(pat: Pattern, elem_dofs, elem_edges, ndofs_h1: int, dtype=torch.float64,
+                          diag: torch.Tensor | None = None, out=None):
+    """Discrete gradient (vertices -> edges) in CSR: (row_ptr, col_idx, values)
+    with two entries per row; `pat` is the H(curl) pattern of elem_edges.
+    `out` may hold preallocated (row_ptr, col_idx, values)."""
+    lib = load_library()
+    dev = pat.row_ptr.device
+    ed = _dev_tensor(elem_dofs, torch.int32, "elem_dofs", dev)
+    ee = _dev_tensor(elem_edges, torch.int32, "elem_edges", dev)
+    if out is None:
+        rp = torch.empty(pat.nrows + 1, dtype=torch.int32, device=dev)
+        ci = torch.empty(2 * pat.nrows, dtype=torch.int32, device=dev)
+        v = torch.empty(2 * pat.nrows, dtype=dtype, device=dev)
+    else:
+        rp, ci, v = out
+        if rp.numel() != pat.nrows + 1 or ci.numel() != 2 * pat.nrows or v.numel() != 2 * pat.nrows or \
+                v.dtype != dtype or rp.dtype != torch.int32 or ci.dtype != torch.int32:
+            raise ValueError("out must be (row_ptr [nrows+1] int32, col_idx [2 nrows] int32, values [2 nrows] dtype)")
+    _check(lib.lor_discrete_gradient(pat.p, pat.nel, ndofs_h1, pat.nrows, _ptr(ed), _ptr(ee), ctypes.byref(pat.sched),
+                                     _ptr(rp), _ptr(ci), _ptr(v), _dtype_code(dtype), _ptr(diag), _stream()))
+    return rp, ci, v
+
+
+def lor_interp_nodes(nodes, p: int, q: int, out: torch.Tensor | None = None) -> torch.Tensor:
+    """High-order mesh nodes [nel, (q+1)^3, ncomp] -> LOR lattice E-vector
+    [nel, (p+1)^3, ncomp] (float64, on the current CUDA device)."""
+    lib = load_library()
+    dev = torch.device("cuda") if not (torch.is_tensor(nodes) and nodes.is_cuda) else nodes.device
+    X = _dev_tensor(nodes, torch.float64, "nodes", dev)
+    if X.dim() != 3 or X.shape[1] != (q + 1) ** 3:
+        raise ValueError("nodes must have shape [nel, (q+1)^3, ncomp]")
+    nel, _, nc = X.shape
+    if out is None:
+        out = torch.empty((nel, (p + 1) ** 3, nc), dtype=torch.float64, device=dev)
+    _check(lib.lor_interp_nodes(p, q, nel, nc, _ptr(X), _ptr(out), _stream()))
+    return out
+
+
+def lor_evec_to_tvec(pat: Pattern, evec: torch.Tensor, diag: torch.Tensor | None = None,
+                     out: torch.Tensor | None = None) -> torch.Tensor:
+    """E-vector [nel, (p+1)^3, ncomp] -> T-vector [nrows, ncomp] by first
+    incidence; `pat` is the H1 pattern of the element map."""
+    lib = load_library()
+    dev = pat.row_ptr.device
+    E = _dev_tensor(evec, torch.float64, "evec", dev)
+    if E.dim() != 3 or E.shape[0] != pat.nel or E.shape[1] != (pat.p + 1) ** 3:
+        raise ValueError("evec must have shape [nel, (p+1)^3, ncomp]")
+    nc = E.shape[2]
+    if out is None:
+        out = torch.empty((pat.nrows, nc), dtype=torch.float64, device=dev)
+    _check(lib.lor_evec_to_tvec(pat.p, pat.nel, pat.nrows, ctypes.byref(pat.sched), nc, _ptr(E), _ptr(out),
+                                _ptr(diag), _stream()))
+    return out
 
 
 class LorH1(torch.autograd.Function):

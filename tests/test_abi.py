@@ -112,3 +112,25 @@ def test_eliminate_argument_errors():
     assert call(v=None) == L.LOR_EINVAL
     # nothing to do: no launch, OK
     assert call(nrows=0, nnz=0, ness=0) == L.LOR_OK
+
+
+def test_aux_argument_errors():
+    lib = pkg.load_library()
+    s = L.LorSched()
+    assert lib.lor_discrete_gradient(0, 1, 8, 12, FAKE, FAKE, ctypes.byref(s), FAKE, FAKE, FAKE, 0, None,
+                                     None) == L.LOR_EINVAL
+    assert lib.lor_discrete_gradient(2, 1, 8, 1 << 30, FAKE, FAKE, ctypes.byref(s), FAKE, FAKE, FAKE, 0, None,
+                                     None) == L.LOR_EOVERFLOW
+    assert lib.lor_discrete_gradient(2, 1, 27, 54, FAKE, FAKE, ctypes.byref(s), FAKE, FAKE, FAKE, 5, None,
+                                     None) == L.LOR_EINVAL
+    # a schedule without its device part
+    s.dev = None
+    rc = lib.lor_discrete_gradient(2, 1, 27, 54, FAKE, FAKE, ctypes.byref(s), FAKE, FAKE, FAKE, 0, None, None)
+    assert rc == L.LOR_EINVAL and "sched" in _err(lib)
+    assert lib.lor_interp_nodes(0, 2, 4, 3, FAKE, FAKE, None) == L.LOR_EINVAL
+    assert lib.lor_interp_nodes(2, 9, 4, 3, FAKE, FAKE, None) == L.LOR_EINVAL and "q = 9" in _err(lib)
+    assert lib.lor_interp_nodes(2, 2, 4, 4, FAKE, FAKE, None) == L.LOR_EINVAL
+    assert lib.lor_interp_nodes(2, 2, 4, 3, None, FAKE, None) == L.LOR_EINVAL
+    assert lib.lor_interp_nodes(2, 2, 0, 3, None, None, None) == L.LOR_OK
+    assert lib.lor_evec_to_tvec(2, 1, 27, ctypes.byref(s), 0, FAKE, FAKE, None, None) == L.LOR_EINVAL
+    assert lib.lor_evec_to_tvec(2, 1, 27, ctypes.byref(s), 3, FAKE, FAKE, None, None) == L.LOR_EINVAL

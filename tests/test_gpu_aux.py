@@ -1,0 +1,120 @@
+"""GPU parity of the auxiliary LOR data (discrete gradient, LOR coordinate
+vector) against the CPU oracle, through the C ABI (Python binding)."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import meshgen
+import paper_2210_12253_amd as lor
+from oracle import lor_oracle as orc
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda:0")
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+GRAD_CASES = [(2, 1, False), (2, 2, True), (3, 3, True), (1, 5, True), (2, 6, False)]
+
+
+@pytest.mark.parametrize("case", GRAD_CASES, ids=[f"n{c[0]}p{c[1]}-r{int(c[2])}" for c in GRAD_CASES])
+def test_discrete_gradient_small_parity(case):
+    n, p, perturb = case
+    _say("case", case)
+    m = meshgen.cartesian_mesh(n, p, 0.0)
+    ee, ned = meshgen.nd_edge_map(n, p)
+    if perturb:
+        m, _, ee = meshgen.reorient_elements(m, seed=n + p, kappa=None, elem_edges=ee)
+        ee, _ = meshgen.flip_edge_signs(ee, ned, seed=n * p)
+    rp, ci, v = orc.discrete_gradient(m["elem_dofs"], ee, p, ned)
+    pat = lor.lor_pattern(lor.LOR_ND, p, torch.from_numpy(ee).to(DEV), ned)
+    for dtype in (torch.float64, torch.float32):
+        diag = torch.zeros(2, dtype=torch.int32, device=DEV)
+        grp, gci, gv = lor.lor_discrete_gradient(pat, m["elem_dofs"], ee, m["ndofs"], dtype=dtype, diag=diag)
+        torch.cuda.synchronize()
+        assert torch.equal(grp.cpu().to(torch.int64), rp)
+        assert torch.equal(gci.cpu().to(torch.int64), ci)
+        assert torch.equal(gv.cpu(), v.to(dtype))
+        assert diag.cpu().tolist() == [0, 0]
+
+
+def test_discrete_gradient_full_size():
+    """H(curl) p=3 on 24^3 (1,151,064 edges), every entry against the oracle."""
+    m = meshgen.config_mesh("c4_nd_p3_curved")
+    ee = m["elem_edges"]
+    rp, ci, v = orc.discrete_gradient(m["elem_dofs"], ee, 3, m["nedges"])
+    pat = lor.lor_pattern(lor.LOR_ND, 3, torch.from_numpy(ee).to(DEV), m["nedges"])
+    grp, gci, gv = lor.lor_discrete_gradient(pat, m["elem_dofs"], ee, m["ndofs"])
+    torch.cuda.synchronize()
+    assert torch.equal(grp.cpu().to(torch.int64), rp)
+    assert torch.equal(gci.cpu().to(torch.int64), ci)
+    assert torch.equal(gv.cpu(), v)
+
+
+INTERP_CASES = [(2, 3, 1, 0.0), (2, 4, 2, 0.1), (1, 6, 3, 0.1), (2, 2, 5, 0.1), (1, 3, 8, 0.05), (2, 5, 5, 0.1)]
+
+
+@pytest.mark.parametrize("case", INTERP_CASES, ids=[f"n{c[0]}p{c[1]}q{c[2]}" for c in INTERP_CASES])
+def test_interp_nodes_small_parity(case):
+    n, p, q, amp = case
+    _say("case", case)
+    X = meshgen.ho_nodes(n, q, amp)
+    want = orc.interp_nodes(X, p, q)
+    got = lor.lor_interp_nodes(torch.from_numpy(X).to(DEV), p, q)
+    torch.cuda.synchronize()
+    assert float((got.cpu() - want).abs().max()) <= 1e-13
+    # one and two components
+    got1 = lor.lor_interp_nodes(torch.from_numpy(X[..., :1].copy()).to(DEV), p, q)
+    got2 = lor.lor_interp_nodes(torch.from_numpy(X[..., 1:].copy()).to(DEV), p, q)
+    torch.cuda.synchronize()
+    assert float((got1.cpu() - want[..., :1]).abs().max()) <= 1e-13
+    assert float((got2.cpu() - want[..., 1:]).abs().max()) <= 1e-13
+
+
+def test_evec_to_tvec_parity_first_incidence():
+    """A renumbered mesh whose E-vector differs per element: each dof must
+    take its first incidence's value, bit for bit."""
+    m, _ = meshgen.renumber_vertices(meshgen.cartesian_mesh(3, 2, 0.0), seed=2)
+    ed = m["elem_dofs"]
+    g = torch.Generator().manual_seed(5)
+    E = torch.randn(ed.shape + (3,), generator=g, dtype=torch.float64)
+    want = orc.evec_to_tvec(E, ed, m["ndofs"])
+    pat = lor.lor_pattern(lor.LOR_H1, 2, torch.from_numpy(ed).to(DEV), m["ndofs"])
+    diag = torch.zeros(1, dtype=torch.int32, device=DEV)
+    got = lor.lor_evec_to_tvec(pat, E.to(DEV), diag=diag)
+    torch.cuda.synchronize()
+    assert torch.equal(got.cpu(), want) and diag.item() == 0
+    # dofs that no element touches are counted and left at 0
+    pat2 = lor.lor_pattern(lor.LOR_H1, 2, torch.from_numpy(ed).to(DEV), m["ndofs"] + 5)
+    got2 = lor.lor_evec_to_tvec(pat2, E.to(DEV), diag=diag)
+    torch.cuda.synchronize()
+    assert diag.item() == 5 and torch.equal(got2.cpu()[: m["ndofs"]], want)
+    assert bool((got2.cpu()[m["ndofs"]:] == 0).all())
+
+
+def test_coordinate_vector_full_size():
+    """The headline mesh size (32^3 elements, p = 6) from degree-2 curved
+    nodes: the E-vector against the oracle, sampled elements; the T-vector
+    against the oracle's deduplication of the oracle's E-vector, all dofs; and
+    every copy of a shared vertex agrees across elements (to rounding)."""
+    n, p, q = 32, 6, 2
+    X = meshgen.ho_nodes(n, q, 0.1)
+    m = meshgen.cartesian_mesh(n, p, 0.0)
+    pat = lor.lor_pattern(lor.LOR_H1, p, torch.from_numpy(m["elem_dofs"]).to(DEV), m["ndofs"])
+    E = lor.lor_interp_nodes(torch.from_numpy(X).to(DEV), p, q)
+    T = lor.lor_evec_to_tvec(pat, E)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(0)
+    els = np.unique(np.concatenate([[0, n ** 3 - 1], rng.integers(0, n ** 3, 300)]))
+    want_s = orc.interp_nodes(X[els], p, q)
+    assert float((E.cpu()[els] - want_s).abs().max()) <= 1e-13
+    want_E = orc.interp_nodes(X, p, q)
+    want_T = orc.evec_to_tvec(want_E, m["elem_dofs"], m["ndofs"])
+    assert float((T.cpu() - want_T).abs().max()) <= 1e-13
+    spread = (E - T[torch.from_numpy(m["elem_dofs"]).long().to(DEV)]).abs().max()
+    assert float(spread) <= 1e-13
