@@ -38,6 +38,7 @@ __all__ = [
     "cartesian_mesh",
     "affine_mesh",
     "nd_edge_map",
+    "face_map",
     "kappa_field",
     "cotangent",
     "renumber_vertices",
@@ -172,6 +173,44 @@ def nd_edge_map(n: int, p: int) -> tuple[np.ndarray, int]:
                 X, Y, Z = p * ex + i, p * ey + j, p * ez + k
                 out[:, ll] = 2 * M * N * N + X + N * (Y + N * Z)
     return out.astype(np.int32), 3 * M * N * N
+
+
+def face_map(n: int, p: int) -> tuple[np.ndarray, int]:
+    """Signed element-to-face map [n^3, 3p^2(p+1)] int32 of the LOR mesh faces
+    (the lowest-order Raviart-Thomas dofs) and the face count.
+
+    Local faces: x-faces (normal +x) first, index i + (p+1)*(j + p*k) with
+    i <= p, j, k < p; then y-faces at offset p^2(p+1), index i + p*(j + (p+1)*k)
+    with j <= p; then z-faces at offset 2p^2(p+1), index i + p*(j + p*k) with
+    k <= p.  Global faces, M = n*p, N = M + 1: x-faces X + N*(Y + M*Z); y-faces
+    N*M^2 + X + M*(Y + N*Z); z-faces 2*N*M^2 + X + M*(Y + M*Z); every face
+    normal points along +axis, and a negative entry -1-f means face f with the
+    opposite orientation (as for edges)."""
+    M = n * p
+    N = M + 1
+    q = p + 1
+    ne = n ** 3
+    e = np.arange(ne)
+    ex, ey, ez = e % n, (e // n) % n, e // (n * n)
+    out = np.empty((ne, 3 * p * p * q), dtype=np.int64)
+    for k in range(p):
+        for j in range(p):
+            for i in range(q):
+                X, Y, Z = p * ex + i, p * ey + j, p * ez + k
+                out[:, i + q * (j + p * k)] = X + N * (Y + M * Z)
+    off = p * p * q
+    for k in range(p):
+        for j in range(q):
+            for i in range(p):
+                X, Y, Z = p * ex + i, p * ey + j, p * ez + k
+                out[:, off + i + p * (j + q * k)] = N * M * M + X + M * (Y + N * Z)
+    off = 2 * p * p * q
+    for k in range(q):
+        for j in range(p):
+            for i in range(p):
+                X, Y, Z = p * ex + i, p * ey + j, p * ez + k
+                out[:, off + i + p * (j + p * k)] = 2 * N * M * M + X + M * (Y + M * Z)
+    return out.astype(np.int32), 3 * N * M * M
 
 
 def kappa_field(nel: int, p: int, sigma: float, seed: int = 0, batch: int | None = None,
@@ -336,8 +375,9 @@ def _sym_edge_index(p: int, perm, flips):
 
 
 def flip_edge_signs(elem_edges: np.ndarray, nedges: int, seed: int):
-    """Reverse the global orientation of a random half of the edges.  Returns the
-    new signed map and the +-1 vector S with A' = S A S."""
+    """Reverse the global orientation of a random half of the edges (or of the
+    faces, given a signed face map).  Returns the new signed map and the +-1
+    vector S with A' = S A S."""
     rng = np.random.default_rng(seed)
     s = np.where(rng.random(nedges) < 0.5, -1, 1).astype(np.int64)
     old = elem_edges.astype(np.int64)

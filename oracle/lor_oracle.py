@@ -56,6 +56,7 @@ __all__ = [
     "nd_rows",
     "discrete_gradient",
     "eliminate_bc",
+    "discrete_curl",
     "lagrange_matrix",
     "interp_nodes",
     "evec_to_tvec",
@@ -422,6 +423,75 @@ def discrete_gradient(elem_dofs, elem_edges, p: int, nedges: int):
     J = torch.stack([ed[e, v0[l]], ed[e, v1[l]]], dim=1)
     A = torch.stack([-sig, sig], dim=1)
     row_ptr = torch.arange(0, 2 * nedges + 1, 2, dtype=torch.int64)
+    return row_ptr, J.reshape(-1), A.reshape(-1)
+
+
+# ------------------------------------------------------- auxiliary: curl
+
+def _local_face_edges(p: int):
+    """For every local face of a degree-p macro element, its 4 local edges and
+    the sign of each in the face's boundary circulation (right-hand rule about
+    the face normal, which points along +axis): x-face boundary runs +y, +z,
+    -y, -z; y-face +z, +x, -z, -x; z-face +x, +y, -x, -y (Stokes: the flux of
+    curl u through the face is the circulation of u around it)."""
+    q = p + 1
+
+    def xe(i, j, k):
+        return i + p * (j + q * k)
+
+    def ye(i, j, k):
+        return p * q * q + i + q * (j + p * k)
+
+    def ze(i, j, k):
+        return 2 * p * q * q + i + q * (j + q * k)
+
+    out = []
+    for k in range(p):
+        for j in range(p):
+            for i in range(q):
+                out.append([(ye(i, j, k), 1), (ze(i, j + 1, k), 1), (ye(i, j, k + 1), -1), (ze(i, j, k), -1)])
+    for k in range(p):
+        for j in range(q):
+            for i in range(p):
+                out.append([(ze(i, j, k), 1), (xe(i, j, k + 1), 1), (ze(i + 1, j, k), -1), (xe(i, j, k), -1)])
+    for k in range(q):
+        for j in range(p):
+            for i in range(p):
+                out.append([(xe(i, j, k), 1), (ye(i + 1, j, k), 1), (xe(i, j + 1, k), -1), (ye(i, j, k), -1)])
+    return out
+
+
+def discrete_curl(elem_edges, elem_faces, p: int, nfaces: int):
+    """Discrete curl (LOR edges -> LOR faces) in CSR (auxiliary computations of
+    Step S1.2): row f (a face) has 4 entries, one per edge of the face, equal
+    to sigma_f * sigma_e * s, with s the edge's sign in the face circulation on
+    the reference macro element and sigma_f, sigma_e the orientation signs of
+    the signed face and edge maps.  As for the gradient, each face is taken
+    from its first incidence (lowest element, then lowest local face); the
+    entries keep the local circulation order (+, +, -, - before the signs).
+    Returns (row_ptr, col_idx, values)."""
+    fe = torch.as_tensor(elem_faces).to(torch.int64)
+    ee = torch.as_tensor(elem_edges).to(torch.int64)
+    nlocf = fe.shape[1]
+    tab = _local_face_edges(p)
+    if len(tab) != nlocf:
+        raise ValueError("face map does not match p")
+    le = torch.tensor([[t[0] for t in row] for row in tab], dtype=torch.int64)   # [nlocf, 4]
+    ls = torch.tensor([[t[1] for t in row] for row in tab], dtype=torch.float64)
+    raw = fe.reshape(-1)
+    gid = torch.where(raw < 0, -1 - raw, raw)
+    flat = torch.arange(gid.numel())
+    none = gid.numel()
+    first = torch.full((nfaces,), none, dtype=torch.int64).scatter_reduce(0, gid, flat, reduce="amin")
+    if bool((first == none).any()):
+        raise ValueError("face map does not cover every face")
+    e, lf = first // nlocf, first % nlocf
+    sf = torch.where(raw[first] < 0, -1.0, 1.0).to(torch.float64)
+    eraw = ee[e[:, None], le[lf]]                                                 # [nfaces, 4]
+    J = torch.where(eraw < 0, -1 - eraw, eraw)
+    se = torch.where(eraw < 0, -1.0, 1.0).to(torch.float64)
+    A = sf[:, None] * se * ls[lf]
+    row_ptr = torch.arange(0, 4 * nfaces + 1, 4, dtype=torch.int64)
     return row_ptr, J.reshape(-1), A.reshape(-1)
 
 
