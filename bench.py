@@ -476,7 +476,21 @@ def bench_aux(lor, meshgen, pat_h1, args, dev):
         res["gradient"] = {"ms": ms, "value": ned / (ms * 1e-3) / 1e9, "unit": "GDOF/s (edges)",
                            "workload": "discrete gradient, H(curl) p=3 24^3 (1,151,064 edges), FP64",
                            "roofline": rl(48 * ned, ms)}
-        del pat, rp, ci, v, ee, ed
+        fm, nf = meshgen.face_map(24, 3)
+        fm = torch.from_numpy(fm).to(dev)
+        ws = torch.empty(nf, dtype=torch.int32, device=dev)
+        crp = torch.empty(nf + 1, dtype=torch.int32, device=dev)
+        cci = torch.empty(4 * nf, dtype=torch.int32, device=dev)
+        cv = torch.empty(4 * nf, dtype=torch.float64, device=dev)
+        ms_c = time_it(lambda: lor.lor_discrete_curl(3, ee, fm, ned, nf, workspace=ws, out=(crp, cci, cv), device=dev),
+                       args.steps, args.warmup)
+        # face map read twice (owner pass, row pass: 4 + 4 per face incidence,
+        # two incidences per interior face) + owner fill/atomic/read 12 +
+        # 4 edge-map entries 16 + row pointer 4 + columns 16 + FP64 values 32
+        res["curl"] = {"ms": ms_c, "value": nf / (ms_c * 1e-3) / 1e9, "unit": "GDOF/s (faces)",
+                       "workload": "discrete curl, p=3 24^3 (%d faces), FP64" % nf,
+                       "roofline": rl(int(8 * fm.numel() + (12 + 16 + 4 + 16 + 32) * nf), ms_c)}
+        del pat, rp, ci, v, ee, ed, fm, ws, crp, cci, cv
         n, p, q = 32, 6, 2
         X = torch.from_numpy(meshgen.ho_nodes(n, q, 0.1)).to(dev)
         E = torch.empty((n ** 3, (p + 1) ** 3, 3), dtype=torch.float64, device=dev)

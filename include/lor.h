@@ -262,6 +262,37 @@ int lor_discrete_gradient(int p, int64_t nel, int64_t ndofs_h1, int64_t nedges, 
                           int32_t* col_idx, void* values, int dtype, int32_t* diag, void* stream);
 
 /*
+ * lor_discrete_curl -- the discrete curl matrix C (LOR edges -> LOR faces)
+ * that the auxiliary-space divergence solver needs (Section 3, Step S1.2,
+ * auxiliary computations): row f (face f) has 4 entries, one per boundary
+ * edge of the face, value sigma_f * sigma_e * s with s = +1, +1, -1, -1 the
+ * edge's sign in the face's circulation (right-hand rule about the face's
+ * +axis normal: x-face boundary +y, +z, -y, -z; y-face +z, +x, -z, -x; z-face
+ * +x, +y, -x, -y) on the reference macro element, and sigma_f, sigma_e the
+ * signs of the face and edge maps.  Each face is taken from its first
+ * incidence (lowest element, then lowest local face); entries stay in that
+ * circulation order.
+ *
+ *   elem_edges  [nel][3p(p+1)^2] signed edge map (as for lor_assemble_nd).
+ *   elem_faces  [nel][3p^2(p+1)] signed face map: x-faces (normal +x) first,
+ *               local index i + (p+1)(j + p k) with i <= p; then y-faces at
+ *               offset p^2(p+1), index i + p(j + (p+1)k) with j <= p; then
+ *               z-faces at offset 2p^2(p+1), index i + p(j + p k) with k <= p;
+ *               entry f >= 0 is face f with the local orientation, f < 0 is
+ *               face -1-f with the opposite one.
+ *   workspace   [nfaces] int32 device buffer (first incidence of every face).
+ *   row_ptr     [nfaces+1] int32, col_idx [4*nfaces] int32, values [4*nfaces]
+ *               in dtype: written.
+ *   diag        NULL or device int32[2]: [0] += faces in no element (row of
+ *               four zeros at column 0); [1] += face ids >= nfaces in the face
+ *               map (ignored) or edge ids >= nedges written.  Caller zeroes it.
+ * Asynchronous on `stream`.  Errors: LOR_EINVAL, LOR_EOVERFLOW.
+ */
+int lor_discrete_curl(int p, int64_t nel, int64_t nedges, int64_t nfaces, const int32_t* elem_edges,
+                      const int32_t* elem_faces, int32_t* workspace, int32_t* row_ptr, int32_t* col_idx,
+                      void* values, int dtype, int32_t* diag, void* stream);
+
+/*
  * lor_interp_nodes -- LOR vertex coordinates as an E-vector (Section 3,
  * auxiliary computations; the coordinate-vector kernels of Section 4): the
  * degree-q high-order mesh, given by its nodes at the tensor Gauss-Lobatto

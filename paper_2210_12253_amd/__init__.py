@@ -18,6 +18,7 @@ from .lor import (  # noqa: F401
     lor_assemble_backward,
     lor_assemble_h1,
     lor_assemble_nd,
+    lor_discrete_curl,
     lor_discrete_gradient,
     lor_eliminate_bc,
     lor_evec_to_tvec,

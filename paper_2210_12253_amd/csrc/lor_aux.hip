@@ -1,11 +1,13 @@
 // Auxiliary LOR data for the auxiliary-space solvers (Section 3, Step S1.2,
-// auxiliary computations): the discrete gradient matrix, the interpolation of
+// auxiliary computations): the discrete gradient and curl matrices, the interpolation of
 // the high-order mesh nodes to the LOR (Gauss-Lobatto) lattice as an E-vector,
 // and the E-vector to T-vector deduplication of those coordinates.
 //
 // Every per-dof kernel takes the dof's data from its first incidence (lowest
 // element, then lowest local index), read from the sorted incidence lists of
-// the lor_pattern schedule: one thread per dof, as the paper threads them.
+// the lor_pattern schedule (for faces, which have no schedule, from an
+// atomic-minimum pass over the face map): one thread per dof, as the paper
+// threads them.
 #include <algorithm>
 #include <cmath>
 
@@ -74,6 +76,99 @@ __global__ __launch_bounds__(kAuxThreads) void k_discrete_gradient(
   col_idx[2 * g + 1] = j1;
   values[2 * g] = -s;
   values[2 * g + 1] = s;
+}
+
+// ------------------------------------------------------- discrete curl
+
+__global__ __launch_bounds__(kAuxThreads) void k_fill_owner(int32_t* __restrict__ owner, int64_t n) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) owner[i] = INT32_MAX;
+}
+
+// owner[f] = lowest flat index e * nlocf + lf of the faces map that names f
+__global__ __launch_bounds__(kAuxThreads) void k_face_owner(const int32_t* __restrict__ elem_faces, int64_t total,
+                                                            int64_t nfaces, int32_t* __restrict__ owner,
+                                                            int32_t* __restrict__ diag) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= total) return;
+  const int32_t raw = elem_faces[i];
+  const int32_t f = raw < 0 ? -1 - raw : raw;
+  if (f >= nfaces) {
+    if (diag) atomicAdd(&diag[1], 1);
+    return;
+  }
+  atomicMin(&owner[f], static_cast<int32_t>(i));
+}
+
+// The 4 boundary edges of local face lf of a degree-p macro element and their
+// signs in the face's circulation (right-hand rule about the +axis normal):
+// x-face boundary +y, +z, -y, -z; y-face +z, +x, -z, -x; z-face +x, +y, -x, -y.
+__device__ __forceinline__ void local_face_edges(int p, int lf, int (&le)[4]) {
+  const int q = p + 1;
+  const int nfx = p * p * q, nex = p * q * q;
+  auto xe = [&](int i, int j, int k) { return i + p * (j + q * k); };
+  auto ye = [&](int i, int j, int k) { return nex + i + q * (j + p * k); };
+  auto ze = [&](int i, int j, int k) { return 2 * nex + i + q * (j + q * k); };
+  if (lf < nfx) {
+    const int i = lf % q, j = (lf / q) % p, k = lf / (q * p);
+    le[0] = ye(i, j, k);
+    le[1] = ze(i, j + 1, k);
+    le[2] = ye(i, j, k + 1);
+    le[3] = ze(i, j, k);
+  } else if (lf < 2 * nfx) {
+    const int m = lf - nfx;
+    const int i = m % p, j = (m / p) % q, k = m / (p * q);
+    le[0] = ze(i, j, k);
+    le[1] = xe(i, j, k + 1);
+    le[2] = ze(i + 1, j, k);
+    le[3] = xe(i, j, k);
+  } else {
+    const int m = lf - 2 * nfx;
+    const int i = m % p, j = (m / p) % p, k = m / (p * p);
+    le[0] = xe(i, j, k);
+    le[1] = ye(i + 1, j, k);
+    le[2] = xe(i, j + 1, k);
+    le[3] = ye(i, j, k);
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kAuxThreads) void k_discrete_curl(
+    int p, int64_t nfaces, int64_t nedges, const int32_t* __restrict__ elem_edges,
+    const int32_t* __restrict__ elem_faces, const int32_t* __restrict__ owner, int32_t* __restrict__ row_ptr,
+    int32_t* __restrict__ col_idx, T* __restrict__ values, int32_t* __restrict__ diag) {
+  const int64_t f = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (f >= nfaces) return;
+  const int q = p + 1;
+  const int nlocf = 3 * p * p * q, nloce = 3 * p * q * q;
+  row_ptr[f] = static_cast<int32_t>(4 * f);
+  if (f == nfaces - 1) row_ptr[nfaces] = static_cast<int32_t>(4 * nfaces);
+  const int32_t inc = owner[f];
+  int32_t cols[4] = {0, 0, 0, 0};
+  T vals[4] = {T(0), T(0), T(0), T(0)};
+  if (inc != INT32_MAX) {
+    const int32_t e = inc / nlocf;
+    const int lf = inc - e * nlocf;
+    const T sf = elem_faces[inc] < 0 ? T(-1) : T(1);
+    int le[4];
+    local_face_edges(p, lf, le);
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int32_t raw = elem_edges[static_cast<int64_t>(e) * nloce + le[s]];
+      const int32_t g = raw < 0 ? -1 - raw : raw;
+      if (g >= nedges && diag) atomicAdd(&diag[1], 1);
+      cols[s] = g;
+      const T se = raw < 0 ? T(-1) : T(1);
+      vals[s] = (s < 2 ? sf : -sf) * se;
+    }
+  } else if (diag) {
+    atomicAdd(&diag[0], 1);  // face in no element: its row is left as four zeros at column 0
+  }
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    col_idx[4 * f + s] = cols[s];
+    values[4 * f + s] = vals[s];
+  }
 }
 
 // ------------------------------------------- node interpolation (E-vector)
@@ -232,6 +327,39 @@ extern "C" int lor_discrete_gradient(int p, int64_t nel, int64_t ndofs_h1, int64
                                                                inc_list, row_ptr, col_idx, static_cast<float*>(values),
                                                                diag);
   LOR_LAUNCHED("k_discrete_gradient");
+  return LOR_OK;
+}
+
+extern "C" int lor_discrete_curl(int p, int64_t nel, int64_t nedges, int64_t nfaces, const int32_t* elem_edges,
+                                 const int32_t* elem_faces, int32_t* workspace, int32_t* row_ptr, int32_t* col_idx,
+                                 void* values, int dtype, int32_t* diag, void* stream) {
+  clear_error();
+  if (p < 1 || p > LOR_MAX_P) LOR_FAIL(LOR_EINVAL, "p = %d outside [1, %d]", p, LOR_MAX_P);
+  if (nel < 0 || nedges < 1 || nfaces < 1) LOR_FAIL(LOR_EINVAL, "nel < 0, nedges < 1 or nfaces < 1");
+  if (4 * nfaces >= (int64_t(1) << 31)) LOR_FAIL(LOR_EOVERFLOW, "4 * nfaces >= 2^31");
+  const int64_t nlocf = 3 * p * p * (p + 1);
+  if (nel * nlocf >= (int64_t(1) << 31)) LOR_FAIL(LOR_EOVERFLOW, "nel * 3p^2(p+1) >= 2^31");
+  if (nedges >= (int64_t(1) << 31)) LOR_FAIL(LOR_EOVERFLOW, "nedges >= 2^31");
+  if (dtype != LOR_F64 && dtype != LOR_F32) LOR_FAIL(LOR_EINVAL, "dtype must be LOR_F64 or LOR_F32");
+  if (!workspace || !row_ptr || !col_idx || !values) LOR_FAIL(LOR_EINVAL, "workspace or an output pointer is NULL");
+  if (nel > 0 && (!elem_edges || !elem_faces)) LOR_FAIL(LOR_EINVAL, "elem_edges or elem_faces is NULL");
+  hipStream_t st = as_stream(stream);
+  k_fill_owner<<<static_cast<unsigned>(ceil_div(nfaces, kAuxThreads)), kAuxThreads, 0, st>>>(workspace, nfaces);
+  LOR_LAUNCHED("k_fill_owner");
+  if (nel > 0) {
+    const int64_t total = nel * nlocf;
+    k_face_owner<<<static_cast<unsigned>(ceil_div(total, kAuxThreads)), kAuxThreads, 0, st>>>(elem_faces, total,
+                                                                                              nfaces, workspace, diag);
+    LOR_LAUNCHED("k_face_owner");
+  }
+  const unsigned blocks = static_cast<unsigned>(ceil_div(nfaces, kAuxThreads));
+  if (dtype == LOR_F64)
+    k_discrete_curl<double><<<blocks, kAuxThreads, 0, st>>>(p, nfaces, nedges, elem_edges, elem_faces, workspace,
+                                                            row_ptr, col_idx, static_cast<double*>(values), diag);
+  else
+    k_discrete_curl<float><<<blocks, kAuxThreads, 0, st>>>(p, nfaces, nedges, elem_edges, elem_faces, workspace,
+                                                           row_ptr, col_idx, static_cast<float*>(values), diag);
+  LOR_LAUNCHED("k_discrete_curl");
   return LOR_OK;
 }
 

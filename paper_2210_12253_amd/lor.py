@@ -32,6 +32,7 @@ ABI_SYMBOLS = (
     "lor_backward_workspace",
     "lor_eliminate_bc",
     "lor_discrete_gradient",
+    "lor_discrete_curl",
     "lor_interp_nodes",
     "lor_evec_to_tvec",
     "lor_sched_bytes",
@@ -108,6 +109,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.lor_discrete_gradient.argtypes = [i32, i64, i64, i64, vp, vp, ctypes.POINTER(LorSched), vp, vp, vp, i32,
                                           vp, vp]
     lib.lor_discrete_gradient.restype = i32
+    lib.lor_discrete_curl.argtypes = [i32, i64, i64, i64, vp, vp, vp, vp, vp, vp, i32, vp, vp]
+    lib.lor_discrete_curl.restype = i32
     lib.lor_interp_nodes.argtypes = [i32, i32, i64, i32, vp, vp, vp]
     lib.lor_interp_nodes.restype = i32
     lib.lor_evec_to_tvec.argtypes = [i32, i64, i64, ctypes.POINTER(LorSched), i32, vp, vp, vp, vp]
@@ -304,6 +307,31 @@ def lor_discrete_gradient(pat: Pattern, elem_dofs, elem_edges, ndofs_h1: int, dt
             raise ValueError("out must be (row_ptr [nrows+1] int32, col_idx [2 nrows] int32, values [2 nrows] dtype)")
     _check(lib.lor_discrete_gradient(pat.p, pat.nel, ndofs_h1, pat.nrows, _ptr(ed), _ptr(ee), ctypes.byref(pat.sched),
                                      _ptr(rp), _ptr(ci), _ptr(v), _dtype_code(dtype), _ptr(diag), _stream()))
+    return rp, ci, v
+
+
+def lor_discrete_curl(p: int, elem_edges, elem_faces, nedges: int, nfaces: int, dtype=torch.float64,
+                      diag: torch.Tensor | None = None, workspace: torch.Tensor | None = None, out=None,
+                      device=None):
+    """Discrete curl (edges -> faces) in CSR: (row_ptr, col_idx, values) with
+    four entries per row.  `out` may hold preallocated outputs."""
+    lib = load_library()
+    dev = torch.device("cuda") if device is None else torch.device(device)
+    ee = _dev_tensor(elem_edges, torch.int32, "elem_edges", dev)
+    fm = _dev_tensor(elem_faces, torch.int32, "elem_faces", dev)
+    nel = fm.shape[0]
+    if ee.shape[0] != nel:
+        raise ValueError("elem_edges and elem_faces must have one row per element")
+    if workspace is None:
+        workspace = torch.empty(nfaces, dtype=torch.int32, device=dev)
+    if out is None:
+        rp = torch.empty(nfaces + 1, dtype=torch.int32, device=dev)
+        ci = torch.empty(4 * nfaces, dtype=torch.int32, device=dev)
+        v = torch.empty(4 * nfaces, dtype=dtype, device=dev)
+    else:
+        rp, ci, v = out
+    _check(lib.lor_discrete_curl(p, nel, nedges, nfaces, _ptr(ee), _ptr(fm), _ptr(workspace), _ptr(rp), _ptr(ci),
+                                 _ptr(v), _dtype_code(dtype), _ptr(diag), _stream()))
     return rp, ci, v
 
 

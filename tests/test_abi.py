@@ -134,3 +134,14 @@ def test_aux_argument_errors():
     assert lib.lor_interp_nodes(2, 2, 0, 3, None, None, None) == L.LOR_OK
     assert lib.lor_evec_to_tvec(2, 1, 27, ctypes.byref(s), 0, FAKE, FAKE, None, None) == L.LOR_EINVAL
     assert lib.lor_evec_to_tvec(2, 1, 27, ctypes.byref(s), 3, FAKE, FAKE, None, None) == L.LOR_EINVAL
+
+
+def test_curl_argument_errors():
+    lib = pkg.load_library()
+    ok = [2, 8, 300, 240, FAKE, FAKE, FAKE, FAKE, FAKE, FAKE, L.LOR_F64, None, None]
+    assert lib.lor_discrete_curl(*([7] + ok[1:])) == L.LOR_EINVAL
+    assert lib.lor_discrete_curl(*(ok[:3] + [0] + ok[4:])) == L.LOR_EINVAL
+    assert lib.lor_discrete_curl(*(ok[:3] + [1 << 30] + ok[4:])) == L.LOR_EOVERFLOW
+    assert lib.lor_discrete_curl(*(ok[:6] + [None] + ok[7:])) == L.LOR_EINVAL
+    assert lib.lor_discrete_curl(*(ok[:10] + [9] + ok[11:])) == L.LOR_EINVAL
+    assert lib.lor_discrete_curl(*(ok[:4] + [None] + ok[5:])) == L.LOR_EINVAL
