@@ -54,6 +54,10 @@ __all__ = [
     "h1_rows",
     "nd_matrix",
     "nd_rows",
+    "rt_subelement_faces",
+    "rt_subelement_matrices",
+    "rt_matrix",
+    "rt_rows",
     "discrete_gradient",
     "eliminate_bc",
     "discrete_curl",
@@ -226,6 +230,132 @@ def nd_subelement_matrices(X: torch.Tensor, kappa: torch.Tensor, beta) -> torch.
     M = torch.einsum("sq,sqac,sqbc->sab", w * det, Nphys, Nphys)
     M = M * (bet[:, None, None] if bet.dim() == 1 else bet)
     return K + M
+
+
+# --------------------------------------------------------------------- H(div)
+
+def _rt_reference():
+    """Lowest-order Raviart-Thomas reference basis R[q, a, 3] and divergences
+    D[a] at the Gauss points.  Face a: x-faces (xi = a0) -> a0, y-faces
+    (eta = b) -> 2 + b, z-faces (zeta = c) -> 4 + c; each has unit flux through
+    its own face with the +axis normal and none through the others:
+    x-face a0: (l_a0(xi), 0, 0), divergence l_a0' = +-1, and cyclically."""
+    pts, w = _quad_points()
+    R = torch.zeros(8, 6, 3, dtype=torch.float64)
+    D = torch.zeros(6, dtype=torch.float64)
+    for q, (x, y, z) in enumerate(pts):
+        for t in range(2):
+            R[q, t, 0] = _l(t, x)
+            R[q, 2 + t, 1] = _l(t, y)
+            R[q, 4 + t, 2] = _l(t, z)
+    for t in range(2):
+        D[t] = D[2 + t] = D[4 + t] = _dl(t)
+    return R, D, w
+
+
+def rt_subelement_faces(elem_faces: torch.Tensor, p: int):
+    """Global face ids and orientation signs [nel, p^3, 6] of every subelement
+    (local faces as in the input generator's face map)."""
+    q = p + 1
+    fm = torch.as_tensor(elem_faces).to(torch.int64)
+    idx = torch.empty(p ** 3, 6, dtype=torch.int64)
+    ox, oy, oz = 0, p * p * q, 2 * p * p * q
+    for k in range(p):
+        for j in range(p):
+            for i in range(p):
+                s = i + p * (j + p * k)
+                for t in range(2):
+                    idx[s, t] = ox + (i + t) + q * (j + p * k)
+                    idx[s, 2 + t] = oy + i + p * ((j + t) + q * k)
+                    idx[s, 4 + t] = oz + i + p * (j + p * (k + t))
+    raw = fm[:, idx]
+    sign = torch.where(raw < 0, -1.0, 1.0).to(torch.float64)
+    gid = torch.where(raw < 0, -1 - raw, raw)
+    return gid, sign
+
+
+def rt_subelement_matrices(X: torch.Tensor, kappa: torch.Tensor, beta) -> torch.Tensor:
+    """Lowest-order Raviart-Thomas div-div + mass of trilinear subelements,
+    2x2x2 Gauss, in the local (+axis) orientation.  Contravariant Piola map:
+    N = J R_hat / det J, div N = D_hat / det J.
+      K_ab = sum_q w kappa det(J) divN_a divN_b,
+      M_ab = sum_q w beta  det(J) N_a . N_b.
+    X: [S, 8, 3]; returns [S, 6, 6]."""
+    _, grad, _ = _q1_reference()
+    Rr, Dr, w = _rt_reference()
+    J = torch.einsum("svr,qvc->sqrc", X, grad)
+    det = torch.linalg.det(J)
+    if bool((det <= 0).any()):
+        raise ValueError("inverted LOR subelement (det J <= 0 at a quadrature point)")
+    Nphys = torch.einsum("sqrc,qac->sqar", J, Rr) / det[:, :, None, None]
+    Dphys = Dr[None, None, :] / det[:, :, None]
+    kap = torch.as_tensor(kappa, dtype=torch.float64)
+    bet = torch.as_tensor(beta, dtype=torch.float64)
+    K = torch.einsum("sq,sqa,sqb->sab", w * det, Dphys, Dphys) * kap[:, None, None]
+    M = torch.einsum("sq,sqac,sqbc->sab", w * det, Nphys, Nphys)
+    M = M * (bet[:, None, None] if bet.dim() == 1 else bet)
+    return K + M
+
+
+def _coo_rt(coords, elem_dofs, elem_faces, p, kappa, beta, elems=None, chunk=4096):
+    coords = _as_f64(coords)
+    kappa = _as_f64(kappa)
+    ed = torch.as_tensor(elem_dofs)
+    fm = torch.as_tensor(elem_faces)
+    if elems is not None:
+        elems = torch.as_tensor(elems, dtype=torch.int64)
+        ed, fm, kappa = ed[elems], fm[elems], kappa[elems]
+        if isinstance(beta, torch.Tensor) and beta.dim() > 0:
+            beta = beta[elems]
+    R, C, V = [], [], []
+    nel = ed.shape[0]
+    for e0 in range(0, nel, chunk):
+        e1 = min(nel, e0 + chunk)
+        sv = h1_subelement_vertices(ed[e0:e1], p).reshape(-1, 8)
+        gid, sg = rt_subelement_faces(fm[e0:e1], p)
+        gid = gid.reshape(-1, 6)
+        sg = sg.reshape(-1, 6)
+        X = coords[sv]
+        kap = kappa[e0:e1].reshape(-1)
+        bet = beta[e0:e1].reshape(-1) if (isinstance(beta, torch.Tensor) and beta.dim() > 0) else beta
+        A = rt_subelement_matrices(X, kap, bet) * (sg[:, :, None] * sg[:, None, :])
+        R.append(gid[:, :, None].expand(-1, 6, 6).reshape(-1))
+        C.append(gid[:, None, :].expand(-1, 6, 6).reshape(-1))
+        V.append(A.reshape(-1))
+    return torch.cat(R), torch.cat(C), torch.cat(V)
+
+
+def rt_matrix(coords, elem_dofs, elem_faces, p: int, kappa, beta, nfaces: int):
+    """Assembled LOR H(div) matrix (kappa div-div + beta mass) in CSR; rows and
+    columns are global faces with the orientation given by the sign of the
+    signed face map (the lowest-order Raviart-Thomas element on the refined
+    mesh, the lowest-order interpolation-histopolation case)."""
+    R, C, V = _coo_rt(coords, elem_dofs, elem_faces, p, kappa, beta)
+    return coo_to_csr(R, C, V, nfaces)
+
+
+def rt_rows(coords, elem_dofs, elem_faces, p: int, kappa, beta, rows):
+    """The listed rows of the H(div) LOR matrix (same definition as rt_matrix)."""
+    rows = torch.unique(torch.as_tensor(rows, dtype=torch.int64))
+    fm = torch.as_tensor(elem_faces).to(torch.int64)
+    gid = torch.where(fm < 0, -1 - fm, fm)
+    elems = _elements_touching(gid, rows)
+    R, C, V = _coo_rt(coords, elem_dofs, elem_faces, p, kappa, beta, elems=elems)
+    keep = torch.isin(R, rows)
+    R, C, V = R[keep], C[keep], V[keep]
+    pos = torch.searchsorted(rows, R)
+    stride = int(C.max().item()) + 1 if C.numel() else 1
+    key = pos * stride + C
+    order = torch.argsort(key, stable=True)
+    ks = key[order]
+    uniq, inverse = torch.unique_consecutive(ks, return_inverse=True)
+    values = torch.zeros(uniq.numel(), dtype=torch.float64).index_add(0, inverse, V[order])
+    r = uniq // stride
+    col_idx = uniq - r * stride
+    counts = torch.bincount(r, minlength=rows.numel())
+    row_ptr = torch.zeros(rows.numel() + 1, dtype=torch.int64)
+    row_ptr[1:] = torch.cumsum(counts, 0)
+    return rows, row_ptr, col_idx, values
 
 
 # ------------------------------------------------------------------ assembly

@@ -783,3 +783,100 @@ def test_discrete_curl_first_incidence_rows():
                 s_e = 1 if r >= 0 else -1
                 assert ci[4 * f + slot].item() == g and v[4 * f + slot].item() == s_f * s_e * s
     assert len(done) == nf and torch.equal(rp, torch.arange(0, 4 * nf + 1, 4))
+
+
+# ------------------------------------------------------------------- H(div)
+
+def _rt_setup(n, p, amp, seed):
+    m = meshgen.cartesian_mesh(n, p, amp)
+    ee, ned = meshgen.nd_edge_map(n, p)
+    fm, nf = meshgen.face_map(n, p)
+    ee, _ = meshgen.flip_edge_signs(ee, ned, seed=seed)
+    fm, _ = meshgen.flip_edge_signs(fm, nf, seed=seed + 1)
+    kap = meshgen.kappa_field(m["nel"], p, 1.0, seed=seed + 2)
+    return m, ee, ned, fm, nf, kap
+
+
+@pytest.mark.parametrize("n,p", [(2, 2), (1, 3)])
+def test_rt_exact_sequence(n, p):
+    """With the (pinned) discrete curl C, on a curved mesh with flipped edge
+    and face orientations: K_div C = 0 (div of a curl) and, with the RT mass
+    weighted by kappa per subelement, C^T M_RT C = K_curl, the (pinned) ND
+    curl-curl with the same kappa (curl N_e = sum_f C_fe RT_f pointwise under
+    the Piola maps, same 2x2x2 rule)."""
+    m, ee, ned, fm, nf, kap = _rt_setup(n, p, 0.1, seed=n + 3 * p)
+    crp, cci, cv = orc.discrete_curl(ee, fm, p, nf)
+    C = dense(crp, cci, cv, ned)
+    rp, ci, v = orc.rt_matrix(m["coords"], m["elem_dofs"], fm, p, kap, 0.0, nf)
+    K = dense(rp, ci, v)
+    assert np.abs(K @ C).max() <= 1e-14 * np.abs(K).max() * np.abs(C).sum(axis=0).max()
+    rp, ci, v = orc.rt_matrix(m["coords"], m["elem_dofs"], fm, p, torch.zeros_like(kap), kap, nf)
+    Mrt = dense(rp, ci, v)
+    rp, ci, v = orc.nd_matrix(m["coords"], m["elem_dofs"], ee, p, kap, 0.0, ned)
+    Kc = dense(rp, ci, v)
+    assert np.abs(C.T @ Mrt @ C - Kc).max() <= 1e-13 * np.abs(Kc).max()
+    assert np.abs(K - K.T).max() <= 1e-14 * np.abs(K).max()
+
+
+def test_rt_affine_fields():
+    """On a parallelepiped mesh, for u = alpha X + b (div u = 3 alpha), face
+    dofs = flux u(centre).(t1 x t2) (exact for linear u on a parallelogram):
+    U^T K U = kappa (3 alpha)^2 vol; for constant u, U^T M U = beta |u|^2 vol.
+    Faces and their vectors are rebuilt here from the lattice."""
+    p, n = 2, 2
+    Am, t = _affine()
+    m = meshgen.affine_mesh(n, p, Am, t)
+    fm, nf = meshgen.face_map(n, p)
+    M_, N = n * p, n * p + 1
+    X = m["coords"]
+
+    def P(x, y, z):
+        return X[x + N * (y + N * z)]
+    centres, areas = np.zeros((nf, 3)), np.zeros((nf, 3))
+    for f in range(nf):
+        if f < N * M_ * M_:
+            x, y, z = f % N, (f // N) % M_, f // (N * M_)
+            o = P(x, y, z)
+            t1, t2 = P(x, y + 1, z) - o, P(x, y, z + 1) - o
+        elif f < 2 * N * M_ * M_:
+            h = f - N * M_ * M_
+            x, y, z = h % M_, (h // M_) % N, h // (M_ * N)
+            o = P(x, y, z)
+            t1, t2 = P(x, y, z + 1) - o, P(x + 1, y, z) - o
+        else:
+            h = f - 2 * N * M_ * M_
+            x, y, z = h % M_, (h // M_) % M_, h // (M_ * M_)
+            o = P(x, y, z)
+            t1, t2 = P(x + 1, y, z) - o, P(x, y + 1, z) - o
+        centres[f] = o + 0.5 * (t1 + t2)
+        areas[f] = np.cross(t1, t2)
+    vol = np.linalg.det(Am)
+    alpha, b = 0.7, np.array([0.2, -0.5, 0.9])
+    U = np.einsum("ij,ij->i", alpha * centres + b, areas)
+    kap = torch.full((m["nel"], p ** 3), 1.3, dtype=torch.float64)
+    rp, ci, v = orc.rt_matrix(X, m["elem_dofs"], fm, p, kap, 0.0, nf)
+    K = dense(rp, ci, v)
+    assert abs(U @ K @ U - 1.3 * 9 * alpha ** 2 * vol) <= 1e-12 * 1.3 * 9 * alpha ** 2 * vol
+    Uc = areas @ b
+    rp, ci, v = orc.rt_matrix(X, m["elem_dofs"], fm, p, torch.zeros_like(kap), 0.6, nf)
+    Mm = dense(rp, ci, v)
+    assert abs(Uc @ Mm @ Uc - 0.6 * (b @ b) * vol) <= 1e-12 * 0.6 * (b @ b) * vol
+
+
+def test_rt_pattern_count_and_sign_flip():
+    """nnz = nfaces + 30 M^3 on an M^3 lattice (every face couples to itself
+    and to the 5 other faces of each of its one or two subelements); flipping
+    face orientations gives S A S."""
+    n, p = 2, 2
+    m = meshgen.cartesian_mesh(n, p, 0.1)
+    fm, nf = meshgen.face_map(n, p)
+    kap = meshgen.kappa_field(m["nel"], p, 1.0, seed=4)
+    rp, ci, v = orc.rt_matrix(m["coords"], m["elem_dofs"], fm, p, kap, 0.8, nf)
+    M_ = n * p
+    assert rp[-1].item() == nf + 30 * M_ ** 3
+    cnt = (rp[1:] - rp[:-1])
+    assert int(cnt.max()) == 11 and int(cnt.min()) == 6
+    fm2, S = meshgen.flip_edge_signs(fm, nf, seed=6)
+    rp2, ci2, v2 = orc.rt_matrix(m["coords"], m["elem_dofs"], fm2, p, kap, 0.8, nf)
+    A, A2 = dense(rp, ci, v), dense(rp2, ci2, v2)
+    assert np.abs(A2 - S[:, None] * A * S[None, :]).max() <= 1e-14 * np.abs(A).max()
