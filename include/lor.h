@@ -55,7 +55,7 @@ typedef enum {
   LOR_EUNSUPPORTED = -4   /* valid input outside what this build handles */
 } lor_status;
 
-typedef enum { LOR_H1 = 0, LOR_ND = 1 } lor_space;
+typedef enum { LOR_H1 = 0, LOR_ND = 1, LOR_RT = 2 } lor_space;
 typedef enum { LOR_F64 = 0, LOR_F32 = 1 } lor_dtype;
 /* Diagonal entry of an eliminated row (lor_eliminate_bc). */
 typedef enum { LOR_DIAG_ONE = 0, LOR_DIAG_KEEP = 1, LOR_DIAG_ZERO = 2 } lor_diag_policy;
@@ -116,7 +116,8 @@ typedef struct lor_sched {
  * lor_pattern -- sparsity pattern (steps A1/A2: the shared local column pattern,
  * row counts, scan, column fill) and the assembly schedule.
  *
- *   space     LOR_H1: rows are mesh vertices; LOR_ND: rows are mesh edges.
+ *   space     LOR_H1: rows are mesh vertices; LOR_ND: rows are mesh edges;
+ *             LOR_RT: rows are mesh faces.
  *   p         polynomial degree, 1 <= p <= LOR_MAX_P.
  *   nel       number of (macro) elements, >= 0.
  *   nrows     number of global dofs (vertices or edges).
@@ -127,6 +128,9 @@ typedef struct lor_sched {
  *             (offset 2p(p+1)^2, index i + (p+1)(j + (p+1)k)); a local edge
  *             points along its +axis; entry v >= 0 is edge v with that
  *             orientation, v < 0 is edge -1-v with the opposite one.
+ *             LOR_RT: nloc = 3p^2(p+1) signed global face ids, in the layout
+ *             and sign convention given at lor_discrete_curl (normals along
+ *             +axis locally).
  *   row_ptr   [nrows+1] int32, written in phase 1.
  *   nnz       HOST int64, written in phase 1.
  *   col_idx   NULL selects phase 1.  Otherwise [nnz] int32, written in phase 2
@@ -187,6 +191,25 @@ int lor_assemble_h1(int p, int64_t nel, int64_t ndofs, int batch, const int32_t*
  */
 int lor_assemble_nd(int p, int64_t nel, int64_t ndofs_h1, int64_t nedges, int batch,
                     const int32_t* elem_dofs, const int32_t* elem_edges, const double* coords,
+                    const void* kappa, double beta, const int32_t* row_ptr, const lor_sched* sched,
+                    void* values, int dtype, unsigned flags, double det_ratio_thresh,
+                    int32_t* diag, void* stream);
+
+/*
+ * lor_assemble_rt -- values of the LOR H(div) matrix (Section 2.3: the
+ * lowest-order interpolation-histopolation case is the lowest-order
+ * Raviart-Thomas element on the LOR mesh; Step S1.2 with orientation signs,
+ * A2): on each subelement, with the contravariant Piola map N = J n / det J,
+ *   K_ab = sum_q w det J (div n_a / det J)(div n_b / det J),
+ *   M_ab = sum_q w det J (J n_a / det J).(J n_b / det J),
+ * times sigma_a sigma_b from the signed face map; A = kappa_s K + beta M.
+ *   elem_dofs   [nel][(p+1)^3] vertex map (geometry).
+ *   elem_faces  [nel][3p^2(p+1)] signed face map (the one given to lor_pattern
+ *               with LOR_RT; layout as at lor_discrete_curl).
+ *   nfaces      number of rows.  Other arguments as for lor_assemble_h1.
+ */
+int lor_assemble_rt(int p, int64_t nel, int64_t ndofs_h1, int64_t nfaces, int batch,
+                    const int32_t* elem_dofs, const int32_t* elem_faces, const double* coords,
                     const void* kappa, double beta, const int32_t* row_ptr, const lor_sched* sched,
                     void* values, int dtype, unsigned flags, double det_ratio_thresh,
                     int32_t* diag, void* stream);

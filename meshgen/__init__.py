@@ -440,13 +440,14 @@ def random_dofs(ndofs: int, count: int, seed: int, duplicates: bool = True) -> n
 
 # ---------------------------------------------------------------- named workloads
 
-#: The five workloads of the benchmark plan: (space, n, p, amp, sigma, beta, batch).
+#: The named workloads: (space, n, p, amp, sigma, beta, batch).
 CONFIGS = {
     "c1_h1_p2_uniform": dict(space="h1", n=4, p=2, amp=0.0, sigma=0.0, beta=0.0, batch=1),
     "c2_h1_p4_curved": dict(space="h1", n=16, p=4, amp=0.1, sigma=1.0, beta=1.0, batch=1),
     "c3_h1_p6_curved": dict(space="h1", n=32, p=6, amp=0.1, sigma=2.0, beta=1.0, batch=1),
     "c4_nd_p3_curved": dict(space="nd", n=24, p=3, amp=0.1, sigma=1.0, beta=1.0, batch=1),
     "c5_h1_p4_backward": dict(space="h1", n=16, p=4, amp=0.1, sigma=1.0, beta=1.0, batch=8),
+    "c6_rt_p3_curved": dict(space="rt", n=24, p=3, amp=0.1, sigma=1.0, beta=1.0, batch=1),
 }
 
 
@@ -468,4 +469,8 @@ def config_mesh(name: str, seed: int = 0) -> dict:
         ee, ned = nd_edge_map(c["n"], c["p"])
         m["elem_edges"] = ee
         m["nedges"] = ned
+    if c["space"] == "rt":
+        fm, nf = face_map(c["n"], c["p"])
+        m["elem_faces"] = fm
+        m["nfaces"] = nf
     return m

@@ -11,6 +11,7 @@ from .lor import (  # noqa: F401
     LOR_F64,
     LOR_H1,
     LOR_ND,
+    LOR_RT,
     LorError,
     LorH1,
     Pattern,
@@ -18,6 +19,7 @@ from .lor import (  # noqa: F401
     lor_assemble_backward,
     lor_assemble_h1,
     lor_assemble_nd,
+    lor_assemble_rt,
     lor_discrete_curl,
     lor_discrete_gradient,
     lor_eliminate_bc,

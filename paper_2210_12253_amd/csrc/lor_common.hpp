@@ -59,6 +59,7 @@ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 // Local dof counts per element.
 inline int nloc_h1(int p) { return (p + 1) * (p + 1) * (p + 1); }
 inline int nloc_nd(int p) { return 3 * p * (p + 1) * (p + 1); }
+inline int nloc_rt(int p) { return 3 * p * p * (p + 1); }
 
 // Per-element table entry: bits 0..6 = position of the entry inside its CSR
 // row, bit 7 = this element is the first (lowest colour) contributor.

@@ -8,10 +8,11 @@
 // pointer, then fills the columns.  This file does the integer half of that:
 //
 //   * reference element: the local stencil (which local dofs a local dof
-//     couples to: the 27-point lattice neighbourhood for vertices, the edges of
-//     the shared subelements for Nedelec edges), computed once on the host and
+//     couples to: the 27-point lattice neighbourhood for vertices, the edges
+//     (faces) of the shared subelements for Nedelec edges (Raviart-Thomas
+//     faces)), computed once on the host and
 //     copied into the schedule -- the analogue of the shared column array J_hat;
-//   * vertex/edge -> (element, local dof) incidence lists (transpose of the
+//   * vertex/edge/face -> (element, local dof) incidence lists (transpose of the
 //     element map, counting sort, each list sorted so the result is
 //     deterministic);
 //   * per row: the sorted union of the local stencils of every incident
@@ -181,7 +182,94 @@ static RefElem build_ref_nd(int p) {
   return r;
 }
 
-static RefElem build_ref(int space, int p) { return space == LOR_H1 ? build_ref_h1(p) : build_ref_nd(p); }
+static int rt_local(int p, int ax, int i, int j, int k) {
+  const int q = p + 1;
+  if (ax == 0) return i + q * (j + p * k);
+  if (ax == 1) return p * p * q + i + p * (j + q * k);
+  return 2 * p * p * q + i + p * (j + p * k);
+}
+
+// The 6 local faces of subelement (i,j,k): x-faces (xi = t) -> t, y-faces
+// (eta = t) -> 2 + t, z-faces (zeta = t) -> 4 + t.
+static void rt_sub_faces(int p, int i, int j, int k, int out[6]) {
+  for (int t = 0; t < 2; ++t) {
+    out[t] = rt_local(p, 0, i + t, j, k);
+    out[2 + t] = rt_local(p, 1, i, j + t, k);
+    out[4 + t] = rt_local(p, 2, i, j, k + t);
+  }
+}
+
+static int pair6(int u, int v) {
+  if (u > v) std::swap(u, v);
+  return 6 * u - (u * (u - 1)) / 2 + (v - u);
+}
+
+// Raviart-Thomas faces: every face couples to the faces of the (one or two)
+// subelements holding it; the recipe lists those subelements' contributions.
+static RefElem build_ref_rt(int p) {
+  RefElem r;
+  const int q = p + 1;
+  r.nloc = 3 * p * p * q;
+  std::vector<std::vector<int>> nbr(r.nloc);
+  std::vector<std::vector<int>> subs(r.nloc);
+  for (int k = 0; k < p; ++k)
+    for (int j = 0; j < p; ++j)
+      for (int i = 0; i < p; ++i) {
+        int fc[6];
+        rt_sub_faces(p, i, j, k, fc);
+        const int s = i + p * (j + p * k);
+        for (int u = 0; u < 6; ++u) {
+          subs[fc[u]].push_back(s);
+          for (int v = 0; v < 6; ++v) nbr[fc[u]].push_back(fc[v]);
+        }
+      }
+  r.st_ptr.push_back(0);
+  for (int l = 0; l < r.nloc; ++l) {
+    auto& v = nbr[l];
+    std::sort(v.begin(), v.end());
+    v.erase(std::unique(v.begin(), v.end()), v.end());
+    std::vector<int>& sl = subs[l];
+    std::sort(sl.begin(), sl.end());
+    for (int c : v) {
+      r.st_col.push_back(c);
+      r.ent_row.push_back(static_cast<uint16_t>(l));
+      uint64_t rec = ~0ull;
+      int m = 0;
+      for (int s : sl) {
+        const int si = s % p, sj = (s / p) % p, sk = s / (p * p);
+        int fc[6];
+        rt_sub_faces(p, si, sj, sk, fc);
+        int u = -1, w = -1;
+        for (int t = 0; t < 6; ++t) {
+          if (fc[t] == l) u = t;
+          if (fc[t] == c) w = t;
+        }
+        if (u < 0 || w < 0) continue;
+        const uint64_t code = static_cast<uint64_t>((s << 7) | pair6(u, w));
+        rec &= ~(0xffffull << (16 * m));
+        rec |= code << (16 * m);
+        ++m;
+      }
+      r.recipe64.push_back(rec);
+    }
+    r.st_ptr.push_back(static_cast<int32_t>(r.st_col.size()));
+  }
+  r.nent = static_cast<int>(r.st_col.size());
+  // one face on each coarse face: elements sharing a face dof share one of these
+  for (int t = 0; t < 2; ++t) {
+    r.reps.push_back(rt_local(p, 0, t * p, 0, 0));
+    r.reps.push_back(rt_local(p, 1, 0, t * p, 0));
+    r.reps.push_back(rt_local(p, 2, 0, 0, t * p));
+  }
+  std::sort(r.reps.begin(), r.reps.end());
+  return r;
+}
+
+static RefElem build_ref(int space, int p) {
+  if (space == LOR_H1) return build_ref_h1(p);
+  if (space == LOR_ND) return build_ref_nd(p);
+  return build_ref_rt(p);
+}
 
 // ------------------------------------------------------------------- scan
 
@@ -628,16 +716,17 @@ extern "C" int lor_pattern(int space, int p, int64_t nel, int64_t nrows, const i
                            int32_t* row_ptr, int64_t* nnz, int32_t* col_idx, lor_sched* sched,
                            void* stream) {
   clear_error();
-  if (space != LOR_H1 && space != LOR_ND) LOR_FAIL(LOR_EINVAL, "space must be LOR_H1 or LOR_ND");
+  if (space != LOR_H1 && space != LOR_ND && space != LOR_RT)
+    LOR_FAIL(LOR_EINVAL, "space must be LOR_H1, LOR_ND or LOR_RT");
   if (p < 1 || p > LOR_MAX_P) LOR_FAIL(LOR_EINVAL, "p = %d outside [1, %d]", p, LOR_MAX_P);
   if (nel < 0) LOR_FAIL(LOR_EINVAL, "nel < 0");
   if (nrows < 1) LOR_FAIL(LOR_EINVAL, "nrows < 1");
   if (!row_ptr || !nnz || !sched) LOR_FAIL(LOR_EINVAL, "row_ptr, nnz and sched must not be NULL");
   if (nel > 0 && !elem_map) LOR_FAIL(LOR_EINVAL, "elem_map is NULL");
-  const int nloc = space == LOR_H1 ? nloc_h1(p) : nloc_nd(p);
+  const int nloc = space == LOR_H1 ? nloc_h1(p) : space == LOR_ND ? nloc_nd(p) : nloc_rt(p);
   if (nel * static_cast<int64_t>(nloc) >= INT32_MAX) LOR_FAIL(LOR_EOVERFLOW, "nel * nloc >= 2^31");
   if (nrows >= INT32_MAX) LOR_FAIL(LOR_EOVERFLOW, "nrows >= 2^31 - 1");
-  const int is_signed = space == LOR_ND;
+  const int is_signed = space != LOR_H1;
   hipStream_t st = as_stream(stream);
   const RefElem ref = build_ref(space, p);
   const int64_t total = nel * nloc;
