@@ -317,6 +317,7 @@ def main():
         out["aux"] = bench_aux(lor, meshgen, pat, args, dev)
         out["backward"] = bench_backward(lor, meshgen, args, dev)
         out["nd"] = bench_nd(lor, meshgen, args, dev)
+        out["rt"] = bench_rt(lor, meshgen, args, dev)
         log("fp32 pencil eigenvalues")
         out["fp32"]["pencil_eigs"] = bench_fp32_pencil(lor, meshgen, dev, full=args.pencil_full)
         log("cpu baseline")
@@ -507,6 +508,28 @@ def bench_aux(lor, meshgen, pat_h1, args, dev):
     except lor.LorError as e:
         res["error"] = str(e)
     return res
+
+
+def bench_rt(lor, meshgen, args, dev):
+    import torch
+    try:
+        m = meshgen.config_mesh("c6_rt_p3_curved")
+        ed = torch.from_numpy(m["elem_dofs"]).to(dev)
+        fm = torch.from_numpy(m["elem_faces"]).to(dev)
+        x = torch.from_numpy(m["coords"]).to(dev)
+        pat = lor.lor_pattern(lor.LOR_RT, m["p"], fm, m["nfaces"])
+        res = {}
+        for name, dt in (("f64", torch.float64), ("f32", torch.float32)):
+            k = m["kappa"].to(dev, dt)
+            out = torch.empty(pat.nnz, dtype=dt, device=dev)
+            ms = time_it(lambda: lor.lor_assemble_rt(pat, ed, fm, x, k, 1.0, m["ndofs"], dtype=dt, out=out),
+                         args.steps, args.warmup)
+            res[name] = {"ms": ms, "value": m["nfaces"] / (ms * 1e-3) / 1e6, "unit": "MDOF/s"}
+        res["workload"] = "H(div) LOR assembly, p=3, 24^3 curved hexes, kappa sigma=1, beta=1"
+        res["rows"], res["nnz"], res["ncolors"] = m["nfaces"], pat.nnz, pat.ncolors
+        return res
+    except lor.LorError as e:
+        return {"error": str(e)}
 
 
 def bench_nd(lor, meshgen, args, dev):

@@ -33,10 +33,11 @@ struct RTCfg {
   static constexpr int NENTP = (NENT + 15) / 16 * 16;
   static constexpr int THREADS = 256;
   static constexpr int PER_EL = NSUB * 21 * static_cast<int>(sizeof(R)) + NENTP + NLOCV * 24 + NLOCF * 5;
-  // latency bound like the H(curl) kernel: small groups, several resident
-  // workgroups per CU (2 in FP64, 4 in FP32, as LDS allows)
+  // latency bound like the H(curl) kernel: small groups (2 elements at
+  // p = 3) and up to 4 resident workgroups per CU, as LDS allows; the RT
+  // integration needs ~128 VGPRs, so FP64 does not spill at 4 either
   static constexpr bool F64 = sizeof(R) == 8;
-  static constexpr int BUDGET = F64 ? 50 * 1024 : 30 * 1024;
+  static constexpr int BUDGET = F64 ? 16 * 1024 : 12 * 1024;
   static constexpr int E0 = THREADS / NSUB < 64 ? THREADS / NSUB : 64;
   static constexpr int E1 = BUDGET / PER_EL;
   static constexpr int E = (E0 < E1 ? E0 : E1) > 0 ? (E0 < E1 ? E0 : E1) : 1;
@@ -44,7 +45,7 @@ struct RTCfg {
   static constexpr int CH = 8;  // phase-2 entries per lane handled together
   static constexpr int MAXCHUNK = 256;
   static constexpr int LDS = E * PER_EL + 2 * MAXCHUNK * 4 + 256;
-  static constexpr int WPC0 = F64 ? 2 : 4;
+  static constexpr int WPC0 = 4;
   static constexpr int WPC1 = 160 * 1024 / LDS;
   static constexpr int WPC = (WPC0 < WPC1 ? WPC0 : WPC1) > 0 ? (WPC0 < WPC1 ? WPC0 : WPC1) : 1;
   static_assert(E * NSUB <= THREADS, "one subelement per lane");
