@@ -215,6 +215,40 @@ int lor_assemble_rt(int p, int64_t nel, int64_t ndofs_h1, int64_t nfaces, int ba
                     int32_t* diag, void* stream);
 
 /*
+ * lor_refine_map -- the LOR mesh made explicit: every subelement of every
+ * macro element becomes an element of its own with 8 vertex ids (the setup the
+ * paper's unstructured comparator needs; Section 4, assembly results).
+ *   elem_dofs  [nel][(p+1)^3] vertex map.
+ *   sub_map    [nel * p^3][8] int32, written: element e p^3 + s (s = i + p(j +
+ *              p k)), corner v = a + 2b + 4c -> vertex (i+a, j+b, k+c) of e.
+ * Asynchronous on `stream`.  Errors: LOR_EINVAL, LOR_EOVERFLOW.
+ */
+int lor_refine_map(int p, int64_t nel, const int32_t* elem_dofs, int32_t* sub_map, void* stream);
+
+/*
+ * lor_assemble_h1_unstructured -- the generic comparator of Section 4's
+ * assembly results: the same H1 LOR matrix (FP64) assembled without the
+ * macro-element structure.  One group of 8 lanes per trilinear element, one
+ * lane per element dof: the element's 8x8 matrix, then each lane adds its row
+ * into the global CSR matrix (position by binary search in the row, FP64
+ * atomic add).  The summation order varies between runs (rounding-level
+ * differences; not bitwise reproducible, unlike lor_assemble_h1).
+ *   nsub, sub_map   [nsub][8] element vertex ids (e.g. from lor_refine_map).
+ *   kappa           [nsub] FP64 per element; beta scalar.
+ *   row_ptr, col_idx, nnz   the CSR pattern (e.g. lor_pattern of the macro mesh).
+ *   values          [nnz] FP64, zeroed then accumulated.
+ *   diag            NULL or device int32[2]: [0] += element entries whose
+ *                   column is not in the row, or elements with a vertex id
+ *                   outside [0, ndofs) (skipped); [1] += elements with
+ *                   det J <= 0 at a quadrature point.  The caller zeroes it.
+ * Asynchronous on `stream`.  Errors: LOR_EINVAL, LOR_EOVERFLOW.
+ */
+int lor_assemble_h1_unstructured(int64_t nsub, int64_t ndofs, int64_t nnz, const int32_t* sub_map,
+                                 const double* coords, const double* kappa, double beta,
+                                 const int32_t* row_ptr, const int32_t* col_idx, double* values,
+                                 int32_t* diag, void* stream);
+
+/*
  * lor_assemble_backward -- adjoint of lor_assemble_h1 with respect to kappa and
  * the vertex coordinates, for the loss L = sum_b <grad_values[b], values[b]>:
  *   grad_kappa[b][e][s] = dL/dkappa[b][e][s]                   (overwritten)

@@ -18,6 +18,7 @@ from .lor import (  # noqa: F401
     load_library,
     lor_assemble_backward,
     lor_assemble_h1,
+    lor_assemble_h1_unstructured,
     lor_assemble_nd,
     lor_assemble_rt,
     lor_discrete_curl,
@@ -26,4 +27,5 @@ from .lor import (  # noqa: F401
     lor_evec_to_tvec,
     lor_interp_nodes,
     lor_pattern,
+    lor_refine_map,
 )

@@ -30,6 +30,8 @@ ABI_SYMBOLS = (
     "lor_assemble_nd",
     "lor_assemble_rt",
     "lor_assemble_backward",
+    "lor_refine_map",
+    "lor_assemble_h1_unstructured",
     "lor_backward_workspace",
     "lor_eliminate_bc",
     "lor_discrete_gradient",
@@ -119,6 +121,10 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.lor_interp_nodes.restype = i32
     lib.lor_evec_to_tvec.argtypes = [i32, i64, i64, ctypes.POINTER(LorSched), i32, vp, vp, vp, vp]
     lib.lor_evec_to_tvec.restype = i32
+    lib.lor_refine_map.argtypes = [i32, i64, vp, vp, vp]
+    lib.lor_refine_map.restype = i32
+    lib.lor_assemble_h1_unstructured.argtypes = [i64, i64, i64, vp, vp, vp, f64, vp, vp, vp, vp, vp]
+    lib.lor_assemble_h1_unstructured.restype = i32
     lib.lor_backward_workspace.argtypes = [i32, i64]
     lib.lor_backward_workspace.restype = sz
     lib.lor_sched_bytes.argtypes = []
@@ -389,6 +395,39 @@ def lor_evec_to_tvec(pat: Pattern, evec: torch.Tensor, diag: torch.Tensor | None
         out = torch.empty((pat.nrows, nc), dtype=torch.float64, device=dev)
     _check(lib.lor_evec_to_tvec(pat.p, pat.nel, pat.nrows, ctypes.byref(pat.sched), nc, _ptr(E), _ptr(out),
                                 _ptr(diag), _stream()))
+    return out
+
+
+def lor_refine_map(p: int, elem_dofs, device=None, out: torch.Tensor | None = None) -> torch.Tensor:
+    """Explicit LOR mesh: [nel * p^3, 8] int32 vertex ids of every subelement."""
+    lib = load_library()
+    dev = torch.device("cuda") if device is None else torch.device(device)
+    ed = _dev_tensor(elem_dofs, torch.int32, "elem_dofs", dev)
+    nel = ed.shape[0]
+    if out is None:
+        out = torch.empty((nel * p ** 3, 8), dtype=torch.int32, device=dev)
+    elif out.shape != (nel * p ** 3, 8) or out.dtype != torch.int32:
+        raise ValueError("out must be [nel * p^3, 8] int32")
+    _check(lib.lor_refine_map(p, nel, _ptr(ed), _ptr(out), _stream()))
+    return out
+
+
+def lor_assemble_h1_unstructured(pat: Pattern, sub_map, coords, kappa, beta: float,
+                                 diag: torch.Tensor | None = None, out: torch.Tensor | None = None) -> torch.Tensor:
+    """The generic comparator: the H1 LOR matrix (FP64) from the explicit LOR
+    mesh with per-element dense matrices and atomic adds (not bitwise
+    reproducible).  `pat` supplies the CSR pattern; kappa is per subelement."""
+    lib = load_library()
+    dev = pat.row_ptr.device
+    sm = _dev_tensor(sub_map, torch.int32, "sub_map", dev)
+    x = _dev_tensor(coords, torch.float64, "coords", dev)
+    k = _dev_tensor(kappa, torch.float64, "kappa", dev).reshape(-1)
+    if sm.dim() != 2 or sm.shape[1] != 8 or k.numel() != sm.shape[0]:
+        raise ValueError("sub_map must be [nsub, 8] and kappa hold one value per element")
+    if out is None:
+        out = torch.empty(pat.nnz, dtype=torch.float64, device=dev)
+    _check(lib.lor_assemble_h1_unstructured(sm.shape[0], pat.nrows, pat.nnz, _ptr(sm), _ptr(x), _ptr(k), float(beta),
+                                            _ptr(pat.row_ptr), _ptr(pat.col_idx), _ptr(out), _ptr(diag), _stream()))
     return out
 
 
