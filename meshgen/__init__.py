@@ -36,10 +36,12 @@ import torch
 __all__ = [
     "gll_points",
     "cartesian_mesh",
+    "cartesian_mesh_2d",
     "affine_mesh",
     "nd_edge_map",
     "face_map",
     "kappa_field",
+    "kappa_field_2d",
     "cotangent",
     "renumber_vertices",
     "permute_elements",
@@ -132,6 +134,31 @@ def cartesian_mesh(n: int, p: int, amp: float = 0.0) -> dict:
         "nel": n ** 3,
         "ndofs": N ** 3,
     }
+
+
+def cartesian_mesh_2d(n: int, p: int, amp: float = 0.0) -> dict:
+    """n^2 quadrilaterals of degree p on the unit square (the 2D variant):
+    element e = ex + n*ey, local vertex i + (p+1)*j, global vertex X + N*Y with
+    N = n*p + 1 on the Gauss-Lobatto lattice, every lattice vertex moved by
+        x' = x + A sin(2 pi y),  y' = y + A sin(2 pi x),   A = amp / n.
+    Returns coords [N^2, 2] float64, elem_dofs [n^2, (p+1)^2] int32, n, p, N,
+    nel, ndofs."""
+    N = n * p + 1
+    q = p + 1
+    x1 = _lattice_1d(n, p)
+    X, Y = np.meshgrid(x1, x1, indexing="xy")   # [Y][X]
+    X, Y = X.reshape(-1), Y.reshape(-1)
+    A = amp / n
+    if A != 0.0:
+        tp = 2.0 * math.pi
+        X, Y = X + A * np.sin(tp * Y), Y + A * np.sin(tp * X)
+    e = np.arange(n * n)
+    ex, ey = e % n, e // n
+    j, i = np.meshgrid(np.arange(q), np.arange(q), indexing="ij")
+    i, j = i.reshape(-1), j.reshape(-1)          # local vertex i + q*j
+    g = (p * ex[:, None] + i[None, :]) + N * (p * ey[:, None] + j[None, :])
+    return {"coords": np.stack([X, Y], axis=1).astype(np.float64), "elem_dofs": g.astype(np.int32),
+            "n": n, "p": p, "N": N, "nel": n * n, "ndofs": N * N}
 
 
 def affine_mesh(n: int, p: int, A: np.ndarray, t: np.ndarray) -> dict:
@@ -228,6 +255,15 @@ def kappa_field(nel: int, p: int, sigma: float, seed: int = 0, batch: int | None
     z = torch.randn((B, nel, p, p, p), generator=g, dtype=torch.float64)
     k = torch.exp(sigma * z).reshape(B, nel, p ** 3)
     return k[0] if batch is None else k
+
+
+def kappa_field_2d(nel: int, p: int, sigma: float, seed: int = 0) -> torch.Tensor:
+    """2D counterpart of kappa_field: exp(sigma z) per subelement, z drawn as
+    randn((nel, p, p)) (index [e][j][i], subelement i + p*j), float64."""
+    g = torch.Generator(device="cpu")
+    g.manual_seed(seed)
+    z = torch.randn((nel, p, p), generator=g, dtype=torch.float64)
+    return torch.exp(sigma * z).reshape(nel, p * p)
 
 
 def cotangent(batch: int, nnz: int, seed: int = 1) -> torch.Tensor:
@@ -448,12 +484,19 @@ CONFIGS = {
     "c4_nd_p3_curved": dict(space="nd", n=24, p=3, amp=0.1, sigma=1.0, beta=1.0, batch=1),
     "c5_h1_p4_backward": dict(space="h1", n=16, p=4, amp=0.1, sigma=1.0, beta=1.0, batch=8),
     "c6_rt_p3_curved": dict(space="rt", n=24, p=3, amp=0.1, sigma=1.0, beta=1.0, batch=1),
+    "c7_h1_2d_p6_curved": dict(space="h1_2d", n=512, p=6, amp=0.1, sigma=2.0, beta=1.0, batch=1),
 }
 
 
 def config_mesh(name: str, seed: int = 0) -> dict:
     """Mesh, coefficients (and edge map for H(curl)) of a named workload."""
     c = CONFIGS[name]
+    if c["space"] == "h1_2d":
+        m = cartesian_mesh_2d(c["n"], c["p"], c["amp"])
+        m["kappa"] = kappa_field_2d(m["nel"], c["p"], c["sigma"], seed)
+        m["beta"] = c["beta"]
+        m["config"] = dict(c, name=name)
+        return m
     m = cartesian_mesh(c["n"], c["p"], c["amp"])
     if c["sigma"] == 0.0:
         kap = torch.ones((m["nel"], c["p"] ** 3), dtype=torch.float64)

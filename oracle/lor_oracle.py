@@ -54,6 +54,8 @@ __all__ = [
     "h1_rows",
     "nd_matrix",
     "nd_rows",
+    "h1_matrix_2d",
+    "h1_rows_2d",
     "rt_subelement_faces",
     "rt_subelement_matrices",
     "rt_matrix",
@@ -230,6 +232,89 @@ def nd_subelement_matrices(X: torch.Tensor, kappa: torch.Tensor, beta) -> torch.
     M = torch.einsum("sq,sqac,sqbc->sab", w * det, Nphys, Nphys)
     M = M * (bet[:, None, None] if bet.dim() == 1 else bet)
     return K + M
+
+
+# ------------------------------------------------------------------ H1 in 2D
+
+def _q1_reference_2d():
+    """Bilinear shape functions phi[q, v] and reference gradients g[q, v, c] at
+    the 2x2 Gauss points q = q1 + 2 q2 (weight 1/4); vertex v = a + 2b at
+    reference corner (a, b)."""
+    phi = torch.zeros(4, 4, dtype=torch.float64)
+    grad = torch.zeros(4, 4, 2, dtype=torch.float64)
+    for q2 in range(2):
+        for q1 in range(2):
+            q = q1 + 2 * q2
+            x, y = GAUSS_T[q1], GAUSS_T[q2]
+            for v in range(4):
+                a, b = v & 1, v >> 1
+                phi[q, v] = _l(a, x) * _l(b, y)
+                grad[q, v, 0] = _dl(a) * _l(b, y)
+                grad[q, v, 1] = _l(a, x) * _dl(b)
+    return phi, grad, 0.25
+
+
+def _coo_h1_2d(coords, elem_dofs, p, kappa, beta, elems=None):
+    """The 2D variant of the LOR mesh and matrix (p x p bilinear subelements
+    per quadrilateral macro element, Q1 diffusion + mass, 2x2 Gauss):
+      K_uv = sum_q w kappa det(J) (J^-T g_u).(J^-T g_v),  M_uv = sum_q w beta det(J) phi_u phi_v."""
+    X = _as_f64(coords)
+    kap = _as_f64(kappa)
+    ed = torch.as_tensor(elem_dofs).to(torch.int64)
+    if elems is not None:
+        elems = torch.as_tensor(elems, dtype=torch.int64)
+        ed, kap = ed[elems], kap[elems]
+    q = p + 1
+    idx = torch.empty(p * p, 4, dtype=torch.int64)
+    for j in range(p):
+        for i in range(p):
+            for v in range(4):
+                a, b = v & 1, v >> 1
+                idx[i + p * j, v] = (i + a) + q * (j + b)
+    sv = ed[:, idx].reshape(-1, 4)
+    Xs = X[sv]                                                   # [S, 4, 2]
+    phi, grad, w = _q1_reference_2d()
+    J = torch.einsum("svr,qvc->sqrc", Xs, grad)
+    det = torch.linalg.det(J)
+    if bool((det <= 0).any()):
+        raise ValueError("inverted LOR subelement (det J <= 0 at a quadrature point)")
+    Jinv = torch.linalg.inv(J)
+    gp = torch.einsum("qvr,sqrc->sqvc", grad, Jinv)
+    K = torch.einsum("sq,sqvc,squc->svu", w * det, gp, gp) * kap.reshape(-1)[:, None, None]
+    M = torch.einsum("sq,qv,qu->svu", w * det, phi, phi) * float(beta)
+    A = K + M
+    R = sv[:, :, None].expand(-1, 4, 4).reshape(-1)
+    C = sv[:, None, :].expand(-1, 4, 4).reshape(-1)
+    return R, C, A.reshape(-1)
+
+
+def h1_matrix_2d(coords, elem_dofs, p: int, kappa, beta, ndofs: int | None = None):
+    """Assembled 2D LOR H1 matrix in CSR (9 nonzeros per interior row)."""
+    R, C, V = _coo_h1_2d(coords, elem_dofs, p, kappa, beta)
+    n = int(ndofs) if ndofs is not None else int(torch.as_tensor(coords).shape[0])
+    return coo_to_csr(R, C, V, n)
+
+
+def h1_rows_2d(coords, elem_dofs, p: int, kappa, beta, rows):
+    """The listed rows of the 2D LOR H1 matrix (same definition as h1_matrix_2d)."""
+    rows = torch.unique(torch.as_tensor(rows, dtype=torch.int64))
+    ed = torch.as_tensor(elem_dofs).to(torch.int64)
+    elems = _elements_touching(ed, rows)
+    R, C, V = _coo_h1_2d(coords, elem_dofs, p, kappa, beta, elems=elems)
+    keep = torch.isin(R, rows)
+    R, C, V = R[keep], C[keep], V[keep]
+    pos = torch.searchsorted(rows, R)
+    stride = int(C.max().item()) + 1 if C.numel() else 1
+    key = pos * stride + C
+    order = torch.argsort(key, stable=True)
+    uniq, inverse = torch.unique_consecutive(key[order], return_inverse=True)
+    values = torch.zeros(uniq.numel(), dtype=torch.float64).index_add(0, inverse, V[order])
+    r = uniq // stride
+    col_idx = uniq - r * stride
+    counts = torch.bincount(r, minlength=rows.numel())
+    row_ptr = torch.zeros(rows.numel() + 1, dtype=torch.int64)
+    row_ptr[1:] = torch.cumsum(counts, 0)
+    return rows, row_ptr, col_idx, values
 
 
 # --------------------------------------------------------------------- H(div)

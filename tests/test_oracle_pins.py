@@ -880,3 +880,77 @@ def test_rt_pattern_count_and_sign_flip():
     rp2, ci2, v2 = orc.rt_matrix(m["coords"], m["elem_dofs"], fm2, p, kap, 0.8, nf)
     A, A2 = dense(rp, ci, v), dense(rp2, ci2, v2)
     assert np.abs(A2 - S[:, None] * A * S[None, :]).max() <= 1e-14 * np.abs(A).max()
+
+
+# ----------------------------------------------------------------- H1 in 2D
+
+def test_h1_2d_closed_form_uniform_square():
+    """Uniform lattice (p <= 2, where the Gauss-Lobatto points are
+    equispaced): every entry equals (#cells holding both vertices) x (the
+    bilinear cell-matrix entry for their offset), stiffness 2/3, -1/6, -1/3
+    and mass h^2 (1/9, 1/18, 1/36) for offsets differing in 0, 1, 2
+    coordinates -- derived from 1D element matrices by tensor products."""
+    n, p = 3, 2
+    m = meshgen.cartesian_mesh_2d(n, p, 0.0)
+    N = m["N"]
+    h = 1.0 / (N - 1)
+    kap = torch.full((m["nel"], p * p), 1.7, dtype=torch.float64)
+    rp, ci, v = orc.h1_matrix_2d(m["coords"], m["elem_dofs"], p, kap, 0.9)
+    S1 = np.array([[1.0, -1.0], [-1.0, 1.0]])
+    M1 = np.array([[2.0, 1.0], [1.0, 2.0]]) / 6.0
+    Kc = 1.7 * (np.kron(M1, S1) + np.kron(S1, M1))   # cell matrix, vertex a + 2b
+    Mc = 0.9 * h * h * np.kron(M1, M1)
+    want = np.zeros((N * N, N * N))
+    for cy in range(N - 1):
+        for cx in range(N - 1):
+            g = [(cx + a) + N * (cy + b) for b in range(2) for a in range(2)]
+            for u in range(4):
+                for w in range(4):
+                    want[g[u], g[w]] += Kc[u, w] + Mc[u, w]
+    A = dense(rp, ci, v)
+    assert np.abs(A - want).max() <= 1e-14 * np.abs(want).max()
+    c = N * 2 + 2
+    assert abs(A[c, c] - 1.7 * 8 / 3 - 0.9 * 4 * h * h / 9) <= 1e-14
+
+
+def test_h1_2d_row_sums_and_area():
+    """Curved quads, random kappa: stiffness rows sum to 0 (constants are in
+    the kernel); with kappa = 0 and beta = 1 the sum of all entries is the
+    area of the bilinear mesh, computed here cell by cell with the shoelace
+    formula (2x2 Gauss integrates det J of a bilinear map exactly)."""
+    n, p = 3, 4
+    m = meshgen.cartesian_mesh_2d(n, p, 0.15)
+    kap = meshgen.kappa_field_2d(m["nel"], p, 1.0, seed=2)
+    rp, ci, v = orc.h1_matrix_2d(m["coords"], m["elem_dofs"], p, kap, 0.0)
+    A = dense(rp, ci, v)
+    assert np.abs(A.sum(axis=1)).max() <= 1e-13 * np.abs(A).max()
+    assert np.abs(A - A.T).max() <= 1e-14 * np.abs(A).max()
+    rp, ci, v = orc.h1_matrix_2d(m["coords"], m["elem_dofs"], p, torch.zeros_like(kap), 1.0)
+    X = m["coords"]
+    N = m["N"]
+    area = 0.0
+    for cy in range(N - 1):
+        for cx in range(N - 1):
+            P = [X[(cx + a) + N * (cy + b)] for a, b in ((0, 0), (1, 0), (1, 1), (0, 1))]
+            area += 0.5 * sum(P[k][0] * P[(k + 1) % 4][1] - P[(k + 1) % 4][0] * P[k][1] for k in range(4))
+    assert abs(float(v.sum()) - area) <= 1e-13
+
+
+def test_h1_2d_affine_energy_and_pattern():
+    """Affine map x -> B x + t: for u = a . x, U^T K U = kappa |a|^2 area;
+    nnz = (3N - 2)^2 and 9 entries per interior row (the 2D counts of
+    Section 4.1 follow from the same formula, see the count pin)."""
+    n, p = 2, 3
+    m = meshgen.cartesian_mesh_2d(n, p, 0.0)
+    B = np.array([[1.2, 0.3], [-0.2, 0.8]])
+    X = m["coords"] @ B.T + np.array([0.4, -1.0])
+    kap = torch.full((m["nel"], p * p), 0.6, dtype=torch.float64)
+    rp, ci, v = orc.h1_matrix_2d(X, m["elem_dofs"], p, kap, 0.0)
+    a = np.array([0.7, -1.1])
+    U = X @ a
+    K = dense(rp, ci, v)
+    want = 0.6 * (a @ a) * np.linalg.det(B)
+    assert abs(U @ K @ U - want) <= 1e-12 * want
+    N = m["N"]
+    assert rp[-1].item() == (3 * N - 2) ** 2
+    assert int((rp[1:] - rp[:-1]).max()) == 9
