@@ -319,6 +319,7 @@ def main():
         out["backward"] = bench_backward(lor, meshgen, args, dev)
         out["nd"] = bench_nd(lor, meshgen, args, dev)
         out["rt"] = bench_rt(lor, meshgen, args, dev)
+        out["h1_2d"] = bench_2d(lor, meshgen, args, dev)
         log("fp32 pencil eigenvalues")
         out["fp32"]["pencil_eigs"] = bench_fp32_pencil(lor, meshgen, dev, full=args.pencil_full)
         log("cpu baseline")
@@ -528,6 +529,29 @@ def bench_unstructured(lor, meshgen, m, pat, ms_macro, args, dev):
         return {"ms": ms, "value": m["ndofs"] / (ms * 1e-3) / 1e6, "unit": "MDOF/s",
                 "refine_map_ms": ms_map, "macro_speedup": ms / ms_macro,
                 "workload": "H1 p=6 32^3 as 7,077,888 explicit trilinear elements, FP64, atomic adds"}
+    except lor.LorError as e:
+        return {"error": str(e)}
+
+
+def bench_2d(lor, meshgen, args, dev):
+    """The paper's 2D workload (Section 4.1): H1 p=6 on 512^2 quadrilaterals,
+    9,443,329 rows and 84,953,089 nonzeros."""
+    import torch
+    try:
+        m = meshgen.config_mesh("c7_h1_2d_p6_curved")
+        ed = torch.from_numpy(m["elem_dofs"]).to(dev)
+        x = torch.from_numpy(m["coords"]).to(dev)
+        pat = lor.lor_pattern(lor.LOR_H1_2D, 6, ed, m["ndofs"])
+        res = {}
+        for name, dt in (("f64", torch.float64), ("f32", torch.float32)):
+            k = m["kappa"].to(dev, dt)
+            out = torch.empty(pat.nnz, dtype=dt, device=dev)
+            ms = time_it(lambda: lor.lor_assemble_h1_2d(pat, ed, x, k, m["beta"], dtype=dt, out=out),
+                         args.steps, args.warmup)
+            res[name] = {"ms": ms, "value": m["ndofs"] / (ms * 1e-3) / 1e6, "unit": "MDOF/s"}
+        res["workload"] = "2D H1 LOR assembly, p=6, 512^2 curved quadrilaterals, kappa sigma=2, beta=1"
+        res["rows"], res["nnz"], res["ncolors"] = m["ndofs"], pat.nnz, pat.ncolors
+        return res
     except lor.LorError as e:
         return {"error": str(e)}
 

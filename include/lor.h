@@ -55,7 +55,7 @@ typedef enum {
   LOR_EUNSUPPORTED = -4   /* valid input outside what this build handles */
 } lor_status;
 
-typedef enum { LOR_H1 = 0, LOR_ND = 1, LOR_RT = 2 } lor_space;
+typedef enum { LOR_H1 = 0, LOR_ND = 1, LOR_RT = 2, LOR_H1_2D = 3 } lor_space;
 typedef enum { LOR_F64 = 0, LOR_F32 = 1 } lor_dtype;
 /* Diagonal entry of an eliminated row (lor_eliminate_bc). */
 typedef enum { LOR_DIAG_ONE = 0, LOR_DIAG_KEEP = 1, LOR_DIAG_ZERO = 2 } lor_diag_policy;
@@ -117,7 +117,8 @@ typedef struct lor_sched {
  * row counts, scan, column fill) and the assembly schedule.
  *
  *   space     LOR_H1: rows are mesh vertices; LOR_ND: rows are mesh edges;
- *             LOR_RT: rows are mesh faces.
+ *             LOR_RT: rows are mesh faces; LOR_H1_2D: rows are the vertices
+ *             of a 2D (quadrilateral) mesh.
  *   p         polynomial degree, 1 <= p <= LOR_MAX_P.
  *   nel       number of (macro) elements, >= 0.
  *   nrows     number of global dofs (vertices or edges).
@@ -128,6 +129,8 @@ typedef struct lor_sched {
  *             (offset 2p(p+1)^2, index i + (p+1)(j + (p+1)k)); a local edge
  *             points along its +axis; entry v >= 0 is edge v with that
  *             orientation, v < 0 is edge -1-v with the opposite one.
+ *             LOR_H1_2D: nloc = (p+1)^2 global vertex ids, local vertex
+ *             i + (p+1)j.
  *             LOR_RT: nloc = 3p^2(p+1) signed global face ids, in the layout
  *             and sign convention given at lor_discrete_curl (normals along
  *             +axis locally).
@@ -213,6 +216,25 @@ int lor_assemble_rt(int p, int64_t nel, int64_t ndofs_h1, int64_t nfaces, int ba
                     const void* kappa, double beta, const int32_t* row_ptr, const lor_sched* sched,
                     void* values, int dtype, unsigned flags, double det_ratio_thresh,
                     int32_t* diag, void* stream);
+
+/*
+ * lor_assemble_h1_2d -- values of the 2D LOR H1 matrix (the 2D variant of
+ * Step S1.2; Section 4.1 measures it at 9 nonzeros per row): each degree-p
+ * quadrilateral macro element is cut at its Gauss-Lobatto lattice into p^2
+ * bilinear subelements, and A = sum_s kappa_s K^s + beta M^s with
+ *   K_uv = sum_q w det J (J^-T g_u).(J^-T g_v),  M_uv = sum_q w det J phi_u phi_v,
+ * 2x2 Gauss points q (w = 1/4) on each subelement.
+ *   elem_dofs  [nel][(p+1)^2] vertex ids, local vertex i + (p+1)j.
+ *   coords     [ndofs][2] float64.
+ *   kappa      [batch][nel][p^2] in dtype, subelement i + p j.
+ *   sched      from lor_pattern(LOR_H1_2D, p, elem_dofs).
+ * Other arguments, the FP32 form and its fallback (corner-Jacobian ratio of
+ * the 4 corners) as for lor_assemble_h1.
+ */
+int lor_assemble_h1_2d(int p, int64_t nel, int64_t ndofs, int batch, const int32_t* elem_dofs,
+                       const double* coords, const void* kappa, double beta, const int32_t* row_ptr,
+                       const lor_sched* sched, void* values, int dtype, unsigned flags,
+                       double det_ratio_thresh, int32_t* diag, void* stream);
 
 /*
  * lor_refine_map -- the LOR mesh made explicit: every subelement of every

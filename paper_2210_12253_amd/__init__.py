@@ -10,6 +10,7 @@ from .lor import (  # noqa: F401
     LOR_F32,
     LOR_F64,
     LOR_H1,
+    LOR_H1_2D,
     LOR_ND,
     LOR_RT,
     LorError,
@@ -18,6 +19,7 @@ from .lor import (  # noqa: F401
     load_library,
     lor_assemble_backward,
     lor_assemble_h1,
+    lor_assemble_h1_2d,
     lor_assemble_h1_unstructured,
     lor_assemble_nd,
     lor_assemble_rt,

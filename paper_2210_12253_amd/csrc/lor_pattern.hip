@@ -265,9 +265,54 @@ static RefElem build_ref_rt(int p) {
   return r;
 }
 
+// 2D H1 (quadrilateral macro elements, bilinear subelements): the 9-point
+// lattice neighbourhood, with the recipe of every local entry (the <= 4
+// subelements holding both vertices, vertex pair index among the 10 pairs of
+// a subelement's corners v = a + 2b).
+static RefElem build_ref_h1_2d(int p) {
+  RefElem r;
+  const int q = p + 1;
+  r.nloc = q * q;
+  auto pair4 = [](int u, int v) {
+    if (u > v) std::swap(u, v);
+    return 4 * u - (u * (u - 1)) / 2 + (v - u);
+  };
+  r.st_ptr.push_back(0);
+  for (int j = 0; j < q; ++j)
+    for (int i = 0; i < q; ++i) {
+      const int l = i + q * j;
+      for (int dy = -1; dy <= 1; ++dy)
+        for (int dx = -1; dx <= 1; ++dx) {
+          const int a2 = i + dx, b2 = j + dy;
+          if (a2 < 0 || b2 < 0 || a2 > p || b2 > p) continue;
+          r.st_col.push_back(a2 + q * b2);
+          r.ent_row.push_back(static_cast<uint16_t>(l));
+          uint64_t rec = ~0ull;
+          int m = 0;
+          for (int sj = 0; sj < p; ++sj)
+            for (int si = 0; si < p; ++si) {  // increasing subelement index
+              const int u = (i - si) + 2 * (j - sj), w = (a2 - si) + 2 * (b2 - sj);
+              if (i - si < 0 || i - si > 1 || j - sj < 0 || j - sj > 1) continue;
+              if (a2 - si < 0 || a2 - si > 1 || b2 - sj < 0 || b2 - sj > 1) continue;
+              const int s = si + p * sj;
+              rec &= ~(0xffffull << (16 * m));
+              rec |= static_cast<uint64_t>((s << 7) | pair4(u, w)) << (16 * m);
+              ++m;
+            }
+          r.recipe64.push_back(rec);
+        }
+      r.st_ptr.push_back(static_cast<int32_t>(r.st_col.size()));
+    }
+  r.nent = static_cast<int>(r.st_col.size());
+  for (int b = 0; b < 2; ++b)
+    for (int a = 0; a < 2; ++a) r.reps.push_back(a * p + q * (b * p));
+  return r;
+}
+
 static RefElem build_ref(int space, int p) {
   if (space == LOR_H1) return build_ref_h1(p);
   if (space == LOR_ND) return build_ref_nd(p);
+  if (space == LOR_H1_2D) return build_ref_h1_2d(p);
   return build_ref_rt(p);
 }
 
@@ -716,17 +761,20 @@ extern "C" int lor_pattern(int space, int p, int64_t nel, int64_t nrows, const i
                            int32_t* row_ptr, int64_t* nnz, int32_t* col_idx, lor_sched* sched,
                            void* stream) {
   clear_error();
-  if (space != LOR_H1 && space != LOR_ND && space != LOR_RT)
-    LOR_FAIL(LOR_EINVAL, "space must be LOR_H1, LOR_ND or LOR_RT");
+  if (space != LOR_H1 && space != LOR_ND && space != LOR_RT && space != LOR_H1_2D)
+    LOR_FAIL(LOR_EINVAL, "space must be LOR_H1, LOR_ND, LOR_RT or LOR_H1_2D");
   if (p < 1 || p > LOR_MAX_P) LOR_FAIL(LOR_EINVAL, "p = %d outside [1, %d]", p, LOR_MAX_P);
   if (nel < 0) LOR_FAIL(LOR_EINVAL, "nel < 0");
   if (nrows < 1) LOR_FAIL(LOR_EINVAL, "nrows < 1");
   if (!row_ptr || !nnz || !sched) LOR_FAIL(LOR_EINVAL, "row_ptr, nnz and sched must not be NULL");
   if (nel > 0 && !elem_map) LOR_FAIL(LOR_EINVAL, "elem_map is NULL");
-  const int nloc = space == LOR_H1 ? nloc_h1(p) : space == LOR_ND ? nloc_nd(p) : nloc_rt(p);
+  const int nloc = space == LOR_H1      ? nloc_h1(p)
+                   : space == LOR_ND    ? nloc_nd(p)
+                   : space == LOR_H1_2D ? (p + 1) * (p + 1)
+                                        : nloc_rt(p);
   if (nel * static_cast<int64_t>(nloc) >= INT32_MAX) LOR_FAIL(LOR_EOVERFLOW, "nel * nloc >= 2^31");
   if (nrows >= INT32_MAX) LOR_FAIL(LOR_EOVERFLOW, "nrows >= 2^31 - 1");
-  const int is_signed = space != LOR_H1;
+  const int is_signed = space == LOR_ND || space == LOR_RT;
   hipStream_t st = as_stream(stream);
   const RefElem ref = build_ref(space, p);
   const int64_t total = nel * nloc;

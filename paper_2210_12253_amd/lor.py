@@ -16,7 +16,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblor.so")
 
 LOR_OK, LOR_EINVAL, LOR_EOVERFLOW, LOR_EDEVICE, LOR_EUNSUPPORTED = 0, -1, -2, -3, -4
-LOR_H1, LOR_ND, LOR_RT = 0, 1, 2
+LOR_H1, LOR_ND, LOR_RT, LOR_H1_2D = 0, 1, 2, 3
 LOR_F64, LOR_F32 = 0, 1
 LOR_MAX_P = 6
 LOR_MAX_COLORS = 64
@@ -29,6 +29,7 @@ ABI_SYMBOLS = (
     "lor_assemble_h1",
     "lor_assemble_nd",
     "lor_assemble_rt",
+    "lor_assemble_h1_2d",
     "lor_assemble_backward",
     "lor_refine_map",
     "lor_assemble_h1_unstructured",
@@ -107,6 +108,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.lor_assemble_rt.argtypes = [i32, i64, i64, i64, i32, vp, vp, vp, vp, f64, vp, ctypes.POINTER(LorSched), vp,
                                     i32, u32, f64, vp, vp]
     lib.lor_assemble_rt.restype = i32
+    lib.lor_assemble_h1_2d.argtypes = [i32, i64, i64, i32, vp, vp, vp, f64, vp, ctypes.POINTER(LorSched), vp, i32,
+                                       u32, f64, vp, vp]
+    lib.lor_assemble_h1_2d.restype = i32
     lib.lor_assemble_backward.argtypes = [i32, i64, i64, i32, vp, vp, vp, f64, vp, ctypes.POINTER(LorSched), vp, vp,
                                           vp, vp, i32, vp]
     lib.lor_assemble_backward.restype = i32
@@ -249,6 +253,26 @@ def lor_assemble_nd(pat: Pattern, elem_dofs, elem_edges, coords, kappa, beta: fl
     _check(lib.lor_assemble_nd(pat.p, pat.nel, ndofs_h1, pat.nrows, batch, _ptr(ed), _ptr(ee), _ptr(x), _ptr(k),
                                float(beta), _ptr(pat.row_ptr), ctypes.byref(pat.sched), _ptr(out),
                                _dtype_code(dtype), flags, float(det_ratio_thresh), _ptr(diag), _stream()))
+    return out
+
+
+def lor_assemble_h1_2d(pat: Pattern, elem_dofs, coords, kappa, beta: float, dtype=torch.float64,
+                       fp64_fallback: bool = False, det_ratio_thresh: float = 10.0,
+                       diag: torch.Tensor | None = None, out: torch.Tensor | None = None) -> torch.Tensor:
+    """Values of the 2D H1 LOR matrix, [nnz] (or [batch, nnz] for kappa [batch, nel, p^2])."""
+    lib = load_library()
+    dev = pat.row_ptr.device
+    ed = _dev_tensor(elem_dofs, torch.int32, "elem_dofs", dev)
+    x = _dev_tensor(coords, torch.float64, "coords", dev)
+    k = _dev_tensor(kappa, dtype, "kappa", dev)
+    batched = k.dim() == 3
+    batch = k.shape[0] if batched else 1
+    if out is None:
+        out = torch.empty((batch, pat.nnz) if batched else (pat.nnz,), dtype=dtype, device=dev)
+    flags = LOR_FP64_FALLBACK if fp64_fallback else 0
+    _check(lib.lor_assemble_h1_2d(pat.p, pat.nel, pat.nrows, batch, _ptr(ed), _ptr(x), _ptr(k), float(beta),
+                                  _ptr(pat.row_ptr), ctypes.byref(pat.sched), _ptr(out), _dtype_code(dtype), flags,
+                                  float(det_ratio_thresh), _ptr(diag), _stream()))
     return out
 
 

@@ -1,0 +1,95 @@
+"""GPU parity of the 2D LOR H1 path against the CPU oracle, through the C ABI."""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import meshgen
+import paper_2210_12253_amd as lor
+from oracle import lor_oracle as orc
+from tests.gpu_helpers import row_rel_err, transpose_perm
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda:0")
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _assemble(pat, m, kap, beta, dtype=torch.float64, **kw):
+    v = lor.lor_assemble_h1_2d(pat, torch.from_numpy(m["elem_dofs"]), torch.from_numpy(m["coords"]), kap, beta,
+                               dtype=dtype, **kw)
+    torch.cuda.synchronize()
+    return v.cpu()
+
+
+CASES = [(3, 1, 0.1, False), (4, 2, 0.12, True), (3, 3, 0.1, False), (2, 4, 0.1, True), (2, 5, 0.1, False),
+         (3, 6, 0.1, True)]
+
+
+@pytest.mark.parametrize("case", CASES, ids=[f"n{c[0]}p{c[1]}-r{int(c[3])}" for c in CASES])
+def test_h1_2d_small_parity(case):
+    n, p, amp, renumber = case
+    _say("case", case)
+    m = meshgen.cartesian_mesh_2d(n, p, amp)
+    if renumber:
+        m, _ = meshgen.renumber_vertices(m, seed=n + p)
+    kap = meshgen.kappa_field_2d(m["nel"], p, 1.0, seed=n * p)
+    rp, ci, v = orc.h1_matrix_2d(m["coords"], m["elem_dofs"], p, kap, 0.7, m["ndofs"])
+    pat = lor.lor_pattern(lor.LOR_H1_2D, p, torch.from_numpy(m["elem_dofs"]).to(DEV), m["ndofs"])
+    assert torch.equal(pat.row_ptr.cpu().to(torch.int64), rp)
+    assert torch.equal(pat.col_idx.cpu().to(torch.int64), ci)
+    v64 = _assemble(pat, m, kap, 0.7)
+    v32 = _assemble(pat, m, kap.float(), 0.7, dtype=torch.float32, fp64_fallback=True)
+    e64 = row_rel_err(rp, ci, v64, ci, v)
+    e32 = row_rel_err(rp, ci, v32, ci, v)
+    _say(f"  fp64 {e64:.2e} fp32 {e32:.2e} colours {pat.ncolors}")
+    assert e64 <= 1e-12 and e32 <= 1e-6
+    assert torch.equal(v64, v64[transpose_perm(rp, ci)])
+
+
+def test_h1_2d_closed_form_uniform():
+    """Uniform square, kappa = 1, beta = 0: interior rows are the Q1 9-point
+    stencil 8/3, -1/3 (printed form of the bilinear Laplacian)."""
+    n, p = 4, 2
+    m = meshgen.cartesian_mesh_2d(n, p, 0.0)
+    kap = torch.ones((m["nel"], p * p), dtype=torch.float64)
+    pat = lor.lor_pattern(lor.LOR_H1_2D, p, torch.from_numpy(m["elem_dofs"]).to(DEV), m["ndofs"])
+    v = _assemble(pat, m, kap, 0.0)
+    N = m["N"]
+    rp = pat.row_ptr.cpu().long()
+    ci = pat.col_idx.cpu().long()
+    c = N * 3 + 3
+    row = dict(zip(ci[rp[c]:rp[c + 1]].tolist(), v[rp[c]:rp[c + 1]].tolist()))
+    assert abs(row[c] - 8.0 / 3.0) <= 1e-14
+    for d in (1, -1, N, -N, N + 1, N - 1, -N + 1, -N - 1):
+        assert abs(row[c + d] + 1.0 / 3.0) <= 1e-14
+
+
+def test_h1_2d_full_size_counts_and_sampled_rows():
+    """The paper's 2D workload (Section 4.1): 512^2 elements at p = 6 give
+    9,443,329 rows and 84,953,089 nonzeros; sampled rows against the oracle."""
+    with open(os.path.join(GOLDEN, "paper_counts.json")) as f:
+        g = json.load(f)["h1_2d"]
+    m = meshgen.config_mesh("c7_h1_2d_p6_curved")
+    pat = lor.lor_pattern(lor.LOR_H1_2D, 6, torch.from_numpy(m["elem_dofs"]).to(DEV), m["ndofs"])
+    assert m["nel"] == g["elements"] and pat.nrows == g["dofs"] and pat.nnz == g["nnz"]
+    v64 = _assemble(pat, m, m["kappa"], m["beta"])
+    v32 = _assemble(pat, m, m["kappa"].float(), m["beta"], dtype=torch.float32, fp64_fallback=True)
+    N = m["N"]
+    rng = np.random.default_rng(0)
+    pick = [0, N - 1, N * N - 1, (N // 2) * (N + 1), 6 + 6 * N] + list(rng.integers(0, N * N, size=400))
+    rows, rp, ci, v = orc.h1_rows_2d(m["coords"], m["elem_dofs"], 6, m["kappa"], m["beta"], torch.tensor(pick))
+    grp = pat.row_ptr.cpu().to(torch.int64)
+    idx = torch.cat([torch.arange(grp[r], grp[r + 1]) for r in rows.tolist()])
+    assert torch.equal(pat.col_idx.cpu().to(torch.int64)[idx], ci)
+    e64 = row_rel_err(rp, ci, v64[idx], ci, v)
+    e32 = row_rel_err(rp, ci, v32[idx], ci, v)
+    _say(f"sampled rows fp64 {e64:.2e} fp32 {e32:.2e}")
+    assert e64 <= 1e-12 and e32 <= 1e-6
