@@ -93,3 +93,33 @@ def test_h1_2d_full_size_counts_and_sampled_rows():
     e32 = row_rel_err(rp, ci, v32[idx], ci, v)
     _say(f"sampled rows fp64 {e64:.2e} fp32 {e32:.2e}")
     assert e64 <= 1e-12 and e32 <= 1e-6
+
+
+def test_h1_2d_fp32_fallback_batch_and_empty():
+    """A pinched vertex sends its subelements through the FP64 path of the FP32
+    form (diag[0]); a batch of kappa fields equals the single calls; an empty
+    mesh launches nothing."""
+    m = meshgen.cartesian_mesh_2d(1, 2, 0.0)
+    X = m["coords"].copy()
+    X[4] = [0.96, 0.5]   # corner-Jacobian ratio 12.5 in the two right subelements
+    m["coords"] = X
+    kap = torch.ones(1, 4, dtype=torch.float64)
+    rp, ci, v = orc.h1_matrix_2d(X, m["elem_dofs"], 2, kap, 1.0, m["ndofs"])
+    pat = lor.lor_pattern(lor.LOR_H1_2D, 2, torch.from_numpy(m["elem_dofs"]).to(DEV), m["ndofs"])
+    diag = torch.zeros(2, dtype=torch.int32, device=DEV)
+    v32 = _assemble(pat, m, kap.float(), 1.0, dtype=torch.float32, fp64_fallback=True, det_ratio_thresh=10.0,
+                    diag=diag)
+    d = diag.cpu().tolist()
+    assert d[0] > 0 and d[1] == 0
+    assert row_rel_err(rp, ci, v32, ci, v) <= 1e-6
+    m = meshgen.cartesian_mesh_2d(3, 3, 0.1)
+    pat = lor.lor_pattern(lor.LOR_H1_2D, 3, torch.from_numpy(m["elem_dofs"]).to(DEV), m["ndofs"])
+    kb = torch.stack([meshgen.kappa_field_2d(m["nel"], 3, 1.0, seed=s) for s in range(3)])
+    vb = _assemble(pat, m, kb, 0.4)
+    for b in range(3):
+        assert torch.equal(vb[b], _assemble(pat, m, kb[b], 0.4))
+    pat0 = lor.lor_pattern(lor.LOR_H1_2D, 2, torch.zeros((0, 9), dtype=torch.int32, device=DEV), 4)
+    out = lor.lor_assemble_h1_2d(pat0, torch.zeros((0, 9), dtype=torch.int32), torch.zeros((4, 2), dtype=torch.float64),
+                                 torch.zeros((0, 4), dtype=torch.float64), 1.0)
+    torch.cuda.synchronize()
+    assert pat0.nnz == 0 and out.numel() == 0

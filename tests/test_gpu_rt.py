@@ -112,3 +112,27 @@ def test_rt_full_size_sampled_rows_and_exact_sequence():
     x = rng.standard_normal(ned)
     y = K @ (C @ x)
     assert np.abs(y).max() <= 1e-11 * np.abs(K.data).max() * np.abs(x).max()
+
+
+def test_rt_fp32_fallback_and_empty():
+    """A pinched vertex (corner-Jacobian ratio above 10) sends its subelements
+    through the FP64 path of the FP32 form (counted in diag[0]); an empty mesh
+    launches nothing."""
+    m, fm, nf, _ = _setup(1, 2, 0.0, 1.0, seed=3)
+    X = m["coords"].copy()
+    X[13] = [0.96, 0.5, 0.5]
+    m["coords"] = X
+    kap = torch.ones(1, 8, dtype=torch.float64)
+    rp, ci, v = orc.rt_matrix(X, m["elem_dofs"], fm, 2, kap, 1.0, nf)
+    pat = lor.lor_pattern(lor.LOR_RT, 2, torch.from_numpy(fm).to(DEV), nf)
+    diag = torch.zeros(2, dtype=torch.int32, device=DEV)
+    v32 = _assemble(pat, m, fm, kap.float(), 1.0, dtype=torch.float32, fp64_fallback=True, det_ratio_thresh=10.0,
+                    diag=diag)
+    d = diag.cpu().tolist()
+    assert d[0] > 0 and d[1] == 0
+    assert row_rel_err(rp, ci, v32, ci, v) <= 1e-6
+    pat0 = lor.lor_pattern(lor.LOR_RT, 2, torch.zeros((0, 36), dtype=torch.int32, device=DEV), 5)
+    out = lor.lor_assemble_rt(pat0, torch.zeros((0, 27), dtype=torch.int32), torch.zeros((0, 36), dtype=torch.int32),
+                              torch.zeros((5, 3), dtype=torch.float64), torch.zeros((0, 8), dtype=torch.float64), 1.0, 5)
+    torch.cuda.synchronize()
+    assert pat0.nnz == 0 and out.numel() == 0
