@@ -223,8 +223,8 @@ def main():
         print(text)
         return
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); multi-GPU sharding is "
-              f"described in DESIGN.md but not built", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU path "
+              f"(interface-row exchange between element partitions) is not built", file=sys.stderr)
         sys.exit(2)
 
     import torch

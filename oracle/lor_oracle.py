@@ -24,7 +24,7 @@ What it computes is the plain definition of the LOR matrices, written out:
   sort below computes (COO = the unassembled block-diagonal A_hat, the sort and
   segment sum = the Boolean assembly operator).
 
-Readings of points the paper leaves open (each one is listed in the design doc):
+Readings of points the paper leaves open (the HIP path takes the same ones):
 * Subelement quadrature: 2x2x2 Gauss-Legendre (weights 1/8 on the unit cube).
 * Coefficients: kappa constant per subelement, beta a scalar (or, for tests, a
   per-subelement tensor).  Consistent (not lumped) mass.
