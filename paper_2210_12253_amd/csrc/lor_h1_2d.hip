@@ -28,14 +28,16 @@ struct H12Cfg {
   static constexpr int THREADS = 256;
   static constexpr int PER_EL = NSUB * 10 * static_cast<int>(sizeof(R)) + NENTP + NLOC * 20;
   static constexpr int E0 = THREADS / NSUB < 64 ? THREADS / NSUB : 64;
-  static constexpr int E1 = (24 * 1024) / PER_EL;
+  // small groups (5 elements at p = 6 in both precisions) and up to 6
+  // resident workgroups per CU: the kernel is latency bound
+  static constexpr int E1 = (sizeof(R) == 8 ? 24 * 1024 : 16 * 1024) / PER_EL;
   static constexpr int E = (E0 < E1 ? E0 : E1) > 0 ? (E0 < E1 ? E0 : E1) : 1;
   static constexpr int TWE = NENTP / 4;
   static constexpr int CH = 8;
   static constexpr int MAXCHUNK = 256;
   static constexpr int LDS = E * PER_EL + 2 * MAXCHUNK * 4 + 256;
   static constexpr int WPC1 = 160 * 1024 / LDS;
-  static constexpr int WPC = WPC1 < 4 ? (WPC1 > 0 ? WPC1 : 1) : 4;  // resident workgroups per CU
+  static constexpr int WPC = WPC1 < 6 ? (WPC1 > 0 ? WPC1 : 1) : 6;  // resident workgroups per CU
   static_assert(E * NSUB <= THREADS, "one subelement per lane");
 };
 
