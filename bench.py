@@ -45,6 +45,36 @@ def algorithmic_bytes_h1(nel, p, ndofs, nnz, vbytes, batch=1):
             + (ndofs + 1) * 4)             # row_ptr
 
 
+def algorithmic_bytes_vec(nel, p, nrows, ndofs_h1, nnz, vbytes, nloc_map):
+    """H(curl) / H(div): values written once, coords, vertex map, signed edge
+    or face map (nloc_map entries per element), kappa and row_ptr read once."""
+    q = p + 1
+    return (nnz * vbytes + ndofs_h1 * 3 * 8 + nel * q ** 3 * 4 + nel * nloc_map * 4 + nel * p ** 3 * vbytes
+            + (nrows + 1) * 4)
+
+
+def algorithmic_bytes_2d(nel, p, ndofs, nnz, vbytes):
+    """2D H1: values written once, 2D coords, vertex map, kappa, row_ptr."""
+    q = p + 1
+    return nnz * vbytes + ndofs * 2 * 8 + nel * q * q * 4 + nel * p * p * vbytes + (ndofs + 1) * 4
+
+
+def algorithmic_bytes_backward(nel, p, ndofs, nnz, vbytes, batch):
+    """Adjoint: the cotangent read once per batch entry, coords, vertex map,
+    row_ptr and incidence lists read once, kappa read and its gradient
+    written per batch entry, the element coordinate adjoints written and read
+    back once (E-vector workspace), the vertex gradient written once."""
+    q = p + 1
+    return (batch * nnz * vbytes + ndofs * 24 + nel * q ** 3 * 4 + 2 * batch * nel * p ** 3 * vbytes
+            + (ndofs + 1) * 4 * 2 + nel * q ** 3 * 4 + 2 * nel * q ** 3 * 24 + ndofs * 24)
+
+
+def roofline_of(bytes_, ms):
+    ach = bytes_ / (ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+            "algorithmic_bytes": bytes_}
+
+
 def time_it(fn, steps, warmup):
     import torch
     for _ in range(warmup):
@@ -396,7 +426,9 @@ def bench_backward(lor, meshgen, args, dev):
                          args.steps, args.warmup)
             fwd = time_it(lambda: lor.lor_assemble_h1(pat, ed, x, k, 1.0, dtype=dt), args.steps, args.warmup)
             res[name] = {"ms": ms, "value": 8 * m["ndofs"] / (ms * 1e-3) / 1e6, "unit": "MDOF/s (batch*rows)",
-                         "forward_batch8_ms": fwd}
+                         "forward_batch8_ms": fwd,
+                         "roofline": roofline_of(algorithmic_bytes_backward(m["nel"], m["p"], m["ndofs"], pat.nnz,
+                                                                            dt.itemsize, 8), ms)}
         res["workload"] = "backward of H1 p=4, 16^3 curved hexes, batch 8 kappa fields"
         res["speedup_f32_vs_f64"] = res["f64"]["ms"] / res["f32"]["ms"]
         return res
@@ -548,7 +580,9 @@ def bench_2d(lor, meshgen, args, dev):
             out = torch.empty(pat.nnz, dtype=dt, device=dev)
             ms = time_it(lambda: lor.lor_assemble_h1_2d(pat, ed, x, k, m["beta"], dtype=dt, out=out),
                          args.steps, args.warmup)
-            res[name] = {"ms": ms, "value": m["ndofs"] / (ms * 1e-3) / 1e6, "unit": "MDOF/s"}
+            res[name] = {"ms": ms, "value": m["ndofs"] / (ms * 1e-3) / 1e6, "unit": "MDOF/s",
+                         "roofline": roofline_of(algorithmic_bytes_2d(m["nel"], 6, m["ndofs"], pat.nnz, dt.itemsize),
+                                                 ms)}
         res["workload"] = "2D H1 LOR assembly, p=6, 512^2 curved quadrilaterals, kappa sigma=2, beta=1"
         res["rows"], res["nnz"], res["ncolors"] = m["ndofs"], pat.nnz, pat.ncolors
         return res
@@ -570,7 +604,10 @@ def bench_rt(lor, meshgen, args, dev):
             out = torch.empty(pat.nnz, dtype=dt, device=dev)
             ms = time_it(lambda: lor.lor_assemble_rt(pat, ed, fm, x, k, 1.0, m["ndofs"], dtype=dt, out=out),
                          args.steps, args.warmup)
-            res[name] = {"ms": ms, "value": m["nfaces"] / (ms * 1e-3) / 1e6, "unit": "MDOF/s"}
+            p = m["p"]
+            res[name] = {"ms": ms, "value": m["nfaces"] / (ms * 1e-3) / 1e6, "unit": "MDOF/s",
+                         "roofline": roofline_of(algorithmic_bytes_vec(m["nel"], p, m["nfaces"], m["ndofs"], pat.nnz,
+                                                                       dt.itemsize, 3 * p * p * (p + 1)), ms)}
         res["workload"] = "H(div) LOR assembly, p=3, 24^3 curved hexes, kappa sigma=1, beta=1"
         res["rows"], res["nnz"], res["ncolors"] = m["nfaces"], pat.nnz, pat.ncolors
         return res
@@ -592,7 +629,10 @@ def bench_nd(lor, meshgen, args, dev):
             out = torch.empty(pat.nnz, dtype=dt, device=dev)
             ms = time_it(lambda: lor.lor_assemble_nd(pat, ed, ee, x, k, 1.0, m["ndofs"], dtype=dt, out=out),
                          args.steps, args.warmup)
-            res[name] = {"ms": ms, "value": m["nedges"] / (ms * 1e-3) / 1e6, "unit": "MDOF/s"}
+            p = m["p"]
+            res[name] = {"ms": ms, "value": m["nedges"] / (ms * 1e-3) / 1e6, "unit": "MDOF/s",
+                         "roofline": roofline_of(algorithmic_bytes_vec(m["nel"], p, m["nedges"], m["ndofs"], pat.nnz,
+                                                                       dt.itemsize, 3 * p * (p + 1) ** 2), ms)}
         res["workload"] = "H(curl) LOR assembly, p=3, 24^3 curved hexes, kappa sigma=1, beta=1"
         res["rows"], res["nnz"] = m["nedges"], pat.nnz
         return res
