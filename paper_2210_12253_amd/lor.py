@@ -168,6 +168,32 @@ def _dev_tensor(t, dtype, name, device) -> torch.Tensor:
     return t
 
 
+def _out(out, shape, dtype, device, name="out") -> torch.Tensor:
+    """A caller-supplied output (or workspace) buffer must match exactly: the
+    kernels write every element of it and nothing beyond."""
+    shape = tuple(int(x) for x in shape)
+    if out is None:
+        return torch.empty(shape, dtype=dtype, device=device)
+    if tuple(out.shape) != shape or out.dtype != dtype or out.device != device or not out.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous {dtype} tensor of shape {shape} on {device}")
+    return out
+
+
+def _need(t: torch.Tensor, numel: int, name: str) -> None:
+    """The kernels index every array by the pattern's sizes: a wrong size would
+    make them read or write outside it, so it is rejected here."""
+    if t.numel() != int(numel):
+        raise ValueError(f"{name} has {t.numel()} elements, expected {int(numel)}")
+
+
+def _diag(diag, n: int, device):
+    if diag is None:
+        return None
+    if diag.dtype != torch.int32 or diag.device != device or diag.numel() < n or not diag.is_contiguous():
+        raise ValueError(f"diag must be a contiguous int32 tensor of at least {n} elements on {device}")
+    return diag
+
+
 def _dtype_code(dtype) -> int:
     if dtype == torch.float64:
         return LOR_F64
@@ -199,6 +225,12 @@ def lor_pattern(space: int, p: int, elem_map: torch.Tensor, nrows: int, device=N
     lib = load_library()
     device = torch.device("cuda") if device is None else torch.device(device)
     em = _dev_tensor(elem_map, torch.int32, "elem_map", device)
+    nloc = {LOR_H1: (p + 1) ** 3, LOR_ND: 3 * p * (p + 1) ** 2, LOR_RT: 3 * p * p * (p + 1),
+            LOR_H1_2D: (p + 1) ** 2}.get(space)
+    if nloc is None:
+        raise ValueError("space must be LOR_H1, LOR_ND, LOR_RT or LOR_H1_2D")
+    if em.dim() != 2 or em.shape[1] != nloc:
+        raise ValueError(f"elem_map must have shape [nel, {nloc}] for this space and p")
     nel = em.shape[0]
     row_ptr = torch.empty(nrows + 1, dtype=torch.int32, device=device)
     nnz = ctypes.c_int64(0)
@@ -226,8 +258,12 @@ def lor_assemble_h1(pat: Pattern, elem_dofs, coords, kappa, beta: float, dtype=t
     k = _dev_tensor(kappa, dtype, "kappa", dev)
     batched = k.dim() == 3
     batch = k.shape[0] if batched else 1
-    if out is None:
-        out = torch.empty((batch, pat.nnz) if batched else (pat.nnz,), dtype=dtype, device=dev)
+    p = pat.p
+    _need(ed, pat.nel * (p + 1) ** 3, "elem_dofs")
+    _need(x, pat.nrows * 3, "coords")
+    _need(k, batch * pat.nel * p ** 3, "kappa")
+    diag = _diag(diag, 2, dev)
+    out = _out(out, (batch, pat.nnz) if batched else (pat.nnz,), dtype, dev)
     flags = LOR_FP64_FALLBACK if fp64_fallback else 0
     _check(lib.lor_assemble_h1(pat.p, pat.nel, pat.nrows, batch, _ptr(ed), _ptr(x), _ptr(k), float(beta),
                                _ptr(pat.row_ptr), ctypes.byref(pat.sched), _ptr(out), _dtype_code(dtype), flags,
@@ -247,8 +283,13 @@ def lor_assemble_nd(pat: Pattern, elem_dofs, elem_edges, coords, kappa, beta: fl
     k = _dev_tensor(kappa, dtype, "kappa", dev)
     batched = k.dim() == 3
     batch = k.shape[0] if batched else 1
-    if out is None:
-        out = torch.empty((batch, pat.nnz) if batched else (pat.nnz,), dtype=dtype, device=dev)
+    p = pat.p
+    _need(ed, pat.nel * (p + 1) ** 3, "elem_dofs")
+    _need(ee, pat.nel * 3 * p * (p + 1) ** 2, "elem_edges")
+    _need(x, ndofs_h1 * 3, "coords")
+    _need(k, batch * pat.nel * p ** 3, "kappa")
+    diag = _diag(diag, 2, dev)
+    out = _out(out, (batch, pat.nnz) if batched else (pat.nnz,), dtype, dev)
     flags = LOR_FP64_FALLBACK if fp64_fallback else 0
     _check(lib.lor_assemble_nd(pat.p, pat.nel, ndofs_h1, pat.nrows, batch, _ptr(ed), _ptr(ee), _ptr(x), _ptr(k),
                                float(beta), _ptr(pat.row_ptr), ctypes.byref(pat.sched), _ptr(out),
@@ -267,8 +308,12 @@ def lor_assemble_h1_2d(pat: Pattern, elem_dofs, coords, kappa, beta: float, dtyp
     k = _dev_tensor(kappa, dtype, "kappa", dev)
     batched = k.dim() == 3
     batch = k.shape[0] if batched else 1
-    if out is None:
-        out = torch.empty((batch, pat.nnz) if batched else (pat.nnz,), dtype=dtype, device=dev)
+    p = pat.p
+    _need(ed, pat.nel * (p + 1) ** 2, "elem_dofs")
+    _need(x, pat.nrows * 2, "coords")
+    _need(k, batch * pat.nel * p ** 2, "kappa")
+    diag = _diag(diag, 2, dev)
+    out = _out(out, (batch, pat.nnz) if batched else (pat.nnz,), dtype, dev)
     flags = LOR_FP64_FALLBACK if fp64_fallback else 0
     _check(lib.lor_assemble_h1_2d(pat.p, pat.nel, pat.nrows, batch, _ptr(ed), _ptr(x), _ptr(k), float(beta),
                                   _ptr(pat.row_ptr), ctypes.byref(pat.sched), _ptr(out), _dtype_code(dtype), flags,
@@ -288,8 +333,13 @@ def lor_assemble_rt(pat: Pattern, elem_dofs, elem_faces, coords, kappa, beta: fl
     k = _dev_tensor(kappa, dtype, "kappa", dev)
     batched = k.dim() == 3
     batch = k.shape[0] if batched else 1
-    if out is None:
-        out = torch.empty((batch, pat.nnz) if batched else (pat.nnz,), dtype=dtype, device=dev)
+    p = pat.p
+    _need(ed, pat.nel * (p + 1) ** 3, "elem_dofs")
+    _need(fm, pat.nel * 3 * p * p * (p + 1), "elem_faces")
+    _need(x, ndofs_h1 * 3, "coords")
+    _need(k, batch * pat.nel * p ** 3, "kappa")
+    diag = _diag(diag, 2, dev)
+    out = _out(out, (batch, pat.nnz) if batched else (pat.nnz,), dtype, dev)
     flags = LOR_FP64_FALLBACK if fp64_fallback else 0
     _check(lib.lor_assemble_rt(pat.p, pat.nel, ndofs_h1, pat.nrows, batch, _ptr(ed), _ptr(fm), _ptr(x), _ptr(k),
                                float(beta), _ptr(pat.row_ptr), ctypes.byref(pat.sched), _ptr(out),
@@ -308,11 +358,19 @@ def lor_assemble_backward(pat: Pattern, elem_dofs, coords, kappa, beta: float, g
     gv = _dev_tensor(grad_values, dtype, "grad_values", dev)
     batched = k.dim() == 3
     batch = k.shape[0] if batched else 1
+    p = pat.p
+    _need(ed, pat.nel * (p + 1) ** 3, "elem_dofs")
+    _need(x, pat.nrows * 3, "coords")
+    _need(k, batch * pat.nel * p ** 3, "kappa")
+    _need(gv, batch * pat.nnz, "grad_values")
     gk = torch.empty_like(k)
     gx = torch.empty((pat.nrows, 3), dtype=torch.float64, device=dev)
+    wbytes = max(1, int(lib.lor_backward_workspace(pat.p, pat.nel)))
     if workspace is None:
-        workspace = torch.empty(max(1, int(lib.lor_backward_workspace(pat.p, pat.nel))), dtype=torch.uint8,
-                                device=dev)
+        workspace = torch.empty(wbytes, dtype=torch.uint8, device=dev)
+    elif workspace.device != dev or not workspace.is_contiguous() or \
+            workspace.numel() * workspace.element_size() < wbytes:
+        raise ValueError(f"workspace must be a contiguous device buffer of at least {wbytes} bytes")
     _check(lib.lor_assemble_backward(pat.p, pat.nel, pat.nrows, batch, _ptr(ed), _ptr(x), _ptr(k), float(beta),
                                      _ptr(pat.row_ptr), ctypes.byref(pat.sched), _ptr(gv), _ptr(gk), _ptr(gx),
                                      _ptr(workspace), _dtype_code(dtype), _stream()))
@@ -334,8 +392,8 @@ def lor_eliminate_bc(pat: Pattern, values: torch.Tensor, ess_dofs, diag_policy: 
         raise ValueError(f"diag_policy must be one of {tuple(_DIAG_POLICY)}")
     ess = _dev_tensor(ess_dofs, torch.int32, "ess_dofs", dev).reshape(-1)
     batch = values.shape[0] if values.dim() == 2 else 1
-    if marker is None:
-        marker = torch.empty(pat.nrows, dtype=torch.uint8, device=dev)
+    marker = _out(marker, (pat.nrows,), torch.uint8, dev, "marker")
+    diag = _diag(diag, 2, dev)
     _check(lib.lor_eliminate_bc(pat.nrows, pat.nnz, batch, _ptr(pat.row_ptr), _ptr(pat.col_idx), _ptr(values),
                                 _dtype_code(values.dtype), ess.numel(), _ptr(ess), _ptr(marker),
                                 _DIAG_POLICY[diag_policy], _ptr(diag), _stream()))
@@ -351,15 +409,14 @@ def lor_discrete_gradient(pat: Pattern, elem_dofs, elem_edges, ndofs_h1: int, dt
     dev = pat.row_ptr.device
     ed = _dev_tensor(elem_dofs, torch.int32, "elem_dofs", dev)
     ee = _dev_tensor(elem_edges, torch.int32, "elem_edges", dev)
-    if out is None:
-        rp = torch.empty(pat.nrows + 1, dtype=torch.int32, device=dev)
-        ci = torch.empty(2 * pat.nrows, dtype=torch.int32, device=dev)
-        v = torch.empty(2 * pat.nrows, dtype=dtype, device=dev)
-    else:
-        rp, ci, v = out
-        if rp.numel() != pat.nrows + 1 or ci.numel() != 2 * pat.nrows or v.numel() != 2 * pat.nrows or \
-                v.dtype != dtype or rp.dtype != torch.int32 or ci.dtype != torch.int32:
-            raise ValueError("out must be (row_ptr [nrows+1] int32, col_idx [2 nrows] int32, values [2 nrows] dtype)")
+    p = pat.p
+    _need(ed, pat.nel * (p + 1) ** 3, "elem_dofs")
+    _need(ee, pat.nel * 3 * p * (p + 1) ** 2, "elem_edges")
+    diag = _diag(diag, 2, dev)
+    rp, ci, v = out if out is not None else (None, None, None)
+    rp = _out(rp, (pat.nrows + 1,), torch.int32, dev, "row_ptr")
+    ci = _out(ci, (2 * pat.nrows,), torch.int32, dev, "col_idx")
+    v = _out(v, (2 * pat.nrows,), dtype, dev, "values")
     _check(lib.lor_discrete_gradient(pat.p, pat.nel, ndofs_h1, pat.nrows, _ptr(ed), _ptr(ee), ctypes.byref(pat.sched),
                                      _ptr(rp), _ptr(ci), _ptr(v), _dtype_code(dtype), _ptr(diag), _stream()))
     return rp, ci, v
@@ -374,17 +431,15 @@ def lor_discrete_curl(p: int, elem_edges, elem_faces, nedges: int, nfaces: int, 
     dev = torch.device("cuda") if device is None else torch.device(device)
     ee = _dev_tensor(elem_edges, torch.int32, "elem_edges", dev)
     fm = _dev_tensor(elem_faces, torch.int32, "elem_faces", dev)
-    nel = fm.shape[0]
-    if ee.shape[0] != nel:
-        raise ValueError("elem_edges and elem_faces must have one row per element")
-    if workspace is None:
-        workspace = torch.empty(nfaces, dtype=torch.int32, device=dev)
-    if out is None:
-        rp = torch.empty(nfaces + 1, dtype=torch.int32, device=dev)
-        ci = torch.empty(4 * nfaces, dtype=torch.int32, device=dev)
-        v = torch.empty(4 * nfaces, dtype=dtype, device=dev)
-    else:
-        rp, ci, v = out
+    nel = fm.shape[0] if fm.dim() == 2 else 0
+    _need(fm, nel * 3 * p * p * (p + 1), "elem_faces")
+    _need(ee, nel * 3 * p * (p + 1) ** 2, "elem_edges")
+    diag = _diag(diag, 2, dev)
+    workspace = _out(workspace, (nfaces,), torch.int32, dev, "workspace")
+    rp, ci, v = out if out is not None else (None, None, None)
+    rp = _out(rp, (nfaces + 1,), torch.int32, dev, "row_ptr")
+    ci = _out(ci, (4 * nfaces,), torch.int32, dev, "col_idx")
+    v = _out(v, (4 * nfaces,), dtype, dev, "values")
     _check(lib.lor_discrete_curl(p, nel, nedges, nfaces, _ptr(ee), _ptr(fm), _ptr(workspace), _ptr(rp), _ptr(ci),
                                  _ptr(v), _dtype_code(dtype), _ptr(diag), _stream()))
     return rp, ci, v
@@ -396,11 +451,10 @@ def lor_interp_nodes(nodes, p: int, q: int, out: torch.Tensor | None = None) -> 
     lib = load_library()
     dev = torch.device("cuda") if not (torch.is_tensor(nodes) and nodes.is_cuda) else nodes.device
     X = _dev_tensor(nodes, torch.float64, "nodes", dev)
-    if X.dim() != 3 or X.shape[1] != (q + 1) ** 3:
-        raise ValueError("nodes must have shape [nel, (q+1)^3, ncomp]")
+    if X.dim() != 3 or X.shape[1] != (q + 1) ** 3 or not 1 <= X.shape[2] <= 3:
+        raise ValueError("nodes must have shape [nel, (q+1)^3, ncomp] with ncomp in 1..3")
     nel, _, nc = X.shape
-    if out is None:
-        out = torch.empty((nel, (p + 1) ** 3, nc), dtype=torch.float64, device=dev)
+    out = _out(out, (nel, (p + 1) ** 3, nc), torch.float64, dev)
     _check(lib.lor_interp_nodes(p, q, nel, nc, _ptr(X), _ptr(out), _stream()))
     return out
 
@@ -415,8 +469,8 @@ def lor_evec_to_tvec(pat: Pattern, evec: torch.Tensor, diag: torch.Tensor | None
     if E.dim() != 3 or E.shape[0] != pat.nel or E.shape[1] != (pat.p + 1) ** 3:
         raise ValueError("evec must have shape [nel, (p+1)^3, ncomp]")
     nc = E.shape[2]
-    if out is None:
-        out = torch.empty((pat.nrows, nc), dtype=torch.float64, device=dev)
+    diag = _diag(diag, 1, dev)
+    out = _out(out, (pat.nrows, nc), torch.float64, dev)
     _check(lib.lor_evec_to_tvec(pat.p, pat.nel, pat.nrows, ctypes.byref(pat.sched), nc, _ptr(E), _ptr(out),
                                 _ptr(diag), _stream()))
     return out
@@ -427,11 +481,9 @@ def lor_refine_map(p: int, elem_dofs, device=None, out: torch.Tensor | None = No
     lib = load_library()
     dev = torch.device("cuda") if device is None else torch.device(device)
     ed = _dev_tensor(elem_dofs, torch.int32, "elem_dofs", dev)
-    nel = ed.shape[0]
-    if out is None:
-        out = torch.empty((nel * p ** 3, 8), dtype=torch.int32, device=dev)
-    elif out.shape != (nel * p ** 3, 8) or out.dtype != torch.int32:
-        raise ValueError("out must be [nel * p^3, 8] int32")
+    nel = ed.shape[0] if ed.dim() == 2 else 0
+    _need(ed, nel * (p + 1) ** 3, "elem_dofs")
+    out = _out(out, (nel * p ** 3, 8), torch.int32, dev)
     _check(lib.lor_refine_map(p, nel, _ptr(ed), _ptr(out), _stream()))
     return out
 
@@ -448,8 +500,9 @@ def lor_assemble_h1_unstructured(pat: Pattern, sub_map, coords, kappa, beta: flo
     k = _dev_tensor(kappa, torch.float64, "kappa", dev).reshape(-1)
     if sm.dim() != 2 or sm.shape[1] != 8 or k.numel() != sm.shape[0]:
         raise ValueError("sub_map must be [nsub, 8] and kappa hold one value per element")
-    if out is None:
-        out = torch.empty(pat.nnz, dtype=torch.float64, device=dev)
+    _need(x, pat.nrows * 3, "coords")
+    diag = _diag(diag, 2, dev)
+    out = _out(out, (pat.nnz,), torch.float64, dev)
     _check(lib.lor_assemble_h1_unstructured(sm.shape[0], pat.nrows, pat.nnz, _ptr(sm), _ptr(x), _ptr(k), float(beta),
                                             _ptr(pat.row_ptr), _ptr(pat.col_idx), _ptr(out), _ptr(diag), _stream()))
     return out

@@ -196,3 +196,33 @@ def test_h1_c3_paper_counts_and_sampled_rows():
     # structural: every row of the Cartesian p=6 mesh has 8, 12, 18 or 27 entries
     cnt = (grp[1:] - grp[:-1])
     assert int(cnt.max()) == 27 and int(cnt.min()) == 8
+
+
+def test_binding_rejects_wrong_sizes():
+    """Arrays whose size does not match the pattern are rejected by the binding
+    before any kernel is launched (a kernel would index past them)."""
+    m = meshgen.cartesian_mesh(2, 2, 0.0)
+    ed = torch.from_numpy(m["elem_dofs"])
+    x = torch.from_numpy(m["coords"])
+    kap = torch.ones((m["nel"], 8), dtype=torch.float64)
+    with pytest.raises(ValueError, match="elem_map"):
+        lor.lor_pattern(lor.LOR_H1, 2, ed[:, :26].to(DEV), m["ndofs"])
+    pat = lor.lor_pattern(lor.LOR_H1, 2, ed.to(DEV), m["ndofs"])
+    with pytest.raises(ValueError, match="elem_dofs"):
+        lor.lor_assemble_h1(pat, ed[:-1], x, kap, 1.0)
+    with pytest.raises(ValueError, match="coords"):
+        lor.lor_assemble_h1(pat, ed, x[:-1], kap, 1.0)
+    with pytest.raises(ValueError, match="kappa"):
+        lor.lor_assemble_h1(pat, ed, x, kap[:, :7], 1.0)
+    with pytest.raises(ValueError, match="out"):
+        lor.lor_assemble_h1(pat, ed, x, kap, 1.0, out=torch.empty(pat.nnz - 1, dtype=torch.float64, device=DEV))
+    with pytest.raises(ValueError, match="diag"):
+        lor.lor_assemble_h1(pat, ed, x, kap, 1.0, diag=torch.zeros(1, dtype=torch.int32, device=DEV))
+    v = lor.lor_assemble_h1(pat, ed, x, kap, 1.0)
+    with pytest.raises(ValueError, match="marker"):
+        lor.lor_eliminate_bc(pat, v, torch.tensor([0], dtype=torch.int32),
+                             marker=torch.empty(3, dtype=torch.uint8, device=DEV))
+    with pytest.raises(ValueError, match="workspace"):
+        lor.lor_assemble_backward(pat, ed, x, kap, 1.0, torch.zeros(pat.nnz, dtype=torch.float64),
+                                  workspace=torch.empty(4, dtype=torch.uint8, device=DEV))
+    torch.cuda.synchronize()
