@@ -60,13 +60,13 @@ def algorithmic_bytes_2d(nel, p, ndofs, nnz, vbytes):
 
 
 def algorithmic_bytes_backward(nel, p, ndofs, nnz, vbytes, batch):
-    """Adjoint: the cotangent read once per batch entry, coords, vertex map,
-    row_ptr and incidence lists read once, kappa read and its gradient
-    written per batch entry, the element coordinate adjoints written and read
-    back once (E-vector workspace), the vertex gradient written once."""
+    """Adjoint: every input read once (the cotangent per batch entry, coords,
+    vertex map, row_ptr, kappa per batch entry) and every output written once
+    (the kappa gradient per batch entry, the vertex gradient).  The E-vector
+    workspace round trip of this implementation is not counted."""
     q = p + 1
     return (batch * nnz * vbytes + ndofs * 24 + nel * q ** 3 * 4 + 2 * batch * nel * p ** 3 * vbytes
-            + (ndofs + 1) * 4 * 2 + nel * q ** 3 * 4 + 2 * nel * q ** 3 * 24 + ndofs * 24)
+            + (ndofs + 1) * 4 + ndofs * 24)
 
 
 def roofline_of(bytes_, ms):
