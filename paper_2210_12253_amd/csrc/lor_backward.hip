@@ -142,19 +142,25 @@ __global__ __launch_bounds__(256, 1) void k_h1_backward(
               x, y, z, (v & 1) - (u & 1), ((v >> 1) & 1) - ((u >> 1) & 1), (v >> 2) - (u >> 2)));
       }
     }
-    for (int b = 0; b < batch; ++b) {
-      const T* gb = gvals + static_cast<int64_t>(b) * nnz;
-      // the group's cotangent entries in compact (row-contiguous) order
-      T gv[NJ];
+    // the group's cotangent entries in compact (row-contiguous) order; the
+    // next batch entry's gather is issued before this entry's compute so its
+    // latency is hidden (the barriers wait on LDS only)
+    T gv[NJ];
 #pragma unroll
-      for (int j = 0; j < NJ; ++j) gv[j] = gb[gpos[j]];
-      __syncthreads();  // the previous entry of the batch has been consumed
+    for (int j = 0; j < NJ; ++j) gv[j] = gvals[gpos[j]];
+    for (int b = 0; b < batch; ++b) {
+      lds_barrier();  // the previous entry of the batch has been consumed
 #pragma unroll
       for (int j = 0; j < NJ; ++j) {
         const int i = tid + j * TH;
         if (i < ne * NENT) sG[i] = static_cast<double>(gv[j]);
       }
-      __syncthreads();
+      if (b + 1 < batch) {
+        const T* gn = gvals + static_cast<int64_t>(b + 1) * nnz;
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) gv[j] = gn[gpos[j]];
+      }
+      lds_barrier();
       if (act) {
         const R kb = static_cast<R>(kappa[(static_cast<int64_t>(b) * nel + e) * NSUB + s]);
         const double* ge = sG + el * NENT;
