@@ -226,3 +226,49 @@ def test_binding_rejects_wrong_sizes():
         lor.lor_assemble_backward(pat, ed, x, kap, 1.0, torch.zeros(pat.nnz, dtype=torch.float64),
                                   workspace=torch.empty(4, dtype=torch.uint8, device=DEV))
     torch.cuda.synchronize()
+
+
+def test_inverted_subelements_are_counted_in_every_space():
+    """A vertex pushed through the opposite face inverts its subelements: the
+    value kernels still write every entry and count the inverted subelements
+    in diag[1] (H1, H(curl), H(div) and 2D)."""
+    m = meshgen.cartesian_mesh(1, 1, 0.0)
+    X = m["coords"].copy()
+    X[7] = [-0.5, -0.5, -0.5]           # corner (1,1,1) moved past corner (0,0,0)
+    ed = torch.from_numpy(m["elem_dofs"])
+    kap = torch.ones(1, 1, dtype=torch.float64)
+    diag = torch.zeros(2, dtype=torch.int32, device=DEV)
+    pat = lor.lor_pattern(lor.LOR_H1, 1, ed.to(DEV), m["ndofs"])
+    lor.lor_assemble_h1(pat, ed, X, kap, 1.0, diag=diag)
+    torch.cuda.synchronize()
+    assert diag.cpu().tolist() == [0, 1]
+    ee, ned = meshgen.nd_edge_map(1, 1)
+    diag.zero_()
+    pat = lor.lor_pattern(lor.LOR_ND, 1, torch.from_numpy(ee).to(DEV), ned)
+    lor.lor_assemble_nd(pat, ed, ee, X, kap, 1.0, m["ndofs"], diag=diag)
+    torch.cuda.synchronize()
+    assert diag.cpu().tolist() == [0, 1]
+    fm, nf = meshgen.face_map(1, 1)
+    diag.zero_()
+    pat = lor.lor_pattern(lor.LOR_RT, 1, torch.from_numpy(fm).to(DEV), nf)
+    lor.lor_assemble_rt(pat, ed, fm, X, kap, 1.0, m["ndofs"], diag=diag)
+    torch.cuda.synchronize()
+    assert diag.cpu().tolist() == [0, 1]
+    m2 = meshgen.cartesian_mesh_2d(1, 1, 0.0)
+    X2 = m2["coords"].copy()
+    X2[3] = [-0.5, -0.5]
+    diag.zero_()
+    pat = lor.lor_pattern(lor.LOR_H1_2D, 1, torch.from_numpy(m2["elem_dofs"]).to(DEV), m2["ndofs"])
+    lor.lor_assemble_h1_2d(pat, m2["elem_dofs"], X2, kap, 1.0, diag=diag)
+    torch.cuda.synchronize()
+    assert diag.cpu().tolist() == [0, 1]
+
+
+def test_pattern_rejects_a_row_longer_than_the_limit():
+    """20 trilinear elements that share vertex 0 and nothing else give row 0
+    141 nonzeros, above the 127-entry row limit: rejected with a message."""
+    maps = [[0] + [1 + 7 * e + k for k in range(7)] for e in range(20)]
+    em = torch.tensor(maps, dtype=torch.int32)
+    with pytest.raises(lor.LorError, match="nonzeros"):
+        lor.lor_pattern(lor.LOR_H1, 1, em.to(DEV), 1 + 7 * 20)
+    torch.cuda.synchronize()
