@@ -113,6 +113,14 @@ def cpu_baseline(m, sample_elems):
 
 KERNEL_SOURCES = ("lor_h1.hip", "lor_h1_math.hpp", "lor_common.hpp")
 TRAFFIC_FILE = "h1_p6_32cubed_traffic.json"
+VALU_FILE = "h1_p6_32cubed_valu.json"
+# FP64 VALU wave-instruction counters (one rocprofv3 --pmc pass holds all five)
+VALU_COUNTERS = ("SQ_INSTS_VALU_ADD_F64", "SQ_INSTS_VALU_MUL_F64", "SQ_INSTS_VALU_FMA_F64",
+                 "SQ_INSTS_VALU_TRANS_F64", "SQ_INSTS_VALU")
+MI355X_SIMDS = 256 * 4           # 256 CUs x 4 SIMDs
+MI355X_CLOCK_HZ = 2.4e9
+FP64_CYCLES_PER_WAVE_INSTR = 4   # 16 FP64 lanes per SIMD per clock: a wave64 instruction takes 4 clocks
+FP64_PEAK_TFLOPS = 78.6          # vector FP64 (an FMA counts as 2 flops)
 
 
 def kernel_source_hash():
@@ -228,6 +236,60 @@ def summarize_profiles(stats_dir, fetch_dir, write_dir, command):
     return "\n".join(lines) + "\n", out
 
 
+def summarize_valu(pmc_dir, command):
+    """FP64 VALU wave instructions per dispatch of the dominant kernel from one
+    rocprofv3 --pmc run of VALU_COUNTERS: the competing (arithmetic) bound."""
+    per = {}
+    for r in _read_csvs(pmc_dir, "counter_collection.csv"):
+        if "k_h1_assemble<6, double" in r["Kernel_Name"] and r["Counter_Name"] in VALU_COUNTERS:
+            per.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    if any(c not in per for c in VALU_COUNTERS):
+        return f"command: {command}\n\nno VALU counters found for k_h1_assemble<6, double>\n", None
+    avg = {c: sum(v) / len(v) for c, v in per.items()}
+    rec = {
+        "kernel": "k_h1_assemble<6,double,double>",
+        "kernel_source_hash": kernel_source_hash(),
+        "dispatches": len(per[VALU_COUNTERS[0]]),
+        "wave_instr_per_launch": avg,
+        "command": command,
+    }
+    lines = [f"command: {command}", "",
+             f"k_h1_assemble<6,double,double>: {rec['dispatches']} dispatches, wave instructions per dispatch"]
+    lines += [f"  {c:28s} {avg[c]:16.0f}" for c in VALU_COUNTERS]
+    return "\n".join(lines) + "\n", rec
+
+
+def load_valu():
+    """The committed VALU counter record, or None when missing or stale."""
+    path = os.path.join(ROOT, "profiles", VALU_FILE)
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    if t.get("kernel_source_hash") != kernel_source_hash():
+        return {"stale": True, "file": VALU_FILE}
+    return t
+
+
+def valu_bound(rec, avg_launch_us):
+    """FP64 arithmetic bound of one launch from its counted wave instructions:
+    the issue time if every FP64 wave instruction ran back to back on the
+    chip's SIMDs, and the FP64 rate counting all 64 lanes of each instruction
+    (an upper bound on useful flops: masked lanes are counted)."""
+    if rec is None or rec.get("stale"):
+        return rec
+    w = rec["wave_instr_per_launch"]
+    fp64 = sum(w[c] for c in VALU_COUNTERS[:4])
+    flops = 64 * (w["SQ_INSTS_VALU_ADD_F64"] + w["SQ_INSTS_VALU_MUL_F64"] + 2 * w["SQ_INSTS_VALU_FMA_F64"]
+                  + w["SQ_INSTS_VALU_TRANS_F64"])
+    floor_us = fp64 * FP64_CYCLES_PER_WAVE_INSTR / (MI355X_SIMDS * MI355X_CLOCK_HZ) * 1e6
+    ach = flops / (avg_launch_us * 1e-6) / 1e12
+    return {"bound": "alu", "unit": "TFLOP/s", "achieved": ach, "peak": FP64_PEAK_TFLOPS,
+            "frac": ach / FP64_PEAK_TFLOPS, "fp64_wave_instr_per_launch": fp64,
+            "all_valu_wave_instr_per_launch": w["SQ_INSTS_VALU"],
+            "fp64_issue_floor_us": floor_us, "fp64_issue_floor_frac_of_launch": floor_us / avg_launch_us}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -239,9 +301,21 @@ def main():
                     help="FP32 pencil eigenvalues on the 274,625-row mesh instead of the 35,937-row one")
     ap.add_argument("--summarize-profiles", nargs=3, metavar=("STATS_DIR", "FETCH_DIR", "WRITE_DIR"),
                     help="summarise rocprofv3 CSV output of this script (no GPU use)")
+    ap.add_argument("--summarize-valu", metavar="PMC_DIR",
+                    help="summarise a rocprofv3 --pmc run of the FP64 VALU counters (no GPU use)")
     ap.add_argument("--profile-command", default="", help="command recorded in the summary")
     ap.add_argument("--profile-name", default="h1_p6_32cubed_fp64")
     args = ap.parse_args()
+    if args.summarize_valu:
+        text, rec = summarize_valu(args.summarize_valu, args.profile_command)
+        os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
+        with open(os.path.join(ROOT, "profiles", args.profile_name + "_valu.txt"), "w") as f:
+            f.write(text)
+        if rec is not None:
+            with open(os.path.join(ROOT, "profiles", VALU_FILE), "w") as f:
+                json.dump(rec, f, indent=1)
+        print(text)
+        return
     if args.summarize_profiles:
         text, traffic = summarize_profiles(*args.summarize_profiles, args.profile_command)
         os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
@@ -330,6 +404,7 @@ def main():
             "traffic_detail": traffic_detail,
             "copy_calibration": calib,
             "frac_of_measured_copy": ach / calib["GBs"],
+            "competing_bound": valu_bound(load_valu(), avg_launch_us),
         },
         "fp32": {
             "ms_per_step": ms32,
