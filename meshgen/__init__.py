@@ -51,6 +51,9 @@ __all__ = [
     "boundary_edges",
     "random_dofs",
     "ho_nodes",
+    "prism_mesh",
+    "edge_map_from_vertices",
+    "face_map_from_vertices",
     "CONFIGS",
     "config_mesh",
 ]
@@ -472,6 +475,126 @@ def random_dofs(ndofs: int, count: int, seed: int, duplicates: bool = True) -> n
     if duplicates:
         return rng.integers(0, ndofs, size=count).astype(np.int32)
     return rng.permutation(ndofs)[:count].astype(np.int32)
+
+
+# ---------------------------------------------------------------- unstructured
+
+def prism_mesh(p: int, sides: int = 3, layers: int = 2, amp: float = 0.0) -> dict:
+    """A conforming hexahedral mesh that is not a Cartesian grid: the regular
+    `sides`-gon of circumradius 1 is cut into `sides` quadrilaterals around its
+    centre C (quadrilateral k has the corners C, the midpoint M_{k-1} of side
+    k-1, the polygon vertex P_k and the midpoint M_k, with P_k at angle
+    2 pi k / sides and side k joining P_k and P_{k+1}), and the polygon is
+    extruded over z in [0, 1] in `layers` layers.  The edge through C is shared
+    by `sides` elements per layer (3 or 5: irregular valence), the polygon
+    vertices by one.  Element e = k + sides * l; its local corner (a, b, c) is
+    C, M_{k-1}, P_k, M_k for (a, b) = (0,0), (1,0), (1,1), (0,1), at height
+    (l + c) / layers; lattice points come from the bilinear-in-plane map at the
+    Gauss-Lobatto points.  Points shared by neighbouring elements are merged by
+    their coordinates snapped to 1e-9, and the global ids follow the sorted
+    snapped coordinates.  With amp != 0, every lattice vertex is then moved by
+        x' = x + A sin(2 pi y) sin(2 pi z)   (and cyclically),   A = amp / 2.
+    Returns coords, elem_dofs, p, sides, layers, nel, ndofs (as cartesian_mesh,
+    without n and N)."""
+    if sides < 3 or layers < 1:
+        raise ValueError("sides >= 3 and layers >= 1")
+    q = p + 1
+    t = gll_points(p)
+    ang = 2.0 * math.pi * np.arange(sides) / sides
+    P = np.stack([np.cos(ang), np.sin(ang)], axis=1)
+    Mid = 0.5 * (P + np.roll(P, -1, axis=0))          # Mid[k] joins P[k] and P[k+1]
+    C = np.zeros(2)
+    # local lattice parameters, index i + q*(j + q*k)
+    kk, jj, ii = np.meshgrid(np.arange(q), np.arange(q), np.arange(q), indexing="ij")
+    xi, eta, zeta = t[ii.reshape(-1)], t[jj.reshape(-1)], t[kk.reshape(-1)]
+    pts = []
+    for l in range(layers):
+        for k in range(sides):
+            c00, c10, c11, c01 = C, Mid[k - 1], P[k], Mid[k]
+            xy = (((1 - xi) * (1 - eta))[:, None] * c00 + (xi * (1 - eta))[:, None] * c10
+                  + (xi * eta)[:, None] * c11 + ((1 - xi) * eta)[:, None] * c01)
+            z = (l + zeta) / layers
+            pts.append(np.concatenate([xy, z[:, None]], axis=1))
+    pts = np.concatenate(pts, axis=0)
+    key = np.round(pts * 1e9).astype(np.int64)
+    uniq, inv = np.unique(key, axis=0, return_inverse=True)
+    first = np.full(len(uniq), -1, dtype=np.int64)
+    order = np.arange(len(inv))[::-1]
+    first[inv.reshape(-1)[order]] = order               # one representative per merged point
+    coords = pts[first].copy()
+    expect = (1 + sides * p + sides * p * p) * (layers * p + 1)
+    if len(uniq) != expect:
+        raise RuntimeError(f"lattice merge gave {len(uniq)} vertices, expected {expect}")
+    A = amp / 2.0
+    if A != 0.0:
+        tp = 2.0 * math.pi
+        X, Y, Z = coords[:, 0], coords[:, 1], coords[:, 2]
+        sx, sy, sz = np.sin(tp * X), np.sin(tp * Y), np.sin(tp * Z)
+        coords = np.stack([X + A * sy * sz, Y + A * sz * sx, Z + A * sx * sy], axis=1)
+    nel = sides * layers
+    return {"coords": np.ascontiguousarray(coords, dtype=np.float64),
+            "elem_dofs": inv.reshape(nel, q ** 3).astype(np.int32),
+            "p": p, "sides": sides, "layers": layers, "nel": nel, "ndofs": len(uniq)}
+
+
+def edge_map_from_vertices(elem_dofs: np.ndarray, p: int) -> tuple[np.ndarray, int]:
+    """Signed element-to-edge map of any conforming LOR hex mesh, from its
+    vertex map alone: the local edges (numbered as in the module docstring, each
+    along +axis from its first to its second local vertex) are merged by their
+    two global vertex ids; global edge ids follow the sorted (lower id, higher
+    id) pairs, and every global edge points from its lower to its higher vertex
+    id, so an entry is -1-g where the local edge runs the other way."""
+    q = p + 1
+    v0, v1 = [], []
+    for axis, stride, (ni, nj, nk) in ((0, 1, (p, q, q)), (1, q, (q, p, q)), (2, q * q, (q, q, p))):
+        k, j, i = np.meshgrid(np.arange(nk), np.arange(nj), np.arange(ni), indexing="ij")
+        a = (i + q * (j + q * k)).reshape(-1)
+        v0.append(a)
+        v1.append(a + stride)
+    v0, v1 = np.concatenate(v0), np.concatenate(v1)
+    g0 = elem_dofs[:, v0].astype(np.int64)
+    g1 = elem_dofs[:, v1].astype(np.int64)
+    lo, hi = np.minimum(g0, g1), np.maximum(g0, g1)
+    key = np.stack([lo.reshape(-1), hi.reshape(-1)], axis=1)
+    uniq, inv = np.unique(key, axis=0, return_inverse=True)
+    gid = inv.reshape(g0.shape)
+    out = np.where(g0 < g1, gid, -1 - gid)
+    return out.astype(np.int32), len(uniq)
+
+
+def face_map_from_vertices(elem_dofs: np.ndarray, p: int) -> tuple[np.ndarray, int]:
+    """Signed element-to-face map of any conforming LOR hex mesh (local faces
+    numbered as in face_map), from its vertex map alone.  Each local face lists
+    its 4 vertices in the cyclic order whose right-hand normal is the local
+    +axis; faces are merged by their sorted vertex ids (global ids follow the
+    sorted 4-tuples).  The global normal of a face is the one of the cyclic
+    order that, started at its lowest vertex id, visits the lower of that
+    vertex's two neighbours first; an entry is -1-f where the local normal is
+    the opposite one."""
+    q = p + 1
+    cyc = []
+    # x-faces at i (0..p), spanning (j, j+1) x (k, k+1): normal +x = e_y x e_z
+    k, j, i = np.meshgrid(np.arange(p), np.arange(p), np.arange(q), indexing="ij")
+    b = (i + q * (j + q * k)).reshape(-1)
+    cyc.append(np.stack([b, b + q, b + q + q * q, b + q * q], axis=1))
+    # y-faces at j (0..p), spanning (i, i+1) x (k, k+1): normal +y = e_z x e_x
+    k, j, i = np.meshgrid(np.arange(p), np.arange(q), np.arange(p), indexing="ij")
+    b = (i + q * (j + q * k)).reshape(-1)
+    cyc.append(np.stack([b, b + q * q, b + q * q + 1, b + 1], axis=1))
+    # z-faces at k (0..p), spanning (i, i+1) x (j, j+1): normal +z = e_x x e_y
+    k, j, i = np.meshgrid(np.arange(q), np.arange(p), np.arange(p), indexing="ij")
+    b = (i + q * (j + q * k)).reshape(-1)
+    cyc.append(np.stack([b, b + 1, b + 1 + q, b + q], axis=1))
+    cyc = np.concatenate(cyc, axis=0)                   # [nlocf, 4] local vertices
+    g = elem_dofs[:, cyc].astype(np.int64)               # [nel, nlocf, 4]
+    key = np.sort(g, axis=2).reshape(-1, 4)
+    uniq, inv = np.unique(key, axis=0, return_inverse=True)
+    gid = inv.reshape(g.shape[:2])
+    m = np.argmin(g, axis=2)
+    nxt = np.take_along_axis(g, ((m + 1) % 4)[..., None], axis=2)[..., 0]
+    prv = np.take_along_axis(g, ((m + 3) % 4)[..., None], axis=2)[..., 0]
+    out = np.where(nxt < prv, gid, -1 - gid)
+    return out.astype(np.int32), len(uniq)
 
 
 # ---------------------------------------------------------------- named workloads

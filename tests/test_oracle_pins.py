@@ -954,3 +954,67 @@ def test_h1_2d_affine_energy_and_pattern():
     N = m["N"]
     assert rp[-1].item() == (3 * N - 2) ** 2
     assert int((rp[1:] - rp[:-1]).max()) == 9
+
+
+# ------------------------------------------------- irregular-valence hex meshes
+
+PRISMS = [(3, 2, 2), (5, 2, 2), (3, 1, 3)]   # (sides, layers, p)
+
+
+@pytest.mark.parametrize("sides,layers,p", PRISMS)
+def test_prism_h1_invariants_and_axis_rows(sides, layers, p):
+    """The polygon prism has an axis edge shared by `sides` elements per layer.
+    With flat faces the subelements tile the prism exactly and det J is
+    bilinear on each, so the 2-point rule gives total mass = polygon area x 1.
+    On a curved copy the diffusion rows sum to zero and K is symmetric.  A
+    vertex on the axis at an interior lattice level couples to the centre, the
+    first spoke point and the first diagonal point of every quadrilateral on
+    three levels: 3 (1 + 2 sides) columns."""
+    m = meshgen.prism_mesh(p, sides, layers, 0.0)
+    kap = meshgen.kappa_field(m["nel"], p, 1.0, seed=7)
+    rp, ci, v = orc.h1_matrix(m["coords"], m["elem_dofs"], p, torch.zeros_like(kap), 1.0)
+    area = 0.5 * sides * math.sin(2.0 * math.pi / sides)
+    assert abs(float(v.sum()) - area) <= 1e-13
+    X = m["coords"]
+    on_axis = np.flatnonzero((np.abs(X[:, 0]) < 1e-12) & (np.abs(X[:, 1]) < 1e-12))
+    assert len(on_axis) == layers * p + 1
+    lengths = (rp[1:] - rp[:-1]).numpy()
+    for g in on_axis:
+        z = X[g, 2]
+        levels = 2 if (z < 1e-12 or z > 1.0 - 1e-12) else 3
+        assert lengths[g] == levels * (1 + 2 * sides)
+    mc = meshgen.prism_mesh(p, sides, layers, 0.15)
+    rp, ci, v = orc.h1_matrix(mc["coords"], mc["elem_dofs"], p, kap, 0.0)
+    K = dense(rp, ci, v)
+    assert np.abs(K.sum(axis=1)).max() <= 1e-13 * np.abs(K).max()
+    assert np.abs(K - K.T).max() <= 1e-15 * np.abs(K).max()
+
+
+@pytest.mark.parametrize("sides,layers,p", PRISMS)
+def test_prism_nd_rt_exact_sequences(sides, layers, p):
+    """On the curved polygon prism, with edge and face maps built from the
+    vertex map alone: K_curl G = 0 and G^T M_ND G = K_H1 (the gradient written
+    from its definition here), K_div C = 0 and C^T M_RT C = K_curl (the discrete
+    curl of the oracle).  A face or edge whose orientation disagreed between
+    two elements would break the second identity of each pair."""
+    m = meshgen.prism_mesh(p, sides, layers, 0.15)
+    ee, ned = meshgen.edge_map_from_vertices(m["elem_dofs"], p)
+    fm, nf = meshgen.face_map_from_vertices(m["elem_dofs"], p)
+    kap = meshgen.kappa_field(m["nel"], p, 1.0, seed=sides + 10 * p)
+    G = _gradient_from_topology(m, ee, ned, p)
+    rp, ci, v = orc.nd_matrix(m["coords"], m["elem_dofs"], ee, p, kap, 0.0, ned)
+    Kc = dense(rp, ci, v, ned)
+    assert np.abs(Kc @ G).max() <= 1e-13 * np.abs(Kc).max()
+    rp, ci, v = orc.nd_matrix(m["coords"], m["elem_dofs"], ee, p, torch.zeros_like(kap), kap, ned)
+    Mn = dense(rp, ci, v, ned)
+    rp, ci, v = orc.h1_matrix(m["coords"], m["elem_dofs"], p, kap, 0.0)
+    Kh = dense(rp, ci, v)
+    assert np.abs(G.T @ Mn @ G - Kh).max() <= 1e-13 * np.abs(Kh).max()
+    crp, cci, cv = orc.discrete_curl(ee, fm, p, nf)
+    C = dense(crp, cci, cv, ned)
+    rp, ci, v = orc.rt_matrix(m["coords"], m["elem_dofs"], fm, p, kap, 0.0, nf)
+    Kd = dense(rp, ci, v, nf)
+    assert np.abs(Kd @ C).max() <= 1e-14 * np.abs(Kd).max() * np.abs(C).sum(axis=0).max()
+    rp, ci, v = orc.rt_matrix(m["coords"], m["elem_dofs"], fm, p, torch.zeros_like(kap), kap, nf)
+    Mrt = dense(rp, ci, v, nf)
+    assert np.abs(C.T @ Mrt @ C - Kc).max() <= 1e-13 * np.abs(Kc).max()
