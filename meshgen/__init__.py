@@ -52,6 +52,7 @@ __all__ = [
     "random_dofs",
     "ho_nodes",
     "prism_mesh",
+    "polygon_mesh_2d",
     "edge_map_from_vertices",
     "face_map_from_vertices",
     "CONFIGS",
@@ -535,6 +536,48 @@ def prism_mesh(p: int, sides: int = 3, layers: int = 2, amp: float = 0.0) -> dic
     return {"coords": np.ascontiguousarray(coords, dtype=np.float64),
             "elem_dofs": inv.reshape(nel, q ** 3).astype(np.int32),
             "p": p, "sides": sides, "layers": layers, "nel": nel, "ndofs": len(uniq)}
+
+
+def polygon_mesh_2d(p: int, sides: int = 3, amp: float = 0.0) -> dict:
+    """The 2D counterpart of prism_mesh: the regular `sides`-gon of
+    circumradius 1 cut into `sides` quadrilaterals around its centre (corner
+    (a, b) of quadrilateral k is C, M_{k-1}, P_k, M_k for (0,0), (1,0), (1,1),
+    (0,1)), so the centre is shared by `sides` elements.  Local vertex i + q*j;
+    lattice points merged by coordinates snapped to 1e-9, global ids following
+    the sorted snapped coordinates; with amp != 0 every lattice vertex is moved
+    by x' = x + A sin(2 pi y), y' = y + A sin(2 pi x), A = amp / 2.  Returns
+    coords [ndofs, 2], elem_dofs [sides, (p+1)^2], p, sides, nel, ndofs."""
+    if sides < 3:
+        raise ValueError("sides >= 3")
+    q = p + 1
+    t = gll_points(p)
+    ang = 2.0 * math.pi * np.arange(sides) / sides
+    P = np.stack([np.cos(ang), np.sin(ang)], axis=1)
+    Mid = 0.5 * (P + np.roll(P, -1, axis=0))
+    jj, ii = np.meshgrid(np.arange(q), np.arange(q), indexing="ij")
+    xi, eta = t[ii.reshape(-1)], t[jj.reshape(-1)]
+    pts = []
+    for k in range(sides):
+        c10, c11, c01 = Mid[k - 1], P[k], Mid[k]       # c00 is the centre (0, 0)
+        pts.append((xi * (1 - eta))[:, None] * c10 + (xi * eta)[:, None] * c11 + ((1 - xi) * eta)[:, None] * c01)
+    pts = np.concatenate(pts, axis=0)
+    key = np.round(pts * 1e9).astype(np.int64)
+    uniq, inv = np.unique(key, axis=0, return_inverse=True)
+    first = np.full(len(uniq), -1, dtype=np.int64)
+    order = np.arange(len(inv))[::-1]
+    first[inv.reshape(-1)[order]] = order
+    coords = pts[first].copy()
+    expect = 1 + sides * p + sides * p * p
+    if len(uniq) != expect:
+        raise RuntimeError(f"lattice merge gave {len(uniq)} vertices, expected {expect}")
+    A = amp / 2.0
+    if A != 0.0:
+        tp = 2.0 * math.pi
+        X, Y = coords[:, 0], coords[:, 1]
+        coords = np.stack([X + A * np.sin(tp * Y), Y + A * np.sin(tp * X)], axis=1)
+    return {"coords": np.ascontiguousarray(coords, dtype=np.float64),
+            "elem_dofs": inv.reshape(sides, q * q).astype(np.int32),
+            "p": p, "sides": sides, "nel": sides, "ndofs": len(uniq)}
 
 
 def edge_map_from_vertices(elem_dofs: np.ndarray, p: int) -> tuple[np.ndarray, int]:

@@ -89,3 +89,67 @@ def test_prism_rt_parity(case):
                               fp64_fallback=True).cpu()
     torch.cuda.synchronize()
     _check(pat, rp, ci, v64, v32, v)
+
+
+@pytest.mark.parametrize("case", [(3, 2), (5, 3), (5, 6)], ids=["s3p2", "s5p3", "s5p6"])
+def test_polygon_2d_parity(case):
+    """2D H1 on the polygon cut into quadrilaterals around its centre (the
+    centre row couples 1 + 2 sides vertices)."""
+    sides, p = case
+    _say("h1_2d polygon", case)
+    m = meshgen.polygon_mesh_2d(p, sides, 0.12)
+    kap = meshgen.kappa_field_2d(m["nel"], p, 1.0, seed=sides * p)
+    rp, ci, v = orc.h1_matrix_2d(m["coords"], m["elem_dofs"], p, kap, 0.7, m["ndofs"])
+    ed, x = torch.from_numpy(m["elem_dofs"]), torch.from_numpy(m["coords"])
+    pat = lor.lor_pattern(lor.LOR_H1_2D, p, ed.to(DEV), m["ndofs"])
+    assert pat.ncolors >= sides
+    v64 = lor.lor_assemble_h1_2d(pat, ed, x, kap, 0.7).cpu()
+    v32 = lor.lor_assemble_h1_2d(pat, ed, x, kap.float(), 0.7, dtype=torch.float32, fp64_fallback=True).cpu()
+    torch.cuda.synchronize()
+    _check(pat, rp, ci, v64, v32, v)
+
+
+@pytest.mark.parametrize("case", [(3, 2, 2, 2), (5, 1, 3, 3)], ids=["s3l2p2B2", "s5l1p3B3"])
+def test_prism_backward_parity(case):
+    """The adjoint on the prism against autograd through the oracle."""
+    from tests.test_gpu_backward import oracle_loss_grads
+    sides, layers, p, batch = case
+    _say("backward prism", case)
+    m = meshgen.prism_mesh(p, sides, layers, 0.12)
+    kap = meshgen.kappa_field(m["nel"], p, 1.0, seed=5, batch=batch)
+    rp, ci, _ = orc.h1_matrix(m["coords"], m["elem_dofs"], p, kap[0], 0.7)
+    cot = meshgen.cotangent(batch, rp[-1].item(), seed=1)
+    gk_ref, gx_ref = oracle_loss_grads(m, p, kap, 0.7, cot, rp, ci)
+    ed, x = torch.from_numpy(m["elem_dofs"]), torch.from_numpy(m["coords"])
+    pat = lor.lor_pattern(lor.LOR_H1, p, ed.to(DEV), m["ndofs"])
+    for dtype, tol in ((torch.float64, 1e-10), (torch.float32, 1e-5)):
+        gk, gx = lor.lor_assemble_backward(pat, ed, x, kap.to(dtype), 0.7, cot.to(dtype), dtype=dtype)
+        torch.cuda.synchronize()
+        ek = float((gk.cpu().double() - gk_ref).abs().max() / gk_ref.abs().max())
+        ex = float((gx.cpu() - gx_ref).abs().max() / gx_ref.abs().max())
+        _say(f"  {dtype}: kappa {ek:.2e} coords {ex:.2e}")
+        assert ek <= tol and ex <= tol
+
+
+@pytest.mark.parametrize("case", [(3, 2, 2), (5, 2, 3)], ids=["s3l2p2", "s5l2p3"])
+def test_prism_discrete_gradient_and_curl(case):
+    """Bit-exact discrete gradient and curl on the prism (first incidence from
+    the schedule and from the face-owner pass on an irregular mesh)."""
+    sides, layers, p = case
+    _say("aux prism", case)
+    m = meshgen.prism_mesh(p, sides, layers, 0.0)
+    ee, ned = meshgen.edge_map_from_vertices(m["elem_dofs"], p)
+    fm, nf = meshgen.face_map_from_vertices(m["elem_dofs"], p)
+    rp, ci, v = orc.discrete_gradient(m["elem_dofs"], ee, p, ned)
+    pat = lor.lor_pattern(lor.LOR_ND, p, torch.from_numpy(ee).to(DEV), ned)
+    grp, gci, gv = lor.lor_discrete_gradient(pat, m["elem_dofs"], ee, m["ndofs"])
+    torch.cuda.synchronize()
+    assert torch.equal(grp.cpu().to(torch.int64), rp)
+    assert torch.equal(gci.cpu().to(torch.int64), ci)
+    assert torch.equal(gv.cpu(), v)
+    rp, ci, v = orc.discrete_curl(ee, fm, p, nf)
+    crp, cci, cv = lor.lor_discrete_curl(p, ee, fm, ned, nf, device=DEV)
+    torch.cuda.synchronize()
+    assert torch.equal(crp.cpu().to(torch.int64), rp)
+    assert torch.equal(cci.cpu().to(torch.int64), ci)
+    assert torch.equal(cv.cpu(), v)

@@ -1018,3 +1018,23 @@ def test_prism_nd_rt_exact_sequences(sides, layers, p):
     rp, ci, v = orc.rt_matrix(m["coords"], m["elem_dofs"], fm, p, torch.zeros_like(kap), kap, nf)
     Mrt = dense(rp, ci, v, nf)
     assert np.abs(C.T @ Mrt @ C - Kc).max() <= 1e-13 * np.abs(Kc).max()
+
+
+@pytest.mark.parametrize("sides,p", [(3, 2), (5, 3), (5, 1)])
+def test_polygon_2d_invariants(sides, p):
+    """The 2D polygon mesh (centre shared by `sides` quadrilaterals): total
+    mass = polygon area (flat bilinear cells tile it exactly, det J bilinear),
+    zero diffusion row sums and symmetry on a curved copy, and the centre row
+    couples 1 + 2 sides vertices."""
+    m = meshgen.polygon_mesh_2d(p, sides, 0.0)
+    kap = meshgen.kappa_field_2d(m["nel"], p, 1.0, seed=sides)
+    rp, ci, v = orc.h1_matrix_2d(m["coords"], m["elem_dofs"], p, torch.zeros_like(kap), 1.0, m["ndofs"])
+    area = 0.5 * sides * math.sin(2.0 * math.pi / sides)
+    assert abs(float(v.sum()) - area) <= 1e-13
+    c = int(np.flatnonzero(np.abs(m["coords"]).sum(axis=1) < 1e-12)[0])
+    assert int(rp[c + 1] - rp[c]) == 1 + 2 * sides
+    mc = meshgen.polygon_mesh_2d(p, sides, 0.15)
+    rp, ci, v = orc.h1_matrix_2d(mc["coords"], mc["elem_dofs"], p, kap, 0.0, mc["ndofs"])
+    K = dense(rp, ci, v)
+    assert np.abs(K.sum(axis=1)).max() <= 1e-13 * np.abs(K).max()
+    assert np.abs(K - K.T).max() <= 1e-15 * np.abs(K).max()
