@@ -53,6 +53,8 @@ __all__ = [
     "ho_nodes",
     "prism_mesh",
     "polygon_mesh_2d",
+    "tri_split_mesh",
+    "tri_split_mesh_2d",
     "edge_map_from_vertices",
     "face_map_from_vertices",
     "CONFIGS",
@@ -578,6 +580,105 @@ def polygon_mesh_2d(p: int, sides: int = 3, amp: float = 0.0) -> dict:
     return {"coords": np.ascontiguousarray(coords, dtype=np.float64),
             "elem_dofs": inv.reshape(sides, q * q).astype(np.int32),
             "p": p, "sides": sides, "nel": sides, "ndofs": len(uniq)}
+
+
+def _merge_points(pts: np.ndarray, nel: int, nloc: int, expect: int) -> tuple[np.ndarray, np.ndarray]:
+    """Global ids of lattice points shared by neighbouring elements: points are
+    merged by their coordinates snapped to 1e-9 (ids follow the sorted snapped
+    coordinates); returns (coords [ndofs, d], elem_dofs [nel, nloc])."""
+    key = np.round(pts * 1e9).astype(np.int64)
+    uniq, inv = np.unique(key, axis=0, return_inverse=True)
+    if len(uniq) != expect:
+        raise RuntimeError(f"lattice merge gave {len(uniq)} vertices, expected {expect}")
+    first = np.full(len(uniq), -1, dtype=np.int64)
+    order = np.arange(len(inv))[::-1]
+    first[inv.reshape(-1)[order]] = order
+    return pts[first].copy(), inv.reshape(nel, nloc).astype(np.int32)
+
+
+def _tri_split_quads(n: int) -> np.ndarray:
+    """Corners [6 n^2, 4, 2] of the quadrilaterals of the unit square cut into
+    n x n cells, each cell into two triangles by its (0,0)-(1,1) diagonal, each
+    triangle (A, B, C), counter-clockwise, into three quadrilaterals around its
+    centroid G: (A, M_AB, G, M_CA), (B, M_BC, G, M_AB), (C, M_CA, G, M_BC) as
+    local corners (0,0), (1,0), (1,1), (0,1).  Quadrilateral index
+    3 (2 (cx + n cy) + t) + corner."""
+    quads = []
+    for cy in range(n):
+        for cx in range(n):
+            v00 = np.array([cx, cy], dtype=np.float64) / n
+            v10, v11, v01 = v00 + [1.0 / n, 0.0], v00 + [1.0 / n, 1.0 / n], v00 + [0.0, 1.0 / n]
+            for A, B, C in ((v00, v10, v11), (v00, v11, v01)):
+                G = (A + B + C) / 3.0
+                mab, mbc, mca = 0.5 * (A + B), 0.5 * (B + C), 0.5 * (C + A)
+                quads += [(A, mab, G, mca), (B, mbc, G, mab), (C, mca, G, mbc)]
+    return np.array(quads)
+
+
+def _tri_split_count(n: int, p: int) -> int:
+    """Lattice points of the planar mesh of _tri_split_quads(n) at degree p."""
+    return ((n + 1) ** 2 + 2 * n * n + 3 * n * n + 2 * n + (p - 1) * (12 * n * n + 4 * n)
+            + 6 * n * n * (p - 1) ** 2)
+
+
+def tri_split_mesh(n: int, layers: int, p: int, amp: float = 0.0) -> dict:
+    """A conforming hexahedral mesh of the unit cube with irregular valence
+    throughout: the quadrilaterals of _tri_split_quads(n) (vertex valence 3 at
+    the centroids, 4 at the edge midpoints, up to 6 at the grid vertices)
+    extruded over z in [0, 1] in `layers` layers; element
+    e = quad + 6 n^2 * layer, local corner (a, b, c) at quad corner (a, b) and
+    height (layer + c) / layers; Gauss-Lobatto lattice from the
+    bilinear-in-plane map; shared points merged by coordinates (count checked
+    against its closed form); with amp != 0 every lattice vertex is moved by
+    the sinusoidal map of cartesian_mesh with A = amp / n.  Returns coords,
+    elem_dofs, p, n, layers, nel, ndofs."""
+    q = p + 1
+    t = gll_points(p)
+    Q = _tri_split_quads(n)
+    nq = len(Q)
+    kk, jj, ii = np.meshgrid(np.arange(q), np.arange(q), np.arange(q), indexing="ij")
+    xi, eta, zeta = t[ii.reshape(-1)], t[jj.reshape(-1)], t[kk.reshape(-1)]
+    w = np.stack([(1 - xi) * (1 - eta), xi * (1 - eta), xi * eta, (1 - xi) * eta], axis=1)   # [q^3, 4]
+    xy = np.einsum("lc,qcd->qld", w, Q)                                                        # [nq, q^3, 2]
+    pts = []
+    for l in range(layers):
+        z = np.broadcast_to(((l + zeta) / layers)[None, :, None], (nq, q ** 3, 1))
+        pts.append(np.concatenate([xy, z], axis=2))
+    pts = np.concatenate(pts, axis=0).reshape(-1, 3)
+    # planar lattice: vertices (n+1)^2, centroids 2n^2, edge midpoints 3n^2+2n,
+    # plus p-1 interior points on each of the 12n^2+4n quadrilateral edges (two
+    # halves of every triangle edge, three spokes per triangle) and (p-1)^2
+    # inside each of the 6n^2 quadrilaterals
+    n2d = _tri_split_count(n, p)
+    coords, ed = _merge_points(pts, nq * layers, q ** 3, n2d * (layers * p + 1))
+    A = amp / n
+    if A != 0.0:
+        tp = 2.0 * math.pi
+        X, Y, Z = coords[:, 0], coords[:, 1], coords[:, 2]
+        sx, sy, sz = np.sin(tp * X), np.sin(tp * Y), np.sin(tp * Z)
+        coords = np.stack([X + A * sy * sz, Y + A * sz * sx, Z + A * sx * sy], axis=1)
+    return {"coords": np.ascontiguousarray(coords, dtype=np.float64), "elem_dofs": ed, "p": p, "n": n,
+            "layers": layers, "nel": nq * layers, "ndofs": len(coords)}
+
+
+def tri_split_mesh_2d(n: int, p: int, amp: float = 0.0) -> dict:
+    """The planar quadrilateral mesh of tri_split_mesh (local vertex i + q*j),
+    moved with amp != 0 by the sinusoidal map of cartesian_mesh_2d (A = amp/n)."""
+    q = p + 1
+    t = gll_points(p)
+    Q = _tri_split_quads(n)
+    jj, ii = np.meshgrid(np.arange(q), np.arange(q), indexing="ij")
+    xi, eta = t[ii.reshape(-1)], t[jj.reshape(-1)]
+    w = np.stack([(1 - xi) * (1 - eta), xi * (1 - eta), xi * eta, (1 - xi) * eta], axis=1)
+    pts = np.einsum("lc,qcd->qld", w, Q).reshape(-1, 2)
+    coords, ed = _merge_points(pts, len(Q), q * q, _tri_split_count(n, p))
+    A = amp / n
+    if A != 0.0:
+        tp = 2.0 * math.pi
+        X, Y = coords[:, 0], coords[:, 1]
+        coords = np.stack([X + A * np.sin(tp * Y), Y + A * np.sin(tp * X)], axis=1)
+    return {"coords": np.ascontiguousarray(coords, dtype=np.float64), "elem_dofs": ed, "p": p, "n": n,
+            "nel": len(Q), "ndofs": len(coords)}
 
 
 def edge_map_from_vertices(elem_dofs: np.ndarray, p: int) -> tuple[np.ndarray, int]:

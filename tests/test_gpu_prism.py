@@ -1,7 +1,9 @@
-"""GPU parity on hexahedral meshes that are not Cartesian grids: the polygon
-prism (an axis edge shared by 3 or 5 elements per layer, rows of 21 or 33
-vertex columns on the axis, more than 8 colours), for H1, H(curl) and H(div),
-with the edge and face maps built from the vertex map alone."""
+"""GPU parity on hexahedral meshes that are not Cartesian grids, with the edge
+and face maps built from the vertex map alone: the polygon prism (an axis edge
+shared by 3 or 5 elements per layer, rows of 21 or 33 vertex columns on the
+axis, more than 8 colours) and the triangle-split cube (valence 3, 4 and 6
+everywhere, rows of up to 39 vertex columns, hundreds of elements, so every
+colour spans several groups per workgroup)."""
 import sys
 
 import pytest
@@ -152,4 +154,88 @@ def test_prism_discrete_gradient_and_curl(case):
     torch.cuda.synchronize()
     assert torch.equal(crp.cpu().to(torch.int64), rp)
     assert torch.equal(cci.cpu().to(torch.int64), ci)
+    assert torch.equal(cv.cpu(), v)
+
+
+TRI = [(6, 3, 2), (4, 2, 3), (2, 2, 6), (3, 1, 5)]   # (n, layers, p)
+
+
+@pytest.mark.parametrize("case", TRI, ids=[f"n{c[0]}l{c[1]}p{c[2]}" for c in TRI])
+def test_tri_split_parity(case):
+    n, layers, p = case
+    _say("tri-split", case)
+    m = meshgen.tri_split_mesh(n, layers, p, 0.1)
+    kap = meshgen.kappa_field(m["nel"], p, 1.0, seed=n + 10 * p)
+    ed, x = torch.from_numpy(m["elem_dofs"]), torch.from_numpy(m["coords"])
+    rp, ci, v = orc.h1_matrix(m["coords"], m["elem_dofs"], p, kap, 1.0)
+    pat = lor.lor_pattern(lor.LOR_H1, p, ed.to(DEV), m["ndofs"])
+    v64 = lor.lor_assemble_h1(pat, ed, x, kap, 1.0).cpu()
+    v32 = lor.lor_assemble_h1(pat, ed, x, kap.float(), 1.0, dtype=torch.float32, fp64_fallback=True).cpu()
+    torch.cuda.synchronize()
+    _check(pat, rp, ci, v64, v32, v)
+    if p <= 5:
+        ee, ned = meshgen.edge_map_from_vertices(m["elem_dofs"], p)
+        rp, ci, v = orc.nd_matrix(m["coords"], m["elem_dofs"], ee, p, kap, 0.8, ned)
+        pat = lor.lor_pattern(lor.LOR_ND, p, torch.from_numpy(ee).to(DEV), ned)
+        v64 = lor.lor_assemble_nd(pat, ed, torch.from_numpy(ee), x, kap, 0.8, m["ndofs"]).cpu()
+        v32 = lor.lor_assemble_nd(pat, ed, torch.from_numpy(ee), x, kap.float(), 0.8, m["ndofs"],
+                                  dtype=torch.float32, fp64_fallback=True).cpu()
+        torch.cuda.synchronize()
+        _check(pat, rp, ci, v64, v32, v)
+    fm, nf = meshgen.face_map_from_vertices(m["elem_dofs"], p)
+    rp, ci, v = orc.rt_matrix(m["coords"], m["elem_dofs"], fm, p, kap, 1.3, nf)
+    pat = lor.lor_pattern(lor.LOR_RT, p, torch.from_numpy(fm).to(DEV), nf)
+    v64 = lor.lor_assemble_rt(pat, ed, torch.from_numpy(fm), x, kap, 1.3, m["ndofs"]).cpu()
+    v32 = lor.lor_assemble_rt(pat, ed, torch.from_numpy(fm), x, kap.float(), 1.3, m["ndofs"],
+                              dtype=torch.float32, fp64_fallback=True).cpu()
+    torch.cuda.synchronize()
+    _check(pat, rp, ci, v64, v32, v)
+
+
+@pytest.mark.parametrize("case", [(8, 4), (4, 6), (6, 1)], ids=["n8p4", "n4p6", "n6p1"])
+def test_tri_split_2d_parity(case):
+    n, p = case
+    _say("tri-split 2d", case)
+    m = meshgen.tri_split_mesh_2d(n, p, 0.1)
+    kap = meshgen.kappa_field_2d(m["nel"], p, 1.0, seed=n * p)
+    rp, ci, v = orc.h1_matrix_2d(m["coords"], m["elem_dofs"], p, kap, 0.7, m["ndofs"])
+    ed, x = torch.from_numpy(m["elem_dofs"]), torch.from_numpy(m["coords"])
+    pat = lor.lor_pattern(lor.LOR_H1_2D, p, ed.to(DEV), m["ndofs"])
+    v64 = lor.lor_assemble_h1_2d(pat, ed, x, kap, 0.7).cpu()
+    v32 = lor.lor_assemble_h1_2d(pat, ed, x, kap.float(), 0.7, dtype=torch.float32, fp64_fallback=True).cpu()
+    torch.cuda.synchronize()
+    _check(pat, rp, ci, v64, v32, v)
+
+
+def test_tri_split_backward_and_aux():
+    """The adjoint (batch 2) and the bit-exact discrete gradient and curl on
+    the triangle-split cube, n = 3, 2 layers, p = 3 (108 elements)."""
+    from tests.test_gpu_backward import oracle_loss_grads
+    n, layers, p = 3, 2, 3
+    m = meshgen.tri_split_mesh(n, layers, p, 0.1)
+    kap = meshgen.kappa_field(m["nel"], p, 1.0, seed=9, batch=2)
+    rp, ci, _ = orc.h1_matrix(m["coords"], m["elem_dofs"], p, kap[0], 0.7)
+    cot = meshgen.cotangent(2, rp[-1].item(), seed=1)
+    gk_ref, gx_ref = oracle_loss_grads(m, p, kap, 0.7, cot, rp, ci)
+    ed, x = torch.from_numpy(m["elem_dofs"]), torch.from_numpy(m["coords"])
+    pat = lor.lor_pattern(lor.LOR_H1, p, ed.to(DEV), m["ndofs"])
+    for dtype, tol in ((torch.float64, 1e-10), (torch.float32, 1e-5)):
+        gk, gx = lor.lor_assemble_backward(pat, ed, x, kap.to(dtype), 0.7, cot.to(dtype), dtype=dtype)
+        torch.cuda.synchronize()
+        ek = float((gk.cpu().double() - gk_ref).abs().max() / gk_ref.abs().max())
+        ex = float((gx.cpu() - gx_ref).abs().max() / gx_ref.abs().max())
+        _say(f"  backward {dtype}: kappa {ek:.2e} coords {ex:.2e}")
+        assert ek <= tol and ex <= tol
+    ee, ned = meshgen.edge_map_from_vertices(m["elem_dofs"], p)
+    fm, nf = meshgen.face_map_from_vertices(m["elem_dofs"], p)
+    rp, ci, v = orc.discrete_gradient(m["elem_dofs"], ee, p, ned)
+    pat = lor.lor_pattern(lor.LOR_ND, p, torch.from_numpy(ee).to(DEV), ned)
+    grp, gci, gv = lor.lor_discrete_gradient(pat, m["elem_dofs"], ee, m["ndofs"])
+    torch.cuda.synchronize()
+    assert torch.equal(grp.cpu().to(torch.int64), rp) and torch.equal(gci.cpu().to(torch.int64), ci)
+    assert torch.equal(gv.cpu(), v)
+    rp, ci, v = orc.discrete_curl(ee, fm, p, nf)
+    crp, cci, cv = lor.lor_discrete_curl(p, ee, fm, ned, nf, device=DEV)
+    torch.cuda.synchronize()
+    assert torch.equal(crp.cpu().to(torch.int64), rp) and torch.equal(cci.cpu().to(torch.int64), ci)
     assert torch.equal(cv.cpu(), v)

@@ -1038,3 +1038,38 @@ def test_polygon_2d_invariants(sides, p):
     K = dense(rp, ci, v)
     assert np.abs(K.sum(axis=1)).max() <= 1e-13 * np.abs(K).max()
     assert np.abs(K - K.T).max() <= 1e-15 * np.abs(K).max()
+
+
+@pytest.mark.parametrize("n,layers,p", [(2, 1, 2), (2, 2, 1), (1, 2, 3)])
+def test_tri_split_invariants_and_exact_sequences(n, layers, p):
+    """The triangle-split hex mesh of the unit cube (valence 3, 4 and 6):
+    total mass = 1 with flat faces; on a curved copy zero diffusion row sums,
+    symmetry, and the ND and RT exact sequences with vertex-derived edge and
+    face maps; rows at valence-6 vertices inside the cube couple 3 x 13
+    vertices."""
+    m = meshgen.tri_split_mesh(n, layers, p, 0.0)
+    kap = meshgen.kappa_field(m["nel"], p, 1.0, seed=11)
+    rp, ci, v = orc.h1_matrix(m["coords"], m["elem_dofs"], p, torch.zeros_like(kap), 1.0)
+    assert abs(float(v.sum()) - 1.0) <= 1e-13
+    if n >= 2 and layers * p >= 2:
+        assert int((rp[1:] - rp[:-1]).max()) == 39
+    mc = meshgen.tri_split_mesh(n, layers, p, 0.12)
+    rp, ci, v = orc.h1_matrix(mc["coords"], mc["elem_dofs"], p, kap, 0.0)
+    Kh = dense(rp, ci, v)
+    assert np.abs(Kh.sum(axis=1)).max() <= 1e-13 * np.abs(Kh).max()
+    assert np.abs(Kh - Kh.T).max() <= 1e-15 * np.abs(Kh).max()
+    ee, ned = meshgen.edge_map_from_vertices(mc["elem_dofs"], p)
+    fm, nf = meshgen.face_map_from_vertices(mc["elem_dofs"], p)
+    G = _gradient_from_topology(mc, ee, ned, p)
+    rp, ci, v = orc.nd_matrix(mc["coords"], mc["elem_dofs"], ee, p, kap, 0.0, ned)
+    Kc = dense(rp, ci, v, ned)
+    assert np.abs(Kc @ G).max() <= 1e-13 * np.abs(Kc).max()
+    rp, ci, v = orc.nd_matrix(mc["coords"], mc["elem_dofs"], ee, p, torch.zeros_like(kap), kap, ned)
+    assert np.abs(G.T @ dense(rp, ci, v, ned) @ G - Kh).max() <= 1e-13 * np.abs(Kh).max()
+    crp, cci, cv = orc.discrete_curl(ee, fm, p, nf)
+    C = dense(crp, cci, cv, ned)
+    rp, ci, v = orc.rt_matrix(mc["coords"], mc["elem_dofs"], fm, p, torch.zeros_like(kap), kap, nf)
+    assert np.abs(C.T @ dense(rp, ci, v, nf) @ C - Kc).max() <= 1e-13 * np.abs(Kc).max()
+    rp, ci, v = orc.rt_matrix(mc["coords"], mc["elem_dofs"], fm, p, kap, 0.0, nf)
+    Kd = dense(rp, ci, v, nf)
+    assert np.abs(Kd @ C).max() <= 1e-14 * np.abs(Kd).max() * np.abs(C).sum(axis=0).max()
