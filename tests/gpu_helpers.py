@@ -31,3 +31,27 @@ def transpose_perm(rp, ci):
     order = np.argsort(key)
     pos = np.searchsorted(key[order], tkey)
     return order[pos]
+
+
+def check_whole_matrix(pat, *values):
+    """Properties of a complete assembled matrix that hold at any size, checked
+    on the device: columns strictly increasing in every row, a symmetric
+    pattern (the transpose of every entry present exactly once) and bitwise
+    symmetric values for every given value array (same pattern)."""
+    dev = pat.row_ptr.device
+    rp = pat.row_ptr.to(torch.int64)
+    ci = pat.col_idx.to(torch.int64)
+    n = pat.nrows
+    rows = torch.repeat_interleave(torch.arange(n, device=dev), rp[1:] - rp[:-1])
+    same_row = rows[1:] == rows[:-1]
+    assert bool((ci[1:][same_row] > ci[:-1][same_row]).all()), "columns not strictly increasing"
+    del same_row
+    key = rows * n + ci
+    tkey = ci * n + rows
+    del rows
+    order = torch.argsort(tkey)
+    assert torch.equal(tkey[order], key), "pattern not symmetric"
+    del tkey, key
+    for v in values:
+        v = v.reshape(-1, pat.nnz)
+        assert torch.equal(v[:, order], v), "values not bitwise symmetric"

@@ -9,7 +9,7 @@ import torch
 import meshgen
 import paper_2210_12253_amd as lor
 from oracle import lor_oracle as orc
-from tests.gpu_helpers import row_rel_err, transpose_perm
+from tests.gpu_helpers import check_whole_matrix, row_rel_err, transpose_perm
 
 pytestmark = pytest.mark.gpu
 DEV = torch.device("cuda:0")
@@ -285,23 +285,7 @@ def test_h1_c3_full_size_properties():
     pat = _pattern(m)
     v64 = lor.lor_assemble_h1(pat, ed, x, m["kappa"], 1.0)
     v32 = lor.lor_assemble_h1(pat, ed, x, m["kappa"].float(), 1.0, dtype=torch.float32, fp64_fallback=True)
-    rp = pat.row_ptr.to(torch.int64)
-    ci = pat.col_idx.to(torch.int64)
-    n = pat.nrows
-    rows = torch.repeat_interleave(torch.arange(n, device=DEV), rp[1:] - rp[:-1])
-    same_row = rows[1:] == rows[:-1]
-    assert bool((ci[1:][same_row] > ci[:-1][same_row]).all())
-    key = rows * n + ci
-    del same_row
-    tkey = ci * n + rows
-    del rows
-    order = torch.argsort(tkey)
-    assert torch.equal(tkey[order], key)        # the transpose of every entry is present, once
-    del tkey, key
-    # entry order[k] holds (j, i) for the k-th (i, j): values must agree bitwise
-    assert torch.equal(v64[order], v64)
-    assert torch.equal(v32[order], v32)
-    del order
+    check_whole_matrix(pat, v64, v32)
     s64, a64 = float(v64.sum()), float(v64.abs().sum())
     s32, a32 = float(v32.double().sum()), float(v32.double().abs().sum())
     _say(f"c3 sum fp64 {s64:.15f} (|A| {a64:.3e}), fp32 {s32:.9f}")

@@ -10,7 +10,7 @@ import torch
 import meshgen
 import paper_2210_12253_amd as lor
 from oracle import lor_oracle as orc
-from tests.gpu_helpers import row_rel_err, transpose_perm
+from tests.gpu_helpers import check_whole_matrix, row_rel_err, transpose_perm
 
 pytestmark = pytest.mark.gpu
 DEV = torch.device("cuda:0")
@@ -93,6 +93,14 @@ def test_h1_2d_full_size_counts_and_sampled_rows():
     e32 = row_rel_err(rp, ci, v32[idx], ci, v)
     _say(f"sampled rows fp64 {e64:.2e} fp32 {e32:.2e}")
     assert e64 <= 1e-12 and e32 <= 1e-6
+    # the whole matrix: sorted rows, symmetric pattern, bitwise symmetric
+    # values; and with zero diffusion row sums the entries add up to the area
+    # of the mapped square, which is 1 (the boundary displacements A sin(2 pi t)
+    # cancel over the lattice, symmetric about 1/2)
+    check_whole_matrix(pat, v64.to(DEV), v32.to(DEV))
+    s64, a64 = float(v64.sum()), float(v64.abs().sum())
+    _say(f"sum fp64 {s64:.15f} (|A| {a64:.3e})")
+    assert abs(s64 - 1.0) <= 1e-16 * a64
 
 
 def test_h1_2d_fp32_fallback_batch_and_empty():

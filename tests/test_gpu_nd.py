@@ -9,7 +9,7 @@ import torch
 import meshgen
 import paper_2210_12253_amd as lor
 from oracle import lor_oracle as orc
-from tests.gpu_helpers import row_rel_err, transpose_perm
+from tests.gpu_helpers import check_whole_matrix, row_rel_err, transpose_perm
 
 pytestmark = pytest.mark.gpu
 DEV = torch.device("cuda:0")
@@ -95,6 +95,7 @@ def test_nd_c4_counts_and_sampled_rows():
     _say(f"c4 sampled row-rel err fp64 {e64:.3e} fp32 {e32:.3e}")
     assert e64 <= 1e-12 and e32 <= 1e-6
     assert int((grp[1:] - grp[:-1]).max()) == 33
+    check_whole_matrix(pat, v64, v32)
 
 
 def test_nd_exact_sequence_on_gpu_values():

@@ -9,7 +9,7 @@ import torch
 import meshgen
 import paper_2210_12253_amd as lor
 from oracle import lor_oracle as orc
-from tests.gpu_helpers import row_rel_err, transpose_perm
+from tests.gpu_helpers import check_whole_matrix, row_rel_err, transpose_perm
 
 pytestmark = pytest.mark.gpu
 DEV = torch.device("cuda:0")
@@ -104,6 +104,7 @@ def test_rt_full_size_sampled_rows_and_exact_sequence():
     e32 = row_rel_err(rp, ci, v32[idx], ci, v)
     _say(f"sampled rows: fp64 {e64:.2e} fp32 {e32:.2e}")
     assert e64 <= 1e-12 and e32 <= 1e-6
+    check_whole_matrix(pat, v64.to(DEV), v32.to(DEV))
     ee, ned = meshgen.nd_edge_map(24, 3)
     crp, cci, cv = lor.lor_discrete_curl(3, ee, fm, ned, nf, device=DEV)
     kd = _assemble(pat, m, fm, m["kappa"], 0.0)
