@@ -431,6 +431,7 @@ def main():
         out["nd"] = bench_nd(lor, meshgen, args, dev)
         out["rt"] = bench_rt(lor, meshgen, args, dev)
         out["h1_2d"] = bench_2d(lor, meshgen, args, dev)
+        out["h1_unstructured_mesh"] = bench_trisplit(lor, meshgen, args, dev)
         log("fp32 pencil eigenvalues")
         out["fp32"]["pencil_eigs"] = bench_fp32_pencil(lor, meshgen, dev, full=args.pencil_full)
         log("cpu baseline")
@@ -619,6 +620,45 @@ def bench_aux(lor, meshgen, pat_h1, args, dev):
     except lor.LorError as e:
         res["error"] = str(e)
     return res
+
+
+def bench_trisplit(lor, meshgen, args, dev):
+    """The headline form (H1 p=6, kappa sigma 2, beta 1) on an unstructured mesh
+    of the same size: the unit square cut into 16 x 16 cells, two triangles per
+    cell, three quadrilaterals per triangle (vertex valence 3, 4 and 6),
+    extruded in 21 layers: 32,256 hexahedra, 7,071,487 rows."""
+    import torch
+    try:
+        log("unstructured mesh: building inputs")
+        m = meshgen.config_mesh("c8_h1_p6_trisplit")
+        ed = torch.from_numpy(m["elem_dofs"]).to(dev)
+        x = torch.from_numpy(m["coords"]).to(dev)
+        k64 = m["kappa"].to(dev)
+        k32 = k64.float()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        pat = lor.lor_pattern(lor.LOR_H1, 6, ed, m["ndofs"])
+        torch.cuda.synchronize()
+        t_pattern = (time.perf_counter() - t) * 1e3
+        res = {"workload": "H1 diffusion+mass LOR assembly, p=6, triangle-split unstructured hex mesh "
+                           "(16x16 cells, 21 layers, valence 3/4/6), log-normal kappa sigma=2, beta=1",
+               "elements": m["nel"], "rows": m["ndofs"], "nnz": pat.nnz, "ncolors": pat.ncolors,
+               "pattern_ms": t_pattern}
+        out64 = torch.empty(pat.nnz, dtype=torch.float64, device=dev)
+        out32 = torch.empty(pat.nnz, dtype=torch.float32, device=dev)
+        for name, kap, dt, out in (("f64", k64, torch.float64, out64), ("f32", k32, torch.float32, out32)):
+            log(f"unstructured mesh: timing {name}")
+            ms = time_it(lambda: lor.lor_assemble_h1(pat, ed, x, kap, 1.0, dtype=dt, out=out,
+                                                     fp64_fallback=dt == torch.float32),
+                         args.steps, args.warmup)
+            res[name] = {"ms": ms, "value": m["ndofs"] / (ms * 1e-3) / 1e6, "unit": "MDOF/s",
+                         "roofline": roofline_of(algorithmic_bytes_h1(m["nel"], 6, m["ndofs"], pat.nnz,
+                                                                      dt.itemsize), ms)}
+        del out64, out32, pat
+        torch.cuda.empty_cache()
+        return res
+    except lor.LorError as e:
+        return {"error": str(e)}
 
 
 def bench_unstructured(lor, meshgen, m, pat, ms_macro, args, dev):

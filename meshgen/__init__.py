@@ -752,6 +752,8 @@ CONFIGS = {
     "c5_h1_p4_backward": dict(space="h1", n=16, p=4, amp=0.1, sigma=1.0, beta=1.0, batch=8),
     "c6_rt_p3_curved": dict(space="rt", n=24, p=3, amp=0.1, sigma=1.0, beta=1.0, batch=1),
     "c7_h1_2d_p6_curved": dict(space="h1_2d", n=512, p=6, amp=0.1, sigma=2.0, beta=1.0, batch=1),
+    # the headline form on an unstructured mesh of the same size: tri_split_mesh(16, 21 layers)
+    "c8_h1_p6_trisplit": dict(space="h1_tri", n=16, layers=21, p=6, amp=0.1, sigma=2.0, beta=1.0, batch=1),
 }
 
 
@@ -764,7 +766,10 @@ def config_mesh(name: str, seed: int = 0) -> dict:
         m["beta"] = c["beta"]
         m["config"] = dict(c, name=name)
         return m
-    m = cartesian_mesh(c["n"], c["p"], c["amp"])
+    if c["space"] == "h1_tri":
+        m = tri_split_mesh(c["n"], c["layers"], c["p"], c["amp"])
+    else:
+        m = cartesian_mesh(c["n"], c["p"], c["amp"])
     if c["sigma"] == 0.0:
         kap = torch.ones((m["nel"], c["p"] ** 3), dtype=torch.float64)
         if c["batch"] > 1:

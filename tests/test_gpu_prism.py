@@ -6,6 +6,7 @@ everywhere, rows of up to 39 vertex columns, hundreds of elements, so every
 colour spans several groups per workgroup)."""
 import sys
 
+import numpy as np
 import pytest
 import torch
 
@@ -239,3 +240,36 @@ def test_tri_split_backward_and_aux():
     torch.cuda.synchronize()
     assert torch.equal(crp.cpu().to(torch.int64), rp) and torch.equal(cci.cpu().to(torch.int64), ci)
     assert torch.equal(cv.cpu(), v)
+
+
+def test_tri_split_headline_size():
+    """The headline form on the triangle-split mesh at the headline size
+    (32,256 hexahedra, p = 6, 7,071,487 rows), in the launch configuration the
+    benchmark times: sampled rows (including vertices of valence 3 and 6)
+    against the oracle in FP64 and FP32, the whole-matrix properties, and the
+    total of all entries equal to the unit volume (the boundary lattice is
+    symmetric about 1/2 on every face, so the sinusoidal map keeps it)."""
+    from tests.gpu_helpers import check_whole_matrix
+    m = meshgen.config_mesh("c8_h1_p6_trisplit")
+    ed, x = torch.from_numpy(m["elem_dofs"]), torch.from_numpy(m["coords"])
+    pat = lor.lor_pattern(lor.LOR_H1, 6, ed.to(DEV), m["ndofs"])
+    v64 = lor.lor_assemble_h1(pat, ed, x, m["kappa"], 1.0)
+    v32 = lor.lor_assemble_h1(pat, ed, x, m["kappa"].float(), 1.0, dtype=torch.float32, fp64_fallback=True)
+    torch.cuda.synchronize()
+    grp = pat.row_ptr.cpu().to(torch.int64)
+    lens = grp[1:] - grp[:-1]
+    rng = np.random.default_rng(2)
+    longest = torch.nonzero(lens == lens.max()).flatten()[:20].tolist()     # valence-6 vertices
+    pick = longest + [0, m["ndofs"] - 1] + list(rng.integers(0, m["ndofs"], size=300))
+    rows, rp, ci, v = orc.h1_rows(m["coords"], m["elem_dofs"], 6, m["kappa"], 1.0, torch.tensor(pick))
+    idx = torch.cat([torch.arange(grp[r], grp[r + 1]) for r in rows.tolist()])
+    assert torch.equal(pat.col_idx.cpu().to(torch.int64)[idx], ci)
+    e64 = row_rel_err(rp, ci, v64.cpu()[idx], ci, v)
+    e32 = row_rel_err(rp, ci, v32.cpu()[idx], ci, v)
+    s64, a64 = float(v64.sum()), float(v64.abs().sum())
+    _say(f"  colours {pat.ncolors} max row {int(lens.max())} fp64 {e64:.2e} fp32 {e32:.2e} sum-1 {s64 - 1:.2e} "
+         f"|A| {a64:.3e}")
+    assert int(lens.max()) == 39
+    assert e64 <= 1e-12 and e32 <= 1e-6
+    check_whole_matrix(pat, v64, v32)
+    assert abs(s64 - 1.0) <= 1e-17 * a64
