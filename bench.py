@@ -451,9 +451,10 @@ def pencil_extreme_eigs(row_ptr, col_idx, v64, v32, n, niter=400):
     ci = col_idx.to(torch.int64)
     a32 = v32.to(torch.float64)
     scale = 2.0 ** 24
-    E = torch.sparse_csr_tensor(rp, ci, (v64 - a32) * scale, (n, n)).to_sparse_coo()
-    B = torch.sparse_csr_tensor(rp, ci, a32, (n, n)).to_sparse_coo()
     rows = torch.repeat_interleave(torch.arange(n, device=rp.device), rp[1:] - rp[:-1])
+    ij = torch.stack([rows, ci])
+    E = torch.sparse_coo_tensor(ij, (v64 - a32) * scale, (n, n)).coalesce()
+    B = torch.sparse_coo_tensor(ij, a32, (n, n)).coalesce()
     diag = torch.zeros(n, dtype=torch.float64, device=rp.device)
     diag.index_add_(0, rows, torch.where(rows == ci, a32, torch.zeros_like(a32)))
     iK = torch.sparse_coo_tensor(torch.arange(n, device=rp.device).repeat(2, 1), 1.0 / diag, (n, n))
