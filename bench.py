@@ -199,6 +199,18 @@ def summarize_profiles(stats_dir, fetch_dir, write_dir, command):
         lines.append(f"{r['Name'][:70]:70s} {int(r['Calls']):6d} {float(r['AverageNs']) / 1e3:10.2f} "
                      f"{float(r['MinNs']) / 1e3:10.2f} {float(r['MaxNs']) / 1e3:10.2f} "
                      f"{float(r['Percentage']):6.2f}")
+    # the dominant kernel also runs on other meshes in the extras: split its
+    # dispatches by grid size (the headline mesh launches 512 workgroups per colour)
+    by_grid = {}
+    for r in _read_csvs(stats_dir, "kernel_trace_lor.csv") + _read_csvs(stats_dir, "run_kernel_trace.csv"):
+        if "k_h1_assemble<6, double" in r["Kernel_Name"]:
+            dur = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+            by_grid.setdefault(int(r["Grid_Size_X"]), []).append(dur)
+    if by_grid:
+        lines.append("")
+        lines.append("k_h1_assemble<6,double> dispatches by grid size (threads): count, average us")
+        for g, ds in sorted(by_grid.items(), key=lambda kv: -kv[0]):
+            lines.append(f"  {g:9d}  {len(ds):4d}  {sum(ds) / len(ds):8.2f}")
     res = {}
     for key, d, counter in (("fetch", fetch_dir, "FETCH_SIZE"), ("write", write_dir, "WRITE_SIZE")):
         per = {}
