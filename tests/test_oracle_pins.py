@@ -1073,3 +1073,31 @@ def test_tri_split_invariants_and_exact_sequences(n, layers, p):
     rp, ci, v = orc.rt_matrix(mc["coords"], mc["elem_dofs"], fm, p, kap, 0.0, nf)
     Kd = dense(rp, ci, v, nf)
     assert np.abs(Kd @ C).max() <= 1e-14 * np.abs(Kd).max() * np.abs(C).sum(axis=0).max()
+
+
+@pytest.mark.parametrize("n,p", [(2, 1), (2, 2), (2, 3), (1, 4)])
+def test_vertex_derived_maps_match_the_cartesian_maps(n, p):
+    """The generic edge and face maps built from the vertex map alone agree with
+    the Cartesian formulas up to a relabelling of the ids and, per face, one
+    global sign: the same local entities are merged, and two elements sharing
+    an entity agree (or disagree) on its orientation in both maps alike.  On the
+    lexicographic lattice every edge runs from the lower to the higher vertex
+    id, so the generic edge signs are all positive, as the Cartesian ones."""
+    m = meshgen.cartesian_mesh(n, p, 0.0)
+
+    def dec(a):
+        return np.where(a < 0, -1 - a, a)
+
+    ee, ned = meshgen.nd_edge_map(n, p)
+    eg, ng = meshgen.edge_map_from_vertices(m["elem_dofs"], p)
+    assert ng == ned and (eg >= 0).all() and (ee >= 0).all()
+    pairs = set(zip(dec(ee).ravel().tolist(), dec(eg).ravel().tolist()))
+    assert len(pairs) == ned                       # a bijection between the two id sets
+    fm, nf = meshgen.face_map(n, p)
+    fg, nf2 = meshgen.face_map_from_vertices(m["elem_dofs"], p)
+    assert nf2 == nf
+    pairs = set(zip(dec(fm).ravel().tolist(), dec(fg).ravel().tolist()))
+    assert len(pairs) == nf
+    rel = {}
+    for f, r in zip(dec(fm).ravel().tolist(), (np.sign(fm + 0.5) * np.sign(fg + 0.5)).ravel().tolist()):
+        assert rel.setdefault(f, r) == r           # one relative sign per face
