@@ -34,8 +34,11 @@ Readings of points the paper leaves open (the HIP path takes the same ones):
 
 Every function is in float64 and differentiable (torch autograd) in the node
 coordinates and the coefficients, which gives the reference gradient of the
-adjoint kernel.  "Parity unpinned" functions: none (see tests/test_oracle_pins.py
-for the pin of every function).
+adjoint kernel.  "Parity unpinned" functions: none.  tests/test_oracle_pins.py
+pins every whole-matrix function against closed forms, invariants, exact
+sequences or brute force, and every row-subset function (h1_rows, nd_rows,
+rt_rows, h1_rows_2d, the references of the full-size parity tests) against the
+rows of its pinned whole-matrix form.
 """
 from __future__ import annotations
 

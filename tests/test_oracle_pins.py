@@ -882,6 +882,41 @@ def test_rt_pattern_count_and_sign_flip():
     assert np.abs(A2 - S[:, None] * A * S[None, :]).max() <= 1e-14 * np.abs(A).max()
 
 
+def _rows_match(rp, ci, v, r, rp2, ci2, v2):
+    """The rows (r, rp2, ci2, v2) of a row-subset call equal the same rows of
+    the whole matrix: columns bit for bit, values to 1e-15 of the row maximum."""
+    for n, g in enumerate(r.tolist()):
+        a, b = rp[g].item(), rp[g + 1].item()
+        c, d = rp2[n].item(), rp2[n + 1].item()
+        assert torch.equal(ci[a:b], ci2[c:d]), g
+        assert (v[a:b] - v2[c:d]).abs().max() <= 1e-15 * v[a:b].abs().max(), g
+
+
+@pytest.mark.parametrize("reorient", [False, True])
+def test_rt_rows_match_the_whole_matrix(reorient):
+    """rt_rows (the row-subset form used as the reference at full size) gives
+    exactly the rows of rt_matrix, whose own pins are the exact sequence, the
+    affine fields and the sign flip: curved mesh, flipped face signs, and
+    optionally every element rotated by a random cube symmetry (face map then
+    derived from the rotated vertex map)."""
+    n, p = 2, 3
+    m, ee, ned, fm, nf, kap = _rt_setup(n, p, 0.12, seed=17)
+    if reorient:
+        # rotated local frames; faces (and their orientation) re-derived from
+        # the rotated vertex map
+        m, kap, _ = meshgen.reorient_elements(m, seed=18, kappa=kap)
+        fm, nf = meshgen.face_map_from_vertices(m["elem_dofs"], p)
+    rp, ci, v = orc.rt_matrix(m["coords"], m["elem_dofs"], fm, p, kap, 0.7, nf)
+    rows = torch.tensor([0, 1, 37, nf // 2, nf // 3 + 5, nf - 1, 200])
+    r, rp2, ci2, v2 = orc.rt_rows(m["coords"], m["elem_dofs"], fm, p, kap, 0.7, rows)
+    assert torch.equal(r, torch.unique(rows))
+    _rows_match(rp, ci, v, r, rp2, ci2, v2)
+    # every row at once: the subset form reproduces the whole CSR matrix
+    r, rp2, ci2, v2 = orc.rt_rows(m["coords"], m["elem_dofs"], fm, p, kap, 0.7, torch.arange(nf))
+    assert torch.equal(rp2, rp) and torch.equal(ci2, ci)
+    assert (v2 - v).abs().max() <= 1e-15 * v.abs().max()
+
+
 # ----------------------------------------------------------------- H1 in 2D
 
 def test_h1_2d_closed_form_uniform_square():
@@ -954,6 +989,26 @@ def test_h1_2d_affine_energy_and_pattern():
     N = m["N"]
     assert rp[-1].item() == (3 * N - 2) ** 2
     assert int((rp[1:] - rp[:-1]).max()) == 9
+
+
+@pytest.mark.parametrize("mesh", ["cartesian", "polygon"])
+def test_h1_rows_2d_match_the_whole_matrix(mesh):
+    """h1_rows_2d (the row-subset form used as the reference at full size)
+    gives exactly the rows of h1_matrix_2d, whose own pins are the closed
+    form, zero row sums, area and affine energy: curved Cartesian and
+    irregular-valence polygon meshes, random kappa, beta != 0."""
+    p = 3
+    m = meshgen.cartesian_mesh_2d(3, p, 0.15) if mesh == "cartesian" else meshgen.polygon_mesh_2d(p, 5, 0.15)
+    nd = m["coords"].shape[0]
+    kap = meshgen.kappa_field_2d(m["nel"], p, 1.0, seed=5)
+    rp, ci, v = orc.h1_matrix_2d(m["coords"], m["elem_dofs"], p, kap, 0.9, nd)
+    rows = torch.tensor([0, 3, nd // 2, nd - 1, 11, 3])
+    r, rp2, ci2, v2 = orc.h1_rows_2d(m["coords"], m["elem_dofs"], p, kap, 0.9, rows)
+    assert torch.equal(r, torch.unique(rows))
+    _rows_match(rp, ci, v, r, rp2, ci2, v2)
+    r, rp2, ci2, v2 = orc.h1_rows_2d(m["coords"], m["elem_dofs"], p, kap, 0.9, torch.arange(nd))
+    assert torch.equal(rp2, rp) and torch.equal(ci2, ci)
+    assert (v2 - v).abs().max() <= 1e-15 * v.abs().max()
 
 
 # ------------------------------------------------- irregular-valence hex meshes
