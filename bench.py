@@ -536,7 +536,7 @@ def bench_backward(lor, meshgen, args, dev):
         for name, dt in (("f64", torch.float64), ("f32", torch.float32)):
             k = m["kappa"].to(dev, dt)
             gv = meshgen.cotangent(8, pat.nnz, seed=1).to(dev, dt)
-            ws = torch.empty(lor.load_library().lor_backward_workspace(m["p"], m["nel"]), dtype=torch.uint8,
+            ws = torch.empty(lor.load_library().lor_backward_workspace(m["p"], m["nel"], 8, lor.LOR_F64), dtype=torch.uint8,
                              device=dev)
             ms = time_it(lambda: lor.lor_assemble_backward(pat, ed, x, k, 1.0, gv, dtype=dt, workspace=ws),
                          args.steps, args.warmup)

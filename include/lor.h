@@ -277,8 +277,9 @@ int lor_assemble_h1_unstructured(int64_t nsub, int64_t ndofs, int64_t nnz, const
  *   grad_coords[v][c]   = sum_b dL/dcoords[v][c]  (FP64, overwritten; coords are
  *                         shared by the batch, so their gradient is summed)
  *   grad_values  [batch][nnz] in dtype;  grad_kappa [batch][nel][p^3] in dtype.
- *   workspace    device buffer of lor_backward_workspace(p, nel) bytes (holds
- *                the per-element coordinate gradient before the vertex gather).
+ *   workspace    device buffer of lor_backward_workspace(p, nel, batch, dtype)
+ *                bytes (holds the per-element coordinate gradient before the
+ *                vertex gather; fully overwritten, needs no clearing).
  * Subelement geometry is recomputed, not stored.  Arithmetic in dtype; the
  * vertex gather sums in FP64 in a fixed order (deterministic).
  */
@@ -400,8 +401,23 @@ int lor_interp_nodes(int p, int q, int64_t nel, int ncomp, const double* nodes, 
 int lor_evec_to_tvec(int p, int64_t nel, int64_t ndofs, const lor_sched* sched, int ncomp, const double* evec,
                      double* tvec, int32_t* diag, void* stream);
 
-/* Bytes of the `workspace` argument of lor_assemble_backward. */
-size_t lor_backward_workspace(int p, int64_t nel);
+/*
+ * lor_pattern_workspace -- bytes of the schedule's device buffer (sched->dev)
+ * for a mesh of these sizes: the value lor_pattern phase 1 writes into
+ * sched->dev_bytes, known before the pattern is built (the layout depends on
+ * the space, p, nel and nrows only).  0 for invalid arguments (the checks of
+ * lor_pattern).  Host only; no device work.
+ */
+size_t lor_pattern_workspace(int space, int p, int64_t nel, int64_t nrows);
+
+/*
+ * lor_backward_workspace -- bytes of the `workspace` argument of
+ * lor_assemble_backward for these sizes (the per-element coordinate-gradient
+ * E-vector, FP64 [nel][(p+1)^3][3], shared by the batch and by both dtypes).
+ * 0 for invalid arguments (p outside [1, LOR_MAX_P], nel < 0, batch < 1,
+ * unknown dtype).  Host only.
+ */
+size_t lor_backward_workspace(int p, int64_t nel, int batch, int dtype);
 
 /* sizeof(lor_sched) as compiled into the library (for bindings to check their layout). */
 size_t lor_sched_bytes(void);

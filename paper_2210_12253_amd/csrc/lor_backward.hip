@@ -295,8 +295,8 @@ static int dispatch_bw(int p, const lor_sched* s, int batch, const int32_t* ed, 
 
 using namespace lor;
 
-extern "C" size_t lor_backward_workspace(int p, int64_t nel) {
-  if (p < 1 || p > LOR_MAX_P || nel < 0) return 0;
+extern "C" size_t lor_backward_workspace(int p, int64_t nel, int batch, int dtype) {
+  if (p < 1 || p > LOR_MAX_P || nel < 0 || batch < 1 || (dtype != LOR_F64 && dtype != LOR_F32)) return 0;
   return sizeof(double) * 3 * static_cast<size_t>(nel) * nloc_h1(p);
 }
 

@@ -757,6 +757,22 @@ static int upload(const std::vector<T>& v, void* dst, hipStream_t st) {
 
 using namespace lor;
 
+extern "C" size_t lor_pattern_workspace(int space, int p, int64_t nel, int64_t nrows) {
+  if (space != LOR_H1 && space != LOR_ND && space != LOR_RT && space != LOR_H1_2D) return 0;
+  if (p < 1 || p > LOR_MAX_P || nel < 0 || nrows < 1 || nrows >= INT32_MAX) return 0;
+  const int nloc = space == LOR_H1      ? nloc_h1(p)
+                   : space == LOR_ND    ? nloc_nd(p)
+                   : space == LOR_H1_2D ? (p + 1) * (p + 1)
+                                        : nloc_rt(p);
+  if (nel * static_cast<int64_t>(nloc) >= INT32_MAX) return 0;
+  lor_sched s{};
+  s.space = space;
+  s.p = p;
+  s.nel = nel;
+  s.nrows = nrows;
+  return layout(&s, build_ref(space, p));
+}
+
 extern "C" int lor_pattern(int space, int p, int64_t nel, int64_t nrows, const int32_t* elem_map,
                            int32_t* row_ptr, int64_t* nnz, int32_t* col_idx, lor_sched* sched,
                            void* stream) {

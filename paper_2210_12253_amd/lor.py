@@ -34,6 +34,7 @@ ABI_SYMBOLS = (
     "lor_refine_map",
     "lor_assemble_h1_unstructured",
     "lor_backward_workspace",
+    "lor_pattern_workspace",
     "lor_eliminate_bc",
     "lor_discrete_gradient",
     "lor_discrete_curl",
@@ -129,8 +130,10 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.lor_refine_map.restype = i32
     lib.lor_assemble_h1_unstructured.argtypes = [i64, i64, i64, vp, vp, vp, f64, vp, vp, vp, vp, vp]
     lib.lor_assemble_h1_unstructured.restype = i32
-    lib.lor_backward_workspace.argtypes = [i32, i64]
+    lib.lor_backward_workspace.argtypes = [i32, i64, i32, i32]
     lib.lor_backward_workspace.restype = sz
+    lib.lor_pattern_workspace.argtypes = [i32, i32, i64, i64]
+    lib.lor_pattern_workspace.restype = sz
     lib.lor_sched_bytes.argtypes = []
     lib.lor_sched_bytes.restype = sz
     lib.lor_last_error.argtypes = []
@@ -365,7 +368,7 @@ def lor_assemble_backward(pat: Pattern, elem_dofs, coords, kappa, beta: float, g
     _need(gv, batch * pat.nnz, "grad_values")
     gk = torch.empty_like(k)
     gx = torch.empty((pat.nrows, 3), dtype=torch.float64, device=dev)
-    wbytes = max(1, int(lib.lor_backward_workspace(pat.p, pat.nel)))
+    wbytes = max(1, int(lib.lor_backward_workspace(pat.p, pat.nel, batch, _dtype_code(dtype))))
     if workspace is None:
         workspace = torch.empty(wbytes, dtype=torch.uint8, device=dev)
     elif workspace.device != dev or not workspace.is_contiguous() or \

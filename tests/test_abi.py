@@ -25,7 +25,7 @@ def test_exports_every_declared_symbol():
     for name in declared:
         assert hasattr(lib, name), name
     assert set(declared) == set(L.ABI_SYMBOLS)
-    assert lib.lor_abi_version() == 1
+    assert lib.lor_abi_version() == 2
     assert lib.lor_sched_bytes() == ctypes.sizeof(L.LorSched)
 
 
@@ -88,8 +88,30 @@ def test_assemble_argument_errors():
 
 def test_backward_workspace_size():
     lib = pkg.load_library()
-    assert lib.lor_backward_workspace(4, 4096) == 8 * 3 * 4096 * 125
-    assert lib.lor_backward_workspace(0, 10) == 0
+    for batch in (1, 8):
+        for dt in (L.LOR_F64, L.LOR_F32):
+            assert lib.lor_backward_workspace(4, 4096, batch, dt) == 8 * 3 * 4096 * 125
+    assert lib.lor_backward_workspace(0, 10, 1, L.LOR_F64) == 0
+    assert lib.lor_backward_workspace(2, -1, 1, L.LOR_F64) == 0
+    assert lib.lor_backward_workspace(2, 10, 0, L.LOR_F64) == 0
+    assert lib.lor_backward_workspace(2, 10, 1, 7) == 0
+
+
+def test_pattern_workspace_size():
+    """Schedule bytes known before the pattern: positive and 256-aligned for
+    valid sizes, growing with the mesh, 0 where lor_pattern would reject the
+    arguments.  (That it equals phase 1's dev_bytes is checked on the GPU.)"""
+    lib = pkg.load_library()
+    for space in (L.LOR_H1, L.LOR_ND, L.LOR_RT, L.LOR_H1_2D):
+        a = lib.lor_pattern_workspace(space, 3, 8, 1000)
+        b = lib.lor_pattern_workspace(space, 3, 64, 8000)
+        assert a > 0 and a % 256 == 0 and b > a
+    assert lib.lor_pattern_workspace(9, 3, 8, 1000) == 0
+    assert lib.lor_pattern_workspace(L.LOR_H1, 0, 8, 1000) == 0
+    assert lib.lor_pattern_workspace(L.LOR_H1, 7, 8, 1000) == 0
+    assert lib.lor_pattern_workspace(L.LOR_H1, 3, -1, 1000) == 0
+    assert lib.lor_pattern_workspace(L.LOR_H1, 3, 8, 0) == 0
+    assert lib.lor_pattern_workspace(L.LOR_H1, 6, 1 << 30, 1000) == 0
 
 
 def test_eliminate_argument_errors():

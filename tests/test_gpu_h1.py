@@ -291,3 +291,25 @@ def test_h1_c3_full_size_properties():
     _say(f"c3 sum fp64 {s64:.15f} (|A| {a64:.3e}), fp32 {s32:.9f}")
     assert abs(s64 - 1.0) <= 1e-17 * a64      # measured: 9.5e-13 against 2.5e-11
     assert abs(s32 - 1.0) <= 1e-8 * a32       # measured: 4.1e-3 against 2.5e-2
+
+
+@pytest.mark.parametrize("space", ["h1", "nd", "rt", "h1_2d"])
+def test_pattern_workspace_equals_phase1_bytes(space):
+    """lor_pattern_workspace (sizes only) equals the schedule bytes phase 1
+    reports for the same mesh."""
+    lib = lor.load_library()
+    n, p = 3, 3
+    if space == "h1_2d":
+        m = meshgen.cartesian_mesh_2d(n, p, 0.1)
+        emap, nrows, sp = m["elem_dofs"], m["coords"].shape[0], lor.LOR_H1_2D
+    elif space == "h1":
+        m = meshgen.cartesian_mesh(n, p, 0.1)
+        emap, nrows, sp = m["elem_dofs"], m["ndofs"], lor.LOR_H1
+    elif space == "nd":
+        emap, nrows = meshgen.nd_edge_map(n, p)
+        sp = lor.LOR_ND
+    else:
+        emap, nrows = meshgen.face_map(n, p)
+        sp = lor.LOR_RT
+    pat = lor.lor_pattern(sp, p, torch.from_numpy(emap).to(DEV), nrows)
+    assert int(pat.sched.dev_bytes) == lib.lor_pattern_workspace(sp, p, emap.shape[0], nrows)
