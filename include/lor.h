@@ -290,6 +290,31 @@ int lor_assemble_backward(int p, int64_t nel, int64_t ndofs, int batch, const in
                           void* stream);
 
 /*
+ * lor_assemble_backward_noalloc -- lor_assemble_backward without a workspace
+ * argument and without any device allocation, for callers that cannot
+ * allocate: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  The per-element coordinate-gradient E-vector lives in a
+ * workspace built into the library: one array of
+ * lor_backward_noalloc_max_workspace() bytes (32 MiB) per GPU, held from the
+ * first call on that GPU until the process ends.  Its contents carry over
+ * between calls (every call overwrites the part it reads, so nothing needs
+ * clearing); calls that overlap on one GPU (different streams, or host
+ * threads) share it and race -- serialise them.
+ *   Arguments and results as for lor_assemble_backward.
+ *   Errors: as lor_assemble_backward, plus LOR_EUNSUPPORTED when
+ *   lor_backward_workspace(p, nel, batch, dtype) exceeds the built-in size
+ *   (nel * (p+1)^3 at most 1,398,101), LOR_EDEVICE if the workspace address
+ *   cannot be obtained.  No hipMalloc, hipFree or allocating library call.
+ */
+int lor_assemble_backward_noalloc(int p, int64_t nel, int64_t ndofs, int batch, const int32_t* elem_dofs,
+                                  const double* coords, const void* kappa, double beta,
+                                  const int32_t* row_ptr, const lor_sched* sched, const void* grad_values,
+                                  void* grad_kappa, double* grad_coords, int dtype, void* stream);
+
+/* Bytes of the workspace built into lor_assemble_backward_noalloc (per GPU). */
+size_t lor_backward_noalloc_max_workspace(void);
+
+/*
  * lor_eliminate_bc -- elimination of essential boundary conditions from an
  * assembled matrix (Section 3, Step S1.2, step A4), on one device: every entry
  * in the row or the column of an essential dof becomes 0, except the diagonal

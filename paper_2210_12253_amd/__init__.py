@@ -18,6 +18,7 @@ from .lor import (  # noqa: F401
     Pattern,
     load_library,
     lor_assemble_backward,
+    lor_assemble_backward_noalloc,
     lor_assemble_h1,
     lor_assemble_h1_2d,
     lor_assemble_h1_unstructured,

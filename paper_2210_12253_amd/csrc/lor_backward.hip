@@ -11,10 +11,42 @@
 // order (element E-vector), then per global vertex over its sorted
 // incidences (deterministic; coordinates are shared by the batch, so their
 // gradient is the sum over the batch).
+#include <mutex>
+
 #include "lor_common.hpp"
 #include "lor_h1_adjoint.hpp"
 
 namespace lor {
+
+// Workspace of the allocation-free entry point: a file-scope device array, one
+// copy per GPU, alive until the process ends.  Host code never uses its name
+// as an address (on the host it is only a stand-in for the symbol): the
+// device address comes from hipGetSymbolAddress, taken once per device with
+// that device current, and is what the kernels receive.
+constexpr size_t kBwScratchBytes = size_t(32) << 20;
+__device__ __align__(256) unsigned char scratch[kBwScratchBytes];
+
+static int bw_scratch_address(void** out) {
+  static std::mutex mu;
+  static void* addr[64] = {};
+  int dev = -1;
+  LOR_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) LOR_FAIL(LOR_EDEVICE, "device index %d outside [0, 64)", dev);
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[dev]) {
+    void* ptr = nullptr;
+    LOR_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) LOR_FAIL(LOR_EDEVICE, "hipGetSymbolAddress returned NULL for the workspace array");
+    addr[dev] = ptr;
+  }
+  *out = addr[dev];
+  return LOR_OK;
+}
+
+__global__ void k_bw_zero_f64(double* __restrict__ x, int64_t n) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) x[i] = 0.0;
+}
 
 int check_sched(const lor_sched* s, int space, int p, int64_t nel, int64_t nrows);
 
@@ -300,23 +332,30 @@ extern "C" size_t lor_backward_workspace(int p, int64_t nel, int batch, int dtyp
   return sizeof(double) * 3 * static_cast<size_t>(nel) * nloc_h1(p);
 }
 
-extern "C" int lor_assemble_backward(int p, int64_t nel, int64_t ndofs, int batch, const int32_t* elem_dofs,
-                                     const double* coords, const void* kappa, double beta, const int32_t* row_ptr,
-                                     const lor_sched* sched, const void* grad_values, void* grad_kappa,
-                                     double* grad_coords, void* workspace, int dtype, void* stream) {
-  clear_error();
+namespace lor {
+
+// Host-side checks shared by both backward entry points (workspace excluded).
+static int check_bw_args(int p, int64_t nel, int64_t ndofs, int batch, const int32_t* elem_dofs,
+                         const double* coords, const void* kappa, const int32_t* row_ptr, const void* grad_values,
+                         void* grad_kappa, double* grad_coords, int dtype) {
   if (p < 1 || p > LOR_MAX_P) LOR_FAIL(LOR_EINVAL, "p = %d outside [1, %d]", p, LOR_MAX_P);
   if (nel < 0 || ndofs < 1) LOR_FAIL(LOR_EINVAL, "nel < 0 or ndofs < 1");
   if (batch < 1) LOR_FAIL(LOR_EINVAL, "batch < 1");
   if (dtype != LOR_F64 && dtype != LOR_F32) LOR_FAIL(LOR_EINVAL, "dtype must be LOR_F64 or LOR_F32");
   if (!grad_coords) LOR_FAIL(LOR_EINVAL, "grad_coords is NULL");
-  if (nel > 0 && (!elem_dofs || !coords || !kappa || !row_ptr || !grad_values || !grad_kappa || !workspace))
+  if (nel > 0 && (!elem_dofs || !coords || !kappa || !row_ptr || !grad_values || !grad_kappa))
     LOR_FAIL(LOR_EINVAL, "a required pointer is NULL");
-  int rc = check_sched(sched, LOR_H1, p, nel, ndofs);
-  if (rc) return rc;
-  hipStream_t st = as_stream(stream);
+  return LOR_OK;
+}
+
+static int run_bw(int p, int64_t nel, int64_t ndofs, int batch, const int32_t* elem_dofs, const double* coords,
+                  const void* kappa, double beta, const int32_t* row_ptr, const lor_sched* sched,
+                  const void* grad_values, void* grad_kappa, double* grad_coords, void* workspace, int dtype,
+                  hipStream_t st) {
   if (nel == 0) {
-    LOR_HIP(hipMemsetAsync(grad_coords, 0, sizeof(double) * 3 * ndofs, st));
+    // a fill kernel rather than a memset node, so that the call can be captured
+    k_bw_zero_f64<<<static_cast<unsigned>(ceil_div(3 * ndofs, 256)), 256, 0, st>>>(grad_coords, 3 * ndofs);
+    LOR_LAUNCHED("k_bw_zero_f64");
     return LOR_OK;
   }
   if (dtype == LOR_F64)
@@ -324,4 +363,47 @@ extern "C" int lor_assemble_backward(int p, int64_t nel, int64_t ndofs, int batc
                                        grad_kappa, grad_coords, workspace, st);
   return dispatch_bw<float, float>(p, sched, batch, elem_dofs, coords, kappa, beta, row_ptr, grad_values,
                                    grad_kappa, grad_coords, workspace, st);
+}
+
+}  // namespace lor
+
+extern "C" int lor_assemble_backward(int p, int64_t nel, int64_t ndofs, int batch, const int32_t* elem_dofs,
+                                     const double* coords, const void* kappa, double beta, const int32_t* row_ptr,
+                                     const lor_sched* sched, const void* grad_values, void* grad_kappa,
+                                     double* grad_coords, void* workspace, int dtype, void* stream) {
+  clear_error();
+  int rc = check_bw_args(p, nel, ndofs, batch, elem_dofs, coords, kappa, row_ptr, grad_values, grad_kappa,
+                         grad_coords, dtype);
+  if (rc) return rc;
+  if (nel > 0 && !workspace) LOR_FAIL(LOR_EINVAL, "workspace is NULL");
+  rc = check_sched(sched, LOR_H1, p, nel, ndofs);
+  if (rc) return rc;
+  return run_bw(p, nel, ndofs, batch, elem_dofs, coords, kappa, beta, row_ptr, sched, grad_values, grad_kappa,
+                grad_coords, workspace, dtype, as_stream(stream));
+}
+
+extern "C" size_t lor_backward_noalloc_max_workspace(void) { return kBwScratchBytes; }
+
+extern "C" int lor_assemble_backward_noalloc(int p, int64_t nel, int64_t ndofs, int batch,
+                                             const int32_t* elem_dofs, const double* coords, const void* kappa,
+                                             double beta, const int32_t* row_ptr, const lor_sched* sched,
+                                             const void* grad_values, void* grad_kappa, double* grad_coords,
+                                             int dtype, void* stream) {
+  clear_error();
+  int rc = check_bw_args(p, nel, ndofs, batch, elem_dofs, coords, kappa, row_ptr, grad_values, grad_kappa,
+                         grad_coords, dtype);
+  if (rc) return rc;
+  const size_t need = lor_backward_workspace(p, nel, batch, dtype);
+  if (need > kBwScratchBytes)
+    LOR_FAIL(LOR_EUNSUPPORTED,
+             "the backward needs %zu workspace bytes, above the %zu bytes of the built-in workspace "
+             "(nel * (p+1)^3 must be at most %zu); use lor_assemble_backward with a caller workspace",
+             need, kBwScratchBytes, kBwScratchBytes / (3 * sizeof(double)));
+  rc = check_sched(sched, LOR_H1, p, nel, ndofs);
+  if (rc) return rc;
+  void* ws = nullptr;
+  rc = bw_scratch_address(&ws);
+  if (rc) return rc;
+  return run_bw(p, nel, ndofs, batch, elem_dofs, coords, kappa, beta, row_ptr, sched, grad_values, grad_kappa,
+                grad_coords, ws, dtype, as_stream(stream));
 }

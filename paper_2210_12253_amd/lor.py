@@ -35,6 +35,8 @@ ABI_SYMBOLS = (
     "lor_assemble_h1_unstructured",
     "lor_backward_workspace",
     "lor_pattern_workspace",
+    "lor_assemble_backward_noalloc",
+    "lor_backward_noalloc_max_workspace",
     "lor_eliminate_bc",
     "lor_discrete_gradient",
     "lor_discrete_curl",
@@ -115,6 +117,11 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.lor_assemble_backward.argtypes = [i32, i64, i64, i32, vp, vp, vp, f64, vp, ctypes.POINTER(LorSched), vp, vp,
                                           vp, vp, i32, vp]
     lib.lor_assemble_backward.restype = i32
+    lib.lor_assemble_backward_noalloc.argtypes = [i32, i64, i64, i32, vp, vp, vp, f64, vp,
+                                                  ctypes.POINTER(LorSched), vp, vp, vp, i32, vp]
+    lib.lor_assemble_backward_noalloc.restype = i32
+    lib.lor_backward_noalloc_max_workspace.argtypes = []
+    lib.lor_backward_noalloc_max_workspace.restype = sz
     lib.lor_eliminate_bc.argtypes = [i64, i64, i32, vp, vp, vp, i32, i64, vp, vp, i32, vp, vp]
     lib.lor_eliminate_bc.restype = i32
     lib.lor_discrete_gradient.argtypes = [i32, i64, i64, i64, vp, vp, ctypes.POINTER(LorSched), vp, vp, vp, i32,
@@ -377,6 +384,34 @@ def lor_assemble_backward(pat: Pattern, elem_dofs, coords, kappa, beta: float, g
     _check(lib.lor_assemble_backward(pat.p, pat.nel, pat.nrows, batch, _ptr(ed), _ptr(x), _ptr(k), float(beta),
                                      _ptr(pat.row_ptr), ctypes.byref(pat.sched), _ptr(gv), _ptr(gk), _ptr(gx),
                                      _ptr(workspace), _dtype_code(dtype), _stream()))
+    return gk, gx
+
+
+def lor_assemble_backward_noalloc(pat: Pattern, elem_dofs, coords, kappa, beta: float, grad_values,
+                                  dtype=torch.float64, grad_kappa: torch.Tensor | None = None,
+                                  grad_coords: torch.Tensor | None = None):
+    """lor_assemble_backward through the entry point that allocates nothing on
+    the device (its workspace is built into the library, one per GPU; calls
+    that overlap on one GPU race).  Inputs must already be device tensors of
+    the right dtype and outputs may be passed in, so that a captured call
+    allocates nothing either.  Returns (grad_kappa, grad_coords)."""
+    lib = load_library()
+    dev = pat.row_ptr.device
+    ed = _dev_tensor(elem_dofs, torch.int32, "elem_dofs", dev)
+    x = _dev_tensor(coords, torch.float64, "coords", dev)
+    k = _dev_tensor(kappa, dtype, "kappa", dev)
+    gv = _dev_tensor(grad_values, dtype, "grad_values", dev)
+    batch = k.shape[0] if k.dim() == 3 else 1
+    p = pat.p
+    _need(ed, pat.nel * (p + 1) ** 3, "elem_dofs")
+    _need(x, pat.nrows * 3, "coords")
+    _need(k, batch * pat.nel * p ** 3, "kappa")
+    _need(gv, batch * pat.nnz, "grad_values")
+    gk = _out(grad_kappa, tuple(k.shape), dtype, dev, "grad_kappa")
+    gx = _out(grad_coords, (pat.nrows, 3), torch.float64, dev, "grad_coords")
+    _check(lib.lor_assemble_backward_noalloc(pat.p, pat.nel, pat.nrows, batch, _ptr(ed), _ptr(x), _ptr(k),
+                                             float(beta), _ptr(pat.row_ptr), ctypes.byref(pat.sched), _ptr(gv),
+                                             _ptr(gk), _ptr(gx), _dtype_code(dtype), _stream()))
     return gk, gx
 
 
