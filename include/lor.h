@@ -71,6 +71,14 @@ typedef enum { LOR_DIAG_ONE = 0, LOR_DIAG_KEEP = 1, LOR_DIAG_ZERO = 2 } lor_diag
  * det_ratio_thresh (or whose smallest corner Jacobian is <= 0) are integrated
  * with FP64 geometry instead of FP32. */
 #define LOR_FP64_FALLBACK 0x1u
+/* lor_assemble_h1: kernel choice.  By default the FP32 form runs the
+ * owner-computes kernel when the schedule has it (sched->owner) and the FP64
+ * form the coloured kernel (the faster of the two for each form on MI355X);
+ * LOR_COLORED forces the coloured kernel, LOR_OWNER the owner-computes one
+ * (LOR_EUNSUPPORTED if the schedule has none).  Both give the same matrix up
+ * to the order of the floating-point sums. */
+#define LOR_COLORED 0x2u
+#define LOR_OWNER 0x4u
 
 /*
  * Assembly schedule written by lor_pattern and read by the lor_assemble_* calls.
@@ -109,7 +117,19 @@ typedef struct lor_sched {
   size_t off_st_ptr, off_st_col, off_ent_row, off_recipe;
   size_t off_zero;               /* 256 zero bytes (read in place of an old value that is absent) */
   size_t off_order_class;        /* class of order[i] (int32 per element, in colour order) */
-  size_t reserved[6];
+  /* Owner-computes schedule (LOR_H1 only; see lor_assemble_h1).  Present
+   * (owner == 1) when the elements form a box of box[0] x box[1] x box[2]
+   * elements whose lattices continue into each other in one orientation,
+   * every vertex id is base(Y, Z) + X on the global lattice (X, Y, Z), and
+   * every row's columns are its lattice neighbours in (dz, dy, dx) order --
+   * structured meshes, also with the elements permuted; owner == 0 otherwise,
+   * and then only the colour schedule is used. */
+  size_t off_nbr;                /* int32 [nel][8]: +x, +y, +z, +y+z, -x, -y, -z neighbour (-1: none) */
+  size_t off_elem3d;             /* int32 [box[2]][box[1]][box[0]]: element at box position (ex, ey, ez) */
+  size_t off_base;               /* int32 [box[2] p + 1][box[1] p + 1]: vertex id of lattice point (0, Y, Z) */
+  int32_t owner;                 /* 1 if the owner-computes schedule is valid */
+  int32_t box[3];                /* elements along x, y, z */
+  size_t reserved[2];
 } lor_sched;
 
 /*
@@ -170,7 +190,11 @@ int lor_pattern(int space, int p, int64_t nel, int64_t nrows, const int32_t* ele
  *                  subelement matrices in FP32 (FP64 on flagged subelements if
  *                  flags has LOR_FP64_FALLBACK); sums within an element in FP64;
  *                  stored as FP32.
- *   flags          0 or LOR_FP64_FALLBACK (FP32 only).
+ *   flags          LOR_FP64_FALLBACK (FP32 only), and at most one of
+ *                  LOR_COLORED / LOR_OWNER (kernel choice, see above).  The
+ *                  owner-computes kernel sums every row once, whole, in FP64
+ *                  (also in the FP32 form) and stores it once; the coloured
+ *                  kernel adds element by element in colour order.
  *   det_ratio_thresh  threshold of the fallback (e.g. 10).
  *   diag           NULL or device int32[2]: [0] += number of subelements that
  *                  took the FP64 fallback, [1] += number of subelements with a

@@ -440,6 +440,10 @@ static int dispatch_h1(int p, const lor_sched* s, int batch, const int32_t* ed, 
   }
 }
 
+template <typename T, typename R>
+int dispatch_owner(int p, const lor_sched* s, int batch, const int32_t* ed, const double* x, const void* k,
+                   double beta, const int32_t* rp, void* v, unsigned f, double thr, int32_t* diag, hipStream_t st);
+
 // Shared argument checks of the value calls.
 int check_sched(const lor_sched* s, int space, int p, int64_t nel, int64_t nrows) {
   if (!s) LOR_FAIL(LOR_EINVAL, "sched is NULL");
@@ -466,7 +470,8 @@ extern "C" int lor_assemble_h1(int p, int64_t nel, int64_t ndofs, int batch, con
   if (nel < 0 || ndofs < 1) LOR_FAIL(LOR_EINVAL, "nel < 0 or ndofs < 1");
   if (batch < 1 || batch > 65535) LOR_FAIL(LOR_EINVAL, "batch outside [1, 65535]");
   if (dtype != LOR_F64 && dtype != LOR_F32) LOR_FAIL(LOR_EINVAL, "dtype must be LOR_F64 or LOR_F32");
-  if (flags & ~LOR_FP64_FALLBACK) LOR_FAIL(LOR_EINVAL, "unknown flag bits 0x%x", flags);
+  if (flags & ~(LOR_FP64_FALLBACK | LOR_COLORED | LOR_OWNER)) LOR_FAIL(LOR_EINVAL, "unknown flag bits 0x%x", flags);
+  if ((flags & LOR_COLORED) && (flags & LOR_OWNER)) LOR_FAIL(LOR_EINVAL, "LOR_COLORED and LOR_OWNER both set");
   if ((flags & LOR_FP64_FALLBACK) && !(det_ratio_thresh >= 1.0))
     LOR_FAIL(LOR_EINVAL, "det_ratio_thresh must be >= 1");
   if (nel > 0 && (!elem_dofs || !coords || !kappa || !row_ptr || !values))
@@ -475,10 +480,21 @@ extern "C" int lor_assemble_h1(int p, int64_t nel, int64_t ndofs, int batch, con
   if (rc) return rc;
   if (static_cast<int64_t>(batch) * sched->nnz >= (int64_t(1) << 40)) LOR_FAIL(LOR_EOVERFLOW, "batch * nnz too large");
   if (nel == 0) return LOR_OK;
+  if ((flags & LOR_OWNER) && !sched->owner)
+    LOR_FAIL(LOR_EUNSUPPORTED, "LOR_OWNER: the mesh has no owner-computes schedule (its element lattices do not "
+                               "continue across faces in one orientation, or a row is not a full lattice stencil)");
   hipStream_t st = as_stream(stream);
+  // default: owner-computes where the schedule has it, in the FP32 form; the
+  // FP64 form keeps the coloured kernel, which is faster there
+  const bool owner = sched->owner && ((flags & LOR_OWNER) || (!(flags & LOR_COLORED) && dtype == LOR_F32));
+  const unsigned fb = flags & LOR_FP64_FALLBACK;
   if (dtype == LOR_F64)
-    return dispatch_h1<double, double>(p, sched, batch, elem_dofs, coords, kappa, beta, row_ptr, values, 0u,
-                                       det_ratio_thresh, diag, st);
-  return dispatch_h1<float, float>(p, sched, batch, elem_dofs, coords, kappa, beta, row_ptr, values, flags,
-                                   det_ratio_thresh, diag, st);
+    return owner ? dispatch_owner<double, double>(p, sched, batch, elem_dofs, coords, kappa, beta, row_ptr, values,
+                                                  0u, det_ratio_thresh, diag, st)
+                 : dispatch_h1<double, double>(p, sched, batch, elem_dofs, coords, kappa, beta, row_ptr, values, 0u,
+                                               det_ratio_thresh, diag, st);
+  return owner ? dispatch_owner<float, float>(p, sched, batch, elem_dofs, coords, kappa, beta, row_ptr, values, fb,
+                                              det_ratio_thresh, diag, st)
+               : dispatch_h1<float, float>(p, sched, batch, elem_dofs, coords, kappa, beta, row_ptr, values, fb,
+                                           det_ratio_thresh, diag, st);
 }

@@ -673,9 +673,153 @@ __global__ void k_gather_i32(const int32_t* __restrict__ src, const int32_t* __r
   if (i < n) dst[i] = src[idx[i]];
 }
 
+
+// ------------------------------------------------ owner-computes schedule (H1)
+//
+// The owner-computes value kernel works on the global lattice of a box of
+// elements: lattice point (X, Y, Z) has vertex id base(Y, Z) + X, and the
+// cell (X, Y, Z) belongs to element elem3d(X / p, Y / p, Z / p).  These
+// kernels find each element's face neighbours (same lattice orientation),
+// and, once the host has laid the elements out as a box, check everything
+// the value kernel relies on against the element map and the finished
+// pattern; any failure only marks the mesh as not eligible (the colour
+// schedule is always built).
+
+enum : int32_t { kOwnAmbiguous = 1, kOwnAsymmetric = 2, kOwnVertex = 4, kOwnRow = 8, kOwnCover = 16 };
+
+// Slot of a face direction in the neighbour table: +x, +y, +z, (+y+z), -x, -y, -z.
+__host__ __device__ constexpr int nbr_slot(int ax, int sg) { return sg > 0 ? ax : 4 + ax; }
+
+// One thread per (element, face direction): the element f != e whose lattice
+// continues e's lattice across that face (f's layer 0 is e's layer p for a +
+// direction, and the other way round for a - direction, point by point).
+__global__ void k_owner_nbrs(const int32_t* __restrict__ map, int p, int64_t nel,
+                             const int32_t* __restrict__ inc_ptr, const int32_t* __restrict__ inc_list,
+                             int32_t* __restrict__ nbr, int32_t* __restrict__ flag) {
+  const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= nel * 6) return;
+  const int64_t e = t / 6;
+  const int dir = static_cast<int>(t - e * 6);
+  const int ax = dir % 3, sg = dir < 3 ? 1 : -1;
+  const int q = p + 1, nloc = q * q * q;
+  const int stride[3] = {1, q, q * q};
+  const int le = sg > 0 ? p * stride[ax] : 0;  // corner of e on the face
+  const int lf = sg > 0 ? 0 : p * stride[ax];  // the same point in f
+  const int u1 = stride[(ax + 1) % 3], u2 = stride[(ax + 2) % 3];
+  const int32_t* me = map + e * nloc;
+  const int32_t v = me[le];
+  int32_t found = -1;
+  for (int32_t i = inc_ptr[v]; i < inc_ptr[v + 1]; ++i) {
+    const int32_t f = inc_list[i] / nloc;
+    const int32_t l = inc_list[i] - f * nloc;
+    if (f == e || l != lf) continue;
+    const int32_t* mf = map + static_cast<int64_t>(f) * nloc;
+    bool same = true;
+    for (int a = 0; a <= p && same; ++a)
+      for (int b = 0; b <= p && same; ++b) same = mf[lf + a * u1 + b * u2] == me[le + a * u1 + b * u2];
+    if (!same) continue;
+    if (found >= 0) atomicOr(flag, kOwnAmbiguous);
+    found = f;
+  }
+  nbr[e * 8 + nbr_slot(ax, sg)] = found;
+}
+
+// Diagonal neighbour +y+z (the +z neighbour of the +y neighbour) and the
+// symmetry of the face relation.
+__global__ void k_owner_diag(int64_t nel, int32_t* __restrict__ nbr, int32_t* __restrict__ flag) {
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= nel) return;
+  int32_t* n = nbr + e * 8;
+  for (int ax = 0; ax < 3; ++ax) {
+    const int32_t f = n[nbr_slot(ax, 1)];
+    if (f >= 0 && nbr[static_cast<int64_t>(f) * 8 + nbr_slot(ax, -1)] != e) atomicOr(flag, kOwnAsymmetric);
+    const int32_t g = n[nbr_slot(ax, -1)];
+    if (g >= 0 && nbr[static_cast<int64_t>(g) * 8 + nbr_slot(ax, 1)] != e) atomicOr(flag, kOwnAsymmetric);
+  }
+  const int32_t fy = n[1];
+  n[3] = fy >= 0 ? nbr[static_cast<int64_t>(fy) * 8 + 2] : -1;
+  n[7] = -1;
+}
+
+// base(Y, Z): the vertex id at lattice point (0, Y, Z), read from the element
+// at box position (0, min(Y / p, ny - 1), min(Z / p, nz - 1)).
+__global__ void k_owner_base(const int32_t* __restrict__ map, int p, const int32_t* __restrict__ elem3d, int nx,
+                             int ny, int nz, int32_t* __restrict__ base) {
+  const int ly = ny * p + 1, lz = nz * p + 1;
+  const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= static_cast<int64_t>(ly) * lz) return;
+  const int Y = static_cast<int>(t % ly), Z = static_cast<int>(t / ly);
+  const int ey = min(Y / p, ny - 1), ez = min(Z / p, nz - 1);
+  const int q = p + 1;
+  const int32_t e = elem3d[(static_cast<int64_t>(ez) * ny + ey) * nx];
+  base[t] = map[static_cast<int64_t>(e) * q * q * q + q * ((Y - p * ey) + q * (Z - p * ez))];
+}
+
+// One thread per (box position, local vertex): the vertex id equals
+// base(Y, Z) + X at its global lattice point.
+__global__ void k_owner_verts(const int32_t* __restrict__ map, int p, const int32_t* __restrict__ elem3d, int nx,
+                              int ny, int nz, const int32_t* __restrict__ base, int32_t* __restrict__ flag) {
+  const int q = p + 1, nloc = q * q * q;
+  const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t nel = static_cast<int64_t>(nx) * ny * nz;
+  if (t >= nel * nloc) return;
+  const int64_t pos = t / nloc;
+  const int l = static_cast<int>(t - pos * nloc);
+  const int ex = static_cast<int>(pos % nx), ey = static_cast<int>((pos / nx) % ny), ez = static_cast<int>(pos / (static_cast<int64_t>(nx) * ny));
+  const int X = p * ex + l % q, Y = p * ey + (l / q) % q, Z = p * ez + l / (q * q);
+  const int32_t e = elem3d[pos];
+  if (map[static_cast<int64_t>(e) * nloc + l] != base[static_cast<int64_t>(Z) * (ny * p + 1) + Y] + X)
+    atomicOr(flag, kOwnVertex);
+}
+
+// One thread per lattice point: the row of its vertex holds exactly the
+// lattice neighbours present, in (dz, dy, dx) order (which must therefore be
+// increasing), and every vertex is reached once.
+__global__ void k_owner_rows(int p, int nx, int ny, int nz, const int32_t* __restrict__ base, int64_t nrows,
+                             const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col_idx,
+                             int32_t* __restrict__ hit, int32_t* __restrict__ flag) {
+  const int LX = nx * p + 1, LY = ny * p + 1, LZ = nz * p + 1;
+  const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= static_cast<int64_t>(LX) * LY * LZ) return;
+  const int X = static_cast<int>(t % LX), Y = static_cast<int>((t / LX) % LY);
+  const int Z = static_cast<int>(t / (static_cast<int64_t>(LX) * LY));
+  const int64_t v = static_cast<int64_t>(base[static_cast<int64_t>(Z) * LY + Y]) + X;
+  if (v < 0 || v >= nrows) {
+    atomicOr(flag, kOwnRow);
+    return;
+  }
+  atomicAdd(&hit[v], 1);
+  const int xlo = X > 0, xhi = X < LX - 1, ylo = Y > 0, yhi = Y < LY - 1, zlo = Z > 0, zhi = Z < LZ - 1;
+  const int32_t rb = row_ptr[v];
+  if (row_ptr[v + 1] - rb != (1 + xlo + xhi) * (1 + ylo + yhi) * (1 + zlo + zhi)) {
+    atomicOr(flag, kOwnRow);
+    return;
+  }
+  int k = 0;
+  for (int dz = -zlo; dz <= zhi; ++dz)
+    for (int dy = -ylo; dy <= yhi; ++dy)
+      for (int dx = -xlo; dx <= xhi; ++dx, ++k)
+        if (col_idx[rb + k] != base[static_cast<int64_t>(Z + dz) * LY + Y + dy] + X + dx) {
+          atomicOr(flag, kOwnRow);
+          return;
+        }
+}
+
+__global__ void k_owner_cover(const int32_t* __restrict__ hit, int64_t nrows, int32_t* __restrict__ flag) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < nrows && hit[i] != 1) atomicOr(flag, kOwnCover);
+}
+
 // --------------------------------------------------------------- host side
 
 static size_t align256(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
+
+template <typename T>
+static int upload(const std::vector<T>& v, void* dst, hipStream_t st) {
+  if (v.empty()) return LOR_OK;
+  LOR_HIP(hipMemcpyAsync(dst, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice, st));
+  return LOR_OK;
+}
 
 static size_t layout(lor_sched* s, const RefElem& r) {
   size_t off = 0;
@@ -697,7 +841,117 @@ static size_t layout(lor_sched* s, const RefElem& r) {
   s->off_recipe = take(sizeof(uint64_t) * std::max<size_t>(1, r.recipe64.size()));
   s->off_zero = take(256);
   s->off_order_class = take(sizeof(int32_t) * s->nel);
+  s->off_nbr = take(sizeof(int32_t) * 8 * s->nel);
+  s->off_elem3d = take(sizeof(int32_t) * s->nel);
+  // a box has (LY)(LZ) = nrows / LX lattice lines along x, and LX >= p + 1
+  s->off_base = take(sizeof(int32_t) * (s->nrows / (s->p + 1) + 1));
   return off;
+}
+
+// Owner-computes schedule of an H1 mesh: face neighbours, the box layout of
+// the elements, base(Y, Z), and the checks of the value kernel's
+// assumptions.  Leaves sched->owner = 0 if the mesh is not eligible; returns
+// an error only for device failures.
+static int build_owner(lor_sched* s, const int32_t* map, const int32_t* row_ptr, const int32_t* col_idx,
+                       hipStream_t st) {
+  s->owner = 0;
+  s->box[0] = s->box[1] = s->box[2] = 0;
+  const int64_t nel = s->nel;
+  const int p = s->p;
+  if (nel == 0 || s->space != LOR_H1) return LOR_OK;
+  int32_t* d_nbr = dev_at<int32_t>(s, s->off_nbr);
+  DevBuf flag;
+  int rc;
+  if ((rc = flag.alloc(sizeof(int32_t)))) return rc;
+  LOR_HIP(hipMemsetAsync(flag.p, 0, sizeof(int32_t), st));
+  k_owner_nbrs<<<ceil_div(nel * 6, 256), 256, 0, st>>>(map, p, nel, dev_at<int32_t>(s, s->off_inc_ptr),
+                                                       dev_at<int32_t>(s, s->off_inc_list), d_nbr, flag.as<int32_t>());
+  LOR_LAUNCHED("k_owner_nbrs");
+  k_owner_diag<<<ceil_div(nel, 256), 256, 0, st>>>(nel, d_nbr, flag.as<int32_t>());
+  LOR_LAUNCHED("k_owner_diag");
+  int32_t hflag = 0;
+  std::vector<int32_t> nb(static_cast<size_t>(nel) * 8);
+  LOR_HIP(hipMemcpyAsync(&hflag, flag.p, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  LOR_HIP(hipMemcpyAsync(nb.data(), d_nbr, sizeof(int32_t) * nb.size(), hipMemcpyDeviceToHost, st));
+  LOR_HIP(hipStreamSynchronize(st));
+  if (hflag != 0) return LOR_OK;
+  // box layout: from the one element without -x, -y, -z neighbours, walk +x,
+  // +y and +z; every element must be reached exactly once and its neighbours
+  // must be its box neighbours
+  auto N = [&](int64_t e, int slot) { return nb[static_cast<size_t>(e) * 8 + slot]; };
+  int64_t corner = -1;
+  for (int64_t e = 0; e < nel; ++e)
+    if (N(e, 4) < 0 && N(e, 5) < 0 && N(e, 6) < 0) {
+      if (corner >= 0) return LOR_OK;
+      corner = e;
+    }
+  if (corner < 0) return LOR_OK;
+  int64_t dims[3] = {0, 0, 0};
+  for (int ax = 0; ax < 3; ++ax)
+    for (int64_t e = corner; e >= 0 && dims[ax] <= nel; e = N(e, ax)) ++dims[ax];
+  if (dims[0] * dims[1] * dims[2] != nel) return LOR_OK;
+  const int64_t nx = dims[0], ny = dims[1], nz = dims[2];
+  std::vector<int32_t> e3(static_cast<size_t>(nel), -1);
+  std::vector<char> seen(static_cast<size_t>(nel), 0);
+  for (int64_t ez = 0; ez < nz; ++ez)
+    for (int64_t ey = 0; ey < ny; ++ey) {
+      const size_t at = static_cast<size_t>((ez * ny + ey) * nx);
+      int64_t e = ez == 0 && ey == 0 ? corner : ey == 0 ? N(e3[at - nx * ny], 2) : N(e3[at - nx], 1);
+      for (int64_t ex = 0; ex < nx; ++ex) {
+        if (e < 0 || seen[e]) return LOR_OK;
+        seen[e] = 1;
+        e3[at + ex] = static_cast<int32_t>(e);
+        e = N(e, 0);
+      }
+      if (e >= 0) return LOR_OK;
+    }
+  for (int64_t ez = 0; ez < nz; ++ez)
+    for (int64_t ey = 0; ey < ny; ++ey)
+      for (int64_t ex = 0; ex < nx; ++ex) {
+        const int64_t e = e3[(ez * ny + ey) * nx + ex];
+        const int64_t c[3] = {ex, ey, ez}, n[3] = {nx, ny, nz};
+        for (int ax = 0; ax < 3; ++ax) {
+          int64_t up = -1, dn = -1;
+          int64_t cc[3] = {c[0], c[1], c[2]};
+          if (c[ax] + 1 < n[ax]) {
+            cc[ax] = c[ax] + 1;
+            up = e3[(cc[2] * ny + cc[1]) * nx + cc[0]];
+          }
+          cc[ax] = c[ax] - 1;
+          if (c[ax] > 0) dn = e3[(cc[2] * ny + cc[1]) * nx + cc[0]];
+          if (N(e, nbr_slot(ax, 1)) != up || N(e, nbr_slot(ax, -1)) != dn) return LOR_OK;
+        }
+      }
+  if (nx * p + 1 > INT32_MAX || ny * p + 1 > INT32_MAX || nz * p + 1 > INT32_MAX) return LOR_OK;
+  const int64_t LX = nx * p + 1, LY = ny * p + 1, LZ = nz * p + 1;
+  if (LX * LY * LZ != s->nrows || LY * LZ > s->nrows / (p + 1) + 1) return LOR_OK;
+  int32_t* d_e3 = dev_at<int32_t>(s, s->off_elem3d);
+  int32_t* d_base = dev_at<int32_t>(s, s->off_base);
+  if ((rc = upload(e3, d_e3, st))) return rc;
+  k_owner_base<<<ceil_div(LY * LZ, 256), 256, 0, st>>>(map, p, d_e3, static_cast<int>(nx), static_cast<int>(ny),
+                                                     static_cast<int>(nz), d_base);
+  LOR_LAUNCHED("k_owner_base");
+  k_owner_verts<<<ceil_div(nel * nloc_h1(p), 256), 256, 0, st>>>(map, p, d_e3, static_cast<int>(nx),
+                                                                 static_cast<int>(ny), static_cast<int>(nz), d_base,
+                                                                 flag.as<int32_t>());
+  LOR_LAUNCHED("k_owner_verts");
+  DevBuf hit;
+  if ((rc = hit.alloc(sizeof(int32_t) * s->nrows))) return rc;
+  LOR_HIP(hipMemsetAsync(hit.p, 0, sizeof(int32_t) * s->nrows, st));
+  k_owner_rows<<<ceil_div(s->nrows, 256), 256, 0, st>>>(p, static_cast<int>(nx), static_cast<int>(ny),
+                                                        static_cast<int>(nz), d_base, s->nrows, row_ptr, col_idx,
+                                                        hit.as<int32_t>(), flag.as<int32_t>());
+  LOR_LAUNCHED("k_owner_rows");
+  k_owner_cover<<<ceil_div(s->nrows, 256), 256, 0, st>>>(hit.as<int32_t>(), s->nrows, flag.as<int32_t>());
+  LOR_LAUNCHED("k_owner_cover");
+  LOR_HIP(hipMemcpyAsync(&hflag, flag.p, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  LOR_HIP(hipStreamSynchronize(st));
+  if (hflag != 0) return LOR_OK;
+  s->box[0] = static_cast<int32_t>(nx);
+  s->box[1] = static_cast<int32_t>(ny);
+  s->box[2] = static_cast<int32_t>(nz);
+  s->owner = 1;
+  return LOR_OK;
 }
 
 static int read_err(const int32_t* d_err, hipStream_t st, int32_t* h) {
@@ -743,13 +997,6 @@ static int build_incidence(const int32_t* map, int64_t nel, int nloc, int is_sig
   }
   k_sort_inc<<<ceil_div(nrows, 256), 256, 0, st>>>(inc_ptr, inc_list, nrows);
   LOR_LAUNCHED("k_sort_inc");
-  return LOR_OK;
-}
-
-template <typename T>
-static int upload(const std::vector<T>& v, void* dst, hipStream_t st) {
-  if (v.empty()) return LOR_OK;
-  LOR_HIP(hipMemcpyAsync(dst, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice, st));
   return LOR_OK;
 }
 
@@ -849,6 +1096,8 @@ extern "C" int lor_pattern(int space, int p, int64_t nel, int64_t nrows, const i
     sched->ncolors = 0;
     sched->nclass = 0;
     sched->dev = nullptr;
+    sched->owner = 0;
+    sched->box[0] = sched->box[1] = sched->box[2] = 0;
     sched->dev_bytes = layout(sched, ref);
     return LOR_OK;
   }
@@ -1011,5 +1260,5 @@ extern "C" int lor_pattern(int space, int p, int64_t nel, int64_t nrows, const i
   }
   sched->max_row_nnz = 0;
   LOR_HIP(hipStreamSynchronize(st));
-  return LOR_OK;
+  return build_owner(sched, elem_map, row_ptr, col_idx, st);
 }

@@ -21,6 +21,9 @@ LOR_F64, LOR_F32 = 0, 1
 LOR_MAX_P = 6
 LOR_MAX_COLORS = 64
 LOR_FP64_FALLBACK = 0x1
+LOR_COLORED = 0x2
+LOR_OWNER = 0x4
+_KERNEL_FLAGS = {"auto": 0, "colored": LOR_COLORED, "owner": LOR_OWNER}
 LOR_DIAG_ONE, LOR_DIAG_KEEP, LOR_DIAG_ZERO = 0, 1, 2
 _DIAG_POLICY = {"one": LOR_DIAG_ONE, "keep": LOR_DIAG_KEEP, "zero": LOR_DIAG_ZERO}
 
@@ -82,7 +85,12 @@ class LorSched(ctypes.Structure):
         ("off_recipe", ctypes.c_size_t),
         ("off_zero", ctypes.c_size_t),
         ("off_order_class", ctypes.c_size_t),
-        ("reserved", ctypes.c_size_t * 6),
+        ("off_nbr", ctypes.c_size_t),
+        ("off_elem3d", ctypes.c_size_t),
+        ("off_base", ctypes.c_size_t),
+        ("owner", ctypes.c_int32),
+        ("box", ctypes.c_int32 * 3),
+        ("reserved", ctypes.c_size_t * 2),
     ]
 
 
@@ -229,6 +237,11 @@ class Pattern:
     def ncolors(self) -> int:
         return int(self.sched.ncolors)
 
+    @property
+    def owner(self) -> bool:
+        """True if the mesh has the owner-computes schedule (H1 only)."""
+        return bool(self.sched.owner)
+
 
 def lor_pattern(space: int, p: int, elem_map: torch.Tensor, nrows: int, device=None) -> Pattern:
     """Pattern and schedule (lor_pattern phases 1 and 2) on the current CUDA device."""
@@ -259,8 +272,13 @@ def lor_pattern(space: int, p: int, elem_map: torch.Tensor, nrows: int, device=N
 
 def lor_assemble_h1(pat: Pattern, elem_dofs, coords, kappa, beta: float, dtype=torch.float64,
                     fp64_fallback: bool = False, det_ratio_thresh: float = 10.0,
-                    diag: torch.Tensor | None = None, out: torch.Tensor | None = None) -> torch.Tensor:
-    """Values of the H1 LOR matrix, [nnz] (or [batch, nnz] for kappa [batch, nel, p^3])."""
+                    diag: torch.Tensor | None = None, out: torch.Tensor | None = None,
+                    kernel: str = "auto") -> torch.Tensor:
+    """Values of the H1 LOR matrix, [nnz] (or [batch, nnz] for kappa [batch, nel, p^3]).
+    kernel: "auto" (FP32: owner-computes where the schedule has it, else
+    coloured; FP64: coloured), "owner" or "colored"."""
+    if kernel not in _KERNEL_FLAGS:
+        raise ValueError("kernel must be 'auto', 'owner' or 'colored'")
     lib = load_library()
     dev = pat.row_ptr.device
     ed = _dev_tensor(elem_dofs, torch.int32, "elem_dofs", dev)
@@ -274,7 +292,7 @@ def lor_assemble_h1(pat: Pattern, elem_dofs, coords, kappa, beta: float, dtype=t
     _need(k, batch * pat.nel * p ** 3, "kappa")
     diag = _diag(diag, 2, dev)
     out = _out(out, (batch, pat.nnz) if batched else (pat.nnz,), dtype, dev)
-    flags = LOR_FP64_FALLBACK if fp64_fallback else 0
+    flags = (LOR_FP64_FALLBACK if fp64_fallback else 0) | _KERNEL_FLAGS[kernel]
     _check(lib.lor_assemble_h1(pat.p, pat.nel, pat.nrows, batch, _ptr(ed), _ptr(x), _ptr(k), float(beta),
                                _ptr(pat.row_ptr), ctypes.byref(pat.sched), _ptr(out), _dtype_code(dtype), flags,
                                float(det_ratio_thresh), _ptr(diag), _stream()))
@@ -563,4 +581,4 @@ class LorH1(torch.autograd.Function):
         coords, kappa = ctx.saved_tensors
         gk, gx = lor_assemble_backward(ctx.pat, ctx.elem_dofs, coords, kappa, ctx.beta,
                                        grad_values.contiguous(), dtype=kappa.dtype)
-        return gx.to(coords.dtype), gk, None, None, None
+        return gx.to(coords.dtype).reshape(coords.shape), gk.reshape(kappa.shape), None, None, None
