@@ -71,9 +71,8 @@ typedef enum { LOR_DIAG_ONE = 0, LOR_DIAG_KEEP = 1, LOR_DIAG_ZERO = 2 } lor_diag
  * det_ratio_thresh (or whose smallest corner Jacobian is <= 0) are integrated
  * with FP64 geometry instead of FP32. */
 #define LOR_FP64_FALLBACK 0x1u
-/* lor_assemble_h1: kernel choice.  By default the FP32 form runs the
- * owner-computes kernel when the schedule has it (sched->owner) and the FP64
- * form the coloured kernel (the faster of the two for each form on MI355X);
+/* lor_assemble_h1: kernel choice.  By default the owner-computes kernel runs
+ * when the schedule has it (sched->owner) and the coloured kernel otherwise;
  * LOR_COLORED forces the coloured kernel, LOR_OWNER the owner-computes one
  * (LOR_EUNSUPPORTED if the schedule has none).  Both give the same matrix up
  * to the order of the floating-point sums. */

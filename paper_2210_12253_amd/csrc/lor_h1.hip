@@ -484,9 +484,8 @@ extern "C" int lor_assemble_h1(int p, int64_t nel, int64_t ndofs, int batch, con
     LOR_FAIL(LOR_EUNSUPPORTED, "LOR_OWNER: the mesh has no owner-computes schedule (its element lattices do not "
                                "continue across faces in one orientation, or a row is not a full lattice stencil)");
   hipStream_t st = as_stream(stream);
-  // default: owner-computes where the schedule has it, in the FP32 form; the
-  // FP64 form keeps the coloured kernel, which is faster there
-  const bool owner = sched->owner && ((flags & LOR_OWNER) || (!(flags & LOR_COLORED) && dtype == LOR_F32));
+  // default: owner-computes wherever the schedule has it (faster in both forms)
+  const bool owner = sched->owner && !(flags & LOR_COLORED);
   const unsigned fb = flags & LOR_FP64_FALLBACK;
   if (dtype == LOR_F64)
     return owner ? dispatch_owner<double, double>(p, sched, batch, elem_dofs, coords, kappa, beta, row_ptr, values,

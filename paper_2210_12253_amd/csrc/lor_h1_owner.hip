@@ -46,20 +46,23 @@ constexpr int kOwnTile = 8;                  // cells per tile side (one wave: 8
 constexpr int kOwnStride = kOwnTile - 1;     // tiles overlap by one cell
 constexpr int kOwnPts = (kOwnTile + 1) * (kOwnTile + 1);  // lattice points of one tile plane
 
-// Bytes of the wave's slab that holds the cell matrices [pair][lane] and,
-// once the row sums have read them, the finished rows staged per x-line.
+// Layers integrated per step and LDS slab of one wave.  The FP64 form runs
+// one wave per SIMD: its integration wants ~250 VGPRs, and with the carry a
+// second wave per SIMD spills (measured at the headline size: 1.10 ms at one
+// wave, 1.28 ms at two with spills, 1.14 ms at two with the carry in LDS,
+// 1.18 ms with two cells per lane and step).  The FP32 form runs two waves
+// per SIMD.  LPS > 1 (several layers per lane and step) is supported but not
+// used.
 template <typename T, typename R>
-struct OwnSlab {
+struct OwnCfg {
+  static constexpr int LPS = 1;                        // layers per step
+  static constexpr int NPL = LPS + 1;                 // lattice planes in LDS (ring)
+  static constexpr int WPE = sizeof(R) == 8 ? 1 : 2;  // waves per SIMD (second __launch_bounds__ argument)
+  // cell matrices [pair][lane]; once the row sums have read them, the finished
+  // rows of the plane staged per x-line
   static constexpr int CELLS = 36 * 64 * static_cast<int>(sizeof(R));
   static constexpr int ROWS = 64 * 27 * static_cast<int>(sizeof(T));
-  static constexpr int BYTES = CELLS > ROWS ? CELLS : ROWS;
-  // plus the two lattice planes of the layer (FP64 coordinates) and row pointers
-  static constexpr int LDS = BYTES + 2 * kOwnPts * 3 * 8 + 64 * 4;
-  // Waves per SIMD to reserve registers for (the second __launch_bounds__
-  // argument): 2, i.e. 256 VGPRs.  The LDS admits 7 waves per CU in FP64 and
-  // 12 in FP32, but at 3 waves per SIMD (168 VGPRs) the FP32 integration
-  // spills and runs slower (0.72 against 0.69 ms at the headline size).
-  static constexpr int WPE = 2;
+  static constexpr int SLAB = CELLS > ROWS ? CELLS : ROWS;
 };
 
 // FP32 form, strongly curved cell: FP64 geometry and quadrature from the FP64
@@ -94,15 +97,16 @@ __host__ __device__ constexpr int own_off(int u, int v) {
 }
 
 template <int P, typename T, typename R>
-__global__ __launch_bounds__(64, (OwnSlab<T, R>::WPE)) void k_h1_owner(
+__global__ __launch_bounds__(64, (OwnCfg<T, R>::WPE)) void k_h1_owner(
     int nex, int ney, int nez, int ntx, int seglen, const int32_t* __restrict__ elem3d,
     const int32_t* __restrict__ base, const double* __restrict__ coords, const T* __restrict__ kappa, T beta,
     const int32_t* __restrict__ row_ptr, int64_t nel, int64_t nnz, T* __restrict__ values, unsigned flags,
     R det_thresh, int32_t* __restrict__ diag) {
-  constexpr int NSUB = P * P * P;
-  __shared__ __align__(16) unsigned char sSlab[OwnSlab<T, R>::BYTES];
-  __shared__ double sPt[2][kOwnPts * 3];  // lattice planes Z and Z + 1 of the tile
-  __shared__ int32_t sRp[64];             // row pointers of the tile's rows in the current plane
+  using C = OwnCfg<T, R>;
+  constexpr int NSUB = P * P * P, LPS = C::LPS, NPL = C::NPL;
+  __shared__ __align__(16) unsigned char sSlab[C::SLAB];
+  __shared__ double sPt[NPL][kOwnPts * 3];  // lattice planes, ring buffer indexed by Z % NPL
+  __shared__ int32_t sRp[64];               // row pointers of the tile's rows in the plane being stored
   R* const sCell = reinterpret_cast<R*>(sSlab);
   T* const sStg = reinterpret_cast<T*>(sSlab);
 
@@ -160,71 +164,90 @@ __global__ __launch_bounds__(64, (OwnSlab<T, R>::WPE)) void k_h1_owner(
     rp = 0;
     if (row_in && Z <= NZc) rp = row_ptr[base[static_cast<int64_t>(Z) * LY + cY] + cX];
   };
-  auto stage_plane = [&](int buf, const int32_t (&v)[2], const double (&xq)[2][3]) {
+  auto stage_plane = [&](int Z, const int32_t (&v)[2], const double (&xq)[2][3]) {
+    double* pl = sPt[Z % NPL];
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
       const int pidx = lane + 64 * j;
       if (pidx < kOwnPts && v[j] >= 0) {
-        sPt[buf][3 * pidx + 0] = xq[j][0];
-        sPt[buf][3 * pidx + 1] = xq[j][1];
-        sPt[buf][3 * pidx + 2] = xq[j][2];
+        pl[3 * pidx + 0] = xq[j][0];
+        pl[3 * pidx + 1] = xq[j][1];
+        pl[3 * pidx + 2] = xq[j][2];
       }
     }
   };
 
   const int zfirst = zs > 0 ? zs - 1 : zs;  // a segment above the bottom starts one layer lower
-  // prologue: plane zfirst staged; plane zfirst + 1, the vertex ids of the
-  // plane after it, and this layer's coefficients and row pointers in flight
-  int32_t vq[2], vnext[2];
-  double xq[2][3] = {};
+  // the segment writes planes zs .. ze - 1; the last one also writes the top
+  // plane NZc, whose rows only hold the carry
+  const int zend = ze == NZc ? NZc + 1 : ze;
+
+  // Software pipeline, per step of LPS layers from Z: planes Z + 1 .. Z + LPS
+  // are staged from registers, and loads for the next step are issued
+  // (coordinates of its planes, vertex ids one step further, coefficients of
+  // its layers, elements one step further, row pointers of its planes).
+  int32_t vq[LPS][2], vnext[LPS][2];
+  double xq[LPS][2][3] = {};
+  int32_t elq[LPS], elnext[LPS], rpq[LPS];
+  T kq[LPS];
   {
     int32_t v0[2];
     double xp[2][3] = {};
     load_vid(zfirst, v0);
     load_xyz(v0, xp);
-    stage_plane(zfirst & 1, v0, xp);
-    load_vid(zfirst + 1, vq);
-    load_xyz(vq, xq);
-    load_vid(zfirst + 2, vnext);
+    stage_plane(zfirst, v0, xp);
+#pragma unroll
+    for (int L = 0; L < LPS; ++L) {
+      load_vid(zfirst + 1 + L, vq[L]);
+      load_xyz(vq[L], xq[L]);
+      load_vid(zfirst + 1 + LPS + L, vnext[L]);
+      load_elem(zfirst + L, elq[L]);
+      load_kap(zfirst + L, elq[L], kq[L]);
+      load_rp(zfirst + L, rpq[L]);
+      load_elem(zfirst + LPS + L, elnext[L]);
+    }
   }
-  int32_t elq, elnext;
-  T kq;
-  int32_t rpq;
-  load_elem(zfirst, elq);
-  load_kap(zfirst, elq, kq);
-  load_rp(zfirst, rpq);
-  load_elem(zfirst + 1, elnext);
 
   double carry[18];
 #pragma unroll
   for (int o = 0; o < 18; ++o) carry[o] = 0.0;
 
-  // the segment writes planes zs .. ze - 1; the last one also writes the top
-  // plane NZc, whose rows only hold the carry
-  const int zend = ze == NZc ? NZc + 1 : ze;
-  for (int Z = zfirst; Z < zend; ++Z) {
-    const bool prestep = Z < zs;
-    // plane Z + 1 into LDS (plane Z is there from the previous step)
-    stage_plane((Z + 1) & 1, vq, xq);
-    const T kcur = kq;
-    const int32_t elcur = elq;
-    const int32_t rpcur = rpq;
-    // loads for the next step
-    load_xyz(vnext, xq);
-    vq[0] = vnext[0];
-    vq[1] = vnext[1];
-    load_vid(Z + 3, vnext);
-    elq = elnext;
-    load_kap(Z + 1, elq, kq);
-    load_elem(Z + 2, elnext);
-    load_rp(Z + 1, rpq);
-    sRp[lane] = rpcur;
+  for (int Z = zfirst; Z < zend; Z += LPS) {
+#pragma unroll
+    for (int L = 0; L < LPS; ++L) stage_plane(Z + 1 + L, vq[L], xq[L]);
+    int32_t elcur[LPS], rpcur[LPS];
+    T kcur[LPS];
+#pragma unroll
+    for (int L = 0; L < LPS; ++L) {
+      elcur[L] = elq[L];
+      kcur[L] = kq[L];
+      rpcur[L] = rpq[L];
+      load_xyz(vnext[L], xq[L]);
+      vq[L][0] = vnext[L][0];
+      vq[L][1] = vnext[L][1];
+      load_vid(Z + 1 + 2 * LPS + L, vnext[L]);
+      elq[L] = elnext[L];
+      load_kap(Z + LPS + L, elq[L], kq[L]);
+      load_elem(Z + 2 * LPS + L, elnext[L]);
+      load_rp(Z + LPS + L, rpq[L]);
+    }
     __builtin_amdgcn_wave_barrier();
 
-    // cell (cX, cY, Z): 36 entries into the slab
-    if (elcur >= 0) {
-      const double* pz0 = sPt[Z & 1];
-      const double* pz1 = sPt[(Z + 1) & 1];
+    // the cells (cX, cY, Z + L): 36 entries each, straight into the slab for
+    // one layer per step, in registers for several
+    R ent[LPS > 1 ? LPS : 1][LPS > 1 ? 36 : 1];
+#pragma unroll
+    for (int L = 0; L < LPS; ++L) {
+      const int Zl = Z + L;
+      R* out = LPS > 1 ? &ent[L][0] : sCell + lane;
+      constexpr int OS = LPS > 1 ? 1 : 64;  // distance between two entries of the cell
+      if constexpr (LPS > 1) {
+#pragma unroll
+        for (int i = 0; i < 36; ++i) ent[L][i] = R(0);
+      }
+      if (elcur[L] < 0) continue;
+      const double* pz0 = sPt[Zl % NPL];
+      const double* pz1 = sPt[(Zl + 1) % NPL];
       auto load_X = [&](double (&X)[8][3]) {
 #pragma unroll
         for (int v = 0; v < 8; ++v) {
@@ -234,11 +257,10 @@ __global__ __launch_bounds__(64, (OwnSlab<T, R>::WPE)) void k_h1_owner(
           for (int d = 0; d < 3; ++d) X[v][d] = pl[3 * pidx + d];
         }
       };
-      const R kap = static_cast<R>(kcur);
-      R* out = sCell + lane;
+      const R kap = static_cast<R>(kcur[L]);
       // counted once: a cell in a tile's last column (row) is also the first
       // column (row) of the next tile, which counts it
-      const bool own = !prestep && lx < kOwnStride && ly < kOwnStride;
+      const bool own = Zl >= zs && lx < kOwnStride && ly < kOwnStride;
       bool fallback = false;
       if constexpr (!std::is_same<R, double>::value) {
         if (flags & LOR_FP64_FALLBACK) {
@@ -263,83 +285,99 @@ __global__ __launch_bounds__(64, (OwnSlab<T, R>::WPE)) void k_h1_owner(
 #pragma unroll
         for (int u = 0; u < 8; ++u)
 #pragma unroll
-          for (int v = u; v < 8; ++v) out[pair_index(u, v) * 64] = h1_entry<R>(F, u, v);
+          for (int v = u; v < 8; ++v) out[pair_index(u, v) * OS] = h1_entry<R>(F, u, v);
         if (!ok && own && diag) atomicAdd(&diag[1], 1);
       }
       if (fallback) {
+        // FP32 only: computed in the slab (then read back for several layers)
         const bool ok = own_fp64_fallback(pz0, pz1, lx, ly, static_cast<double>(kap), static_cast<double>(beta),
-                                          reinterpret_cast<float*>(out));
+                                          reinterpret_cast<float*>(sCell + lane));
+        if constexpr (LPS > 1) {
+#pragma unroll
+          for (int i = 0; i < 36; ++i) ent[L][i] = sCell[i * 64 + lane];
+        }
         if (own && diag) {
           atomicAdd(&diag[0], 1);
           if (!ok) atomicAdd(&diag[1], 1);
         }
       }
     }
-    __builtin_amdgcn_wave_barrier();
 
-    // row (cX, cY) of plane Z: the carry (c = 1 corners, layer Z - 1) + this
-    // layer's c = 0 corners; this layer's c = 1 corners are the next carry
-    double acc[27];
 #pragma unroll
-    for (int o = 0; o < 27; ++o) acc[o] = o < 18 ? carry[o] : 0.0;
+    for (int L = 0; L < LPS; ++L) {
+      const int Zl = Z + L;
+      if (Zl >= zend) break;
+      __builtin_amdgcn_wave_barrier();
+      if constexpr (LPS > 1) {
 #pragma unroll
-    for (int o = 0; o < 18; ++o) carry[o] = 0.0;
-    if (row_in && Z < NZc) {
+        for (int i = 0; i < 36; ++i) sCell[i * 64 + lane] = ent[L][i];
+      }
+      sRp[lane] = rpcur[L];
+      __builtin_amdgcn_wave_barrier();
+      // row (cX, cY) of plane Zl: the carry (c = 1 corners, layer Zl - 1) +
+      // this layer's c = 0 corners; this layer's c = 1 corners are the next carry
+      double acc[27];
 #pragma unroll
-      for (int b = 0; b < 2; ++b)
+      for (int o = 0; o < 27; ++o) acc[o] = o < 18 ? carry[o] : 0.0;
 #pragma unroll
-        for (int a = 0; a < 2; ++a) {
-          const int sx = lx - a, sy = ly - b;
-          if (sx >= 0 && sy >= 0 && x0 + sx < NXc && y0 + sy < NYc) {
-            const R* cm = sCell + sx + 8 * sy;
-            const int u0 = a + 2 * b, u1 = a + 2 * b + 4;
+      for (int o = 0; o < 18; ++o) carry[o] = 0.0;
+      if (row_in && Zl < NZc) {
 #pragma unroll
-            for (int v = 0; v < 8; ++v) {
-              acc[own_off(u0, v)] += static_cast<double>(cm[pair_index(u0, v) * 64]);
-              carry[own_off(u1, v)] += static_cast<double>(cm[pair_index(u1, v) * 64]);
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+          for (int a = 0; a < 2; ++a) {
+            const int sx = lx - a, sy = ly - b;
+            if (sx >= 0 && sy >= 0 && x0 + sx < NXc && y0 + sy < NYc) {
+              const R* cm = sCell + sx + 8 * sy;
+              const int u0 = a + 2 * b, u1 = a + 2 * b + 4;
+#pragma unroll
+              for (int v = 0; v < 8; ++v) {
+                acc[own_off(u0, v)] += static_cast<double>(cm[pair_index(u0, v) * 64]);
+                carry[own_off(u1, v)] += static_cast<double>(cm[pair_index(u1, v) * 64]);
+              }
             }
           }
-        }
-    }
-    __builtin_amdgcn_wave_barrier();
-    if (prestep) continue;
+      }
+      __builtin_amdgcn_wave_barrier();
+      if (Zl < zs) continue;  // the layer below the segment: carry only
 
-    // stage the owned rows of each x-line in CSR order: a row holds
-    // (x-offsets) x (y-offsets) x (z-offsets) entries, 2 per axis at a
-    // lattice end and 3 elsewhere
-    const int ylo = cY > 0, yhi = cY < NYc, zlo = Z > 0, zhi = Z < NZc;
-    const int ny = 1 + ylo + yhi, nyz = ny * (1 + zlo + zhi);
-    const int xfirst = ti == 0 ? 0 : 1;  // first owned row of the tile's x-lines
-    if (row_own) {
-      const int xlo = cX > 0, xhi = cX < NXc, nx = 1 + xlo + xhi;
-      int before = 0;  // x-offset counts of the owned rows before this one in its line
-      for (int x = xfirst; x < lx; ++x) before += 1 + (x0 + x > 0) + (x0 + x < NXc);
-      T* row = sStg + 27 * 8 * ly + before * nyz + (zlo * ny + ylo) * nx + xlo;
+      // stage the owned rows of each x-line in CSR order: a row holds
+      // (x-offsets) x (y-offsets) x (z-offsets) entries, 2 per axis at a
+      // lattice end and 3 elsewhere
+      const int ylo = cY > 0, yhi = cY < NYc, zlo = Zl > 0, zhi = Zl < NZc;
+      const int ny = 1 + ylo + yhi, nyz = ny * (1 + zlo + zhi);
+      const int xfirst = ti == 0 ? 0 : 1;  // first owned row of the tile's x-lines
+      if (row_own) {
+        const int xlo = cX > 0, xhi = cX < NXc, nx = 1 + xlo + xhi;
+        int before = 0;  // x-offset counts of the owned rows before this one in its line
+        for (int x = xfirst; x < lx; ++x) before += 1 + (x0 + x > 0) + (x0 + x < NXc);
+        T* row = sStg + 27 * 8 * ly + before * nyz + (zlo * ny + ylo) * nx + xlo;
 #pragma unroll
-      for (int dz = -1; dz <= 1; ++dz)
+        for (int dz = -1; dz <= 1; ++dz)
 #pragma unroll
-        for (int dy = -1; dy <= 1; ++dy)
+          for (int dy = -1; dy <= 1; ++dy)
 #pragma unroll
-          for (int dx = -1; dx <= 1; ++dx) {
-            const bool ok = (dx >= 0 || xlo) && (dx <= 0 || xhi) && (dy >= 0 || ylo) && (dy <= 0 || yhi) &&
-                            (dz >= 0 || zlo) && (dz <= 0 || zhi);
-            if (ok) row[dz * nx * ny + dy * nx + dx] = static_cast<T>(acc[(dx + 1) + 3 * (dy + 1) + 9 * (dz + 1)]);
-          }
+            for (int dx = -1; dx <= 1; ++dx) {
+              const bool ok = (dx >= 0 || xlo) && (dx <= 0 || xhi) && (dy >= 0 || ylo) && (dy <= 0 || yhi) &&
+                              (dz >= 0 || zlo) && (dz <= 0 || zhi);
+              if (ok)
+                row[dz * nx * ny + dy * nx + dx] = static_cast<T>(acc[(dx + 1) + 3 * (dy + 1) + 9 * (dz + 1)]);
+            }
+      }
+      __builtin_amdgcn_wave_barrier();
+      // one contiguous span per owned x-line
+      const int xlast = x0 + 7 < NXc ? x0 + 7 : NXc;  // last owned row of the lines
+      int span_x = 0;
+      for (int X = x0 + xfirst; X <= xlast; ++X) span_x += 1 + (X > 0) + (X < NXc);
+      for (int l = tj == 0 ? 0 : 1; l < 8; ++l) {
+        const int Y = y0 + l;
+        if (Y > NYc) break;
+        const int span = span_x * (1 + (Y > 0) + (Y < NYc)) * (1 + zlo + zhi);
+        T* dst = values + sRp[xfirst + 8 * l];
+        const T* src = sStg + 27 * 8 * l;
+        for (int t = lane; t < span; t += 64) __builtin_nontemporal_store(src[t], dst + t);
+      }
     }
-    __builtin_amdgcn_wave_barrier();
-    // one contiguous span per owned x-line
-    const int xlast = x0 + 7 < NXc ? x0 + 7 : NXc;  // last owned row of the lines
-    int span_x = 0;
-    for (int X = x0 + xfirst; X <= xlast; ++X) span_x += 1 + (X > 0) + (X < NXc);
-    for (int l = tj == 0 ? 0 : 1; l < 8; ++l) {
-      const int Y = y0 + l;
-      if (Y > NYc) break;
-      const int span = span_x * (1 + (Y > 0) + (Y < NYc)) * (1 + zlo + zhi);
-      T* dst = values + sRp[xfirst + 8 * l];
-      const T* src = sStg + 27 * 8 * l;
-      for (int t = lane; t < span; t += 64) __builtin_nontemporal_store(src[t], dst + t);
-    }
-    __builtin_amdgcn_wave_barrier();
   }
 }
 

@@ -275,8 +275,8 @@ def lor_assemble_h1(pat: Pattern, elem_dofs, coords, kappa, beta: float, dtype=t
                     diag: torch.Tensor | None = None, out: torch.Tensor | None = None,
                     kernel: str = "auto") -> torch.Tensor:
     """Values of the H1 LOR matrix, [nnz] (or [batch, nnz] for kappa [batch, nel, p^3]).
-    kernel: "auto" (FP32: owner-computes where the schedule has it, else
-    coloured; FP64: coloured), "owner" or "colored"."""
+    kernel: "auto" (owner-computes where the schedule has it, else coloured),
+    "owner" or "colored"."""
     if kernel not in _KERNEL_FLAGS:
         raise ValueError("kernel must be 'auto', 'owner' or 'colored'")
     lib = load_library()
