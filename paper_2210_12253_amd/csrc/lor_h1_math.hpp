@@ -198,6 +198,26 @@ __device__ __forceinline__ void h1_contract_stiffness(const R (&H00)[2][2], cons
   }
 }
 
+// mass: TM[A][B][C] = sum_q D(q) LL_A(xi) LL_B(eta) LL_C(zeta)
+template <typename R>
+__device__ __forceinline__ void h1_contract_mass(const R (&Dq)[2][2][2], R (&TM)[3][3][3]) {
+#pragma unroll
+  for (int al = 0; al < 3; ++al) {
+    R U[2][2];
+#pragma unroll
+    for (int t2 = 0; t2 < 2; ++t2)
+#pragma unroll
+      for (int t3 = 0; t3 < 2; ++t3) U[t2][t3] = R(LL(al, 0)) * Dq[0][t2][t3] + R(LL(al, 1)) * Dq[1][t2][t3];
+#pragma unroll
+    for (int B = 0; B < 3; ++B) {
+      const R t0 = R(LL(B, 0)) * U[0][0] + R(LL(B, 1)) * U[1][0];
+      const R t1 = R(LL(B, 0)) * U[0][1] + R(LL(B, 1)) * U[1][1];
+#pragma unroll
+      for (int Cc = 0; Cc < 3; ++Cc) TM[al][B][Cc] = R(LL(Cc, 0)) * t0 + R(LL(Cc, 1)) * t1;
+    }
+  }
+}
+
 // Factor tables of one subelement; returns false if det J <= 0 at a Gauss point.
 template <typename R>
 __device__ __forceinline__ bool h1_factors(const R (&ex)[2][2][3], const R (&ey)[2][2][3],
@@ -246,22 +266,7 @@ __device__ __forceinline__ bool h1_factors(const R (&ex)[2][2][3], const R (&ey)
         }
       }
   h1_contract_stiffness<R>(H00, H11, H22, Z01, Z02, G12q, F);
-  // mass: TM[A][B][C] = sum_q D(q) LL_A(xi) LL_B(eta) LL_C(zeta)
-#pragma unroll
-  for (int al = 0; al < 3; ++al) {
-    R U[2][2];
-#pragma unroll
-    for (int t2 = 0; t2 < 2; ++t2)
-#pragma unroll
-      for (int t3 = 0; t3 < 2; ++t3) U[t2][t3] = R(LL(al, 0)) * Dq[0][t2][t3] + R(LL(al, 1)) * Dq[1][t2][t3];
-#pragma unroll
-    for (int B = 0; B < 3; ++B) {
-      const R t0 = R(LL(B, 0)) * U[0][0] + R(LL(B, 1)) * U[1][0];
-      const R t1 = R(LL(B, 0)) * U[0][1] + R(LL(B, 1)) * U[1][1];
-#pragma unroll
-      for (int Cc = 0; Cc < 3; ++Cc) F.TM[al][B][Cc] = R(LL(Cc, 0)) * t0 + R(LL(Cc, 1)) * t1;
-    }
-  }
+  h1_contract_mass<R>(Dq, F.TM);
   return ok;
 }
 
