@@ -50,6 +50,10 @@ __global__ void k_bw_zero_f64(double* __restrict__ x, int64_t n) {
 
 int check_sched(const lor_sched* s, int space, int p, int64_t nel, int64_t nrows);
 
+// One small workgroup per group of E elements (one wave where the
+// subelements allow: E p^3 <= 64 lanes), one workgroup per group, so that
+// several independent workgroups share a CU and hide each other's latency
+// (gathers of coordinates and cotangents, LDS round trips).
 template <int P>
 struct BwCfg {
   static constexpr int Q = P + 1;
@@ -58,9 +62,17 @@ struct BwCfg {
   static constexpr int T1 = 3 * P + 1;
   static constexpr int NENT = T1 * T1 * T1;
   static constexpr int NENTP = (NENT + 15) / 16 * 16;
-  static constexpr int E = P == 1 ? 64 : P == 2 ? 16 : P == 3 ? 8 : P == 4 ? 4 : P == 5 ? 2 : 1;
-  static constexpr int THREADS = 256;
+  static constexpr int E = NSUB >= 64 ? 1 : 64 / NSUB;
+  static constexpr int THREADS = (E * NSUB + 63) / 64 * 64;
   static constexpr int TWE = NENTP / 4;
+};
+
+// Waves per SIMD to reserve registers for: FP64 keeps 108 FP64 accumulators
+// per lane, so one wave's worth of registers (the LDS of one workgroup admits
+// several workgroups per CU, each a wave or a few).
+template <typename R>
+struct BwOcc {
+  static constexpr int WPE = sizeof(R) == 8 ? 1 : 2;
 };
 
 // Compact index of stencil entry (vertex (x,y,z), offset (dx,dy,dz)) inside
@@ -77,7 +89,7 @@ __device__ __forceinline__ int compact_index(int x, int y, int z, int dx, int dy
 }
 
 template <int P, typename T, typename R>
-__global__ __launch_bounds__(256, 1) void k_h1_backward(
+__global__ __launch_bounds__(BwCfg<P>::THREADS, (BwOcc<R>::WPE)) void k_h1_backward(
     int64_t nel, int32_t chunk, const int32_t* __restrict__ elem_dofs, const double* __restrict__ coords,
     const T* __restrict__ kappa, T beta, const int32_t* __restrict__ row_ptr, const uint8_t* __restrict__ tables,
     const int32_t* __restrict__ elem_class, int64_t tab_stride, const uint16_t* __restrict__ ent_row, int batch,
@@ -271,18 +283,6 @@ __global__ void k_gather_vertices(const int32_t* __restrict__ inc_ptr, const int
   gcoords[3 * g + 2] = a2;
 }
 
-static int num_cus_bw() {
-  static int cached[64] = {};
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
-  if (cached[dev] == 0) {
-    int n = 0;
-    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) n = 256;
-    cached[dev] = n;
-  }
-  return cached[dev];
-}
-
 template <int P, typename T, typename R>
 static int launch_bw(const lor_sched* sched, int batch, const int32_t* elem_dofs, const double* coords,
                      const void* kappa, double beta, const int32_t* row_ptr, const void* gvals, void* gkappa,
@@ -292,9 +292,7 @@ static int launch_bw(const lor_sched* sched, int batch, const int32_t* elem_dofs
     LOR_FAIL(LOR_EINVAL, "schedule tables do not match p = %d", P);
   const uint8_t* tab = dev_at<uint8_t>(sched, sched->off_tables);
   const int64_t nel = sched->nel;
-  const int64_t groups = ceil_div(nel, C::E);
-  const int64_t gpw = ceil_div(groups, num_cus_bw());
-  const int32_t chunk = static_cast<int32_t>(gpw * C::E);
+  const int32_t chunk = C::E;  // one group of E elements per workgroup
   double* ework = static_cast<double*>(workspace);
   k_h1_backward<P, T, R><<<static_cast<unsigned>(ceil_div(nel, chunk)), C::THREADS, 0, st>>>(
       nel, chunk, elem_dofs, coords, static_cast<const T*>(kappa), static_cast<T>(beta), row_ptr, tab,
