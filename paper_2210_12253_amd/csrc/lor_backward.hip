@@ -102,11 +102,14 @@ __global__ __launch_bounds__(BwCfg<P>::THREADS, (BwOcc<R>::WPE)) void k_h1_backw
   __shared__ double sX[E * NLOC * 3];
   __shared__ int32_t sRp[E * NLOC];
   __shared__ uint32_t sTabW[E * TWE];
-  __shared__ double sGX[GW];            // cotangent entries in compact order, later the corner adjoints
+  // cotangent entries in compact order, later the corner adjoints; in the
+  // arithmetic's precision (both are R values), which halves this buffer in
+  // the FP32 form
+  __shared__ R sGX[GW];
   __shared__ uint16_t sK[64 * TH];      // compact index of each lane's 64 corner pairs, [pair][lane]
   const uint8_t* sTab = reinterpret_cast<const uint8_t*>(sTabW);
-  double* sG = sGX;
-  double* sXb = sGX;
+  R* sG = sGX;
+  R* sXb = sGX;
 
   const int64_t cbeg = static_cast<int64_t>(blockIdx.x) * chunk;
   const int nce = static_cast<int>(nel - cbeg < chunk ? nel - cbeg : chunk);
@@ -197,7 +200,7 @@ __global__ __launch_bounds__(BwCfg<P>::THREADS, (BwOcc<R>::WPE)) void k_h1_backw
 #pragma unroll
       for (int j = 0; j < NJ; ++j) {
         const int i = tid + j * TH;
-        if (i < ne * NENT) sG[i] = static_cast<double>(gv[j]);
+        if (i < ne * NENT) sG[i] = static_cast<R>(gv[j]);
       }
       if (b + 1 < batch) {
         const T* gn = gvals + static_cast<int64_t>(b + 1) * nnz;
@@ -207,7 +210,7 @@ __global__ __launch_bounds__(BwCfg<P>::THREADS, (BwOcc<R>::WPE)) void k_h1_backw
       lds_barrier();
       if (act) {
         const R kb = static_cast<R>(kappa[(static_cast<int64_t>(b) * nel + e) * NSUB + s]);
-        const double* ge = sG + el * NENT;
+        const R* ge = sG + el * NENT;
         R gk = R(0);
         // ordered pairs (u, v) and (v, u) both feed the unique entry {u, v}
 #pragma unroll
@@ -229,7 +232,7 @@ __global__ __launch_bounds__(BwCfg<P>::THREADS, (BwOcc<R>::WPE)) void k_h1_backw
       R gx[2][2][3], gy[2][2][3], gz[2][2][3];
       h1_adjoint<R>(ex, ey, ez, Wk, Wm, static_cast<R>(beta), gx, gy, gz);
       // corner adjoints from the edge adjoints: e = X(hi) - X(lo)
-      double* xb = sXb + el * 24 * NSUB + s;
+      R* xb = sXb + el * 24 * NSUB + s;
 #pragma unroll
       for (int v = 0; v < 8; ++v) {
         const int a = v & 1, b2 = (v >> 1) & 1, c = v >> 2;
@@ -237,7 +240,7 @@ __global__ __launch_bounds__(BwCfg<P>::THREADS, (BwOcc<R>::WPE)) void k_h1_backw
         for (int d = 0; d < 3; ++d) {
           const R val = (a ? gx[b2][c][d] : -gx[b2][c][d]) + (b2 ? gy[a][c][d] : -gy[a][c][d]) +
                         (c ? gz[a][b2][d] : -gz[a][b2][d]);
-          xb[(v * 3 + d) * NSUB] = static_cast<double>(val);
+          xb[(v * 3 + d) * NSUB] = val;
         }
       }
     }
@@ -254,7 +257,7 @@ __global__ __launch_bounds__(BwCfg<P>::THREADS, (BwOcc<R>::WPE)) void k_h1_backw
         if (sx >= 0 && sx < P && sy >= 0 && sy < P && sz >= 0 && sz < P) {
           const int s2 = sx + P * (sy + P * sz);
 #pragma unroll
-          for (int d = 0; d < 3; ++d) acc[d] += sXb[el2 * 24 * NSUB + (u * 3 + d) * NSUB + s2];
+          for (int d = 0; d < 3; ++d) acc[d] += static_cast<double>(sXb[el2 * 24 * NSUB + (u * 3 + d) * NSUB + s2]);
         }
       }
       double* w = ework + ((e0 + el2) * NLOC + l) * 3;
