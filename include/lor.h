@@ -117,18 +117,19 @@ typedef struct lor_sched {
   size_t off_zero;               /* 256 zero bytes (read in place of an old value that is absent) */
   size_t off_order_class;        /* class of order[i] (int32 per element, in colour order) */
   /* Owner-computes schedule (LOR_H1 only; see lor_assemble_h1).  Present
-   * (owner == 1) when the elements form a box of box[0] x box[1] x box[2]
-   * elements whose lattices continue into each other in one orientation,
-   * every vertex id is base(Y, Z) + X on the global lattice (X, Y, Z), and
-   * every row's columns are its lattice neighbours in (dz, dy, dx) order --
-   * structured meshes, also with the elements permuted; owner == 0 otherwise,
+   * (owner == 1) when the mesh is a box lattice: the elements tile a box of
+   * box[0] x box[1] x box[2] elements, each with its local axes along the box
+   * axes, and the vertex at point (X, Y, Z) of the global lattice of
+   * (LX, LY, LZ) = (box[0] p + 1, box[1] p + 1, box[2] p + 1) points has id
+   * X + LX (Y + LY Z) -- structured meshes, also with the elements in any
+   * order.  Such meshes also get their pattern, colours (by the parities of
+   * the box position) and rank tables in closed form.  owner == 0 otherwise,
    * and then only the colour schedule is used. */
-  size_t off_nbr;                /* int32 [nel][8]: +x, +y, +z, +y+z, -x, -y, -z neighbour (-1: none) */
   size_t off_elem3d;             /* int32 [box[2]][box[1]][box[0]]: element at box position (ex, ey, ez) */
-  size_t off_base;               /* int32 [box[2] p + 1][box[1] p + 1]: vertex id of lattice point (0, Y, Z) */
+  size_t off_base;               /* int32 [LZ][LY]: vertex id of lattice point (0, Y, Z) */
   int32_t owner;                 /* 1 if the owner-computes schedule is valid */
   int32_t box[3];                /* elements along x, y, z */
-  size_t reserved[2];
+  size_t reserved[3];
 } lor_sched;
 
 /*

@@ -20,6 +20,6 @@ void clear_error() { g_last_error.clear(); }
 
 extern "C" const char* lor_last_error(void) { return lor::g_last_error.c_str(); }
 
-extern "C" int lor_abi_version(void) { return 2; }
+extern "C" int lor_abi_version(void) { return 3; }
 
 extern "C" size_t lor_sched_bytes(void) { return sizeof(lor_sched); }

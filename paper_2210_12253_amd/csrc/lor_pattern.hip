@@ -56,6 +56,52 @@ struct DevBuf {
   }
 };
 
+static size_t align256(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
+
+// Bump allocator over one device allocation that holds the temporaries of one
+// call, so that no call allocates (and, through hipFree, synchronises) per
+// step.  Slices are handed out in order; release() returns everything taken
+// after a mark.  All work runs on one stream, so a released slice can be
+// handed out again at once.
+struct Arena {
+  DevBuf buf;
+  size_t cap = 0, used = 0;
+  int alloc(size_t bytes) {
+    cap = bytes;
+    used = 0;
+    return buf.alloc(bytes);
+  }
+  template <typename T>
+  T* take(size_t count) {
+    const size_t end = used + align256(sizeof(T) * std::max<size_t>(count, 1));
+    if (end > cap) return nullptr;
+    T* r = reinterpret_cast<T*>(static_cast<char*>(buf.p) + used);
+    used = end;
+    return r;
+  }
+  void release(size_t mark) { used = mark; }
+};
+
+// Releases, on scope exit, everything taken from the arena in the scope.
+struct ArenaScope {
+  Arena& a;
+  size_t mark;
+  explicit ArenaScope(Arena& arena) : a(arena), mark(arena.used) {}
+  ~ArenaScope() { a.release(mark); }
+};
+
+// Bytes an Arena::take of count T's consumes.
+template <typename T>
+static size_t arena_bytes(size_t count) {
+  return align256(sizeof(T) * std::max<size_t>(count, 1));
+}
+
+#define LOR_TAKE(PTR, ARENA, T, N)                                             \
+  do {                                                                         \
+    (PTR) = (ARENA).template take<T>(N);                                       \
+    if (!(PTR)) LOR_FAIL(LOR_EDEVICE, "internal error: scratch arena too small"); \
+  } while (0)
+
 // ---------------------------------------------------------- reference element
 
 struct RefElem {
@@ -363,26 +409,33 @@ __global__ void k_scan_total(const TI* __restrict__ in, int64_t n, int64_t* __re
   if (threadIdx.x == 0 && blockIdx.x == 0) out[n] = (n == 0) ? 0 : out[n - 1] + static_cast<int64_t>(in[n - 1]);
 }
 
-// Exclusive scan of n values into out[0..n], out[n] = total.
+// Scratch bytes of scan_exclusive over n values.
+static size_t scan_ws_bytes(int64_t n) {
+  if (n == 0) return 0;
+  const int64_t nt = ceil_div(n, kScanTile);
+  return 2 * arena_bytes<int64_t>(nt + 1) + (nt > 1 ? scan_ws_bytes(nt) : 0);
+}
+
+// Exclusive scan of n values into out[0..n], out[n] = total; tile sums in
+// scan_ws_bytes(n) bytes of the arena.
 template <typename TI>
-static int scan_exclusive(const TI* in, int64_t n, int64_t* out, hipStream_t st) {
+static int scan_exclusive(const TI* in, int64_t n, int64_t* out, Arena& a, hipStream_t st) {
   if (n == 0) {
     k_scan_total<TI><<<1, 1, 0, st>>>(in, 0, out);
     LOR_LAUNCHED("k_scan_total");
     return LOR_OK;
   }
   const int64_t ntiles = ceil_div(n, kScanTile);
-  DevBuf sums, offs;
-  int rc = sums.alloc(sizeof(int64_t) * (ntiles + 1));
-  if (rc) return rc;
-  rc = offs.alloc(sizeof(int64_t) * (ntiles + 1));
-  if (rc) return rc;
-  k_scan_tiles<TI><<<ntiles, kScanThreads, 0, st>>>(in, n, out, sums.as<int64_t>());
+  ArenaScope scope(a);
+  int64_t *sums, *offs;
+  LOR_TAKE(sums, a, int64_t, ntiles + 1);
+  LOR_TAKE(offs, a, int64_t, ntiles + 1);
+  k_scan_tiles<TI><<<ntiles, kScanThreads, 0, st>>>(in, n, out, sums);
   LOR_LAUNCHED("k_scan_tiles");
   if (ntiles > 1) {
-    rc = scan_exclusive<int64_t>(sums.as<int64_t>(), ntiles, offs.as<int64_t>(), st);
+    const int rc = scan_exclusive<int64_t>(sums, ntiles, offs, a, st);
     if (rc) return rc;
-    k_scan_add<<<ceil_div(n, 256), 256, 0, st>>>(out, n, offs.as<int64_t>());
+    k_scan_add<<<ceil_div(n, 256), 256, 0, st>>>(out, n, offs);
     LOR_LAUNCHED("k_scan_add");
   }
   k_scan_total<TI><<<1, 1, 0, st>>>(in, n, out);
@@ -522,7 +575,7 @@ __global__ void k_jp_round(const int32_t* __restrict__ map, int nloc, int is_sig
                            const int32_t* __restrict__ reps, int nreps,
                            const int32_t* __restrict__ inc_ptr, const int32_t* __restrict__ inc_list,
                            int64_t nel, int32_t* color, int32_t* __restrict__ ncolored,
-                           int32_t* __restrict__ err) {
+                           int32_t* __restrict__ maxcolor, int32_t* __restrict__ err) {
   const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (e >= nel) return;
   if (__hip_atomic_load(&color[e], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= 0) return;
@@ -552,6 +605,7 @@ __global__ void k_jp_round(const int32_t* __restrict__ map, int nloc, int is_sig
   }
   __hip_atomic_store(&color[e], c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   atomicAdd(ncolored, 1);
+  atomicMax(maxcolor, c);
 }
 
 // Every dof's incident elements must carry pairwise different colours.
@@ -578,10 +632,18 @@ __global__ void k_color_flags(const int32_t* __restrict__ color, int64_t nel, in
   if (e < nel) f[e] = (color[e] == c) ? 1 : 0;
 }
 
+// Colour c's elements, in element order, to order[cptr[c] ..]; cptr[c] was
+// written by the previous colour's k_color_next (so no host round trip per
+// colour).
 __global__ void k_color_scatter(const int32_t* __restrict__ color, int64_t nel, int c,
-                                const int64_t* __restrict__ pos, int32_t base, int32_t* __restrict__ order) {
+                                const int64_t* __restrict__ pos, const int32_t* __restrict__ cptr,
+                                int32_t* __restrict__ order) {
   const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (e < nel && color[e] == c) order[base + pos[e]] = static_cast<int32_t>(e);
+  if (e < nel && color[e] == c) order[cptr[c] + pos[e]] = static_cast<int32_t>(e);
+}
+
+__global__ void k_color_next(const int64_t* __restrict__ pos, int64_t nel, int c, int32_t* __restrict__ cptr) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) cptr[c + 1] = cptr[c] + static_cast<int32_t>(pos[nel]);
 }
 
 // Position of every local stencil entry inside its CSR row; lowest colour per nnz.
@@ -674,145 +736,203 @@ __global__ void k_gather_i32(const int32_t* __restrict__ src, const int32_t* __r
 }
 
 
-// ------------------------------------------------ owner-computes schedule (H1)
+// ------------------------------------------------------------ box lattice (H1)
 //
-// The owner-computes value kernel works on the global lattice of a box of
-// elements: lattice point (X, Y, Z) has vertex id base(Y, Z) + X, and the
-// cell (X, Y, Z) belongs to element elem3d(X / p, Y / p, Z / p).  These
-// kernels find each element's face neighbours (same lattice orientation),
-// and, once the host has laid the elements out as a box, check everything
-// the value kernel relies on against the element map and the finished
-// pattern; any failure only marks the mesh as not eligible (the colour
-// schedule is always built).
+// An H1 mesh of degree p is a box lattice when its elements tile a box of
+// nx x ny x nz elements with every element's local axes along the box axes,
+// and the vertex at point (X, Y, Z) of the global lattice of
+// (LX, LY, LZ) = (nx p + 1, ny p + 1, nz p + 1) points has the lexicographic
+// id X + LX (Y + LY Z) -- the structured meshes of the paper's benchmarks,
+// with the elements in any order.  On such a mesh everything the general path
+// searches for has a closed form:
+//   * two lattice points share a subcell of some element exactly when they
+//     differ by at most one along every axis, so the row of (X, Y, Z) holds
+//     the in-box points of its 3 x 3 x 3 neighbourhood, and their ids increase
+//     in (dz, dy, dx) order.  Along one axis a point has 1 + [X > 0] +
+//     [X < LX - 1] neighbours, so row lengths are products of per-axis counts
+//     and the row pointer is a sum of products of their prefix sums;
+//   * colouring elements by the parities of their box position is proper
+//     (elements sharing a vertex differ by at most one along every axis) and
+//     is what the greedy colouring produces for elements in box order;
+//   * the position of an entry in its row depends only on which neighbours
+//     its row point has, and its first contributor only on the colours of the
+//     elements holding both points; for an element both follow from whether it
+//     touches each of the six box faces and from its parities, so elements
+//     agreeing in those share one rank table.
+// The owner-computes value kernel relies on exactly this layout.
 
-enum : int32_t { kOwnAmbiguous = 1, kOwnAsymmetric = 2, kOwnVertex = 4, kOwnRow = 8, kOwnCover = 16 };
+struct BoxLattice {
+  int64_t LX = 0, LY = 0, LZ = 0;
+  int nx = 0, ny = 0, nz = 0;
+};
 
-// Slot of a face direction in the neighbour table: +x, +y, +z, (+y+z), -x, -y, -z.
-__host__ __device__ constexpr int nbr_slot(int ax, int sg) { return sg > 0 ? ax : 4 + ax; }
-
-// One thread per (element, face direction): the element f != e whose lattice
-// continues e's lattice across that face (f's layer 0 is e's layer p for a +
-// direction, and the other way round for a - direction, point by point).
-__global__ void k_owner_nbrs(const int32_t* __restrict__ map, int p, int64_t nel,
-                             const int32_t* __restrict__ inc_ptr, const int32_t* __restrict__ inc_list,
-                             int32_t* __restrict__ nbr, int32_t* __restrict__ flag) {
-  const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (t >= nel * 6) return;
-  const int64_t e = t / 6;
-  const int dir = static_cast<int>(t - e * 6);
-  const int ax = dir % 3, sg = dir < 3 ? 1 : -1;
-  const int q = p + 1, nloc = q * q * q;
-  const int stride[3] = {1, q, q * q};
-  const int le = sg > 0 ? p * stride[ax] : 0;  // corner of e on the face
-  const int lf = sg > 0 ? 0 : p * stride[ax];  // the same point in f
-  const int u1 = stride[(ax + 1) % 3], u2 = stride[(ax + 2) % 3];
-  const int32_t* me = map + e * nloc;
-  const int32_t v = me[le];
-  int32_t found = -1;
-  for (int32_t i = inc_ptr[v]; i < inc_ptr[v + 1]; ++i) {
-    const int32_t f = inc_list[i] / nloc;
-    const int32_t l = inc_list[i] - f * nloc;
-    if (f == e || l != lf) continue;
-    const int32_t* mf = map + static_cast<int64_t>(f) * nloc;
-    bool same = true;
-    for (int a = 0; a <= p && same; ++a)
-      for (int b = 0; b <= p && same; ++b) same = mf[lf + a * u1 + b * u2] == me[le + a * u1 + b * u2];
-    if (!same) continue;
-    if (found >= 0) atomicOr(flag, kOwnAmbiguous);
-    found = f;
-  }
-  nbr[e * 8 + nbr_slot(ax, sg)] = found;
+// Neighbours of a lattice point along one axis of L points (L >= 2), and their
+// sum over the points before X (X in [0, L]).
+__host__ __device__ __forceinline__ int box_count(int64_t X, int64_t L) { return 1 + (X > 0) + (X < L - 1); }
+__host__ __device__ __forceinline__ int64_t box_prefix(int64_t X, int64_t L) {
+  return X == 0 ? 0 : 3 * X - 1 - (X == L ? 1 : 0);
 }
 
-// Diagonal neighbour +y+z (the +z neighbour of the +y neighbour) and the
-// symmetry of the face relation.
-__global__ void k_owner_diag(int64_t nel, int32_t* __restrict__ nbr, int32_t* __restrict__ flag) {
-  const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (e >= nel) return;
-  int32_t* n = nbr + e * 8;
-  for (int ax = 0; ax < 3; ++ax) {
-    const int32_t f = n[nbr_slot(ax, 1)];
-    if (f >= 0 && nbr[static_cast<int64_t>(f) * 8 + nbr_slot(ax, -1)] != e) atomicOr(flag, kOwnAsymmetric);
-    const int32_t g = n[nbr_slot(ax, -1)];
-    if (g >= 0 && nbr[static_cast<int64_t>(g) * 8 + nbr_slot(ax, 1)] != e) atomicOr(flag, kOwnAsymmetric);
-  }
-  const int32_t fy = n[1];
-  n[3] = fy >= 0 ? nbr[static_cast<int64_t>(fy) * 8 + 2] : -1;
-  n[7] = -1;
-}
-
-// base(Y, Z): the vertex id at lattice point (0, Y, Z), read from the element
-// at box position (0, min(Y / p, ny - 1), min(Z / p, nz - 1)).
-__global__ void k_owner_base(const int32_t* __restrict__ map, int p, const int32_t* __restrict__ elem3d, int nx,
-                             int ny, int nz, int32_t* __restrict__ base) {
-  const int ly = ny * p + 1, lz = nz * p + 1;
-  const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (t >= static_cast<int64_t>(ly) * lz) return;
-  const int Y = static_cast<int>(t % ly), Z = static_cast<int>(t / ly);
-  const int ey = min(Y / p, ny - 1), ez = min(Z / p, nz - 1);
+// Element 0's vertices at local (0,0,0), (1,0,0), (0,1,0), (0,0,1): the lattice
+// strides, if the mesh is a box lattice.
+__global__ void k_box_probe(const int32_t* __restrict__ map, int p, int32_t* __restrict__ out) {
   const int q = p + 1;
-  const int32_t e = elem3d[(static_cast<int64_t>(ez) * ny + ey) * nx];
-  base[t] = map[static_cast<int64_t>(e) * q * q * q + q * ((Y - p * ey) + q * (Z - p * ez))];
+  const int i = threadIdx.x;
+  if (i < 4) out[i] = map[i == 0 ? 0 : i == 1 ? 1 : i == 2 ? q : q * q];
 }
 
-// One thread per (box position, local vertex): the vertex id equals
-// base(Y, Z) + X at its global lattice point.
-__global__ void k_owner_verts(const int32_t* __restrict__ map, int p, const int32_t* __restrict__ elem3d, int nx,
-                              int ny, int nz, const int32_t* __restrict__ base, int32_t* __restrict__ flag) {
+// One thread per (element, local vertex): every vertex id must be the
+// lexicographic id of its lattice point, the element's corner a lattice point
+// of the element grid; the element claims its box position (pos3d starts at
+// -1), and a position claimed twice marks the mesh as no box lattice.  With
+// nel = nx ny nz elements placed at distinct positions, every position is
+// taken.
+__global__ void k_box_place(const int32_t* __restrict__ map, int p, int64_t nel, int64_t LX, int64_t LY, int64_t LZ,
+                            int nx, int ny, int32_t* __restrict__ elem3d, int32_t* __restrict__ flag) {
   const int q = p + 1, nloc = q * q * q;
   const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  const int64_t nel = static_cast<int64_t>(nx) * ny * nz;
   if (t >= nel * nloc) return;
-  const int64_t pos = t / nloc;
-  const int l = static_cast<int>(t - pos * nloc);
-  const int ex = static_cast<int>(pos % nx), ey = static_cast<int>((pos / nx) % ny), ez = static_cast<int>(pos / (static_cast<int64_t>(nx) * ny));
-  const int X = p * ex + l % q, Y = p * ey + (l / q) % q, Z = p * ez + l / (q * q);
+  const int64_t e = t / nloc;
+  const int l = static_cast<int>(t - e * nloc);
+  const int64_t v0 = map[e * nloc];
+  const int64_t X0 = v0 % LX, Y0 = (v0 / LX) % LY, Z0 = v0 / (LX * LY);
+  bool bad = v0 < 0 || Z0 >= LZ || X0 % p != 0 || Y0 % p != 0 || Z0 % p != 0 || X0 + p >= LX || Y0 + p >= LY ||
+             Z0 + p >= LZ;
+  const int lx = l % q, ly = (l / q) % q, lz = l / (q * q);
+  bad = bad || map[t] != v0 + lx + LX * (ly + LY * lz);
+  if (!bad && l == 0) {
+    const int64_t pos = ((Z0 / p) * ny + Y0 / p) * nx + X0 / p;
+    bad = atomicCAS(&elem3d[pos], -1, static_cast<int32_t>(e)) != -1;
+  }
+  // one atomic per wave at most (a mesh that is no box lattice fails almost
+  // everywhere)
+  const uint64_t m = __ballot(bad);
+  if (m != 0 && (threadIdx.x & 63) == static_cast<unsigned>(__ffsll(static_cast<long long>(m)) - 1))
+    atomicOr(flag, 1);
+}
+
+// Row pointer of the lattice pattern, entries [0, nrows].
+__global__ void k_box_row_ptr(int64_t LX, int64_t LY, int64_t LZ, int32_t* __restrict__ row_ptr) {
+  const int64_t n = LX * LY * LZ;
+  const int64_t v = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (v > n) return;
+  const int64_t SX = 3 * LX - 2, SY = 3 * LY - 2, SZ = 3 * LZ - 2;
+  if (v == n) {
+    row_ptr[v] = static_cast<int32_t>(SX * SY * SZ);
+    return;
+  }
+  const int64_t X = v % LX, Y = (v / LX) % LY, Z = v / (LX * LY);
+  const int64_t cz = box_count(Z, LZ), cyz = box_count(Y, LY) * cz;
+  row_ptr[v] = static_cast<int32_t>(box_prefix(Z, LZ) * SY * SX + cz * box_prefix(Y, LY) * SX +
+                                    cyz * box_prefix(X, LX));
+}
+
+// Columns of one lattice line (Y, Z) per workgroup: the line's rows are
+// consecutive, and so are their entries; consecutive threads write
+// consecutive entries.  Entry o of the line belongs to row X, where the rows
+// before X hold (3X - 1) cyz entries; inside a row, entries run in
+// (dz, dy, dx) order.  The caller's row pointer is checked against the
+// lattice's.
+constexpr int kBoxColThreads = 256;
+__global__ __launch_bounds__(kBoxColThreads) void k_box_cols(int64_t LX, int64_t LY, int64_t LZ,
+                                                             const int32_t* __restrict__ row_ptr,
+                                                             int32_t* __restrict__ col_idx,
+                                                             int32_t* __restrict__ err) {
+  const int64_t line = blockIdx.x;
+  const int64_t Y = line % LY, Z = line / LY;
+  const int cy = box_count(Y, LY), cz = box_count(Z, LZ), cyz = cy * cz;
+  const int64_t SX = 3 * LX - 2, SY = 3 * LY - 2;
+  const int64_t start = box_prefix(Z, LZ) * SY * SX + cz * box_prefix(Y, LY) * SX;
+  const int64_t v0 = line * LX;
+  bool bad = false;
+  for (int64_t X = threadIdx.x; X <= LX; X += kBoxColThreads)
+    bad = bad || row_ptr[v0 + X] != start + cyz * box_prefix(X, LX);
+  if (bad) atomicOr(err, kErrRowCount);
+  const int ylo = Y > 0, zlo = Z > 0;
+  const int total = static_cast<int>(SX) * cyz;
+  const int64_t lx = LX;
+  for (int o = threadIdx.x; o < total; o += kBoxColThreads) {
+    const int X = (o + cyz) / (3 * cyz);
+    const int xlo = X > 0, cx = 1 + xlo + (X < lx - 1);
+    const int u = o - (X == 0 ? 0 : (3 * X - 1) * cyz);
+    const int izy = u / cx, ix = u - izy * cx;
+    const int iz = izy / cy, iy = izy - iz * cy;
+    const int64_t col = ((Z + iz - zlo) * LY + (Y + iy - ylo)) * LX + (X + ix - xlo);
+    col_idx[start + o] = static_cast<int32_t>(col);
+  }
+}
+
+// Per box position: the element's colour (parities, over the axes with more
+// than one element) and its table class key (per axis: touches the low face,
+// touches the high face, parity).
+__global__ void k_box_color_key(const int32_t* __restrict__ elem3d, int nx, int ny, int nz, int wx, int wy, int wz,
+                                int32_t* __restrict__ color, int32_t* __restrict__ key) {
+  const int64_t pos = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (pos >= static_cast<int64_t>(nx) * ny * nz) return;
+  const int ex = static_cast<int>(pos % nx), ey = static_cast<int>((pos / nx) % ny);
+  const int ez = static_cast<int>(pos / (static_cast<int64_t>(nx) * ny));
   const int32_t e = elem3d[pos];
-  if (map[static_cast<int64_t>(e) * nloc + l] != base[static_cast<int64_t>(Z) * (ny * p + 1) + Y] + X)
-    atomicOr(flag, kOwnVertex);
+  color[e] = (ex & 1) * wx + (ey & 1) * wy + (ez & 1) * wz;
+  auto axis = [](int c, int n) { return (c == 0 ? 1 : 0) | (c == n - 1 ? 2 : 0) | ((c & 1) << 2); };
+  key[e] = axis(ex, nx) | (axis(ey, ny) << 3) | (axis(ez, nz) << 6);
 }
 
-// One thread per lattice point: the row of its vertex holds exactly the
-// lattice neighbours present, in (dz, dy, dx) order (which must therefore be
-// increasing), and every vertex is reached once.
-__global__ void k_owner_rows(int p, int nx, int ny, int nz, const int32_t* __restrict__ base, int64_t nrows,
-                             const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col_idx,
-                             int32_t* __restrict__ hit, int32_t* __restrict__ flag) {
-  const int LX = nx * p + 1, LY = ny * p + 1, LZ = nz * p + 1;
+// Rank table of class c from its representative element rep[c]: position of
+// every stencil entry in its row, and the first-contributor bit (the
+// element's colour is the lowest among the elements holding both points of
+// the entry; on a box lattice every element holding both has the entry).
+// Padding bytes of the table are zeroed.
+__global__ void k_box_rank(const int32_t* __restrict__ map, int nloc, int nent, int64_t stride,
+                           const uint16_t* __restrict__ ent_row, const int32_t* __restrict__ ent_col,
+                           const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col_idx,
+                           const int32_t* __restrict__ color, const int32_t* __restrict__ inc_ptr,
+                           const int32_t* __restrict__ inc_list, const int32_t* __restrict__ rep, int64_t ncls,
+                           uint8_t* __restrict__ tables, int32_t* __restrict__ err) {
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= ncls * stride) return;
+  const int64_t c = idx / stride;
+  const int k = static_cast<int>(idx - c * stride);
+  uint8_t* tab = tables + idx;
+  if (k >= nent) {
+    *tab = 0;
+    return;
+  }
+  const int32_t e = rep[c];
+  const int32_t* me = map + static_cast<int64_t>(e) * nloc;
+  const int32_t g = me[ent_row[k]], col = me[ent_col[k]];
+  int32_t lo = row_ptr[g], hi = row_ptr[g + 1];
+  const int32_t start = lo;
+  while (lo < hi) {
+    const int32_t mid = (lo + hi) >> 1;
+    if (col_idx[mid] < col)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  if (lo >= row_ptr[g + 1] || col_idx[lo] != col) {
+    atomicOr(err, kErrRankMissing);
+    *tab = 0;
+    return;
+  }
+  int32_t lowest = INT32_MAX;
+  for (int32_t i = inc_ptr[g]; i < inc_ptr[g + 1]; ++i) {
+    const int32_t f = inc_list[i] / nloc;
+    for (int32_t j = inc_ptr[col]; j < inc_ptr[col + 1]; ++j)
+      if (inc_list[j] / nloc == f) {
+        lowest = min(lowest, color[f]);
+        break;
+      }
+  }
+  *tab = static_cast<uint8_t>((lo - start) | (lowest == color[e] ? kFirstBit : 0));
+}
+
+// base(Y, Z) = id of lattice point (0, Y, Z), read by the owner-computes kernel.
+__global__ void k_box_base(int64_t LX, int64_t nlines, int32_t* __restrict__ base) {
   const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (t >= static_cast<int64_t>(LX) * LY * LZ) return;
-  const int X = static_cast<int>(t % LX), Y = static_cast<int>((t / LX) % LY);
-  const int Z = static_cast<int>(t / (static_cast<int64_t>(LX) * LY));
-  const int64_t v = static_cast<int64_t>(base[static_cast<int64_t>(Z) * LY + Y]) + X;
-  if (v < 0 || v >= nrows) {
-    atomicOr(flag, kOwnRow);
-    return;
-  }
-  atomicAdd(&hit[v], 1);
-  const int xlo = X > 0, xhi = X < LX - 1, ylo = Y > 0, yhi = Y < LY - 1, zlo = Z > 0, zhi = Z < LZ - 1;
-  const int32_t rb = row_ptr[v];
-  if (row_ptr[v + 1] - rb != (1 + xlo + xhi) * (1 + ylo + yhi) * (1 + zlo + zhi)) {
-    atomicOr(flag, kOwnRow);
-    return;
-  }
-  int k = 0;
-  for (int dz = -zlo; dz <= zhi; ++dz)
-    for (int dy = -ylo; dy <= yhi; ++dy)
-      for (int dx = -xlo; dx <= xhi; ++dx, ++k)
-        if (col_idx[rb + k] != base[static_cast<int64_t>(Z + dz) * LY + Y + dy] + X + dx) {
-          atomicOr(flag, kOwnRow);
-          return;
-        }
-}
-
-__global__ void k_owner_cover(const int32_t* __restrict__ hit, int64_t nrows, int32_t* __restrict__ flag) {
-  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i < nrows && hit[i] != 1) atomicOr(flag, kOwnCover);
+  if (t < nlines) base[t] = static_cast<int32_t>(t * LX);
 }
 
 // --------------------------------------------------------------- host side
-
-static size_t align256(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
 
 template <typename T>
 static int upload(const std::vector<T>& v, void* dst, hipStream_t st) {
@@ -841,117 +961,10 @@ static size_t layout(lor_sched* s, const RefElem& r) {
   s->off_recipe = take(sizeof(uint64_t) * std::max<size_t>(1, r.recipe64.size()));
   s->off_zero = take(256);
   s->off_order_class = take(sizeof(int32_t) * s->nel);
-  s->off_nbr = take(sizeof(int32_t) * 8 * s->nel);
   s->off_elem3d = take(sizeof(int32_t) * s->nel);
   // a box has (LY)(LZ) = nrows / LX lattice lines along x, and LX >= p + 1
   s->off_base = take(sizeof(int32_t) * (s->nrows / (s->p + 1) + 1));
   return off;
-}
-
-// Owner-computes schedule of an H1 mesh: face neighbours, the box layout of
-// the elements, base(Y, Z), and the checks of the value kernel's
-// assumptions.  Leaves sched->owner = 0 if the mesh is not eligible; returns
-// an error only for device failures.
-static int build_owner(lor_sched* s, const int32_t* map, const int32_t* row_ptr, const int32_t* col_idx,
-                       hipStream_t st) {
-  s->owner = 0;
-  s->box[0] = s->box[1] = s->box[2] = 0;
-  const int64_t nel = s->nel;
-  const int p = s->p;
-  if (nel == 0 || s->space != LOR_H1) return LOR_OK;
-  int32_t* d_nbr = dev_at<int32_t>(s, s->off_nbr);
-  DevBuf flag;
-  int rc;
-  if ((rc = flag.alloc(sizeof(int32_t)))) return rc;
-  LOR_HIP(hipMemsetAsync(flag.p, 0, sizeof(int32_t), st));
-  k_owner_nbrs<<<ceil_div(nel * 6, 256), 256, 0, st>>>(map, p, nel, dev_at<int32_t>(s, s->off_inc_ptr),
-                                                       dev_at<int32_t>(s, s->off_inc_list), d_nbr, flag.as<int32_t>());
-  LOR_LAUNCHED("k_owner_nbrs");
-  k_owner_diag<<<ceil_div(nel, 256), 256, 0, st>>>(nel, d_nbr, flag.as<int32_t>());
-  LOR_LAUNCHED("k_owner_diag");
-  int32_t hflag = 0;
-  std::vector<int32_t> nb(static_cast<size_t>(nel) * 8);
-  LOR_HIP(hipMemcpyAsync(&hflag, flag.p, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-  LOR_HIP(hipMemcpyAsync(nb.data(), d_nbr, sizeof(int32_t) * nb.size(), hipMemcpyDeviceToHost, st));
-  LOR_HIP(hipStreamSynchronize(st));
-  if (hflag != 0) return LOR_OK;
-  // box layout: from the one element without -x, -y, -z neighbours, walk +x,
-  // +y and +z; every element must be reached exactly once and its neighbours
-  // must be its box neighbours
-  auto N = [&](int64_t e, int slot) { return nb[static_cast<size_t>(e) * 8 + slot]; };
-  int64_t corner = -1;
-  for (int64_t e = 0; e < nel; ++e)
-    if (N(e, 4) < 0 && N(e, 5) < 0 && N(e, 6) < 0) {
-      if (corner >= 0) return LOR_OK;
-      corner = e;
-    }
-  if (corner < 0) return LOR_OK;
-  int64_t dims[3] = {0, 0, 0};
-  for (int ax = 0; ax < 3; ++ax)
-    for (int64_t e = corner; e >= 0 && dims[ax] <= nel; e = N(e, ax)) ++dims[ax];
-  if (dims[0] * dims[1] * dims[2] != nel) return LOR_OK;
-  const int64_t nx = dims[0], ny = dims[1], nz = dims[2];
-  std::vector<int32_t> e3(static_cast<size_t>(nel), -1);
-  std::vector<char> seen(static_cast<size_t>(nel), 0);
-  for (int64_t ez = 0; ez < nz; ++ez)
-    for (int64_t ey = 0; ey < ny; ++ey) {
-      const size_t at = static_cast<size_t>((ez * ny + ey) * nx);
-      int64_t e = ez == 0 && ey == 0 ? corner : ey == 0 ? N(e3[at - nx * ny], 2) : N(e3[at - nx], 1);
-      for (int64_t ex = 0; ex < nx; ++ex) {
-        if (e < 0 || seen[e]) return LOR_OK;
-        seen[e] = 1;
-        e3[at + ex] = static_cast<int32_t>(e);
-        e = N(e, 0);
-      }
-      if (e >= 0) return LOR_OK;
-    }
-  for (int64_t ez = 0; ez < nz; ++ez)
-    for (int64_t ey = 0; ey < ny; ++ey)
-      for (int64_t ex = 0; ex < nx; ++ex) {
-        const int64_t e = e3[(ez * ny + ey) * nx + ex];
-        const int64_t c[3] = {ex, ey, ez}, n[3] = {nx, ny, nz};
-        for (int ax = 0; ax < 3; ++ax) {
-          int64_t up = -1, dn = -1;
-          int64_t cc[3] = {c[0], c[1], c[2]};
-          if (c[ax] + 1 < n[ax]) {
-            cc[ax] = c[ax] + 1;
-            up = e3[(cc[2] * ny + cc[1]) * nx + cc[0]];
-          }
-          cc[ax] = c[ax] - 1;
-          if (c[ax] > 0) dn = e3[(cc[2] * ny + cc[1]) * nx + cc[0]];
-          if (N(e, nbr_slot(ax, 1)) != up || N(e, nbr_slot(ax, -1)) != dn) return LOR_OK;
-        }
-      }
-  if (nx * p + 1 > INT32_MAX || ny * p + 1 > INT32_MAX || nz * p + 1 > INT32_MAX) return LOR_OK;
-  const int64_t LX = nx * p + 1, LY = ny * p + 1, LZ = nz * p + 1;
-  if (LX * LY * LZ != s->nrows || LY * LZ > s->nrows / (p + 1) + 1) return LOR_OK;
-  int32_t* d_e3 = dev_at<int32_t>(s, s->off_elem3d);
-  int32_t* d_base = dev_at<int32_t>(s, s->off_base);
-  if ((rc = upload(e3, d_e3, st))) return rc;
-  k_owner_base<<<ceil_div(LY * LZ, 256), 256, 0, st>>>(map, p, d_e3, static_cast<int>(nx), static_cast<int>(ny),
-                                                     static_cast<int>(nz), d_base);
-  LOR_LAUNCHED("k_owner_base");
-  k_owner_verts<<<ceil_div(nel * nloc_h1(p), 256), 256, 0, st>>>(map, p, d_e3, static_cast<int>(nx),
-                                                                 static_cast<int>(ny), static_cast<int>(nz), d_base,
-                                                                 flag.as<int32_t>());
-  LOR_LAUNCHED("k_owner_verts");
-  DevBuf hit;
-  if ((rc = hit.alloc(sizeof(int32_t) * s->nrows))) return rc;
-  LOR_HIP(hipMemsetAsync(hit.p, 0, sizeof(int32_t) * s->nrows, st));
-  k_owner_rows<<<ceil_div(s->nrows, 256), 256, 0, st>>>(p, static_cast<int>(nx), static_cast<int>(ny),
-                                                        static_cast<int>(nz), d_base, s->nrows, row_ptr, col_idx,
-                                                        hit.as<int32_t>(), flag.as<int32_t>());
-  LOR_LAUNCHED("k_owner_rows");
-  k_owner_cover<<<ceil_div(s->nrows, 256), 256, 0, st>>>(hit.as<int32_t>(), s->nrows, flag.as<int32_t>());
-  LOR_LAUNCHED("k_owner_cover");
-  LOR_HIP(hipMemcpyAsync(&hflag, flag.p, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-  LOR_HIP(hipStreamSynchronize(st));
-  if (hflag != 0) return LOR_OK;
-  s->box[0] = static_cast<int32_t>(nx);
-  s->box[1] = static_cast<int32_t>(ny);
-  s->box[2] = static_cast<int32_t>(nz);
-  s->owner = 1;
-  return LOR_OK;
 }
 
 static int read_err(const int32_t* d_err, hipStream_t st, int32_t* h) {
@@ -971,32 +984,330 @@ static int report_err(int32_t e) {
   return LOR_OK;
 }
 
+// Scratch bytes of build_incidence.
+static size_t incidence_ws_bytes(int64_t nrows) {
+  return arena_bytes<int32_t>(nrows + 1) + arena_bytes<int64_t>(nrows + 1) + scan_ws_bytes(nrows);
+}
+
 // Incidence lists (transpose of the element map) into inc_ptr / inc_list.
 static int build_incidence(const int32_t* map, int64_t nel, int nloc, int is_signed, int64_t nrows,
-                           int32_t* inc_ptr, int32_t* inc_list, int32_t* d_err, hipStream_t st) {
+                           int32_t* inc_ptr, int32_t* inc_list, int32_t* d_err, Arena& a, hipStream_t st) {
   const int64_t total = nel * nloc;
-  DevBuf cnt, ptr64;
-  int rc = cnt.alloc(sizeof(int32_t) * (nrows + 1));
-  if (rc) return rc;
-  rc = ptr64.alloc(sizeof(int64_t) * (nrows + 1));
-  if (rc) return rc;
-  LOR_HIP(hipMemsetAsync(cnt.p, 0, sizeof(int32_t) * (nrows + 1), st));
+  ArenaScope scope(a);
+  int32_t* cnt;
+  int64_t* ptr64;
+  LOR_TAKE(cnt, a, int32_t, nrows + 1);
+  LOR_TAKE(ptr64, a, int64_t, nrows + 1);
+  LOR_HIP(hipMemsetAsync(cnt, 0, sizeof(int32_t) * (nrows + 1), st));
   if (total > 0) {
-    k_count_inc<<<ceil_div(total, 256), 256, 0, st>>>(map, total, nrows, is_signed, cnt.as<int32_t>(), d_err);
+    k_count_inc<<<ceil_div(total, 256), 256, 0, st>>>(map, total, nrows, is_signed, cnt, d_err);
     LOR_LAUNCHED("k_count_inc");
   }
-  rc = scan_exclusive<int32_t>(cnt.as<int32_t>(), nrows, ptr64.as<int64_t>(), st);
+  int rc = scan_exclusive<int32_t>(cnt, nrows, ptr64, a, st);
   if (rc) return rc;
-  k_i64_to_i32<<<ceil_div(nrows + 1, 256), 256, 0, st>>>(ptr64.as<int64_t>(), nrows + 1, inc_ptr);
+  k_i64_to_i32<<<ceil_div(nrows + 1, 256), 256, 0, st>>>(ptr64, nrows + 1, inc_ptr);
   LOR_LAUNCHED("k_i64_to_i32");
-  LOR_HIP(hipMemsetAsync(cnt.p, 0, sizeof(int32_t) * (nrows + 1), st));
+  LOR_HIP(hipMemsetAsync(cnt, 0, sizeof(int32_t) * (nrows + 1), st));
   if (total > 0) {
-    k_fill_inc<<<ceil_div(total, 256), 256, 0, st>>>(map, total, nrows, is_signed, inc_ptr,
-                                                     cnt.as<int32_t>(), inc_list);
+    k_fill_inc<<<ceil_div(total, 256), 256, 0, st>>>(map, total, nrows, is_signed, inc_ptr, cnt, inc_list);
     LOR_LAUNCHED("k_fill_inc");
   }
   k_sort_inc<<<ceil_div(nrows, 256), 256, 0, st>>>(inc_ptr, inc_list, nrows);
   LOR_LAUNCHED("k_sort_inc");
+  return LOR_OK;
+}
+
+// Box-lattice detection of an H1 mesh (see the box lattice kernels): the
+// lattice strides from element 0, then every element checked and placed in
+// elem3d (nel int32, device).  *found is false when the mesh is no box
+// lattice; an error is returned only for device failures.
+static int find_box(const int32_t* map, int p, int64_t nel, int64_t nrows, int32_t* elem3d, Arena& a,
+                    hipStream_t st, BoxLattice* box, bool* found) {
+  *found = false;
+  if (nel == 0) return LOR_OK;
+  ArenaScope scope(a);
+  int32_t* probe;
+  LOR_TAKE(probe, a, int32_t, 5);
+  int rc;
+  k_box_probe<<<1, 64, 0, st>>>(map, p, probe);
+  LOR_LAUNCHED("k_box_probe");
+  int32_t h[4];
+  LOR_HIP(hipMemcpyAsync(h, probe, sizeof(h), hipMemcpyDeviceToHost, st));
+  LOR_HIP(hipStreamSynchronize(st));
+  const int64_t q = p + 1;
+  const int64_t LX = static_cast<int64_t>(h[2]) - h[0], LXY = static_cast<int64_t>(h[3]) - h[0];
+  if (static_cast<int64_t>(h[1]) - h[0] != 1 || LX < q || LXY < LX * q || LXY % LX != 0 || nrows % LXY != 0)
+    return LOR_OK;
+  const int64_t LY = LXY / LX, LZ = nrows / LXY;
+  if (LZ < q || (LX - 1) % p != 0 || (LY - 1) % p != 0 || (LZ - 1) % p != 0) return LOR_OK;
+  const int64_t nx = (LX - 1) / p, ny = (LY - 1) / p, nz = (LZ - 1) / p;
+  if (nx * ny * nz != nel) return LOR_OK;
+  int32_t* flag = probe + 4;
+  LOR_HIP(hipMemsetAsync(flag, 0, sizeof(int32_t), st));
+  k_fill_i32<<<ceil_div(nel, 256), 256, 0, st>>>(elem3d, nel, -1);
+  LOR_LAUNCHED("k_fill_i32");
+  k_box_place<<<ceil_div(nel * q * q * q, 256), 256, 0, st>>>(map, p, nel, LX, LY, LZ, static_cast<int>(nx),
+                                                              static_cast<int>(ny), elem3d, flag);
+  LOR_LAUNCHED("k_box_place");
+  int32_t hflag = 0;
+  if ((rc = read_err(flag, st, &hflag))) return rc;
+  if (hflag != 0) return LOR_OK;
+  box->LX = LX;
+  box->LY = LY;
+  box->LZ = LZ;
+  box->nx = static_cast<int>(nx);
+  box->ny = static_cast<int>(ny);
+  box->nz = static_cast<int>(nz);
+  *found = true;
+  return LOR_OK;
+}
+
+static int order_by_color(lor_sched* s, int64_t nel, int nc, Arena& a, hipStream_t st);
+
+// Distinct class keys of k_box_color_key (9 bits).
+constexpr int kBoxKeys = 512;
+
+static int64_t box_nnz(const BoxLattice& b) { return (3 * b.LX - 2) * (3 * b.LY - 2) * (3 * b.LZ - 2); }
+
+// Phase 2 on a box lattice: columns, colours, one rank table per class, the
+// owner-computes fields.  elem3d (in the schedule) is filled by find_box.
+static int box_schedule(lor_sched* s, const RefElem& ref, const BoxLattice& b, const int32_t* map,
+                        const int32_t* row_ptr, int32_t* col_idx, int32_t* d_err, Arena& a, hipStream_t st) {
+  const int64_t nel = s->nel;
+  int rc;
+  int32_t herr = 0;
+  k_box_cols<<<b.LY * b.LZ, kBoxColThreads, 0, st>>>(b.LX, b.LY, b.LZ, row_ptr, col_idx, d_err);
+  LOR_LAUNCHED("k_box_cols");
+  // colours from the parities of the axes with more than one element
+  int w = 1;
+  const int wx = b.nx > 1 ? w : 0;
+  w <<= b.nx > 1;
+  const int wy = b.ny > 1 ? w : 0;
+  w <<= b.ny > 1;
+  const int wz = b.nz > 1 ? w : 0;
+  w <<= b.nz > 1;  // number of colours
+  int32_t* d_color = dev_at<int32_t>(s, s->off_color);
+  int32_t* d_class = dev_at<int32_t>(s, s->off_class);
+  const int32_t* d_e3 = dev_at<int32_t>(s, s->off_elem3d);
+  k_box_color_key<<<ceil_div(nel, 256), 256, 0, st>>>(d_e3, b.nx, b.ny, b.nz, wx, wy, wz, d_color, d_class);
+  LOR_LAUNCHED("k_box_color_key");
+  if ((rc = order_by_color(s, nel, w, a, st))) return rc;
+  // classes numbered by first appearance in element order, the first element
+  // of a class its representative
+  std::vector<int32_t> key(static_cast<size_t>(nel)), rep;
+  LOR_HIP(hipMemcpyAsync(key.data(), d_class, sizeof(int32_t) * nel, hipMemcpyDeviceToHost, st));
+  LOR_HIP(hipStreamSynchronize(st));
+  std::vector<int32_t> cls_of_key(kBoxKeys, -1);
+  for (int64_t e = 0; e < nel; ++e) {
+    int32_t& c = cls_of_key[key[e]];
+    if (c < 0) {
+      c = static_cast<int32_t>(rep.size());
+      rep.push_back(static_cast<int32_t>(e));
+    }
+    key[e] = c;
+  }
+  const int64_t ncls = static_cast<int64_t>(rep.size());
+  ArenaScope scope(a);
+  int32_t* drep;
+  LOR_TAKE(drep, a, int32_t, kBoxKeys);
+  if ((rc = upload(key, d_class, st))) return rc;
+  if ((rc = upload(rep, drep, st))) return rc;
+  k_box_rank<<<ceil_div(ncls * s->tab_stride, 256), 256, 0, st>>>(
+      map, s->nloc, ref.nent, s->tab_stride, dev_at<uint16_t>(s, s->off_ent_row), dev_at<int32_t>(s, s->off_st_col),
+      row_ptr, col_idx, d_color, dev_at<int32_t>(s, s->off_inc_ptr), dev_at<int32_t>(s, s->off_inc_list),
+      drep, ncls, dev_at<uint8_t>(s, s->off_tables), d_err);
+  LOR_LAUNCHED("k_box_rank");
+  k_gather_i32<<<ceil_div(nel, 256), 256, 0, st>>>(d_class, dev_at<int32_t>(s, s->off_order), nel,
+                                                  dev_at<int32_t>(s, s->off_order_class));
+  LOR_LAUNCHED("k_gather_i32");
+  const int64_t nlines = b.LY * b.LZ;
+  k_box_base<<<ceil_div(nlines, 256), 256, 0, st>>>(b.LX, nlines, dev_at<int32_t>(s, s->off_base));
+  LOR_LAUNCHED("k_box_base");
+  if ((rc = read_err(d_err, st, &herr))) return rc;
+  if ((rc = report_err(herr))) return rc;
+  s->nclass = ncls;
+  s->box[0] = b.nx;
+  s->box[1] = b.ny;
+  s->box[2] = b.nz;
+  s->owner = 1;
+  return LOR_OK;
+}
+
+// Scratch bytes of order_by_color.
+static size_t order_ws_bytes(int64_t nel) {
+  return arena_bytes<int32_t>(nel) + arena_bytes<int64_t>(nel + 1) + arena_bytes<int32_t>(LOR_MAX_COLORS + 1) +
+         scan_ws_bytes(nel);
+}
+
+// Element order by colour (stable: within a colour, by element index) and the
+// colour pointer, for colours 0 .. nc - 1 (every element's colour below nc).
+static int order_by_color(lor_sched* s, int64_t nel, int nc, Arena& a, hipStream_t st) {
+  for (int c = 0; c <= LOR_MAX_COLORS; ++c) s->color_ptr[c] = 0;
+  s->ncolors = 0;
+  if (nel == 0) return LOR_OK;
+  if (nc < 1 || nc > LOR_MAX_COLORS) LOR_FAIL(LOR_EUNSUPPORTED, "%d colours (at most %d)", nc, LOR_MAX_COLORS);
+  int32_t* d_color = dev_at<int32_t>(s, s->off_color);
+  int32_t* d_order = dev_at<int32_t>(s, s->off_order);
+  ArenaScope scope(a);
+  int32_t *flags, *cptr;
+  int64_t* pos;
+  LOR_TAKE(flags, a, int32_t, nel);
+  LOR_TAKE(pos, a, int64_t, nel + 1);
+  LOR_TAKE(cptr, a, int32_t, LOR_MAX_COLORS + 1);
+  k_fill_i32<<<1, 64, 0, st>>>(cptr, 1, 0);
+  LOR_LAUNCHED("k_fill_i32");
+  int rc;
+  for (int c = 0; c < nc; ++c) {
+    k_color_flags<<<ceil_div(nel, 256), 256, 0, st>>>(d_color, nel, c, flags);
+    LOR_LAUNCHED("k_color_flags");
+    if ((rc = scan_exclusive<int32_t>(flags, nel, pos, a, st))) return rc;
+    k_color_scatter<<<ceil_div(nel, 256), 256, 0, st>>>(d_color, nel, c, pos, cptr, d_order);
+    LOR_LAUNCHED("k_color_scatter");
+    k_color_next<<<1, 64, 0, st>>>(pos, nel, c, cptr);
+    LOR_LAUNCHED("k_color_next");
+  }
+  int32_t h[LOR_MAX_COLORS + 1];
+  LOR_HIP(hipMemcpyAsync(h, cptr, sizeof(int32_t) * (nc + 1), hipMemcpyDeviceToHost, st));
+  LOR_HIP(hipStreamSynchronize(st));
+  if (h[nc] != nel) LOR_FAIL(LOR_EDEVICE, "colour order incomplete");
+  for (int c = 0; c <= nc; ++c) s->color_ptr[c] = h[c];
+  for (int c = nc + 1; c <= LOR_MAX_COLORS; ++c) s->color_ptr[c] = h[nc];
+  s->ncolors = nc;
+  return LOR_OK;
+}
+
+// Jones-Plassmann rounds launched between two reads of the colouring
+// progress (rounds after the last element is coloured return at once).
+constexpr int kJpRoundsPerCheck = 16;
+
+// Phase 2 on any mesh: columns from the incidence lists, greedy colouring,
+// rank tables of every element, then one stored table per distinct table.
+static int general_schedule(lor_sched* s, const RefElem& ref, int is_signed, const int32_t* map,
+                            const int32_t* row_ptr, int32_t* col_idx, int32_t* d_err, Arena& a, hipStream_t st) {
+  const int64_t nel = s->nel, nrows = s->nrows, nnzv = s->nnz;
+  const int nloc = s->nloc;
+  int32_t* d_color = dev_at<int32_t>(s, s->off_color);
+  int32_t* d_class = dev_at<int32_t>(s, s->off_class);
+  uint8_t* d_tab = dev_at<uint8_t>(s, s->off_tables);
+  const int32_t* d_inc_ptr = dev_at<int32_t>(s, s->off_inc_ptr);
+  const int32_t* d_inc_list = dev_at<int32_t>(s, s->off_inc_list);
+  int rc;
+  int32_t herr = 0;
+  int ncolors = 0;
+  k_row_cols<true><<<ceil_div(nrows, kRowThreads), kRowThreads, 0, st>>>(
+      map, nloc, is_signed, d_inc_ptr, d_inc_list, dev_at<int32_t>(s, s->off_st_ptr),
+      dev_at<int32_t>(s, s->off_st_col), nrows, nullptr, row_ptr, col_idx, d_err);
+  LOR_LAUNCHED("k_row_cols<fill>");
+  if ((rc = read_err(d_err, st, &herr))) return rc;
+  if ((rc = report_err(herr))) return rc;
+
+  // colouring
+  int32_t *reps, *ncol;
+  {
+    ArenaScope scope(a);
+    LOR_TAKE(reps, a, int32_t, ref.reps.size());
+    LOR_TAKE(ncol, a, int32_t, 2);  // coloured elements, highest colour
+    if ((rc = upload(ref.reps, reps, st))) return rc;
+    k_fill_i32<<<1, 64, 0, st>>>(ncol, 2, 0);
+    LOR_LAUNCHED("k_fill_i32");
+    if (nel > 0) {
+      k_fill_i32<<<ceil_div(nel, 256), 256, 0, st>>>(d_color, nel, -1);
+      LOR_LAUNCHED("k_fill_i32");
+    }
+    int32_t colored[2] = {0, 0};
+    for (int64_t round = 0; colored[0] < nel; round += kJpRoundsPerCheck) {
+      if (round > nel) LOR_FAIL(LOR_EDEVICE, "element colouring did not converge");
+      for (int r = 0; r < kJpRoundsPerCheck; ++r) {
+        k_jp_round<<<ceil_div(nel, 256), 256, 0, st>>>(map, nloc, is_signed, reps, static_cast<int>(ref.reps.size()),
+                                                       d_inc_ptr, d_inc_list, nel, d_color, ncol, ncol + 1, d_err);
+        LOR_LAUNCHED("k_jp_round");
+      }
+      LOR_HIP(hipMemcpyAsync(colored, ncol, sizeof(colored), hipMemcpyDeviceToHost, st));
+      if ((rc = read_err(d_err, st, &herr))) return rc;
+      if ((rc = report_err(herr))) return rc;
+    }
+    ncolors = nel > 0 ? colored[1] + 1 : 0;
+  }
+  k_check_colors<<<ceil_div(nrows, 256), 256, 0, st>>>(d_inc_ptr, d_inc_list, nloc, nrows, d_color, d_err);
+  LOR_LAUNCHED("k_check_colors");
+  if ((rc = read_err(d_err, st, &herr))) return rc;
+  if ((rc = report_err(herr))) return rc;
+  if ((rc = order_by_color(s, nel, ncolors, a, st))) return rc;
+
+  // rank tables
+  {
+    DevBuf mincol;
+    if ((rc = mincol.alloc(sizeof(int32_t) * std::max<int64_t>(1, nnzv)))) return rc;
+    const int64_t tot = nel * ref.nent;
+    k_fill_i32<<<ceil_div(std::max<int64_t>(1, nnzv), 256), 256, 0, st>>>(mincol.as<int32_t>(), nnzv, INT32_MAX);
+    LOR_LAUNCHED("k_fill_i32");
+    if (tot > 0) {
+      LOR_HIP(hipMemsetAsync(d_tab, 0, static_cast<size_t>(nel) * s->tab_stride, st));
+      k_rank_pass0<<<ceil_div(tot, 256), 256, 0, st>>>(map, nloc, is_signed, ref.nent, s->tab_stride,
+                                                        dev_at<uint16_t>(s, s->off_ent_row),
+                                                        dev_at<int32_t>(s, s->off_st_col), row_ptr, col_idx,
+                                                        d_color, tot, mincol.as<int32_t>(), d_tab, d_err);
+      LOR_LAUNCHED("k_rank_pass0");
+      k_rank_pass1<<<ceil_div(tot, 256), 256, 0, st>>>(map, nloc, is_signed, ref.nent, s->tab_stride,
+                                                        dev_at<uint16_t>(s, s->off_ent_row), row_ptr, d_color, tot,
+                                                        mincol.as<int32_t>(), d_tab);
+      LOR_LAUNCHED("k_rank_pass1");
+    }
+    if ((rc = read_err(d_err, st, &herr))) return rc;
+    if ((rc = report_err(herr))) return rc;
+  }
+  // element classes (identical rank tables share one stored table)
+  s->nclass = nel;
+  if (nel > 0) {
+    const int64_t words = s->tab_stride / 4;
+    uint32_t* tabw = dev_at<uint32_t>(s, s->off_tables);
+    DevBuf hash;
+    if ((rc = hash.alloc(sizeof(uint64_t) * nel))) return rc;
+    k_table_hash<<<ceil_div(nel, 256), 256, 0, st>>>(tabw, words, nel, hash.as<uint64_t>());
+    LOR_LAUNCHED("k_table_hash");
+    std::vector<uint64_t> h(static_cast<size_t>(nel));
+    LOR_HIP(hipMemcpyAsync(h.data(), hash.p, sizeof(uint64_t) * nel, hipMemcpyDeviceToHost, st));
+    LOR_HIP(hipStreamSynchronize(st));
+    std::unordered_map<uint64_t, int32_t> first;
+    std::vector<int32_t> cls(static_cast<size_t>(nel)), rep;
+    for (int64_t e = 0; e < nel; ++e) {
+      auto it = first.find(h[e]);
+      if (it == first.end()) {
+        it = first.emplace(h[e], static_cast<int32_t>(rep.size())).first;
+        rep.push_back(static_cast<int32_t>(e));
+      }
+      cls[e] = it->second;
+    }
+    const int64_t ncls = static_cast<int64_t>(rep.size());
+    DevBuf drep, mism;
+    if ((rc = drep.alloc(sizeof(int32_t) * ncls))) return rc;
+    if ((rc = mism.alloc(sizeof(int32_t)))) return rc;
+    if ((rc = upload(cls, d_class, st))) return rc;
+    if ((rc = upload(rep, drep.p, st))) return rc;
+    LOR_HIP(hipMemsetAsync(mism.p, 0, sizeof(int32_t), st));
+    k_table_verify<<<ceil_div(nel * words, 256), 256, 0, st>>>(tabw, words, nel, d_class, drep.as<int32_t>(),
+                                                              mism.as<int32_t>());
+    LOR_LAUNCHED("k_table_verify");
+    int32_t hm = 0;
+    if ((rc = read_err(mism.as<int32_t>(), st, &hm))) return rc;
+    if (hm == 0 && ncls < nel) {
+      DevBuf tmp;
+      if ((rc = tmp.alloc(static_cast<size_t>(ncls) * s->tab_stride))) return rc;
+      k_table_gather<<<ceil_div(ncls * words, 256), 256, 0, st>>>(tabw, words, ncls, drep.as<int32_t>(),
+                                                                  tmp.as<uint32_t>());
+      LOR_LAUNCHED("k_table_gather");
+      LOR_HIP(hipMemcpyAsync(tabw, tmp.p, static_cast<size_t>(ncls) * s->tab_stride, hipMemcpyDeviceToDevice, st));
+      LOR_HIP(hipStreamSynchronize(st));
+      s->nclass = ncls;
+    } else {
+      // a hash collision (or nothing to share): every element keeps its own table
+      k_iota_i32<<<ceil_div(nel, 256), 256, 0, st>>>(d_class, nel);
+      LOR_LAUNCHED("k_iota_i32");
+    }
+    k_gather_i32<<<ceil_div(nel, 256), 256, 0, st>>>(d_class, dev_at<int32_t>(s, s->off_order), nel,
+                                                    dev_at<int32_t>(s, s->off_order_class));
+    LOR_LAUNCHED("k_gather_i32");
+  }
   return LOR_OK;
 }
 
@@ -1040,7 +1351,6 @@ extern "C" int lor_pattern(int space, int p, int64_t nel, int64_t nrows, const i
   const int is_signed = space == LOR_ND || space == LOR_RT;
   hipStream_t st = as_stream(stream);
   const RefElem ref = build_ref(space, p);
-  const int64_t total = nel * nloc;
   int rc;
   if (col_idx != nullptr) {
     if (!sched->dev) LOR_FAIL(LOR_EINVAL, "sched->dev is NULL (allocate sched->dev_bytes after phase 1)");
@@ -1051,39 +1361,63 @@ extern "C" int lor_pattern(int space, int p, int64_t nel, int64_t nrows, const i
     if (layout(&probe, ref) != sched->dev_bytes) LOR_FAIL(LOR_EINVAL, "sched->dev_bytes changed since phase 1");
   }
 
-  DevBuf err, st_ptr, st_col;
-  if ((rc = err.alloc(sizeof(int32_t)))) return rc;
-  LOR_HIP(hipMemsetAsync(err.p, 0, sizeof(int32_t), st));
+  // temporaries of this call, in one allocation
+  const size_t box_ws = arena_bytes<int32_t>(1) + arena_bytes<int32_t>(5) + arena_bytes<int32_t>(nel);
+  Arena a;
+  int32_t* d_err;
   int32_t herr = 0;
+  BoxLattice box;
+  bool is_box = false;
 
   if (col_idx == nullptr) {
     // ---------------------------------------------------------------- phase 1
-    DevBuf inc_ptr, inc_list, cnt, ptr64;
-    if ((rc = inc_ptr.alloc(sizeof(int32_t) * (nrows + 1)))) return rc;
-    if ((rc = inc_list.alloc(sizeof(int32_t) * std::max<int64_t>(1, total)))) return rc;
-    if ((rc = cnt.alloc(sizeof(int32_t) * nrows))) return rc;
-    if ((rc = ptr64.alloc(sizeof(int64_t) * (nrows + 1)))) return rc;
-    if ((rc = st_ptr.alloc(sizeof(int32_t) * ref.st_ptr.size()))) return rc;
-    if ((rc = st_col.alloc(sizeof(int32_t) * ref.st_col.size()))) return rc;
-    if ((rc = upload(ref.st_ptr, st_ptr.p, st))) return rc;
-    if ((rc = upload(ref.st_col, st_col.p, st))) return rc;
-    if ((rc = build_incidence(elem_map, nel, nloc, is_signed, nrows, inc_ptr.as<int32_t>(),
-                              inc_list.as<int32_t>(), err.as<int32_t>(), st)))
-      return rc;
-    if ((rc = read_err(err.as<int32_t>(), st, &herr))) return rc;
-    if ((rc = report_err(herr))) return rc;
-    k_row_cols<false><<<ceil_div(nrows, kRowThreads), kRowThreads, 0, st>>>(
-        elem_map, nloc, is_signed, inc_ptr.as<int32_t>(), inc_list.as<int32_t>(), st_ptr.as<int32_t>(),
-        st_col.as<int32_t>(), nrows, cnt.as<int32_t>(), nullptr, nullptr, err.as<int32_t>());
-    LOR_LAUNCHED("k_row_cols<count>");
-    if ((rc = scan_exclusive<int32_t>(cnt.as<int32_t>(), nrows, ptr64.as<int64_t>(), st))) return rc;
+    if ((rc = a.alloc(box_ws))) return rc;
+    LOR_TAKE(d_err, a, int32_t, 1);
+    LOR_HIP(hipMemsetAsync(d_err, 0, sizeof(int32_t), st));
     int64_t total_nnz = 0;
-    LOR_HIP(hipMemcpyAsync(&total_nnz, ptr64.as<int64_t>() + nrows, sizeof(int64_t), hipMemcpyDeviceToHost, st));
-    if ((rc = read_err(err.as<int32_t>(), st, &herr))) return rc;
-    if ((rc = report_err(herr))) return rc;
-    if (total_nnz >= INT32_MAX) LOR_FAIL(LOR_EOVERFLOW, "nnz = %lld >= 2^31", (long long)total_nnz);
-    k_i64_to_i32<<<ceil_div(nrows + 1, 256), 256, 0, st>>>(ptr64.as<int64_t>(), nrows + 1, row_ptr);
-    LOR_LAUNCHED("k_i64_to_i32");
+    if (space == LOR_H1) {
+      ArenaScope scope(a);
+      int32_t* e3;
+      LOR_TAKE(e3, a, int32_t, nel);
+      if ((rc = find_box(elem_map, p, nel, nrows, e3, a, st, &box, &is_box))) return rc;
+    }
+    if (is_box) {
+      total_nnz = box_nnz(box);
+      if (total_nnz >= INT32_MAX) LOR_FAIL(LOR_EOVERFLOW, "nnz = %lld >= 2^31", (long long)total_nnz);
+      k_box_row_ptr<<<ceil_div(nrows + 1, 256), 256, 0, st>>>(box.LX, box.LY, box.LZ, row_ptr);
+      LOR_LAUNCHED("k_box_row_ptr");
+    } else {
+      Arena g;
+      if ((rc = g.alloc(arena_bytes<int32_t>(nrows + 1) + arena_bytes<int32_t>(nel * nloc) +
+                        arena_bytes<int32_t>(nrows) + arena_bytes<int64_t>(nrows + 1) +
+                        arena_bytes<int32_t>(ref.st_ptr.size()) + arena_bytes<int32_t>(ref.st_col.size()) +
+                        std::max(incidence_ws_bytes(nrows), scan_ws_bytes(nrows)))))
+        return rc;
+      int32_t *inc_ptr, *inc_list, *cnt, *st_ptr, *st_col;
+      int64_t* ptr64;
+      LOR_TAKE(inc_ptr, g, int32_t, nrows + 1);
+      LOR_TAKE(inc_list, g, int32_t, nel * nloc);
+      LOR_TAKE(cnt, g, int32_t, nrows);
+      LOR_TAKE(ptr64, g, int64_t, nrows + 1);
+      LOR_TAKE(st_ptr, g, int32_t, ref.st_ptr.size());
+      LOR_TAKE(st_col, g, int32_t, ref.st_col.size());
+      if ((rc = upload(ref.st_ptr, st_ptr, st))) return rc;
+      if ((rc = upload(ref.st_col, st_col, st))) return rc;
+      if ((rc = build_incidence(elem_map, nel, nloc, is_signed, nrows, inc_ptr, inc_list, d_err, g, st))) return rc;
+      if ((rc = read_err(d_err, st, &herr))) return rc;
+      if ((rc = report_err(herr))) return rc;
+      k_row_cols<false><<<ceil_div(nrows, kRowThreads), kRowThreads, 0, st>>>(
+          elem_map, nloc, is_signed, inc_ptr, inc_list, st_ptr, st_col, nrows, cnt, nullptr, nullptr, d_err);
+      LOR_LAUNCHED("k_row_cols<count>");
+      if ((rc = scan_exclusive<int32_t>(cnt, nrows, ptr64, g, st))) return rc;
+      LOR_HIP(hipMemcpyAsync(&total_nnz, ptr64 + nrows, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+      if ((rc = read_err(d_err, st, &herr))) return rc;
+      if ((rc = report_err(herr))) return rc;
+      if (total_nnz >= INT32_MAX) LOR_FAIL(LOR_EOVERFLOW, "nnz = %lld >= 2^31", (long long)total_nnz);
+      k_i64_to_i32<<<ceil_div(nrows + 1, 256), 256, 0, st>>>(ptr64, nrows + 1, row_ptr);
+      LOR_LAUNCHED("k_i64_to_i32");
+      LOR_HIP(hipStreamSynchronize(st));
+    }
     LOR_HIP(hipStreamSynchronize(st));
     *nnz = total_nnz;
     sched->space = space;
@@ -1103,162 +1437,30 @@ extern "C" int lor_pattern(int space, int p, int64_t nel, int64_t nrows, const i
   }
 
   // ------------------------------------------------------------------ phase 2
-  const int64_t nnzv = *nnz;
-  int32_t* d_order = dev_at<int32_t>(sched, sched->off_order);
-  int32_t* d_color = dev_at<int32_t>(sched, sched->off_color);
-  int32_t* d_class = dev_at<int32_t>(sched, sched->off_class);
-  uint8_t* d_tab = dev_at<uint8_t>(sched, sched->off_tables);
-  int32_t* d_inc_ptr = dev_at<int32_t>(sched, sched->off_inc_ptr);
-  int32_t* d_inc_list = dev_at<int32_t>(sched, sched->off_inc_list);
-  int32_t* d_st_ptr = dev_at<int32_t>(sched, sched->off_st_ptr);
-  int32_t* d_st_col = dev_at<int32_t>(sched, sched->off_st_col);
-  uint16_t* d_ent_row = dev_at<uint16_t>(sched, sched->off_ent_row);
-  uint64_t* d_recipe = dev_at<uint64_t>(sched, sched->off_recipe);
-  DevBuf reps;
-  if ((rc = reps.alloc(sizeof(int32_t) * ref.reps.size()))) return rc;
-  if ((rc = upload(ref.st_ptr, d_st_ptr, st))) return rc;
-  if ((rc = upload(ref.st_col, d_st_col, st))) return rc;
-  if ((rc = upload(ref.ent_row, d_ent_row, st))) return rc;
-  if ((rc = upload(ref.recipe64, d_recipe, st))) return rc;
-  if ((rc = upload(ref.reps, reps.p, st))) return rc;
-  LOR_HIP(hipMemsetAsync(dev_at<uint8_t>(sched, sched->off_zero), 0, 256, st));
-
-  if ((rc = build_incidence(elem_map, nel, nloc, is_signed, nrows, d_inc_ptr, d_inc_list, err.as<int32_t>(), st)))
+  if ((rc = a.alloc(box_ws + incidence_ws_bytes(nrows) + order_ws_bytes(nel) +
+                    arena_bytes<int32_t>(std::max<size_t>(ref.reps.size(), kBoxKeys)) + arena_bytes<int32_t>(2))))
     return rc;
-  k_row_cols<true><<<ceil_div(nrows, kRowThreads), kRowThreads, 0, st>>>(
-      elem_map, nloc, is_signed, d_inc_ptr, d_inc_list, d_st_ptr, d_st_col, nrows, nullptr, row_ptr, col_idx,
-      err.as<int32_t>());
-  LOR_LAUNCHED("k_row_cols<fill>");
-  if ((rc = read_err(err.as<int32_t>(), st, &herr))) return rc;
-  if ((rc = report_err(herr))) return rc;
-
-  // colouring
-  DevBuf ncol;
-  if ((rc = ncol.alloc(sizeof(int32_t)))) return rc;
-  LOR_HIP(hipMemsetAsync(ncol.p, 0, sizeof(int32_t), st));
-  if (nel > 0) {
-    k_fill_i32<<<ceil_div(nel, 256), 256, 0, st>>>(d_color, nel, -1);
-    LOR_LAUNCHED("k_fill_i32");
-  }
-  int32_t colored = 0;
-  for (int64_t round = 0; colored < nel; ++round) {
-    if (round > nel) LOR_FAIL(LOR_EDEVICE, "element colouring did not converge");
-    k_jp_round<<<ceil_div(nel, 256), 256, 0, st>>>(elem_map, nloc, is_signed, reps.as<int32_t>(),
-                                                   static_cast<int>(ref.reps.size()), d_inc_ptr, d_inc_list,
-                                                   nel, d_color, ncol.as<int32_t>(), err.as<int32_t>());
-    LOR_LAUNCHED("k_jp_round");
-    LOR_HIP(hipMemcpyAsync(&colored, ncol.p, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-    if ((rc = read_err(err.as<int32_t>(), st, &herr))) return rc;
-    if ((rc = report_err(herr))) return rc;
-  }
-  k_check_colors<<<ceil_div(nrows, 256), 256, 0, st>>>(d_inc_ptr, d_inc_list, nloc, nrows, d_color,
-                                                       err.as<int32_t>());
-  LOR_LAUNCHED("k_check_colors");
-  if ((rc = read_err(err.as<int32_t>(), st, &herr))) return rc;
-  if ((rc = report_err(herr))) return rc;
-
-  // element order by colour (stable)
-  {
-    DevBuf flags, pos;
-    if ((rc = flags.alloc(sizeof(int32_t) * std::max<int64_t>(1, nel)))) return rc;
-    if ((rc = pos.alloc(sizeof(int64_t) * (nel + 1)))) return rc;
-    int32_t base = 0;
-    int nc = 0;
-    sched->color_ptr[0] = 0;
-    for (int c = 0; c < LOR_MAX_COLORS && base < nel; ++c) {
-      k_color_flags<<<ceil_div(nel, 256), 256, 0, st>>>(d_color, nel, c, flags.as<int32_t>());
-      LOR_LAUNCHED("k_color_flags");
-      if ((rc = scan_exclusive<int32_t>(flags.as<int32_t>(), nel, pos.as<int64_t>(), st))) return rc;
-      k_color_scatter<<<ceil_div(nel, 256), 256, 0, st>>>(d_color, nel, c, pos.as<int64_t>(), base, d_order);
-      LOR_LAUNCHED("k_color_scatter");
-      int64_t cnt = 0;
-      LOR_HIP(hipMemcpyAsync(&cnt, pos.as<int64_t>() + nel, sizeof(int64_t), hipMemcpyDeviceToHost, st));
-      LOR_HIP(hipStreamSynchronize(st));
-      base += static_cast<int32_t>(cnt);
-      sched->color_ptr[c + 1] = base;
-      nc = c + 1;
-    }
-    if (base != nel) LOR_FAIL(LOR_EDEVICE, "colour order incomplete");
-    sched->ncolors = nc;
-    for (int c = nc + 1; c <= LOR_MAX_COLORS; ++c) sched->color_ptr[c] = base;
-  }
-
-  // rank tables
-  {
-    DevBuf mincol;
-    if ((rc = mincol.alloc(sizeof(int32_t) * std::max<int64_t>(1, nnzv)))) return rc;
-    const int64_t tot = nel * ref.nent;
-    k_fill_i32<<<ceil_div(std::max<int64_t>(1, nnzv), 256), 256, 0, st>>>(mincol.as<int32_t>(), nnzv, INT32_MAX);
-    LOR_LAUNCHED("k_fill_i32");
-    if (tot > 0) {
-      LOR_HIP(hipMemsetAsync(d_tab, 0, static_cast<size_t>(nel) * sched->tab_stride, st));
-      k_rank_pass0<<<ceil_div(tot, 256), 256, 0, st>>>(elem_map, nloc, is_signed, ref.nent, sched->tab_stride,
-                                                        d_ent_row, d_st_col,
-                                                        row_ptr, col_idx, d_color, tot, mincol.as<int32_t>(), d_tab,
-                                                        err.as<int32_t>());
-      LOR_LAUNCHED("k_rank_pass0");
-      k_rank_pass1<<<ceil_div(tot, 256), 256, 0, st>>>(elem_map, nloc, is_signed, ref.nent, sched->tab_stride,
-                                                        d_ent_row, row_ptr,
-                                                        d_color, tot, mincol.as<int32_t>(), d_tab);
-      LOR_LAUNCHED("k_rank_pass1");
-    }
-    if ((rc = read_err(err.as<int32_t>(), st, &herr))) return rc;
-    if ((rc = report_err(herr))) return rc;
-  }
-  // element classes (identical rank tables share one stored table)
-  sched->nclass = nel;
-  if (nel > 0) {
-    const int64_t words = sched->tab_stride / 4;
-    uint32_t* tabw = dev_at<uint32_t>(sched, sched->off_tables);
-    DevBuf hash;
-    if ((rc = hash.alloc(sizeof(uint64_t) * nel))) return rc;
-    k_table_hash<<<ceil_div(nel, 256), 256, 0, st>>>(tabw, words, nel, hash.as<uint64_t>());
-    LOR_LAUNCHED("k_table_hash");
-    std::vector<uint64_t> h(static_cast<size_t>(nel));
-    LOR_HIP(hipMemcpyAsync(h.data(), hash.p, sizeof(uint64_t) * nel, hipMemcpyDeviceToHost, st));
-    LOR_HIP(hipStreamSynchronize(st));
-    std::unordered_map<uint64_t, int32_t> first;
-    std::vector<int32_t> cls(static_cast<size_t>(nel)), rep;
-    for (int64_t e = 0; e < nel; ++e) {
-      auto it = first.find(h[e]);
-      if (it == first.end()) {
-        it = first.emplace(h[e], static_cast<int32_t>(rep.size())).first;
-        rep.push_back(static_cast<int32_t>(e));
-      }
-      cls[e] = it->second;
-    }
-    const int64_t ncls = static_cast<int64_t>(rep.size());
-    DevBuf drep, mism;
-    if ((rc = drep.alloc(sizeof(int32_t) * ncls))) return rc;
-    if ((rc = mism.alloc(sizeof(int32_t)))) return rc;
-    if ((rc = upload(cls, d_class, st))) return rc;
-    if ((rc = upload(rep, drep.p, st))) return rc;
-    LOR_HIP(hipMemsetAsync(mism.p, 0, sizeof(int32_t), st));
-    k_table_verify<<<ceil_div(nel * words, 256), 256, 0, st>>>(tabw, words, nel, d_class, drep.as<int32_t>(),
-                                                              mism.as<int32_t>());
-    LOR_LAUNCHED("k_table_verify");
-    int32_t hm = 0;
-    if ((rc = read_err(mism.as<int32_t>(), st, &hm))) return rc;
-    if (hm == 0 && ncls < nel) {
-      DevBuf tmp;
-      if ((rc = tmp.alloc(static_cast<size_t>(ncls) * sched->tab_stride))) return rc;
-      k_table_gather<<<ceil_div(ncls * words, 256), 256, 0, st>>>(tabw, words, ncls, drep.as<int32_t>(),
-                                                                  tmp.as<uint32_t>());
-      LOR_LAUNCHED("k_table_gather");
-      LOR_HIP(hipMemcpyAsync(tabw, tmp.p, static_cast<size_t>(ncls) * sched->tab_stride, hipMemcpyDeviceToDevice,
-                             st));
-      LOR_HIP(hipStreamSynchronize(st));
-      sched->nclass = ncls;
-    } else {
-      // a hash collision (or nothing to share): every element keeps its own table
-      k_iota_i32<<<ceil_div(nel, 256), 256, 0, st>>>(d_class, nel);
-      LOR_LAUNCHED("k_iota_i32");
-    }
-    k_gather_i32<<<ceil_div(nel, 256), 256, 0, st>>>(d_class, d_order, nel,
-                                                    dev_at<int32_t>(sched, sched->off_order_class));
-    LOR_LAUNCHED("k_gather_i32");
-  }
+  LOR_TAKE(d_err, a, int32_t, 1);
+  LOR_HIP(hipMemsetAsync(d_err, 0, sizeof(int32_t), st));
+  if ((rc = upload(ref.st_ptr, dev_at<int32_t>(sched, sched->off_st_ptr), st))) return rc;
+  if ((rc = upload(ref.st_col, dev_at<int32_t>(sched, sched->off_st_col), st))) return rc;
+  if ((rc = upload(ref.ent_row, dev_at<uint16_t>(sched, sched->off_ent_row), st))) return rc;
+  if ((rc = upload(ref.recipe64, dev_at<uint64_t>(sched, sched->off_recipe), st))) return rc;
+  LOR_HIP(hipMemsetAsync(dev_at<uint8_t>(sched, sched->off_zero), 0, 256, st));
+  if ((rc = build_incidence(elem_map, nel, nloc, is_signed, nrows, dev_at<int32_t>(sched, sched->off_inc_ptr),
+                            dev_at<int32_t>(sched, sched->off_inc_list), d_err, a, st)))
+    return rc;
+  sched->owner = 0;
+  sched->box[0] = sched->box[1] = sched->box[2] = 0;
   sched->max_row_nnz = 0;
+  if (space == LOR_H1 &&
+      (rc = find_box(elem_map, p, nel, nrows, dev_at<int32_t>(sched, sched->off_elem3d), a, st, &box, &is_box)))
+    return rc;
+  if (is_box)
+    rc = box_schedule(sched, ref, box, elem_map, row_ptr, col_idx, d_err, a, st);
+  else
+    rc = general_schedule(sched, ref, is_signed, elem_map, row_ptr, col_idx, d_err, a, st);
+  if (rc) return rc;
   LOR_HIP(hipStreamSynchronize(st));
-  return build_owner(sched, elem_map, row_ptr, col_idx, st);
+  return LOR_OK;
 }

@@ -85,12 +85,11 @@ class LorSched(ctypes.Structure):
         ("off_recipe", ctypes.c_size_t),
         ("off_zero", ctypes.c_size_t),
         ("off_order_class", ctypes.c_size_t),
-        ("off_nbr", ctypes.c_size_t),
         ("off_elem3d", ctypes.c_size_t),
         ("off_base", ctypes.c_size_t),
         ("owner", ctypes.c_int32),
         ("box", ctypes.c_int32 * 3),
-        ("reserved", ctypes.c_size_t * 2),
+        ("reserved", ctypes.c_size_t * 3),
     ]
 
 

@@ -20,7 +20,7 @@ int main(void) {
   lor_sched s;
   int64_t nnz = 0;
   const int32_t* fake = (const int32_t*)(uintptr_t)0x1000; /* never dereferenced */
-  expect(lor_abi_version() == 2, "ABI version 2");
+  expect(lor_abi_version() == 3, "ABI version 3");
   expect(lor_sched_bytes() == sizeof(lor_sched), "schedule size agrees with the header");
   memset(&s, 0, sizeof s);
   expect(lor_pattern(LOR_H1, 0, 1, 8, fake, (int32_t*)fake, &nnz, NULL, &s, NULL) == LOR_EINVAL, "p = 0 rejected");

@@ -25,7 +25,7 @@ def test_exports_every_declared_symbol():
     for name in declared:
         assert hasattr(lib, name), name
     assert set(declared) == set(L.ABI_SYMBOLS)
-    assert lib.lor_abi_version() == 2
+    assert lib.lor_abi_version() == 3
     assert lib.lor_sched_bytes() == ctypes.sizeof(L.LorSched)
 
 
