@@ -124,7 +124,9 @@ typedef struct lor_sched {
    * X + LX (Y + LY Z) -- structured meshes, also with the elements in any
    * order.  Such meshes also get their pattern, colours (by the parities of
    * the box position) and rank tables in closed form.  owner == 0 otherwise,
-   * and then only the colour schedule is used. */
+   * and then only the colour schedule is used.  Phase 1 already sets owner
+   * and box (a box lattice needs fewer schedule bytes); phase 2 fills the
+   * arrays. */
   size_t off_elem3d;             /* int32 [box[2]][box[1]][box[0]]: element at box position (ex, ey, ez) */
   size_t off_base;               /* int32 [LZ][LY]: vertex id of lattice point (0, Y, Z) */
   int32_t owner;                 /* 1 if the owner-computes schedule is valid */
@@ -452,9 +454,10 @@ int lor_evec_to_tvec(int p, int64_t nel, int64_t ndofs, const lor_sched* sched, 
 
 /*
  * lor_pattern_workspace -- bytes of the schedule's device buffer (sched->dev)
- * for a mesh of these sizes: the value lor_pattern phase 1 writes into
- * sched->dev_bytes, known before the pattern is built (the layout depends on
- * the space, p, nel and nrows only).  0 for invalid arguments (the checks of
+ * for a mesh of these sizes, known before the pattern is built: an upper
+ * bound of the value lor_pattern phase 1 writes into sched->dev_bytes, equal
+ * to it unless the mesh is an H1 box lattice (see lor_sched.owner), whose
+ * schedule stores fewer rank tables.  0 for invalid arguments (the checks of
  * lor_pattern).  Host only; no device work.
  */
 size_t lor_pattern_workspace(int space, int p, int64_t nel, int64_t nrows);

@@ -142,6 +142,40 @@ def cartesian_mesh(n: int, p: int, amp: float = 0.0) -> dict:
     }
 
 
+def box_mesh(nx: int, ny: int, nz: int, p: int, amp: float = 0.0) -> dict:
+    """nx x ny x nz hexes of degree p on the box [0, nx/m] x [0, ny/m] x [0, nz/m]
+    (m = max(nx, ny, nz)), numbered like cartesian_mesh: element
+    ex + nx (ey + ny ez), lattice vertex X + LX (Y + LY Z) with LX = nx p + 1
+    (and so on), local vertex i + (p+1)(j + (p+1)k); every lattice vertex moved
+    by the map of cartesian_mesh with A = amp / m.  box_mesh(n, n, n, p, amp)
+    equals cartesian_mesh(n, p, amp)."""
+    m = max(nx, ny, nz)
+    q = p + 1
+    L = (nx * p + 1, ny * p + 1, nz * p + 1)
+    x1 = [_lattice_1d(n, p) * (n / m) for n in (nx, ny, nz)]
+    Z, Y, X = np.meshgrid(x1[2], x1[1], x1[0], indexing="ij")
+    X, Y, Z = X.reshape(-1), Y.reshape(-1), Z.reshape(-1)
+    A = amp / m
+    if A != 0.0:
+        tp = 2.0 * math.pi
+        sx, sy, sz = np.sin(tp * X), np.sin(tp * Y), np.sin(tp * Z)
+        X, Y, Z = X + A * sy * sz, Y + A * sz * sx, Z + A * sx * sy
+    coords = np.stack([X, Y, Z], axis=1).astype(np.float64)
+    e = np.arange(nx * ny * nz)
+    ex, ey, ez = e % nx, (e // nx) % ny, e // (nx * ny)
+    l = np.arange(q ** 3)
+    i, j, k = l % q, (l // q) % q, l // (q * q)
+    g = (p * ex[:, None] + i) + L[0] * ((p * ey[:, None] + j) + L[1] * (p * ez[:, None] + k))
+    return {
+        "coords": coords,
+        "elem_dofs": g.astype(np.int32),
+        "p": p,
+        "box": (nx, ny, nz),
+        "nel": nx * ny * nz,
+        "ndofs": L[0] * L[1] * L[2],
+    }
+
+
 def cartesian_mesh_2d(n: int, p: int, amp: float = 0.0) -> dict:
     """n^2 quadrilaterals of degree p on the unit square (the 2D variant):
     element e = ex + n*ey, local vertex i + (p+1)*j, global vertex X + N*Y with

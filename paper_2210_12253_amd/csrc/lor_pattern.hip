@@ -627,23 +627,39 @@ __global__ void k_check_colors(const int32_t* __restrict__ inc_ptr, const int32_
   }
 }
 
-__global__ void k_color_flags(const int32_t* __restrict__ color, int64_t nel, int c, int32_t* __restrict__ f) {
-  const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (e < nel) f[e] = (color[e] == c) ? 1 : 0;
+// Stable sort of the elements by colour, one wave per 64 consecutive
+// elements: k_color_hist counts each colour in the wave (cnt is colour-major,
+// [nc][nblk]); after an exclusive scan of cnt into off, element e of colour c
+// goes to off[c][wave] + (lanes below it with colour c).  Elements whose
+// colour is outside [0, nc) are left out (the caller checks the total).
+__global__ __launch_bounds__(64) void k_color_hist(const int32_t* __restrict__ color, int64_t nel, int nc,
+                                                   int64_t nblk, int32_t* __restrict__ cnt) {
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * 64 + threadIdx.x;
+  const int32_t c = e < nel ? color[e] : -1;
+  for (int cc = 0; cc < nc; ++cc) {
+    const uint64_t m = __ballot(c == cc);
+    if (threadIdx.x == 0) cnt[cc * nblk + blockIdx.x] = __popcll(m);
+  }
 }
 
-// Colour c's elements, in element order, to order[cptr[c] ..]; cptr[c] was
-// written by the previous colour's k_color_next (so no host round trip per
-// colour).
-__global__ void k_color_scatter(const int32_t* __restrict__ color, int64_t nel, int c,
-                                const int64_t* __restrict__ pos, const int32_t* __restrict__ cptr,
-                                int32_t* __restrict__ order) {
-  const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (e < nel && color[e] == c) order[cptr[c] + pos[e]] = static_cast<int32_t>(e);
+__global__ __launch_bounds__(64) void k_color_place(const int32_t* __restrict__ color, int64_t nel, int nc,
+                                                    int64_t nblk, const int64_t* __restrict__ off,
+                                                    int32_t* __restrict__ order) {
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * 64 + threadIdx.x;
+  const int32_t c = e < nel ? color[e] : -1;
+  const uint64_t below = (1ull << threadIdx.x) - 1ull;
+  int64_t at = -1;
+  for (int cc = 0; cc < nc; ++cc) {
+    const uint64_t m = __ballot(c == cc);
+    if (c == cc) at = off[cc * nblk + blockIdx.x] + __popcll(m & below);
+  }
+  if (at >= 0) order[at] = static_cast<int32_t>(e);
 }
 
-__global__ void k_color_next(const int64_t* __restrict__ pos, int64_t nel, int c, int32_t* __restrict__ cptr) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) cptr[c + 1] = cptr[c] + static_cast<int32_t>(pos[nel]);
+// Colour pointer: colour c starts at off[c][0]; off[nc * nblk] is the total.
+__global__ void k_color_ptr(const int64_t* __restrict__ off, int nc, int64_t nblk, int32_t* __restrict__ cptr) {
+  const int c = threadIdx.x;
+  if (c <= nc) cptr[c] = static_cast<int32_t>(off[c * nblk]);
 }
 
 // Position of every local stencil entry inside its CSR row; lowest colour per nnz.
@@ -761,6 +777,10 @@ __global__ void k_gather_i32(const int32_t* __restrict__ src, const int32_t* __r
 //     agreeing in those share one rank table.
 // The owner-computes value kernel relies on exactly this layout.
 
+// Distinct class keys of k_box_color_key (9 bits): a box lattice needs at
+// most this many rank tables.
+constexpr int kBoxKeys = 512;
+
 struct BoxLattice {
   int64_t LX = 0, LY = 0, LZ = 0;
   int nx = 0, ny = 0, nz = 0;
@@ -787,22 +807,25 @@ __global__ void k_box_probe(const int32_t* __restrict__ map, int p, int32_t* __r
 // -1), and a position claimed twice marks the mesh as no box lattice.  With
 // nel = nx ny nz elements placed at distinct positions, every position is
 // taken.
-__global__ void k_box_place(const int32_t* __restrict__ map, int p, int64_t nel, int64_t LX, int64_t LY, int64_t LZ,
+template <int P>
+__global__ void k_box_place(const int32_t* __restrict__ map, int32_t nel, int32_t LX, int32_t LY, int32_t LZ,
                             int nx, int ny, int32_t* __restrict__ elem3d, int32_t* __restrict__ flag) {
-  const int q = p + 1, nloc = q * q * q;
-  const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (t >= nel * nloc) return;
-  const int64_t e = t / nloc;
-  const int l = static_cast<int>(t - e * nloc);
-  const int64_t v0 = map[e * nloc];
-  const int64_t X0 = v0 % LX, Y0 = (v0 / LX) % LY, Z0 = v0 / (LX * LY);
-  bool bad = v0 < 0 || Z0 >= LZ || X0 % p != 0 || Y0 % p != 0 || Z0 % p != 0 || X0 + p >= LX || Y0 + p >= LY ||
-             Z0 + p >= LZ;
-  const int lx = l % q, ly = (l / q) % q, lz = l / (q * q);
-  bad = bad || map[t] != v0 + lx + LX * (ly + LY * lz);
-  if (!bad && l == 0) {
-    const int64_t pos = ((Z0 / p) * ny + Y0 / p) * nx + X0 / p;
-    bad = atomicCAS(&elem3d[pos], -1, static_cast<int32_t>(e)) != -1;
+  constexpr int Q = P + 1, NLOC = Q * Q * Q;
+  const int32_t t = static_cast<int32_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= nel * NLOC) return;  // nel * NLOC < 2^31
+  const int32_t e = t / NLOC;
+  const int l = t - e * NLOC;
+  const int32_t v0 = map[e * NLOC];
+  const int lx = l % Q, ly = (l / Q) % Q, lz = l / (Q * Q);
+  bool bad = map[t] != v0 + lx + LX * (ly + LY * lz);
+  if (l == 0) {
+    const int32_t X0 = v0 % LX, Y0 = (v0 / LX) % LY, Z0 = v0 / (LX * LY);
+    bad = bad || v0 < 0 || Z0 >= LZ || X0 % P != 0 || Y0 % P != 0 || Z0 % P != 0 || X0 + P >= LX ||
+          Y0 + P >= LY || Z0 + P >= LZ;
+    if (!bad) {
+      const int64_t pos = (static_cast<int64_t>(Z0 / P) * ny + Y0 / P) * nx + X0 / P;
+      bad = atomicCAS(&elem3d[pos], -1, e) != -1;
+    }
   }
   // one atomic per wave at most (a mesh that is no box lattice fails almost
   // everywhere)
@@ -829,36 +852,73 @@ __global__ void k_box_row_ptr(int64_t LX, int64_t LY, int64_t LZ, int32_t* __res
 
 // Columns of one lattice line (Y, Z) per workgroup: the line's rows are
 // consecutive, and so are their entries; consecutive threads write
-// consecutive entries.  Entry o of the line belongs to row X, where the rows
-// before X hold (3X - 1) cyz entries; inside a row, entries run in
-// (dz, dy, dx) order.  The caller's row pointer is checked against the
-// lattice's.
+// consecutive entries.  With C = cy cz neighbour lines, row 0 holds entries
+// [0, 2C), interior row X >= 1 holds [(3X - 1) C, (3X + 2) C), the last row
+// the final 2C; inside a row, entries run in (dz, dy, dx) order.  The line's
+// (cy, cz) are template arguments, so the divisions are by constants.  The
+// caller's row pointer is checked against the lattice's.
 constexpr int kBoxColThreads = 256;
-__global__ __launch_bounds__(kBoxColThreads) void k_box_cols(int64_t LX, int64_t LY, int64_t LZ,
+
+template <int CY, int CZ>
+__device__ __forceinline__ void box_line_cols(int32_t LX, int32_t LY, int32_t Y, int32_t Z, int64_t start,
+                                              int32_t* __restrict__ col_idx) {
+  constexpr int C = CY * CZ;
+  const int ylo = Y > 0, zlo = Z > 0;
+  // id of lattice point (0, Y - ylo + iy, Z - zlo + iz) = b0 + iz LX LY + iy LX
+  const int32_t b0 = ((Z - zlo) * LY + (Y - ylo)) * LX;
+  const int32_t lxy = LX * LY;
+  const int32_t total = (3 * LX - 2) * C, last = (3 * LX - 4) * C;
+  for (int32_t o = threadIdx.x; o < total; o += kBoxColThreads) {
+    int32_t X, izy, col;
+    if (o < 2 * C) {  // row 0: dx in {0, 1}
+      X = 0;
+      izy = o >> 1;
+      col = o & 1;
+    } else if (o >= last) {  // row LX - 1: dx in {-1, 0}
+      const int32_t u = o - last;
+      X = LX - 1;
+      izy = u >> 1;
+      col = X - 1 + (u & 1);
+    } else {  // interior row: dx in {-1, 0, 1}
+      const int32_t w = o - 2 * C;
+      const int32_t r = w / (3 * C);
+      const int32_t u = w - r * (3 * C);
+      X = r + 1;
+      izy = u / 3;
+      col = X - 1 + (u - 3 * izy);
+    }
+    const int32_t iz = izy / CY, iy = izy - iz * CY;
+    col_idx[start + o] = b0 + iz * lxy + iy * LX + col;
+  }
+}
+
+__global__ __launch_bounds__(kBoxColThreads) void k_box_cols(int32_t LX, int32_t LY, int32_t LZ,
                                                              const int32_t* __restrict__ row_ptr,
                                                              int32_t* __restrict__ col_idx,
                                                              int32_t* __restrict__ err) {
-  const int64_t line = blockIdx.x;
-  const int64_t Y = line % LY, Z = line / LY;
+  const int32_t line = blockIdx.x;
+  const int32_t Y = line % LY, Z = line / LY;
   const int cy = box_count(Y, LY), cz = box_count(Z, LZ), cyz = cy * cz;
-  const int64_t SX = 3 * LX - 2, SY = 3 * LY - 2;
+  const int64_t SX = 3 * static_cast<int64_t>(LX) - 2, SY = 3 * static_cast<int64_t>(LY) - 2;
   const int64_t start = box_prefix(Z, LZ) * SY * SX + cz * box_prefix(Y, LY) * SX;
-  const int64_t v0 = line * LX;
+  const int64_t v0 = static_cast<int64_t>(line) * LX;
   bool bad = false;
-  for (int64_t X = threadIdx.x; X <= LX; X += kBoxColThreads)
+  for (int32_t X = threadIdx.x; X <= LX; X += kBoxColThreads)
     bad = bad || row_ptr[v0 + X] != start + cyz * box_prefix(X, LX);
   if (bad) atomicOr(err, kErrRowCount);
-  const int ylo = Y > 0, zlo = Z > 0;
-  const int total = static_cast<int>(SX) * cyz;
-  const int64_t lx = LX;
-  for (int o = threadIdx.x; o < total; o += kBoxColThreads) {
-    const int X = (o + cyz) / (3 * cyz);
-    const int xlo = X > 0, cx = 1 + xlo + (X < lx - 1);
-    const int u = o - (X == 0 ? 0 : (3 * X - 1) * cyz);
-    const int izy = u / cx, ix = u - izy * cx;
-    const int iz = izy / cy, iy = izy - iz * cy;
-    const int64_t col = ((Z + iz - zlo) * LY + (Y + iy - ylo)) * LX + (X + ix - xlo);
-    col_idx[start + o] = static_cast<int32_t>(col);
+  // cy, cz in {2, 3}: every axis has at least two lattice points
+  switch (cy * 4 + cz) {
+#define LOR_BOX_LINE(A, B)                             \
+  case A * 4 + B:                                      \
+    box_line_cols<A, B>(LX, LY, Y, Z, start, col_idx); \
+    break;
+    LOR_BOX_LINE(2, 2)
+    LOR_BOX_LINE(2, 3)
+    LOR_BOX_LINE(3, 2)
+    LOR_BOX_LINE(3, 3)
+#undef LOR_BOX_LINE
+    default:
+      break;
   }
 }
 
@@ -952,7 +1012,10 @@ static size_t layout(lor_sched* s, const RefElem& r) {
   s->off_color = take(sizeof(int32_t) * s->nel);
   s->off_class = take(sizeof(int32_t) * s->nel);
   s->tab_stride = (r.nent + 15) / 16 * 16;
-  s->off_tables = take(static_cast<size_t>(s->nel) * s->tab_stride);
+  // one rank table per element at most; a box lattice (found in phase 1) has
+  // at most kBoxKeys distinct ones
+  const int64_t ntab = s->owner ? std::min<int64_t>(s->nel, kBoxKeys) : s->nel;
+  s->off_tables = take(static_cast<size_t>(ntab) * s->tab_stride);
   s->off_inc_ptr = take(sizeof(int32_t) * (s->nrows + 1));
   s->off_inc_list = take(sizeof(int32_t) * s->nel * r.nloc);
   s->off_st_ptr = take(sizeof(int32_t) * r.st_ptr.size());
@@ -1046,8 +1109,25 @@ static int find_box(const int32_t* map, int p, int64_t nel, int64_t nrows, int32
   LOR_HIP(hipMemsetAsync(flag, 0, sizeof(int32_t), st));
   k_fill_i32<<<ceil_div(nel, 256), 256, 0, st>>>(elem3d, nel, -1);
   LOR_LAUNCHED("k_fill_i32");
-  k_box_place<<<ceil_div(nel * q * q * q, 256), 256, 0, st>>>(map, p, nel, LX, LY, LZ, static_cast<int>(nx),
-                                                              static_cast<int>(ny), elem3d, flag);
+  const int64_t threads = nel * q * q * q;
+  const int32_t lx = static_cast<int32_t>(LX), ly = static_cast<int32_t>(LY), lz = static_cast<int32_t>(LZ);
+  const int32_t ne = static_cast<int32_t>(nel);
+  const int inx = static_cast<int>(nx), iny = static_cast<int>(ny);
+  switch (p) {
+#define LOR_BOX_PLACE(PP)                                                                              \
+  case PP:                                                                                             \
+    k_box_place<PP><<<ceil_div(threads, 256), 256, 0, st>>>(map, ne, lx, ly, lz, inx, iny, elem3d, flag); \
+    break;
+    LOR_BOX_PLACE(1)
+    LOR_BOX_PLACE(2)
+    LOR_BOX_PLACE(3)
+    LOR_BOX_PLACE(4)
+    LOR_BOX_PLACE(5)
+    LOR_BOX_PLACE(6)
+#undef LOR_BOX_PLACE
+    default:
+      LOR_FAIL(LOR_EINVAL, "p = %d outside [1, %d]", p, LOR_MAX_P);
+  }
   LOR_LAUNCHED("k_box_place");
   int32_t hflag = 0;
   if ((rc = read_err(flag, st, &hflag))) return rc;
@@ -1064,9 +1144,6 @@ static int find_box(const int32_t* map, int p, int64_t nel, int64_t nrows, int32
 
 static int order_by_color(lor_sched* s, int64_t nel, int nc, Arena& a, hipStream_t st);
 
-// Distinct class keys of k_box_color_key (9 bits).
-constexpr int kBoxKeys = 512;
-
 static int64_t box_nnz(const BoxLattice& b) { return (3 * b.LX - 2) * (3 * b.LY - 2) * (3 * b.LZ - 2); }
 
 // Phase 2 on a box lattice: columns, colours, one rank table per class, the
@@ -1076,7 +1153,8 @@ static int box_schedule(lor_sched* s, const RefElem& ref, const BoxLattice& b, c
   const int64_t nel = s->nel;
   int rc;
   int32_t herr = 0;
-  k_box_cols<<<b.LY * b.LZ, kBoxColThreads, 0, st>>>(b.LX, b.LY, b.LZ, row_ptr, col_idx, d_err);
+  k_box_cols<<<b.LY * b.LZ, kBoxColThreads, 0, st>>>(static_cast<int32_t>(b.LX), static_cast<int32_t>(b.LY),
+                                                     static_cast<int32_t>(b.LZ), row_ptr, col_idx, d_err);
   LOR_LAUNCHED("k_box_cols");
   // colours from the parities of the axes with more than one element
   int w = 1;
@@ -1135,8 +1213,9 @@ static int box_schedule(lor_sched* s, const RefElem& ref, const BoxLattice& b, c
 
 // Scratch bytes of order_by_color.
 static size_t order_ws_bytes(int64_t nel) {
-  return arena_bytes<int32_t>(nel) + arena_bytes<int64_t>(nel + 1) + arena_bytes<int32_t>(LOR_MAX_COLORS + 1) +
-         scan_ws_bytes(nel);
+  const int64_t n = LOR_MAX_COLORS * ceil_div(nel, 64);
+  return arena_bytes<int32_t>(n) + arena_bytes<int64_t>(n + 1) + arena_bytes<int32_t>(LOR_MAX_COLORS + 1) +
+         scan_ws_bytes(n);
 }
 
 // Element order by colour (stable: within a colour, by element index) and the
@@ -1146,26 +1225,23 @@ static int order_by_color(lor_sched* s, int64_t nel, int nc, Arena& a, hipStream
   s->ncolors = 0;
   if (nel == 0) return LOR_OK;
   if (nc < 1 || nc > LOR_MAX_COLORS) LOR_FAIL(LOR_EUNSUPPORTED, "%d colours (at most %d)", nc, LOR_MAX_COLORS);
-  int32_t* d_color = dev_at<int32_t>(s, s->off_color);
+  const int32_t* d_color = dev_at<int32_t>(s, s->off_color);
   int32_t* d_order = dev_at<int32_t>(s, s->off_order);
+  const int64_t nblk = ceil_div(nel, 64), n = nc * nblk;
   ArenaScope scope(a);
-  int32_t *flags, *cptr;
-  int64_t* pos;
-  LOR_TAKE(flags, a, int32_t, nel);
-  LOR_TAKE(pos, a, int64_t, nel + 1);
+  int32_t *cnt, *cptr;
+  int64_t* off;
+  LOR_TAKE(cnt, a, int32_t, n);
+  LOR_TAKE(off, a, int64_t, n + 1);
   LOR_TAKE(cptr, a, int32_t, LOR_MAX_COLORS + 1);
-  k_fill_i32<<<1, 64, 0, st>>>(cptr, 1, 0);
-  LOR_LAUNCHED("k_fill_i32");
+  k_color_hist<<<nblk, 64, 0, st>>>(d_color, nel, nc, nblk, cnt);
+  LOR_LAUNCHED("k_color_hist");
   int rc;
-  for (int c = 0; c < nc; ++c) {
-    k_color_flags<<<ceil_div(nel, 256), 256, 0, st>>>(d_color, nel, c, flags);
-    LOR_LAUNCHED("k_color_flags");
-    if ((rc = scan_exclusive<int32_t>(flags, nel, pos, a, st))) return rc;
-    k_color_scatter<<<ceil_div(nel, 256), 256, 0, st>>>(d_color, nel, c, pos, cptr, d_order);
-    LOR_LAUNCHED("k_color_scatter");
-    k_color_next<<<1, 64, 0, st>>>(pos, nel, c, cptr);
-    LOR_LAUNCHED("k_color_next");
-  }
+  if ((rc = scan_exclusive<int32_t>(cnt, n, off, a, st))) return rc;
+  k_color_place<<<nblk, 64, 0, st>>>(d_color, nel, nc, nblk, off, d_order);
+  LOR_LAUNCHED("k_color_place");
+  k_color_ptr<<<1, 128, 0, st>>>(off, nc, nblk, cptr);
+  LOR_LAUNCHED("k_color_ptr");
   int32_t h[LOR_MAX_COLORS + 1];
   LOR_HIP(hipMemcpyAsync(h, cptr, sizeof(int32_t) * (nc + 1), hipMemcpyDeviceToHost, st));
   LOR_HIP(hipStreamSynchronize(st));
@@ -1430,8 +1506,10 @@ extern "C" int lor_pattern(int space, int p, int64_t nel, int64_t nrows, const i
     sched->ncolors = 0;
     sched->nclass = 0;
     sched->dev = nullptr;
-    sched->owner = 0;
-    sched->box[0] = sched->box[1] = sched->box[2] = 0;
+    sched->owner = is_box ? 1 : 0;
+    sched->box[0] = is_box ? box.nx : 0;
+    sched->box[1] = is_box ? box.ny : 0;
+    sched->box[2] = is_box ? box.nz : 0;
     sched->dev_bytes = layout(sched, ref);
     return LOR_OK;
   }
@@ -1450,12 +1528,14 @@ extern "C" int lor_pattern(int space, int p, int64_t nel, int64_t nrows, const i
   if ((rc = build_incidence(elem_map, nel, nloc, is_signed, nrows, dev_at<int32_t>(sched, sched->off_inc_ptr),
                             dev_at<int32_t>(sched, sched->off_inc_list), d_err, a, st)))
     return rc;
+  const bool box1 = sched->owner == 1;
   sched->owner = 0;
   sched->box[0] = sched->box[1] = sched->box[2] = 0;
   sched->max_row_nnz = 0;
   if (space == LOR_H1 &&
       (rc = find_box(elem_map, p, nel, nrows, dev_at<int32_t>(sched, sched->off_elem3d), a, st, &box, &is_box)))
     return rc;
+  if (is_box != box1) LOR_FAIL(LOR_EINVAL, "elem_map is not the one phase 1 saw");
   if (is_box)
     rc = box_schedule(sched, ref, box, elem_map, row_ptr, col_idx, d_err, a, st);
   else

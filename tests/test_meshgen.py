@@ -1,0 +1,33 @@
+"""The synthetic box meshes themselves: box_mesh on a cube is cartesian_mesh,
+and on any box every lattice vertex is used by exactly the elements whose
+closed boxes contain it."""
+import numpy as np
+import pytest
+
+import meshgen
+
+
+@pytest.mark.parametrize("n,p", [(1, 1), (2, 3), (3, 2)])
+def test_box_mesh_on_a_cube_is_cartesian_mesh(n, p):
+    a, b = meshgen.cartesian_mesh(n, p, 0.1), meshgen.box_mesh(n, n, n, p, 0.1)
+    assert np.array_equal(a["elem_dofs"], b["elem_dofs"])
+    assert np.array_equal(a["coords"], b["coords"])
+    assert a["ndofs"] == b["ndofs"] and a["nel"] == b["nel"]
+
+
+@pytest.mark.parametrize("box,p", [((3, 2, 1), 2), ((1, 1, 4), 3), ((2, 3, 2), 1)])
+def test_box_mesh_incidence(box, p):
+    m = meshgen.box_mesh(*box, p)
+    L = [n * p + 1 for n in box]
+    counts = np.bincount(m["elem_dofs"].reshape(-1), minlength=m["ndofs"])
+    v = np.arange(m["ndofs"])
+    X, Y, Z = v % L[0], (v // L[0]) % L[1], v // (L[0] * L[1])
+
+    def per_axis(c, n):
+        # a point on an interior element face along this axis lies in two elements
+        return np.where((c % p == 0) & (c > 0) & (c < n * p), 2, 1)
+
+    assert np.array_equal(counts, per_axis(X, box[0]) * per_axis(Y, box[1]) * per_axis(Z, box[2]))
+    # the perturbed lattice keeps the box corners where they were
+    assert np.allclose(m["coords"][0], 0.0)
+    assert np.allclose(m["coords"][-1], np.array(box) / max(box))
