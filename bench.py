@@ -206,6 +206,16 @@ KERNELS = {
     "colored_f64": "k_h1_assemble<6, double, double>",
     "colored_f32": "k_h1_assemble<6, float, float>",
 }
+# profiled workloads: summary name -> (kernels, their sources); the records
+# are written by --summarize-profiles / --summarize-valu with --profile-name
+PROFILE_SETS = {
+    "h1_p6_32cubed": (KERNELS, KERNEL_SOURCES),
+    "backward_p4_16cubed_b8": ({
+        "backward_f64": "k_h1_backward<4, double>",
+        "backward_f32": "k_h1_backward<4, float>",
+        "gather_vertices": "k_gather_vertices",
+    }, ("lor_backward.hip", "lor_h1_adjoint.hpp", "lor_h1_math.hpp", "lor_common.hpp")),
+}
 # VALU wave-instruction counters (one rocprofv3 --pmc pass holds all five)
 VALU_COUNTERS = ("SQ_INSTS_VALU_ADD_F64", "SQ_INSTS_VALU_MUL_F64", "SQ_INSTS_VALU_FMA_F64",
                  "SQ_INSTS_VALU_TRANS_F64", "SQ_INSTS_VALU")
@@ -215,36 +225,37 @@ CYCLES_PER_WAVE_INSTR = 4        # 16 lanes per SIMD per clock (FP64, and FP32 w
 FP64_PEAK_TFLOPS = 78.6          # vector FP64 (an FMA counts as 2 flops)
 
 
-def kernel_source_hash():
-    """Hash of the sources of the headline kernels: counters taken on other code are stale."""
+def kernel_source_hash(sources=KERNEL_SOURCES):
+    """Hash of the sources of the profiled kernels: counters taken on other code are stale."""
     import hashlib
     h = hashlib.sha256()
-    for name in KERNEL_SOURCES:
+    for name in sources:
         with open(os.path.join(ROOT, "paper_2210_12253_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
 
 
-def _load_record(fname):
+def _load_record(fname, sources=KERNEL_SOURCES):
     path = os.path.join(ROOT, "profiles", fname)
     if not os.path.exists(path):
         return None
     with open(path) as f:
         t = json.load(f)
-    if t.get("kernel_source_hash") != kernel_source_hash():
+    if t.get("kernel_source_hash") != kernel_source_hash(sources):
         return {"stale": True, "file": fname}
     return t
 
 
-def load_traffic(key):
-    """HBM bytes per launch of one headline kernel from the committed
+def load_traffic(key, name="h1_p6_32cubed"):
+    """HBM bytes per launch of one profiled kernel from the committed
     FETCH_SIZE / WRITE_SIZE summary: (bytes, detail), or (None, reason)."""
-    t = _load_record(TRAFFIC_FILE)
+    fname = name + "_traffic.json"
+    t = _load_record(fname, PROFILE_SETS[name][1])
     if t is None or t.get("stale"):
         return None, t
     k = t.get("kernels", {}).get(key)
     if k is None:
-        return None, {"missing": key, "file": TRAFFIC_FILE}
+        return None, {"missing": key, "file": fname}
     return k["bytes_per_launch"], dict(k, fetch_scale=t["fetch_scale"], write_scale=t["write_scale"],
                                        command=t["command"])
 
@@ -287,12 +298,14 @@ def _kernel_key(name):
     return None
 
 
-def summarize_profiles(stats_dir, fetch_dir, write_dir, command):
+def summarize_profiles(stats_dir, fetch_dir, write_dir, command, name="h1_p6_32cubed"):
     """Turn rocprofv3 CSV output of this script into the short text summary
     and the traffic record that bench.py reads.  stats_dir: --kernel-trace
     --stats run; fetch_dir / write_dir: --pmc FETCH_SIZE and --pmc WRITE_SIZE
-    runs (counters in KiB per dispatch), all of `bench.py --skip-extras`, so
-    that the headline kernels run on the headline mesh only."""
+    runs (counters in KiB per dispatch), all of `bench.py --skip-extras` (the
+    headline kernels on the headline mesh only) or of `bench.py
+    --backward-only` (name backward_p4_16cubed_b8)."""
+    kernels, sources = PROFILE_SETS[name]
     lines = [f"command: {command}", ""]
     stats = _read_csvs(stats_dir, "kernel_stats.csv")
     lines.append(f"{'kernel':70s} {'calls':>6s} {'avg_us':>10s} {'min_us':>10s} {'max_us':>10s} {'pct':>6s}")
@@ -330,10 +343,10 @@ def summarize_profiles(stats_dir, fetch_dir, write_dir, command):
     out = None
     if None not in (fc, wc):
         sf, sw = (1 << 30) / fc, (1 << 30) / wc
-        out = {"kernel_source_hash": kernel_source_hash(), "fetch_scale": sf, "write_scale": sw, "command": command,
-               "kernels": {}}
+        out = {"kernel_source_hash": kernel_source_hash(sources), "fetch_scale": sf, "write_scale": sw,
+               "command": command, "kernels": {}}
         lines.append(f"scale: fetch {sf:.4f}, write {sw:.4f}")
-        for key, needle in KERNELS.items():
+        for key, needle in kernels.items():
             fk, nf = pick(res["fetch"], needle)
             wk, nw = pick(res["write"], needle)
             if fk is None or wk is None:
@@ -423,6 +436,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=16384, help="elements of the all-threads CPU oracle sample")
     ap.add_argument("--cpu-sample-1t", type=int, default=1024, help="elements of the one-thread CPU oracle sample")
     ap.add_argument("--skip-extras", action="store_true")
+    ap.add_argument("--backward-only", action="store_true",
+                    help="only the copy calibration and the backward leg (for profiling its kernels)")
     ap.add_argument("--pencil-small", action="store_true",
                     help="FP32 pencil eigenvalues on the 35,937-row mesh instead of the 274,625-row one")
     ap.add_argument("--summarize-profiles", nargs=3, metavar=("STATS_DIR", "FETCH_DIR", "WRITE_DIR"),
@@ -443,12 +458,12 @@ def main():
         print(text)
         return
     if args.summarize_profiles:
-        text, traffic = summarize_profiles(*args.summarize_profiles, args.profile_command)
+        text, traffic = summarize_profiles(*args.summarize_profiles, args.profile_command, args.profile_name)
         os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
         with open(os.path.join(ROOT, "profiles", args.profile_name + ".txt"), "w") as f:
             f.write(text)
         if traffic is not None:
-            with open(os.path.join(ROOT, "profiles", TRAFFIC_FILE), "w") as f:
+            with open(os.path.join(ROOT, "profiles", args.profile_name + "_traffic.json"), "w") as f:
                 json.dump(traffic, f, indent=1)
         print(text)
         return
@@ -463,6 +478,12 @@ def main():
     import paper_2210_12253_amd as lor
 
     dev = torch.device("cuda:0")
+    if args.backward_only:
+        log("copy calibration")
+        calib = copy_calibration(torch, dev)
+        log("backward")
+        print(json.dumps({"backward": bench_backward(lor, meshgen, args, dev), "copy_calibration": calib}))
+        return
     log("building the headline inputs")
     m = meshgen.config_mesh("c3_h1_p6_curved")
     p, nel, ndofs = m["p"], m["nel"], m["ndofs"]
@@ -687,10 +708,15 @@ def bench_backward(lor, meshgen, args, dev):
             ms = time_it(lambda: lor.lor_assemble_backward(pat, ed, x, k, 1.0, gv, dtype=dt, workspace=ws),
                          args.steps, args.warmup)
             fwd = time_it(lambda: lor.lor_assemble_h1(pat, ed, x, k, 1.0, dtype=dt), args.steps, args.warmup)
+            roof = roofline_of(algorithmic_bytes_backward(m["nel"], m["p"], m["ndofs"], pat.nnz, dt.itemsize, 8), ms)
+            # HBM bytes of the backward kernel (and of the vertex gather that
+            # follows it) from the committed counter summary, if it is current
+            tb, detail = load_traffic(f"backward_{name}", "backward_p4_16cubed_b8")
+            tg, _ = load_traffic("gather_vertices", "backward_p4_16cubed_b8")
+            roof.update(kernel=f"k_h1_backward<4,{'double' if name == 'f64' else 'float'}> + k_gather_vertices",
+                        traffic=None if tb is None or tg is None else tb + tg, traffic_detail=detail)
             res[name] = {"ms": ms, "value": 8 * m["ndofs"] / (ms * 1e-3) / 1e6, "unit": "MDOF/s (batch*rows)",
-                         "forward_batch8_ms": fwd,
-                         "roofline": roofline_of(algorithmic_bytes_backward(m["nel"], m["p"], m["ndofs"], pat.nnz,
-                                                                            dt.itemsize, 8), ms)}
+                         "forward_batch8_ms": fwd, "roofline": roof}
         res["workload"] = "backward of H1 p=4, 16^3 curved hexes, batch 8 kappa fields"
         res["speedup_f32_vs_f64"] = res["f64"]["ms"] / res["f32"]["ms"]
         return res
