@@ -79,6 +79,22 @@ __device__ __forceinline__ void lds_barrier() {
   __asm__ volatile("" ::: "memory");
 }
 
+// Box lattices (H1 meshes whose vertex at lattice point (X, Y, Z) has id
+// X + LX (Y + LY Z)): the row of a point holds its in-box 3 x 3 x 3
+// neighbours in (dz, dy, dx) order.  box_count: neighbours of a point along
+// one axis of L >= 2 points; box_prefix: their sum over the points before X
+// (X in [0, L]); box_row_start: the CSR row start of point (X, Y, Z).
+__host__ __device__ __forceinline__ int box_count(int64_t X, int64_t L) { return 1 + (X > 0) + (X < L - 1); }
+__host__ __device__ __forceinline__ int64_t box_prefix(int64_t X, int64_t L) {
+  return X == 0 ? 0 : 3 * X - 1 - (X == L ? 1 : 0);
+}
+__host__ __device__ __forceinline__ int64_t box_row_start(int64_t X, int64_t Y, int64_t Z, int64_t LX, int64_t LY,
+                                                          int64_t LZ) {
+  const int64_t SX = 3 * LX - 2, SY = 3 * LY - 2;
+  const int64_t cz = box_count(Z, LZ), cyz = box_count(Y, LY) * cz;
+  return box_prefix(Z, LZ) * SY * SX + cz * box_prefix(Y, LY) * SX + cyz * box_prefix(X, LX);
+}
+
 template <typename T>
 inline T* dev_at(const lor_sched* s, size_t off) {
   return reinterpret_cast<T*>(static_cast<char*>(s->dev) + off);

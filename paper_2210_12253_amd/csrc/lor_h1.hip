@@ -443,6 +443,7 @@ static int dispatch_h1(int p, const lor_sched* s, int batch, const int32_t* ed, 
 template <typename T, typename R>
 int dispatch_owner(int p, const lor_sched* s, int batch, const int32_t* ed, const double* x, const void* k,
                    double beta, const int32_t* rp, void* v, unsigned f, double thr, int32_t* diag, hipStream_t st);
+bool owner_fits(const lor_sched* s, int tsize);
 
 // Shared argument checks of the value calls.
 int check_sched(const lor_sched* s, int space, int p, int64_t nel, int64_t nrows) {
@@ -484,8 +485,10 @@ extern "C" int lor_assemble_h1(int p, int64_t nel, int64_t ndofs, int batch, con
     LOR_FAIL(LOR_EUNSUPPORTED, "LOR_OWNER: the mesh has no owner-computes schedule (its element lattices do not "
                                "continue across faces in one orientation, or a row is not a full lattice stencil)");
   hipStream_t st = as_stream(stream);
-  // default: owner-computes wherever the schedule has it (faster in both forms)
-  const bool owner = sched->owner && !(flags & LOR_COLORED);
+  // default: owner-computes wherever the schedule has it (faster in both
+  // forms) and its buffer ranges allow
+  const bool owner = sched->owner && !(flags & LOR_COLORED) &&
+                     ((flags & LOR_OWNER) || owner_fits(sched, dtype == LOR_F64 ? 8 : 4));
   const unsigned fb = flags & LOR_FP64_FALLBACK;
   if (dtype == LOR_F64)
     return owner ? dispatch_owner<double, double>(p, sched, batch, elem_dofs, coords, kappa, beta, row_ptr, values,

@@ -3,9 +3,10 @@
 //
 // The coloured kernel (lor_h1.hip) lets every element add into the rows it
 // touches, so the rows on element faces are written piecewise by up to eight
-// launches.  This kernel works on the global lattice of a box-shaped mesh
-// instead (the pattern call checks that the mesh is one: lattice point
-// (X, Y, Z) has vertex id base(Y, Z) + X, cell (X, Y, Z) belongs to element
+// launches.  This kernel works on the global lattice of a box lattice instead
+// (the pattern call checks that the mesh is one: lattice point (X, Y, Z) of
+// the (LX, LY, LZ) points has vertex id X + LX (Y + LY Z), its row starts at
+// box_row_start(X, Y, Z), and cell (X, Y, Z) belongs to element
 // elem3d(X / p, Y / p, Z / p) at local subelement (X % p, Y % p, Z % p)):
 //
 //   * one wave = one worker, no workgroup barriers.  It takes a tile of 8 x 8
@@ -22,7 +23,10 @@
 //     column and row of a tile are integrated twice (by this tile and its
 //     neighbour): 64 cells per 49 rows;
 //   * the finished rows of each x-line are consecutive rows of the matrix;
-//     they are staged in LDS and stored as one contiguous span per line;
+//     they are staged in LDS and stored as one contiguous span per line, with
+//     a fixed number of (predicated) store instructions per step: with a
+//     data-dependent count the compiler cannot tell how many stores are still
+//     in flight when a prefetched value is used, and waits for all of them;
 //   * a segment that starts above the bottom first integrates the layer below
 //     it to build the carry; the topmost segment ends with the top plane,
 //     whose rows only hold the carry.
@@ -46,16 +50,14 @@ constexpr int kOwnTile = 8;                  // cells per tile side (one wave: 8
 constexpr int kOwnStride = kOwnTile - 1;     // tiles overlap by one cell
 constexpr int kOwnPts = (kOwnTile + 1) * (kOwnTile + 1);  // lattice points of one tile plane
 
-// Layers integrated per step and LDS slab of one wave.  The FP64 form runs
-// one wave per SIMD: its integration wants ~250 VGPRs, and with the carry a
-// second wave per SIMD spills (measured at the headline size: 1.10 ms at one
-// wave, 1.28 ms at two with spills, 1.14 ms at two with the carry in LDS,
-// 1.18 ms with two cells per lane and step).  The FP32 form runs two waves
-// per SIMD.  LPS > 1 (several layers per lane and step) is supported but not
-// used.
+// LDS slab of one wave and waves per SIMD.  The FP64 form runs one wave per
+// SIMD: its integration wants ~250 VGPRs, and with the carry a second wave per
+// SIMD spills (measured at the headline size: 1.10 ms at one wave, 1.28 ms at
+// two with spills, 1.14 ms at two with the carry in LDS, 1.18 ms with two cells
+// per lane and step).  The FP32 form runs two waves per SIMD.
 template <typename T, typename R>
 struct OwnCfg {
-  static constexpr int LPS = 1;                        // layers per step
+  static constexpr int LPS = 1;                        // cell layers per step
   static constexpr int NPL = LPS + 1;                 // lattice planes in LDS (ring)
   static constexpr int WPE = sizeof(R) == 8 ? 1 : 2;  // waves per SIMD (second __launch_bounds__ argument)
   // cell matrices [pair][lane]; once the row sums have read them, the finished
@@ -96,22 +98,58 @@ __host__ __device__ constexpr int own_off(int u, int v) {
   return ((v & 1) - (u & 1) + 1) + 3 * (((v >> 1) & 1) - ((u >> 1) & 1) + 1) + 9 * ((v >> 2) - (u >> 2) + 1);
 }
 
+// Most entries of one x-line's span (8 rows of 2 or 3 x-offsets, times 3 x 3),
+// and the store instructions per lane that cover it.
+constexpr int kOwnSpanMax = (2 + 3 * (kOwnTile - 1)) * 9;
+constexpr int kOwnSpanIters = (kOwnSpanMax + 63) / 64;
+
+// Memory is accessed through buffer resources (base, byte range): an access
+// outside the range reads 0 or is dropped, so every load and store is issued
+// unconditionally, in a fixed number per step, and no register is zeroed
+// before a load.  A predicated (exec-masked) access would make the compiler
+// wait for everything in flight before the register is reused or when the
+// number of stores in flight is not known; with one wave per SIMD nothing
+// hides those waits.
+constexpr uint32_t kOwnOut = 0xFFFFFFFFu;  // byte offset outside every range (ranges end below 2^32 - 256)
+constexpr int kOwnRsrcWord3 = 0x00020000;  // raw (untyped) buffer access on gfx9-family parts
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t own_rsrc(const void* base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, static_cast<int>(bytes), kOwnRsrcWord3);
+}
+__device__ __forceinline__ double own_ld_f64(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, static_cast<int>(off), 0, 0));
+}
+__device__ __forceinline__ float own_ld_f32(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, static_cast<int>(off), 0, 0));
+}
+__device__ __forceinline__ int32_t own_ld_i32(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  return __builtin_bit_cast(int32_t, __builtin_amdgcn_raw_buffer_load_b32(r, static_cast<int>(off), 0, 0));
+}
+// non-temporal store (the values are not read again by this launch)
+constexpr int kOwnStoreNT = 2;
+__device__ __forceinline__ void own_st(double x, __amdgpu_buffer_rsrc_t r, uint32_t off) {
+  using u2 = __attribute__((ext_vector_type(2))) unsigned;
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, x), r, static_cast<int>(off), 0, kOwnStoreNT);
+}
+__device__ __forceinline__ void own_st(float x, __amdgpu_buffer_rsrc_t r, uint32_t off) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, x), r, static_cast<int>(off), 0, kOwnStoreNT);
+}
+
 template <int P, typename T, typename R>
 __global__ __launch_bounds__(64, (OwnCfg<T, R>::WPE)) void k_h1_owner(
     int nex, int ney, int nez, int ntx, int seglen, const int32_t* __restrict__ elem3d,
-    const int32_t* __restrict__ base, const double* __restrict__ coords, const T* __restrict__ kappa, T beta,
-    const int32_t* __restrict__ row_ptr, int64_t nel, int64_t nnz, T* __restrict__ values, unsigned flags,
-    R det_thresh, int32_t* __restrict__ diag) {
+    const double* __restrict__ coords, const T* __restrict__ kappa, T beta, int64_t nel, int64_t nnz,
+    T* __restrict__ values, unsigned flags, R det_thresh, int32_t* __restrict__ diag) {
   using C = OwnCfg<T, R>;
-  constexpr int NSUB = P * P * P, LPS = C::LPS, NPL = C::NPL;
+  constexpr int NSUB = P * P * P, NPL = C::NPL;
+  static_assert(C::LPS == 1, "one cell layer per step");
   __shared__ __align__(16) unsigned char sSlab[C::SLAB];
   __shared__ double sPt[NPL][kOwnPts * 3];  // lattice planes, ring buffer indexed by Z % NPL
-  __shared__ int32_t sRp[64];               // row pointers of the tile's rows in the plane being stored
   R* const sCell = reinterpret_cast<R*>(sSlab);
   T* const sStg = reinterpret_cast<T*>(sSlab);
 
   const int NXc = nex * P, NYc = ney * P, NZc = nez * P;  // cells per axis
-  const int LY = NYc + 1;                                   // lattice points per plane along y
+  const int LX = NXc + 1, LY = NYc + 1, LZ = NZc + 1;     // lattice points per axis
   const int lane = threadIdx.x;
   const int ti = blockIdx.x % ntx, tj = blockIdx.x / ntx;
   const int x0 = kOwnStride * ti, y0 = kOwnStride * tj;
@@ -119,6 +157,10 @@ __global__ __launch_bounds__(64, (OwnCfg<T, R>::WPE)) void k_h1_owner(
   const int ze = zs + seglen < NZc ? zs + seglen : NZc;
   kappa += static_cast<int64_t>(blockIdx.z) * nel * NSUB;
   values += static_cast<int64_t>(blockIdx.z) * nnz;
+  // byte ranges below 2^32: checked by the launch
+  const auto rX = own_rsrc(coords, static_cast<uint32_t>(static_cast<int64_t>(LX) * LY * LZ * 24));
+  const auto rK = own_rsrc(kappa, static_cast<uint32_t>(nel * NSUB * static_cast<int64_t>(sizeof(T))));
+  const auto rE = own_rsrc(elem3d, static_cast<uint32_t>(nel * 4));
 
   const int lx = lane & 7, ly = lane >> 3;
   const int cX = x0 + lx, cY = y0 + ly;                // this lane's cell / row column (x, y)
@@ -132,49 +174,50 @@ __global__ __launch_bounds__(64, (OwnCfg<T, R>::WPE)) void k_h1_owner(
     Y = y0 + pidx / (kOwnTile + 1);
     return pidx < kOwnPts && X <= NXc && Y <= NYc;
   };
-  // vertex ids of plane Z (-1 where absent)
-  auto load_vid = [&](int Z, int32_t (&v)[2]) {
+  // coordinates of the tile's points of plane Z (vertex X + LX (Y + LY Z));
+  // absent points read 0 and are never used
+  auto load_xyz = [&](int Z, double (&xq)[2][3]) {
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
       int X, Y;
-      v[j] = -1;
-      if (Z <= NZc && pt_xy(j, X, Y)) v[j] = base[static_cast<int64_t>(Z) * LY + Y] + X;
+      const bool in = Z <= NZc && pt_xy(j, X, Y);
+      // absent points: three distinct offsets past the range (equal ones would
+      // be merged into one load whose result is then copied, which waits)
+      const uint32_t o =
+          in ? static_cast<uint32_t>(24 * (X + LX * (Y + static_cast<int64_t>(LY) * Z))) : kOwnOut - 16u;
+      xq[j][0] = own_ld_f64(rX, o);
+      xq[j][1] = own_ld_f64(rX, o + 8u);
+      xq[j][2] = own_ld_f64(rX, o + 16u);
     }
   };
-  auto load_xyz = [&](const int32_t (&v)[2], double (&xq)[2][3]) {
-#pragma unroll
-    for (int j = 0; j < 2; ++j)
-      if (v[j] >= 0) {
-        const int64_t g = 3 * static_cast<int64_t>(v[j]);
-        xq[j][0] = coords[g + 0];
-        xq[j][1] = coords[g + 1];
-        xq[j][2] = coords[g + 2];
-      }
-  };
-  // element of this lane's cell in layer Z (-1 where absent)
-  auto load_elem = [&](int Z, int32_t& el) {
-    el = -1;
-    if (cell_in && Z < NZc) el = elem3d[(static_cast<int64_t>(Z / P) * ney + cY / P) * nex + cX / P];
-  };
-  auto load_kap = [&](int Z, int32_t el, T& k) {
-    k = T(0);
-    if (el >= 0) k = kappa[static_cast<int64_t>(el) * NSUB + (cX % P) + P * ((cY % P) + P * (Z % P))];
-  };
-  auto load_rp = [&](int Z, int32_t& rp) {
-    rp = 0;
-    if (row_in && Z <= NZc) rp = row_ptr[base[static_cast<int64_t>(Z) * LY + cY] + cX];
-  };
-  auto stage_plane = [&](int Z, const int32_t (&v)[2], const double (&xq)[2][3]) {
+  auto stage_plane = [&](int Z, const double (&xq)[2][3]) {
     double* pl = sPt[Z % NPL];
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
       const int pidx = lane + 64 * j;
-      if (pidx < kOwnPts && v[j] >= 0) {
+      if (pidx < kOwnPts) {
         pl[3 * pidx + 0] = xq[j][0];
         pl[3 * pidx + 1] = xq[j][1];
         pl[3 * pidx + 2] = xq[j][2];
       }
     }
+  };
+  // element of this lane's cell in layer Z (0 where the cell is absent)
+  auto load_elem = [&](int Z) {
+    const bool in = cell_in && Z < NZc;
+    return own_ld_i32(rE, in ? static_cast<uint32_t>(4 * ((static_cast<int64_t>(Z / P) * ney + cY / P) * nex + cX / P))
+                             : kOwnOut);
+  };
+  // coefficient of the cell in layer Z of element el (0 where absent)
+  auto load_kap = [&](int Z, int32_t el) {
+    const bool in = cell_in && Z < NZc;
+    const uint32_t o =
+        in ? static_cast<uint32_t>(sizeof(T) * (static_cast<int64_t>(el) * NSUB + (cX % P) + P * ((cY % P) + P * (Z % P))))
+           : kOwnOut;
+    if constexpr (sizeof(T) == 8)
+      return own_ld_f64(rK, o);
+    else
+      return own_ld_f32(rK, o);
   };
 
   const int zfirst = zs > 0 ? zs - 1 : zs;  // a segment above the bottom starts one layer lower
@@ -182,72 +225,46 @@ __global__ __launch_bounds__(64, (OwnCfg<T, R>::WPE)) void k_h1_owner(
   // plane NZc, whose rows only hold the carry
   const int zend = ze == NZc ? NZc + 1 : ze;
 
-  // Software pipeline, per step of LPS layers from Z: planes Z + 1 .. Z + LPS
-  // are staged from registers, and loads for the next step are issued
-  // (coordinates of its planes, vertex ids one step further, coefficients of
-  // its layers, elements one step further, row pointers of its planes).
-  int32_t vq[LPS][2], vnext[LPS][2];
-  double xq[LPS][2][3] = {};
-  int32_t elq[LPS], elnext[LPS], rpq[LPS];
-  T kq[LPS];
+  // Software pipeline, in place: at step Z the plane Z + 1 is staged from
+  // registers loaded one step earlier and plane Z + 2 is loaded into them;
+  // the coefficient of layer Z was loaded one step earlier, that of layer
+  // Z + 1 is loaded after the integration from the element loaded one step
+  // earlier, which is then replaced by the element of layer Z + 2.
+  double xq[2][3];
+  T kq;
+  int32_t el;
   {
-    int32_t v0[2];
-    double xp[2][3] = {};
-    load_vid(zfirst, v0);
-    load_xyz(v0, xp);
-    stage_plane(zfirst, v0, xp);
+    double xp[2][3];
+    load_xyz(zfirst, xp);
+    stage_plane(zfirst, xp);
+    load_xyz(zfirst + 1, xq);
+    el = load_elem(zfirst);
+    kq = load_kap(zfirst, el);
+    el = load_elem(zfirst + 1);
+    // as many stores as a step issues, all outside their (empty) range: the
+    // loop is then entered with the same memory operations in flight after
+    // each prefetch as on every later step, so the waits the compiler places
+    // at the loop head (merged over both ways in) need not drain the prefetches
+    const auto rNone = own_rsrc(values, 0u);
 #pragma unroll
-    for (int L = 0; L < LPS; ++L) {
-      load_vid(zfirst + 1 + L, vq[L]);
-      load_xyz(vq[L], xq[L]);
-      load_vid(zfirst + 1 + LPS + L, vnext[L]);
-      load_elem(zfirst + L, elq[L]);
-      load_kap(zfirst + L, elq[L], kq[L]);
-      load_rp(zfirst + L, rpq[L]);
-      load_elem(zfirst + LPS + L, elnext[L]);
-    }
+    for (int i = 0; i < 8 * kOwnSpanIters; ++i)  // distinct offsets, so that none is merged away
+      own_st(T(0), rNone, static_cast<uint32_t>((64 * i + lane) * sizeof(T)));
   }
 
   double carry[18];
 #pragma unroll
   for (int o = 0; o < 18; ++o) carry[o] = 0.0;
 
-  for (int Z = zfirst; Z < zend; Z += LPS) {
-#pragma unroll
-    for (int L = 0; L < LPS; ++L) stage_plane(Z + 1 + L, vq[L], xq[L]);
-    int32_t elcur[LPS], rpcur[LPS];
-    T kcur[LPS];
-#pragma unroll
-    for (int L = 0; L < LPS; ++L) {
-      elcur[L] = elq[L];
-      kcur[L] = kq[L];
-      rpcur[L] = rpq[L];
-      load_xyz(vnext[L], xq[L]);
-      vq[L][0] = vnext[L][0];
-      vq[L][1] = vnext[L][1];
-      load_vid(Z + 1 + 2 * LPS + L, vnext[L]);
-      elq[L] = elnext[L];
-      load_kap(Z + LPS + L, elq[L], kq[L]);
-      load_elem(Z + 2 * LPS + L, elnext[L]);
-      load_rp(Z + LPS + L, rpq[L]);
-    }
+  for (int Z = zfirst; Z < zend; ++Z) {
+    stage_plane(Z + 1, xq);
+    load_xyz(Z + 2, xq);
     __builtin_amdgcn_wave_barrier();
 
-    // the cells (cX, cY, Z + L): 36 entries each, straight into the slab for
-    // one layer per step, in registers for several
-    R ent[LPS > 1 ? LPS : 1][LPS > 1 ? 36 : 1];
-#pragma unroll
-    for (int L = 0; L < LPS; ++L) {
-      const int Zl = Z + L;
-      R* out = LPS > 1 ? &ent[L][0] : sCell + lane;
-      constexpr int OS = LPS > 1 ? 1 : 64;  // distance between two entries of the cell
-      if constexpr (LPS > 1) {
-#pragma unroll
-        for (int i = 0; i < 36; ++i) ent[L][i] = R(0);
-      }
-      if (elcur[L] < 0) continue;
-      const double* pz0 = sPt[Zl % NPL];
-      const double* pz1 = sPt[(Zl + 1) % NPL];
+    // the cell (cX, cY, Z): its 36 entries into the slab
+    if (cell_in && Z < NZc) {
+      const double* pz0 = sPt[Z % NPL];
+      const double* pz1 = sPt[(Z + 1) % NPL];
+      R* out = sCell + lane;
       auto load_X = [&](double (&X)[8][3]) {
 #pragma unroll
         for (int v = 0; v < 8; ++v) {
@@ -257,10 +274,10 @@ __global__ __launch_bounds__(64, (OwnCfg<T, R>::WPE)) void k_h1_owner(
           for (int d = 0; d < 3; ++d) X[v][d] = pl[3 * pidx + d];
         }
       };
-      const R kap = static_cast<R>(kcur[L]);
+      const R kap = static_cast<R>(kq);
       // counted once: a cell in a tile's last column (row) is also the first
       // column (row) of the next tile, which counts it
-      const bool own = Zl >= zs && lx < kOwnStride && ly < kOwnStride;
+      const bool own = Z >= zs && lx < kOwnStride && ly < kOwnStride;
       bool fallback = false;
       if constexpr (!std::is_same<R, double>::value) {
         if (flags & LOR_FP64_FALLBACK) {
@@ -285,100 +302,100 @@ __global__ __launch_bounds__(64, (OwnCfg<T, R>::WPE)) void k_h1_owner(
 #pragma unroll
         for (int u = 0; u < 8; ++u)
 #pragma unroll
-          for (int v = u; v < 8; ++v) out[pair_index(u, v) * OS] = h1_entry<R>(F, u, v);
+          for (int v = u; v < 8; ++v) out[pair_index(u, v) * 64] = h1_entry<R>(F, u, v);
         if (!ok && own && diag) atomicAdd(&diag[1], 1);
-      }
-      if (fallback) {
-        // FP32 only: computed in the slab (then read back for several layers)
+      } else {
+        // FP32 only: FP64 geometry, written to the slab
         const bool ok = own_fp64_fallback(pz0, pz1, lx, ly, static_cast<double>(kap), static_cast<double>(beta),
-                                          reinterpret_cast<float*>(sCell + lane));
-        if constexpr (LPS > 1) {
-#pragma unroll
-          for (int i = 0; i < 36; ++i) ent[L][i] = sCell[i * 64 + lane];
-        }
+                                          reinterpret_cast<float*>(out));
         if (own && diag) {
           atomicAdd(&diag[0], 1);
           if (!ok) atomicAdd(&diag[1], 1);
         }
       }
     }
+    kq = load_kap(Z + 1, el);
+    el = load_elem(Z + 2);
+    __builtin_amdgcn_wave_barrier();
 
+    // row (cX, cY) of plane Z: the carry (c = 1 corners, layer Z - 1) + this
+    // layer's c = 0 corners; this layer's c = 1 corners are the next carry
+    double acc[27];
 #pragma unroll
-    for (int L = 0; L < LPS; ++L) {
-      const int Zl = Z + L;
-      if (Zl >= zend) break;
-      __builtin_amdgcn_wave_barrier();
-      if constexpr (LPS > 1) {
+    for (int o = 0; o < 27; ++o) acc[o] = o < 18 ? carry[o] : 0.0;
 #pragma unroll
-        for (int i = 0; i < 36; ++i) sCell[i * 64 + lane] = ent[L][i];
-      }
-      sRp[lane] = rpcur[L];
-      __builtin_amdgcn_wave_barrier();
-      // row (cX, cY) of plane Zl: the carry (c = 1 corners, layer Zl - 1) +
-      // this layer's c = 0 corners; this layer's c = 1 corners are the next carry
-      double acc[27];
+    for (int o = 0; o < 18; ++o) carry[o] = 0.0;
+    if (row_in && Z < NZc) {
 #pragma unroll
-      for (int o = 0; o < 27; ++o) acc[o] = o < 18 ? carry[o] : 0.0;
+      for (int b = 0; b < 2; ++b)
 #pragma unroll
-      for (int o = 0; o < 18; ++o) carry[o] = 0.0;
-      if (row_in && Zl < NZc) {
+        for (int a = 0; a < 2; ++a) {
+          const int sx = lx - a, sy = ly - b;
+          if (sx >= 0 && sy >= 0 && x0 + sx < NXc && y0 + sy < NYc) {
+            const R* cm = sCell + sx + 8 * sy;
+            const int u0 = a + 2 * b, u1 = a + 2 * b + 4;
 #pragma unroll
-        for (int b = 0; b < 2; ++b)
-#pragma unroll
-          for (int a = 0; a < 2; ++a) {
-            const int sx = lx - a, sy = ly - b;
-            if (sx >= 0 && sy >= 0 && x0 + sx < NXc && y0 + sy < NYc) {
-              const R* cm = sCell + sx + 8 * sy;
-              const int u0 = a + 2 * b, u1 = a + 2 * b + 4;
-#pragma unroll
-              for (int v = 0; v < 8; ++v) {
-                acc[own_off(u0, v)] += static_cast<double>(cm[pair_index(u0, v) * 64]);
-                carry[own_off(u1, v)] += static_cast<double>(cm[pair_index(u1, v) * 64]);
-              }
+            for (int v = 0; v < 8; ++v) {
+              acc[own_off(u0, v)] += static_cast<double>(cm[pair_index(u0, v) * 64]);
+              carry[own_off(u1, v)] += static_cast<double>(cm[pair_index(u1, v) * 64]);
             }
           }
-      }
-      __builtin_amdgcn_wave_barrier();
-      if (Zl < zs) continue;  // the layer below the segment: carry only
+        }
+    }
+    __builtin_amdgcn_wave_barrier();
+    if (Z < zs) continue;  // the layer below the segment: carry only
 
-      // stage the owned rows of each x-line in CSR order: a row holds
-      // (x-offsets) x (y-offsets) x (z-offsets) entries, 2 per axis at a
-      // lattice end and 3 elsewhere
-      const int ylo = cY > 0, yhi = cY < NYc, zlo = Zl > 0, zhi = Zl < NZc;
-      const int ny = 1 + ylo + yhi, nyz = ny * (1 + zlo + zhi);
-      const int xfirst = ti == 0 ? 0 : 1;  // first owned row of the tile's x-lines
-      if (row_own) {
-        const int xlo = cX > 0, xhi = cX < NXc, nx = 1 + xlo + xhi;
-        int before = 0;  // x-offset counts of the owned rows before this one in its line
-        for (int x = xfirst; x < lx; ++x) before += 1 + (x0 + x > 0) + (x0 + x < NXc);
-        T* row = sStg + 27 * 8 * ly + before * nyz + (zlo * ny + ylo) * nx + xlo;
+    // stage the owned rows of each x-line in CSR order: a row holds
+    // (x-offsets) x (y-offsets) x (z-offsets) entries, 2 per axis at a
+    // lattice end and 3 elsewhere
+    const int ylo = cY > 0, yhi = cY < NYc, zlo = Z > 0, zhi = Z < NZc;
+    const int ny = 1 + ylo + yhi, nyz = ny * (1 + zlo + zhi);
+    const int xfirst = ti == 0 ? 0 : 1;  // first owned row of the tile's x-lines
+    if (row_own) {
+      const int xlo = cX > 0, xhi = cX < NXc, nx = 1 + xlo + xhi;
+      int before = 0;  // x-offset counts of the owned rows before this one in its line
+      for (int x = xfirst; x < lx; ++x) before += 1 + (x0 + x > 0) + (x0 + x < NXc);
+      T* row = sStg + 27 * 8 * ly + before * nyz + (zlo * ny + ylo) * nx + xlo;
 #pragma unroll
-        for (int dz = -1; dz <= 1; ++dz)
+      for (int dz = -1; dz <= 1; ++dz)
 #pragma unroll
-          for (int dy = -1; dy <= 1; ++dy)
+        for (int dy = -1; dy <= 1; ++dy)
 #pragma unroll
-            for (int dx = -1; dx <= 1; ++dx) {
-              const bool ok = (dx >= 0 || xlo) && (dx <= 0 || xhi) && (dy >= 0 || ylo) && (dy <= 0 || yhi) &&
-                              (dz >= 0 || zlo) && (dz <= 0 || zhi);
-              if (ok)
-                row[dz * nx * ny + dy * nx + dx] = static_cast<T>(acc[(dx + 1) + 3 * (dy + 1) + 9 * (dz + 1)]);
-            }
-      }
-      __builtin_amdgcn_wave_barrier();
-      // one contiguous span per owned x-line
-      const int xlast = x0 + 7 < NXc ? x0 + 7 : NXc;  // last owned row of the lines
-      int span_x = 0;
-      for (int X = x0 + xfirst; X <= xlast; ++X) span_x += 1 + (X > 0) + (X < NXc);
-      for (int l = tj == 0 ? 0 : 1; l < 8; ++l) {
-        const int Y = y0 + l;
-        if (Y > NYc) break;
-        const int span = span_x * (1 + (Y > 0) + (Y < NYc)) * (1 + zlo + zhi);
-        T* dst = values + sRp[xfirst + 8 * l];
-        const T* src = sStg + 27 * 8 * l;
-        for (int t = lane; t < span; t += 64) __builtin_nontemporal_store(src[t], dst + t);
+          for (int dx = -1; dx <= 1; ++dx) {
+            const bool ok = (dx >= 0 || xlo) && (dx <= 0 || xhi) && (dy >= 0 || ylo) && (dy <= 0 || yhi) &&
+                            (dz >= 0 || zlo) && (dz <= 0 || zhi);
+            if (ok) row[dz * nx * ny + dy * nx + dx] = static_cast<T>(acc[(dx + 1) + 3 * (dy + 1) + 9 * (dz + 1)]);
+          }
+    }
+    __builtin_amdgcn_wave_barrier();
+    // one contiguous span per owned x-line, through a buffer resource over
+    // exactly that span (empty for the lines the tile does not own)
+    const int xlast = x0 + 7 < NXc ? x0 + 7 : NXc;  // last owned row of the lines
+    int span_x = 0;
+    for (int X = x0 + xfirst; X <= xlast; ++X) span_x += 1 + (X > 0) + (X < NXc);
+#pragma unroll
+    for (int l = 0; l < 8; ++l) {
+      const int Y = y0 + l;
+      const bool line = (l > 0 || tj == 0) && Y <= NYc;
+      const int span = line ? span_x * box_count(Y, LY) * (1 + zlo + zhi) : 0;
+      const auto rV = own_rsrc(values + (line ? box_row_start(x0 + xfirst, Y, Z, LX, LY, LZ) : 0),
+                               static_cast<uint32_t>(span * sizeof(T)));
+      const T* src = sStg + 27 * 8 * l;
+#pragma unroll
+      for (int it = 0; it < kOwnSpanIters; ++it) {
+        const int t = lane + 64 * it;
+        own_st(src[t < kOwnSpanMax ? t : kOwnSpanMax - 1], rV, static_cast<uint32_t>(t * sizeof(T)));
       }
     }
   }
+}
+
+// Whether the owner-computes kernel's buffer ranges (coordinates, one batch
+// entry's coefficients, the element grid) stay below 2^32 bytes.
+bool owner_fits(const lor_sched* s, int tsize) {
+  const int64_t nsub = static_cast<int64_t>(s->p) * s->p * s->p;
+  const int64_t lim = (int64_t(1) << 32) - 256;
+  return s->nrows * 24 < lim && s->nel * nsub * tsize < lim && s->nel * 4 < lim;
 }
 
 template <int P, typename T, typename R>
@@ -386,8 +403,12 @@ static int launch_owner(const lor_sched* sched, int batch, const void* kappa, do
                         const int32_t* row_ptr, void* values, unsigned flags, double thr, int32_t* diag,
                         hipStream_t st) {
   const int nex = sched->box[0], ney = sched->box[1], nez = sched->box[2];
-  if (nex < 1 || ney < 1 || nez < 1 || static_cast<int64_t>(nex) * ney * nez != sched->nel)
+  if (nex < 1 || ney < 1 || nez < 1 || static_cast<int64_t>(nex) * ney * nez != sched->nel ||
+      (static_cast<int64_t>(nex) * P + 1) * (static_cast<int64_t>(ney) * P + 1) * (static_cast<int64_t>(nez) * P + 1) !=
+          sched->nrows)
     LOR_FAIL(LOR_EINVAL, "the owner-computes schedule does not describe the mesh");
+  if (!owner_fits(sched, static_cast<int>(sizeof(T))))
+    LOR_FAIL(LOR_EUNSUPPORTED, "owner-computes kernel: coordinates or coefficients span 4 GiB or more");
   const int NXc = nex * P, NYc = ney * P, NZc = nez * P;
   const int64_t ntx = ceil_div(NXc, kOwnStride), nty = ceil_div(NYc, kOwnStride);
   const int64_t tiles = ntx * nty;
@@ -400,10 +421,11 @@ static int launch_owner(const lor_sched* sched, int batch, const void* kappa, do
   if (seglen < 8) seglen = std::min<int64_t>(8, NZc);
   nseg = ceil_div(NZc, seglen);
   dim3 grid(static_cast<unsigned>(tiles), static_cast<unsigned>(nseg), static_cast<unsigned>(batch));
+  (void)row_ptr;  // the rows start where the lattice puts them (the pattern call checked row_ptr)
   k_h1_owner<P, T, R><<<grid, 64, 0, st>>>(
       nex, ney, nez, static_cast<int>(ntx), static_cast<int>(seglen), dev_at<int32_t>(sched, sched->off_elem3d),
-      dev_at<int32_t>(sched, sched->off_base), coords, static_cast<const T*>(kappa), static_cast<T>(beta), row_ptr,
-      sched->nel, sched->nnz, static_cast<T*>(values), flags, static_cast<R>(thr), diag);
+      coords, static_cast<const T*>(kappa), static_cast<T>(beta), sched->nel, sched->nnz, static_cast<T*>(values),
+      flags, static_cast<R>(thr), diag);
   LOR_LAUNCHED("k_h1_owner");
   return LOR_OK;
 }

@@ -786,13 +786,6 @@ struct BoxLattice {
   int nx = 0, ny = 0, nz = 0;
 };
 
-// Neighbours of a lattice point along one axis of L points (L >= 2), and their
-// sum over the points before X (X in [0, L]).
-__host__ __device__ __forceinline__ int box_count(int64_t X, int64_t L) { return 1 + (X > 0) + (X < L - 1); }
-__host__ __device__ __forceinline__ int64_t box_prefix(int64_t X, int64_t L) {
-  return X == 0 ? 0 : 3 * X - 1 - (X == L ? 1 : 0);
-}
-
 // Element 0's vertices at local (0,0,0), (1,0,0), (0,1,0), (0,0,1): the lattice
 // strides, if the mesh is a box lattice.
 __global__ void k_box_probe(const int32_t* __restrict__ map, int p, int32_t* __restrict__ out) {
@@ -844,10 +837,7 @@ __global__ void k_box_row_ptr(int64_t LX, int64_t LY, int64_t LZ, int32_t* __res
     row_ptr[v] = static_cast<int32_t>(SX * SY * SZ);
     return;
   }
-  const int64_t X = v % LX, Y = (v / LX) % LY, Z = v / (LX * LY);
-  const int64_t cz = box_count(Z, LZ), cyz = box_count(Y, LY) * cz;
-  row_ptr[v] = static_cast<int32_t>(box_prefix(Z, LZ) * SY * SX + cz * box_prefix(Y, LY) * SX +
-                                    cyz * box_prefix(X, LX));
+  row_ptr[v] = static_cast<int32_t>(box_row_start(v % LX, (v / LX) % LY, v / (LX * LY), LX, LY, LZ));
 }
 
 // Columns of one lattice line (Y, Z) per workgroup: the line's rows are
