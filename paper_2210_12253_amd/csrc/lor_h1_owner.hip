@@ -351,10 +351,12 @@ __global__ __launch_bounds__(64, (OwnCfg<T, R>::WPE)) void k_h1_owner(
     const int ylo = cY > 0, yhi = cY < NYc, zlo = Z > 0, zhi = Z < NZc;
     const int ny = 1 + ylo + yhi, nyz = ny * (1 + zlo + zhi);
     const int xfirst = ti == 0 ? 0 : 1;  // first owned row of the tile's x-lines
+    const int xa = x0 + xfirst;          // first owned row of the lines
+    const int pxa = static_cast<int>(box_prefix(xa, LX));
     if (row_own) {
       const int xlo = cX > 0, xhi = cX < NXc, nx = 1 + xlo + xhi;
-      int before = 0;  // x-offset counts of the owned rows before this one in its line
-      for (int x = xfirst; x < lx; ++x) before += 1 + (x0 + x > 0) + (x0 + x < NXc);
+      // x-offset counts of the owned rows before this one in its line
+      const int before = static_cast<int>(box_prefix(cX, LX)) - pxa;
       T* row = sStg + 27 * 8 * ly + before * nyz + (zlo * ny + ylo) * nx + xlo;
 #pragma unroll
       for (int dz = -1; dz <= 1; ++dz)
@@ -369,17 +371,22 @@ __global__ __launch_bounds__(64, (OwnCfg<T, R>::WPE)) void k_h1_owner(
     }
     __builtin_amdgcn_wave_barrier();
     // one contiguous span per owned x-line, through a buffer resource over
-    // exactly that span (empty for the lines the tile does not own)
+    // exactly that span (empty for the lines the tile does not own).  Row
+    // starts are below nnz < 2^31; line Y of plane Z starts at lb and its
+    // rows from xa on at lb + cy cz box_prefix(xa), and line Y + 1 starts
+    // SX cy cz later
     const int xlast = x0 + 7 < NXc ? x0 + 7 : NXc;  // last owned row of the lines
-    int span_x = 0;
-    for (int X = x0 + xfirst; X <= xlast; ++X) span_x += 1 + (X > 0) + (X < NXc);
+    const int span_x = static_cast<int>(box_prefix(xlast + 1, LX)) - pxa;
+    const int cz = 1 + zlo + zhi, SX = 3 * LX - 2;
+    int lb = static_cast<int>(box_row_start(0, y0, Z, LX, LY, LZ));
 #pragma unroll
     for (int l = 0; l < 8; ++l) {
       const int Y = y0 + l;
+      const int cyz = box_count(Y, LY) * cz;
       const bool line = (l > 0 || tj == 0) && Y <= NYc;
-      const int span = line ? span_x * box_count(Y, LY) * (1 + zlo + zhi) : 0;
-      const auto rV = own_rsrc(values + (line ? box_row_start(x0 + xfirst, Y, Z, LX, LY, LZ) : 0),
-                               static_cast<uint32_t>(span * sizeof(T)));
+      const int span = line ? span_x * cyz : 0;
+      const auto rV = own_rsrc(values + (line ? lb + cyz * pxa : 0), static_cast<uint32_t>(span * sizeof(T)));
+      lb += SX * cyz;
       const T* src = sStg + 27 * 8 * l;
 #pragma unroll
       for (int it = 0; it < kOwnSpanIters; ++it) {
