@@ -67,12 +67,14 @@ struct BwCfg {
   static constexpr int TWE = NENTP / 4;
 };
 
-// Waves per SIMD to reserve registers for: FP64 keeps 108 FP64 accumulators
-// per lane, so one wave's worth of registers (the LDS of one workgroup admits
-// several workgroups per CU, each a wave or a few).
+// Waves per SIMD to reserve registers for: one.  A lane keeps 108
+// accumulators, the next batch entry's gathered cotangents and its 64 packed
+// pair indices in registers; at two waves per SIMD the FP32 form spills
+// (measured at p = 4, 16^3, batch 8: 0.192 ms at two waves with 57 spilled
+// registers, 0.143 ms at one).
 template <typename R>
 struct BwOcc {
-  static constexpr int WPE = sizeof(R) == 8 ? 1 : 2;
+  static constexpr int WPE = 1;
 };
 
 // Compact index of stencil entry (vertex (x,y,z), offset (dx,dy,dz)) inside
@@ -106,7 +108,6 @@ __global__ __launch_bounds__(BwCfg<P>::THREADS, (BwOcc<R>::WPE)) void k_h1_backw
   // arithmetic's precision (both are R values), which halves this buffer in
   // the FP32 form
   __shared__ R sGX[GW];
-  __shared__ uint16_t sK[64 * TH];      // compact index of each lane's 64 corner pairs, [pair][lane]
   const uint8_t* sTab = reinterpret_cast<const uint8_t*>(sTabW);
   R* sG = sGX;
   R* sXb = sGX;
@@ -179,22 +180,32 @@ __global__ __launch_bounds__(BwCfg<P>::THREADS, (BwOcc<R>::WPE)) void k_h1_backw
       for (int u = 0; u < 8; ++u)
 #pragma unroll
         for (int v = u; v < 8; ++v) Kt[pair_index(u, v)] = h1_entry<R>(F, u, v);
-      // compact index of the 64 ordered corner pairs inside the element's table
+    }
+    // compact index of the 64 ordered corner pairs inside the element's table,
+    // two 16-bit indices per register, the same for every batch entry
+    uint32_t kpair[32];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int x = si + (u & 1), y = sj + ((u >> 1) & 1), z = sk + (u >> 2);
+    for (int u = 0; u < 8; ++u) {
+      const int x = si + (u & 1), y = sj + ((u >> 1) & 1), z = sk + (u >> 2);
 #pragma unroll
-        for (int v = 0; v < 8; ++v)
-          sK[(u * 8 + v) * TH + tid] = static_cast<uint16_t>(compact_index<P>(
-              x, y, z, (v & 1) - (u & 1), ((v >> 1) & 1) - ((u >> 1) & 1), (v >> 2) - (u >> 2)));
+      for (int v = 0; v < 8; v += 2) {
+        const uint32_t i0 = static_cast<uint32_t>(
+            compact_index<P>(x, y, z, (v & 1) - (u & 1), ((v >> 1) & 1) - ((u >> 1) & 1), (v >> 2) - (u >> 2)));
+        const uint32_t i1 = static_cast<uint32_t>(compact_index<P>(
+            x, y, z, ((v + 1) & 1) - (u & 1), (((v + 1) >> 1) & 1) - ((u >> 1) & 1), ((v + 1) >> 2) - (u >> 2)));
+        kpair[(u * 8 + v) / 2] = i0 | (i1 << 16);
       }
     }
-    // the group's cotangent entries in compact (row-contiguous) order; the
-    // next batch entry's gather is issued before this entry's compute so its
-    // latency is hidden (the barriers wait on LDS only)
+    // the group's cotangent entries in compact (row-contiguous) order and the
+    // lane's coefficient: those of the next batch entry are loaded before this
+    // entry's compute (unconditionally: the last entry reloads itself), so
+    // that their latency is hidden behind it
+    const int64_t kofs = e * NSUB + s;
     T gv[NJ];
+    T kn;
 #pragma unroll
     for (int j = 0; j < NJ; ++j) gv[j] = gvals[gpos[j]];
+    kn = kappa[kofs];
     for (int b = 0; b < batch; ++b) {
       lds_barrier();  // the previous entry of the batch has been consumed
 #pragma unroll
@@ -202,27 +213,38 @@ __global__ __launch_bounds__(BwCfg<P>::THREADS, (BwOcc<R>::WPE)) void k_h1_backw
         const int i = tid + j * TH;
         if (i < ne * NENT) sG[i] = static_cast<R>(gv[j]);
       }
-      if (b + 1 < batch) {
-        const T* gn = gvals + static_cast<int64_t>(b + 1) * nnz;
+      const R kb = static_cast<R>(kn);
+      {
+        const int bn = b + 1 < batch ? b + 1 : b;
+        const T* gn = gvals + static_cast<int64_t>(bn) * nnz;
 #pragma unroll
         for (int j = 0; j < NJ; ++j) gv[j] = gn[gpos[j]];
+        kn = kappa[static_cast<int64_t>(bn) * nel * NSUB + kofs];
       }
       lds_barrier();
       if (act) {
-        const R kb = static_cast<R>(kappa[(static_cast<int64_t>(b) * nel + e) * NSUB + s]);
         const R* ge = sG + el * NENT;
         R gk = R(0);
-        // ordered pairs (u, v) and (v, u) both feed the unique entry {u, v}
+        // ordered pairs (u, v) and (v, u) both feed the unique entry {u, v};
+        // the 8 entries of a corner row are read first, so that the LDS reads
+        // overlap instead of each waiting for the previous one
 #pragma unroll
-        for (int u = 0; u < 8; ++u)
+        for (int u = 0; u < 8; ++u) {
+          R w[8];
 #pragma unroll
           for (int v = 0; v < 8; ++v) {
-            const R w = static_cast<R>(ge[sK[(u * 8 + v) * TH + tid]]);
-            gk += Kt[pair_index(u, v)] * w;
-            Wk[pair_index(u, v)] += kb * w;
-            Wm[pair_index(u, v)] += w;
+            const uint32_t kp = kpair[(u * 8 + v) / 2];
+            w[v] = ge[(v & 1) ? (kp >> 16) : (kp & 0xFFFFu)];
           }
-        gkappa[(static_cast<int64_t>(b) * nel + e) * NSUB + s] = static_cast<T>(gk);
+          __builtin_amdgcn_sched_barrier(0);  // keep the 8 reads ahead of their uses
+#pragma unroll
+          for (int v = 0; v < 8; ++v) {
+            gk += Kt[pair_index(u, v)] * w[v];
+            Wk[pair_index(u, v)] += kb * w[v];
+            Wm[pair_index(u, v)] += w[v];
+          }
+        }
+        gkappa[static_cast<int64_t>(b) * nel * NSUB + kofs] = static_cast<T>(gk);
       }
     }
     __syncthreads();  // sG is reused for the corner adjoints
