@@ -122,18 +122,56 @@ __global__ __launch_bounds__(BwCfg<P>::THREADS, (BwOcc<R>::WPE)) void k_h1_backw
     const int ne = nce - g * E < E ? nce - g * E : E;
     const int64_t e0 = cbeg + static_cast<int64_t>(g) * E;  // elements e0 .. e0+ne-1
     __syncthreads();
-    for (int i = tid; i < ne * NLOC; i += TH) {
-      const int el = i / NLOC;
-      const int32_t v = elem_dofs[(e0 + el) * NLOC + (i - el * NLOC)];
-      sX[3 * i + 0] = coords[3 * static_cast<int64_t>(v) + 0];
-      sX[3 * i + 1] = coords[3 * static_cast<int64_t>(v) + 1];
-      sX[3 * i + 2] = coords[3 * static_cast<int64_t>(v) + 2];
-      sRp[i] = row_ptr[v];
-    }
-    for (int i = tid; i < ne * TWE; i += TH) {
-      const int el = i / TWE;
-      const uint32_t* row = reinterpret_cast<const uint32_t*>(tables + elem_class[e0 + el] * tab_stride);
-      sTabW[i] = row[i - el * TWE];
+    // staging: every load of a phase is issued before the first is used (a
+    // loop that loads, waits and writes LDS per trip would pay one memory
+    // round trip per trip); indices past the group are clamped, their values
+    // not written
+    {
+      constexpr int NV = (E * NLOC + TH - 1) / TH, NW = (E * TWE + TH - 1) / TH;
+      int32_t vid[NV], cls[NW];
+#pragma unroll
+      for (int k = 0; k < NV; ++k) {
+        const int i = tid + k * TH;
+        const int i2 = i < ne * NLOC ? i : 0;
+        vid[k] = elem_dofs[e0 * NLOC + i2];
+      }
+#pragma unroll
+      for (int k = 0; k < NW; ++k) {
+        const int i = tid + k * TH;
+        cls[k] = elem_class[e0 + (i < ne * TWE ? i : 0) / TWE];
+      }
+      double xv[NV][3];
+      int32_t rpv[NV];
+      uint32_t tw[NW];
+#pragma unroll
+      for (int k = 0; k < NV; ++k) {
+        const int64_t v = vid[k];
+        xv[k][0] = coords[3 * v + 0];
+        xv[k][1] = coords[3 * v + 1];
+        xv[k][2] = coords[3 * v + 2];
+        rpv[k] = row_ptr[v];
+      }
+#pragma unroll
+      for (int k = 0; k < NW; ++k) {
+        const int i = tid + k * TH;
+        const int i2 = i < ne * TWE ? i : 0;
+        tw[k] = reinterpret_cast<const uint32_t*>(tables + cls[k] * tab_stride)[i2 % TWE];
+      }
+#pragma unroll
+      for (int k = 0; k < NV; ++k) {
+        const int i = tid + k * TH;
+        if (i < ne * NLOC) {
+          sX[3 * i + 0] = xv[k][0];
+          sX[3 * i + 1] = xv[k][1];
+          sX[3 * i + 2] = xv[k][2];
+          sRp[i] = rpv[k];
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < NW; ++k) {
+        const int i = tid + k * TH;
+        if (i < ne * TWE) sTabW[i] = tw[k];
+      }
     }
     // CSR position of every compact entry of the group (row pointer + rank)
     int32_t gpos[NJ];
