@@ -202,24 +202,69 @@ __global__ __launch_bounds__(256, (NDCfg<P, R>::WPC)) void k_nd_assemble(
       for (int j = 0; j < NES; ++j) eq[j] = eid_n[j];
       load_ids(g + 2, vid_n, eid_n);
     } else {
-      for (int i = tid; i < ne * NLOCV; i += TH) {
-        const int el = i / NLOCV;
-        const int32_t v = elem_dofs[static_cast<int64_t>(sOrd[g * E + el]) * NLOCV + (i - el * NLOCV)];
-        sX[3 * i + 0] = coords[3 * static_cast<int64_t>(v) + 0];
-        sX[3 * i + 1] = coords[3 * static_cast<int64_t>(v) + 1];
-        sX[3 * i + 2] = coords[3 * static_cast<int64_t>(v) + 2];
+      // every load of a phase before the first use: the map words, then the
+      // coordinates, row pointers, table words and the lane's coefficient
+      // (indices past the group clamped, their values not written)
+      int32_t vid[NVS], eid[NES];
+#pragma unroll
+      for (int j = 0; j < NVS; ++j) {
+        const int i = tid + j * TH;
+        const int i2 = i < ne * NLOCV ? i : 0;
+        const int el = i2 / NLOCV;
+        vid[j] = elem_dofs[static_cast<int64_t>(sOrd[g * E + el]) * NLOCV + (i2 - el * NLOCV)];
       }
-      for (int i = tid; i < ne * NLOCE; i += TH) {
-        const int el = i / NLOCE;
-        const int32_t raw = elem_edges[static_cast<int64_t>(sOrd[g * E + el]) * NLOCE + (i - el * NLOCE)];
-        const int32_t gid = raw < 0 ? -1 - raw : raw;
-        sRp[i] = row_ptr[gid];
-        sSg[i] = raw < 0 ? 1 : 0;
+#pragma unroll
+      for (int j = 0; j < NES; ++j) {
+        const int i = tid + j * TH;
+        const int i2 = i < ne * NLOCE ? i : 0;
+        const int el = i2 / NLOCE;
+        eid[j] = elem_edges[static_cast<int64_t>(sOrd[g * E + el]) * NLOCE + (i2 - el * NLOCE)];
       }
-      for (int i = tid; i < ne * TWE; i += TH) {
-        const int el = i / TWE;
-        const uint32_t* row = reinterpret_cast<const uint32_t*>(tables + sCls[g * E + el] * tab_stride);
-        sTabW[i] = row[i - el * TWE];
+      uint32_t tw[NTS];
+#pragma unroll
+      for (int j = 0; j < NTS; ++j) {
+        const int i = tid + j * TH;
+        const int i2 = i < ne * TWE ? i : 0;
+        const int el = i2 / TWE;
+        tw[j] = reinterpret_cast<const uint32_t*>(tables + sCls[g * E + el] * tab_stride)[i2 - el * TWE];
+      }
+      {
+        const int t2 = tid < ne * NSUB ? tid : 0;
+        const int el = t2 / NSUB;
+        kcur = kappa[static_cast<int64_t>(sOrd[g * E + el]) * NSUB + (t2 - el * NSUB)];
+      }
+      double xv[NVS][3];
+      int32_t rv[NES];
+#pragma unroll
+      for (int j = 0; j < NVS; ++j) {
+        const int64_t v3 = 3 * static_cast<int64_t>(vid[j]);
+        xv[j][0] = coords[v3 + 0];
+        xv[j][1] = coords[v3 + 1];
+        xv[j][2] = coords[v3 + 2];
+      }
+#pragma unroll
+      for (int j = 0; j < NES; ++j) rv[j] = row_ptr[eid[j] < 0 ? -1 - eid[j] : eid[j]];
+#pragma unroll
+      for (int j = 0; j < NVS; ++j) {
+        const int i = tid + j * TH;
+        if (i < ne * NLOCV) {
+          sX[3 * i + 0] = xv[j][0];
+          sX[3 * i + 1] = xv[j][1];
+          sX[3 * i + 2] = xv[j][2];
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < NES; ++j) {
+        const int i = tid + j * TH;
+        if (i < ne * NLOCE) {
+          sRp[i] = rv[j];
+          sSg[i] = eid[j] < 0 ? 1 : 0;
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < NTS; ++j) {
+        const int i = tid + j * TH;
+        if (i < ne * TWE) sTabW[i] = tw[j];
       }
     }
     lds_barrier();
@@ -229,11 +274,7 @@ __global__ __launch_bounds__(256, (NDCfg<P, R>::WPC)) void k_nd_assemble(
       const int el = tid / NSUB;
       const int s = tid - el * NSUB;
       const int si = s % P, sj = (s / P) % P, sk = s / (P * P);
-      R kap;
-      if constexpr (PIPE)
-        kap = static_cast<R>(kcur);
-      else
-        kap = static_cast<R>(kappa[static_cast<int64_t>(sOrd[g * E + el]) * NSUB + s]);
+      const R kap = static_cast<R>(kcur);
       R* out = sSub + el * 78 * NSUB + s;
       auto load_X = [&](double (&X)[8][3]) {
 #pragma unroll
