@@ -44,38 +44,48 @@ __device__ __forceinline__ void local_edge_vertices(int p, int l, int& v0, int& 
   }
 }
 
+// G maps vertex values (the H1 space) to edge values (the lowest-order
+// Nedelec space) of the LOR mesh: the edge dof of edge e is the integral of
+// grad u along e in the edge's global orientation.  For the piecewise
+// trilinear u that integral is the difference of the vertex values at the
+// edge's ends, so with lo -> hi the edge's direction in an element holding it
+// (the local +axis) and sigma = +1 when the global orientation agrees with it,
+// -1 when it is the reverse,
+//   (G u)_e = sigma (u_hi - u_lo).
+// Row e therefore holds two entries, -sigma in column lo and +sigma in column
+// hi.  The element taken is the edge's first incidence, and the entries are
+// kept in the element's (lo, hi) order, not sorted.
 template <typename T>
 __global__ __launch_bounds__(kAuxThreads) void k_discrete_gradient(
     int p, int64_t nedges, int64_t ndofs_h1, const int32_t* __restrict__ elem_dofs,
     const int32_t* __restrict__ elem_edges, const int32_t* __restrict__ inc_ptr, const int32_t* __restrict__ inc_list,
     int32_t* __restrict__ row_ptr, int32_t* __restrict__ col_idx, T* __restrict__ values, int32_t* __restrict__ diag) {
-  const int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (g >= nedges) return;
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= nedges) return;
   const int q = p + 1;
   const int nloce = 3 * p * q * q, nlocv = q * q * q;
-  row_ptr[g] = static_cast<int32_t>(2 * g);
-  if (g == nedges - 1) row_ptr[nedges] = static_cast<int32_t>(2 * nedges);
-  const int32_t a = inc_ptr[g], b = inc_ptr[g + 1];
-  int32_t j0 = 0, j1 = 0;
-  T s = T(0);
-  if (a < b) {
-    const int32_t inc = inc_list[a];
-    const int32_t e = inc / nloce;
-    const int l = inc - e * nloce;
-    const int32_t raw = elem_edges[inc];
-    s = raw < 0 ? T(-1) : T(1);
-    int v0, v1;
-    local_edge_vertices(p, l, v0, v1);
-    j0 = elem_dofs[static_cast<int64_t>(e) * nlocv + v0];
-    j1 = elem_dofs[static_cast<int64_t>(e) * nlocv + v1];
-    if ((j0 < 0 || j0 >= ndofs_h1 || j1 < 0 || j1 >= ndofs_h1) && diag) atomicAdd(&diag[1], 1);
+  // every row has two entries
+  row_ptr[e] = static_cast<int32_t>(2 * e);
+  if (e == nedges - 1) row_ptr[nedges] = static_cast<int32_t>(2 * nedges);
+  int32_t lo = 0, hi = 0;
+  T sigma = T(0);  // an edge in no element keeps a zero row (counted in diag[0])
+  if (inc_ptr[e] < inc_ptr[e + 1]) {
+    const int32_t first = inc_list[inc_ptr[e]];  // element * nloce + local edge
+    const int32_t el = first / nloce;
+    int v_lo, v_hi;
+    local_edge_vertices(p, first - el * nloce, v_lo, v_hi);
+    const int32_t* ev = elem_dofs + static_cast<int64_t>(el) * nlocv;
+    lo = ev[v_lo];
+    hi = ev[v_hi];
+    sigma = elem_edges[first] < 0 ? T(-1) : T(1);
+    if ((lo < 0 || lo >= ndofs_h1 || hi < 0 || hi >= ndofs_h1) && diag) atomicAdd(&diag[1], 1);
   } else if (diag) {
-    atomicAdd(&diag[0], 1);  // edge in no element: its row is left as two zeros at column 0
+    atomicAdd(&diag[0], 1);
   }
-  col_idx[2 * g] = j0;
-  col_idx[2 * g + 1] = j1;
-  values[2 * g] = -s;
-  values[2 * g + 1] = s;
+  col_idx[2 * e] = lo;
+  values[2 * e] = -sigma;
+  col_idx[2 * e + 1] = hi;
+  values[2 * e + 1] = sigma;
 }
 
 // ------------------------------------------------------- discrete curl
