@@ -101,7 +101,9 @@ __global__ __launch_bounds__(BwCfg<P>::THREADS, (BwOcc<R>::WPE)) void k_h1_backw
   constexpr int TH = C::THREADS, TWE = C::TWE;
   constexpr int NJ = (E * NENT + TH - 1) / TH;            // gathered entries per lane
   constexpr int GW = E * NENT > 3 * E * 8 * NSUB ? E * NENT : 3 * E * 8 * NSUB;
-  __shared__ double sX[E * NLOC * 3];
+  // coordinates by component ([d][element vertex]): lanes reading the same
+  // corner of neighbouring subelements then hit consecutive words
+  __shared__ double sX[3 * E * NLOC];
   __shared__ int32_t sRp[E * NLOC];
   __shared__ uint32_t sTabW[E * TWE];
   // cotangent entries in compact order, later the corner adjoints; in the
@@ -161,9 +163,9 @@ __global__ __launch_bounds__(BwCfg<P>::THREADS, (BwOcc<R>::WPE)) void k_h1_backw
       for (int k = 0; k < NV; ++k) {
         const int i = tid + k * TH;
         if (i < ne * NLOC) {
-          sX[3 * i + 0] = xv[k][0];
-          sX[3 * i + 1] = xv[k][1];
-          sX[3 * i + 2] = xv[k][2];
+          sX[i] = xv[k][0];
+          sX[E * NLOC + i] = xv[k][1];
+          sX[2 * E * NLOC + i] = xv[k][2];
           sRp[i] = rpv[k];
         }
       }
@@ -202,7 +204,7 @@ __global__ __launch_bounds__(BwCfg<P>::THREADS, (BwOcc<R>::WPE)) void k_h1_backw
       for (int v = 0; v < 8; ++v) {
         const int lv = (si + (v & 1)) + Q * ((sj + ((v >> 1) & 1)) + Q * (sk + (v >> 2)));
 #pragma unroll
-        for (int d = 0; d < 3; ++d) X[v][d] = sX[3 * (el * NLOC + lv) + d];
+        for (int d = 0; d < 3; ++d) X[v][d] = sX[d * E * NLOC + el * NLOC + lv];
       }
       h1_edges<R>(X, ex, ey, ez);
     };
