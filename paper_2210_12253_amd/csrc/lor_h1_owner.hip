@@ -405,6 +405,19 @@ bool owner_fits(const lor_sched* s, int tsize) {
   return s->nrows * 24 < lim && s->nel * nsub * tsize < lim && s->nel * 4 < lim;
 }
 
+// Compute units of the current device (cached per device).
+static int owner_num_cus() {
+  static int cus[64] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  if (cus[dev] == 0) {
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) n = 256;
+    cus[dev] = n;
+  }
+  return cus[dev];
+}
+
 template <int P, typename T, typename R>
 static int launch_owner(const lor_sched* sched, int batch, const void* kappa, double beta, const double* coords,
                         const int32_t* row_ptr, void* values, unsigned flags, double thr, int32_t* diag,
@@ -420,13 +433,24 @@ static int launch_owner(const lor_sched* sched, int batch, const void* kappa, do
   const int64_t ntx = ceil_div(NXc, kOwnStride), nty = ceil_div(NYc, kOwnStride);
   const int64_t tiles = ntx * nty;
   if (tiles > INT32_MAX) LOR_FAIL(LOR_EOVERFLOW, "too many owner-computes tiles");
-  // split the z-march into segments so that there are several waves per
-  // SIMD slot of the chip; a segment costs one extra cell layer
-  const int64_t want = 8192;
-  int64_t nseg = std::min<int64_t>(NZc, std::max<int64_t>(1, ceil_div(want, tiles)));
-  int64_t seglen = ceil_div(NZc, nseg);
-  if (seglen < 8) seglen = std::min<int64_t>(8, NZc);
-  nseg = ceil_div(NZc, seglen);
+  // Split the z-march into segments (a segment above the bottom costs one
+  // extra cell layer).  The waves run in rounds over the chip's wave slots
+  // (CUs x 4 SIMDs x waves per SIMD), so the launch takes about
+  // ceil(waves / slots) x (layers per wave + 1) layer steps: pick the segment
+  // length (at least 8 layers) that minimises it, so that the last round is
+  // not left mostly idle.
+  const int64_t slots = static_cast<int64_t>(owner_num_cus()) * 4 * OwnCfg<T, R>::WPE;
+  int64_t seglen = NZc, best = -1;
+  for (int64_t len = std::min<int64_t>(8, NZc); len <= NZc; ++len) {
+    const int64_t ns = ceil_div(NZc, len);
+    if (ns > 1 && ceil_div(NZc, ns) != len) continue;  // same split as a shorter length
+    const int64_t cost = ceil_div(tiles * ns * batch, slots) * (len + 1);
+    if (best < 0 || cost < best) {
+      best = cost;
+      seglen = len;
+    }
+  }
+  const int64_t nseg = ceil_div(NZc, seglen);
   dim3 grid(static_cast<unsigned>(tiles), static_cast<unsigned>(nseg), static_cast<unsigned>(batch));
   (void)row_ptr;  // the rows start where the lattice puts them (the pattern call checked row_ptr)
   k_h1_owner<P, T, R><<<grid, 64, 0, st>>>(
