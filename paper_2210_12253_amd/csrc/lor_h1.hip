@@ -128,36 +128,39 @@ __global__ __launch_bounds__(256, (H1Occ<P, R>::WPC)) void k_h1_assemble(
   }
   __syncthreads();
 
+  if (ngr == 0) return;
   auto group_size = [&](int g) { return nce - g * E < E ? nce - g * E : E; };
   // --- prefetch helpers (registers) ----------------------------------------
+  // Every load is issued unconditionally: indices past the group, and groups
+  // past the last, are clamped to valid ones whose values are never used.  A
+  // register reset before a masked load, or a loaded value copied to another
+  // register, makes the compiler wait for the load right there.
   auto load_dofs = [&](int g, int32_t (&d)[RV]) {
+    const int gc = g < ngr ? g : ngr - 1;
+    const int n = group_size(gc);
 #pragma unroll
     for (int j = 0; j < RV; ++j) {
       const int i = tid + j * TH;
-      d[j] = -1;
-      if (g < ngr && i < group_size(g) * NLOC) {
-        const int el = i / NLOC;
-        d[j] = elem_dofs[static_cast<int64_t>(sOrd[g * E + el]) * NLOC + (i - el * NLOC)];
-      }
+      const int i2 = i < n * NLOC ? i : 0;
+      const int el = i2 / NLOC;
+      d[j] = elem_dofs[static_cast<int64_t>(sOrd[gc * E + el]) * NLOC + (i2 - el * NLOC)];
     }
   };
   auto load_geo = [&](const int32_t (&d)[RV], double (&x)[RV][3], int32_t (&rp)[RV]) {
 #pragma unroll
     for (int j = 0; j < RV; ++j) {
-      if (d[j] >= 0) {
-        const int64_t g3 = 3 * static_cast<int64_t>(d[j]);
-        x[j][0] = coords[g3 + 0];
-        x[j][1] = coords[g3 + 1];
-        x[j][2] = coords[g3 + 2];
-        rp[j] = row_ptr[d[j]];
-      }
+      const int64_t g3 = 3 * static_cast<int64_t>(d[j]);
+      x[j][0] = coords[g3 + 0];
+      x[j][1] = coords[g3 + 1];
+      x[j][2] = coords[g3 + 2];
+      rp[j] = row_ptr[d[j]];
     }
   };
-  auto load_kap = [&](int g, T& k) {
-    if (g < ngr && tid < group_size(g) * NSUB) {
-      const int el = tid / NSUB;
-      k = kappa[static_cast<int64_t>(sOrd[g * E + el]) * NSUB + (tid - el * NSUB)];
-    }
+  auto load_kap = [&](int g) {
+    const int gc = g < ngr ? g : ngr - 1;
+    const int t2 = tid < group_size(gc) * NSUB ? tid : 0;
+    const int el = t2 / NSUB;
+    return kappa[static_cast<int64_t>(sOrd[gc * E + el]) * NSUB + (t2 - el * NSUB)];
   };
   auto load_tab = [&](int g, uint32_t (&w)[RW]) {
     if constexpr (E == 1) {
@@ -165,31 +168,35 @@ __global__ __launch_bounds__(256, (H1Occ<P, R>::WPC)) void k_h1_assemble(
 #pragma unroll
       for (int j = 0; j < RW; ++j) {
         const uint32_t i = static_cast<uint32_t>(threadIdx.x) + j * TH;
-        if (i < static_cast<uint32_t>(TWE)) w[j] = row[i];
+        w[j] = row[i < static_cast<uint32_t>(TWE) ? i : 0u];
       }
     } else {
 #pragma unroll
       for (int j = 0; j < RW; ++j) {
         const int i = tid + j * TH;
-        if (g < ngr && i < group_size(g) * TWE) {
-          const int el = i / TWE;
-          const uint32_t* row = reinterpret_cast<const uint32_t*>(tables + sCls[g * E + el] * tab_stride);
-          w[j] = row[i - el * TWE];
-        }
+        const int i2 = i < group_size(g) * TWE ? i : 0;
+        const int el = i2 / TWE;
+        const uint32_t* row = reinterpret_cast<const uint32_t*>(tables + sCls[g * E + el] * tab_stride);
+        w[j] = row[i2 - el * TWE];
       }
     }
   };
 
+  // Pipeline, in place: the geometry of group g is staged from registers at
+  // the start of its step, then the registers receive group g + 1's (from the
+  // element-map words loaded one step earlier), and the map words of g + 2;
+  // the coefficient of group g is used by its integration, after which the
+  // same register receives group g + 1's.
   int32_t dnext[RV];
-  double xq[RV][3] = {};
-  int32_t rq[RV] = {};
-  T kq = T(0);
+  double xq[RV][3];
+  int32_t rq[RV];
+  T kq;
   {
     int32_t d0[RV];
     load_dofs(0, d0);
     load_geo(d0, xq, rq);
     load_dofs(1, dnext);
-    load_kap(0, kq);
+    kq = load_kap(0);
   }
 
   for (int g = 0; g < ngr; ++g) {
@@ -210,11 +217,9 @@ __global__ __launch_bounds__(256, (H1Occ<P, R>::WPC)) void k_h1_assemble(
         sRp[i] = rq[j];
       }
     }
-    const T kcur = kq;
     // prefetch the next group; the loads complete while this group is computed
     load_geo(dnext, xq, rq);
     load_dofs(g + 2, dnext);
-    load_kap(g + 1, kq);
     lds_barrier();
 
     // phase 1: subelement matrices
@@ -230,7 +235,7 @@ __global__ __launch_bounds__(256, (H1Occ<P, R>::WPC)) void k_h1_assemble(
           for (int d = 0; d < 3; ++d) X[v][d] = sX[3 * (el * NLOC + lv) + d];
         }
       };
-      const R kap = static_cast<R>(kcur);
+      const R kap = static_cast<R>(kq);
       R* out = sSub + el * 36 * NSUB + s;
       bool fallback = false;
       if constexpr (!std::is_same<R, double>::value) {
@@ -274,6 +279,7 @@ __global__ __launch_bounds__(256, (H1Occ<P, R>::WPC)) void k_h1_assemble(
         }
       }
     }
+    kq = load_kap(g + 1);  // the next group's coefficient, after this group's last use
     lds_barrier();
 
     // phase 2: local rows.  Lane owns rows tid and tid + 256.  The rank table
