@@ -515,20 +515,34 @@ __global__ void k_sort_inc(const int32_t* __restrict__ inc_ptr, int32_t* __restr
 
 // Columns of row g: sorted union of the local stencils of its incidences.
 // One lane per row; the per-lane working list lives in LDS (odd stride, so
-// lanes working on the same slot hit different banks).
+// lanes working on the same slot hit different banks) and holds CAP columns.
+// The short form (kRowCapShort: every row of the structured meshes and of the
+// irregular test meshes fits) lets several waves share a SIMD; a row that
+// does not fit goes to the list `ovf` and is done again by the full form
+// (LOR_MAX_ROW_NNZ columns, one wave per SIMD).  `rows` (optional) lists the
+// rows to do, else rows 0 .. nlist - 1.  The fill form skips, into `ovf`, the
+// rows that phase 1 counted longer than CAP.
 constexpr int kRowThreads = 64;
-constexpr int kRowStride = LOR_MAX_ROW_NNZ + 2;
+constexpr int kRowCapShort = 40;
 
-template <bool FILL>
+template <bool FILL, int CAP>
 __global__ __launch_bounds__(kRowThreads) void k_row_cols(
     const int32_t* __restrict__ map, int nloc, int is_signed, const int32_t* __restrict__ inc_ptr,
     const int32_t* __restrict__ inc_list, const int32_t* __restrict__ st_ptr,
-    const int32_t* __restrict__ st_col, int64_t nrows, int32_t* __restrict__ cnt,
-    const int32_t* __restrict__ row_ptr, int32_t* __restrict__ col_idx, int32_t* __restrict__ err) {
-  __shared__ int32_t buf[kRowThreads * kRowStride];
-  const int64_t g = static_cast<int64_t>(blockIdx.x) * kRowThreads + threadIdx.x;
-  if (g >= nrows) return;
-  int32_t* b = buf + threadIdx.x * kRowStride;
+    const int32_t* __restrict__ st_col, const int32_t* __restrict__ rows, int64_t nlist,
+    int32_t* __restrict__ cnt, const int32_t* __restrict__ row_ptr, int32_t* __restrict__ col_idx,
+    int32_t* __restrict__ ovf, int32_t* __restrict__ novf, int32_t* __restrict__ err) {
+  constexpr bool FULL = CAP >= LOR_MAX_ROW_NNZ;
+  constexpr int STRIDE = CAP % 2 == 0 ? CAP + 1 : CAP + 2;
+  __shared__ int32_t buf[kRowThreads * STRIDE];
+  const int64_t t = static_cast<int64_t>(blockIdx.x) * kRowThreads + threadIdx.x;
+  if (t >= nlist) return;
+  const int64_t g = rows ? rows[t] : t;
+  if (FILL && !FULL && row_ptr[g + 1] - row_ptr[g] > CAP) {
+    ovf[atomicAdd(novf, 1)] = static_cast<int32_t>(g);
+    return;
+  }
+  int32_t* b = buf + threadIdx.x * STRIDE;
   int n = 0;
   bool overflow = false;
   for (int32_t ii = inc_ptr[g]; ii < inc_ptr[g + 1] && !overflow; ++ii) {
@@ -541,7 +555,7 @@ __global__ __launch_bounds__(kRowThreads) void k_row_cols(
       int pos = n;
       while (pos > 0 && b[pos - 1] > c) --pos;
       if (pos > 0 && b[pos - 1] == c) continue;
-      if (n >= LOR_MAX_ROW_NNZ) {
+      if (n >= CAP) {
         overflow = true;
         break;
       }
@@ -551,8 +565,11 @@ __global__ __launch_bounds__(kRowThreads) void k_row_cols(
     }
   }
   if (overflow) {
-    atomicOr(err, kErrRowTooLong);
     if (!FILL) cnt[g] = 0;
+    if (FULL)
+      atomicOr(err, kErrRowTooLong);
+    else
+      ovf[atomicAdd(novf, 1)] = static_cast<int32_t>(g);
     return;
   }
   if (!FILL) {
@@ -1070,6 +1087,36 @@ static int build_incidence(const int32_t* map, int64_t nel, int nloc, int is_sig
   return LOR_OK;
 }
 
+// Both passes of k_row_cols over all rows: the short form, then the full
+// form over the rows that did not fit (one host read of their number).
+// Scratch: ovf_ws_bytes(nrows).
+static size_t ovf_ws_bytes(int64_t nrows) { return arena_bytes<int32_t>(nrows) + arena_bytes<int32_t>(1); }
+
+template <bool FILL>
+static int row_cols(const int32_t* map, int nloc, int is_signed, const int32_t* inc_ptr, const int32_t* inc_list,
+                    const int32_t* st_ptr, const int32_t* st_col, int64_t nrows, int32_t* cnt, const int32_t* row_ptr,
+                    int32_t* col_idx, int32_t* d_err, Arena& a, hipStream_t st) {
+  if (nrows == 0) return LOR_OK;
+  ArenaScope scope(a);
+  int32_t *ovf, *novf;
+  LOR_TAKE(ovf, a, int32_t, nrows);
+  LOR_TAKE(novf, a, int32_t, 1);
+  LOR_HIP(hipMemsetAsync(novf, 0, sizeof(int32_t), st));
+  k_row_cols<FILL, kRowCapShort><<<ceil_div(nrows, kRowThreads), kRowThreads, 0, st>>>(
+      map, nloc, is_signed, inc_ptr, inc_list, st_ptr, st_col, nullptr, nrows, cnt, row_ptr, col_idx, ovf, novf,
+      d_err);
+  LOR_LAUNCHED("k_row_cols<short>");
+  int32_t h = 0;
+  if (int rc = read_err(novf, st, &h)) return rc;
+  if (h > 0) {
+    k_row_cols<FILL, LOR_MAX_ROW_NNZ><<<ceil_div(h, kRowThreads), kRowThreads, 0, st>>>(
+        map, nloc, is_signed, inc_ptr, inc_list, st_ptr, st_col, ovf, h, cnt, row_ptr, col_idx, nullptr, nullptr,
+        d_err);
+    LOR_LAUNCHED("k_row_cols<full>");
+  }
+  return LOR_OK;
+}
+
 // Box-lattice detection of an H1 mesh (see the box lattice kernels): the
 // lattice strides from element 0, then every element checked and placed in
 // elem3d (nel int32, device).  *found is false when the mesh is no box
@@ -1260,10 +1307,9 @@ static int general_schedule(lor_sched* s, const RefElem& ref, int is_signed, con
   int rc;
   int32_t herr = 0;
   int ncolors = 0;
-  k_row_cols<true><<<ceil_div(nrows, kRowThreads), kRowThreads, 0, st>>>(
-      map, nloc, is_signed, d_inc_ptr, d_inc_list, dev_at<int32_t>(s, s->off_st_ptr),
-      dev_at<int32_t>(s, s->off_st_col), nrows, nullptr, row_ptr, col_idx, d_err);
-  LOR_LAUNCHED("k_row_cols<fill>");
+  if ((rc = row_cols<true>(map, nloc, is_signed, d_inc_ptr, d_inc_list, dev_at<int32_t>(s, s->off_st_ptr),
+                           dev_at<int32_t>(s, s->off_st_col), nrows, nullptr, row_ptr, col_idx, d_err, a, st)))
+    return rc;
   if ((rc = read_err(d_err, st, &herr))) return rc;
   if ((rc = report_err(herr))) return rc;
 
@@ -1457,7 +1503,7 @@ extern "C" int lor_pattern(int space, int p, int64_t nel, int64_t nrows, const i
       if ((rc = g.alloc(arena_bytes<int32_t>(nrows + 1) + arena_bytes<int32_t>(nel * nloc) +
                         arena_bytes<int32_t>(nrows) + arena_bytes<int64_t>(nrows + 1) +
                         arena_bytes<int32_t>(ref.st_ptr.size()) + arena_bytes<int32_t>(ref.st_col.size()) +
-                        std::max(incidence_ws_bytes(nrows), scan_ws_bytes(nrows)))))
+                        std::max({incidence_ws_bytes(nrows), scan_ws_bytes(nrows), ovf_ws_bytes(nrows)}))))
         return rc;
       int32_t *inc_ptr, *inc_list, *cnt, *st_ptr, *st_col;
       int64_t* ptr64;
@@ -1472,9 +1518,9 @@ extern "C" int lor_pattern(int space, int p, int64_t nel, int64_t nrows, const i
       if ((rc = build_incidence(elem_map, nel, nloc, is_signed, nrows, inc_ptr, inc_list, d_err, g, st))) return rc;
       if ((rc = read_err(d_err, st, &herr))) return rc;
       if ((rc = report_err(herr))) return rc;
-      k_row_cols<false><<<ceil_div(nrows, kRowThreads), kRowThreads, 0, st>>>(
-          elem_map, nloc, is_signed, inc_ptr, inc_list, st_ptr, st_col, nrows, cnt, nullptr, nullptr, d_err);
-      LOR_LAUNCHED("k_row_cols<count>");
+      if ((rc = row_cols<false>(elem_map, nloc, is_signed, inc_ptr, inc_list, st_ptr, st_col, nrows, cnt, nullptr,
+                                nullptr, d_err, g, st)))
+        return rc;
       if ((rc = scan_exclusive<int32_t>(cnt, nrows, ptr64, g, st))) return rc;
       LOR_HIP(hipMemcpyAsync(&total_nnz, ptr64 + nrows, sizeof(int64_t), hipMemcpyDeviceToHost, st));
       if ((rc = read_err(d_err, st, &herr))) return rc;
@@ -1505,7 +1551,7 @@ extern "C" int lor_pattern(int space, int p, int64_t nel, int64_t nrows, const i
   }
 
   // ------------------------------------------------------------------ phase 2
-  if ((rc = a.alloc(box_ws + incidence_ws_bytes(nrows) + order_ws_bytes(nel) +
+  if ((rc = a.alloc(box_ws + incidence_ws_bytes(nrows) + order_ws_bytes(nel) + ovf_ws_bytes(nrows) +
                     arena_bytes<int32_t>(std::max<size_t>(ref.reps.size(), kBoxKeys)) + arena_bytes<int32_t>(2))))
     return rc;
   LOR_TAKE(d_err, a, int32_t, 1);
