@@ -50,21 +50,25 @@ constexpr int kOwnTile = 8;                  // cells per tile side (one wave: 8
 constexpr int kOwnStride = kOwnTile - 1;     // tiles overlap by one cell
 constexpr int kOwnPts = (kOwnTile + 1) * (kOwnTile + 1);  // lattice points of one tile plane
 
-// LDS slab of one wave and waves per SIMD.  The FP64 form runs one wave per
-// SIMD: its integration wants ~250 VGPRs, and with the carry a second wave per
-// SIMD spills (measured at the headline size: 1.10 ms at one wave, 1.28 ms at
-// two with spills, 1.14 ms at two with the carry in LDS, 1.18 ms with two cells
-// per lane and step).  The FP32 form runs two waves per SIMD.
+// LDS slab of one wave and waves per SIMD.  Both forms ask for registers for
+// two waves per SIMD.  The FP64 form then spills a few registers (its
+// integration alone wants ~250, and the carry 36 more) and its 22 KB of LDS
+// per wave admit seven waves per CU; measured at the headline size that is
+// still 2% faster than one wave per SIMD without spills (0.777 against
+// 0.795 ms), where nothing hides the LDS round trips.
 template <typename T, typename R>
 struct OwnCfg {
-  static constexpr int LPS = 1;                        // cell layers per step
-  static constexpr int NPL = LPS + 1;                 // lattice planes in LDS (ring)
-  static constexpr int WPE = sizeof(R) == 8 ? 1 : 2;  // waves per SIMD (second __launch_bounds__ argument)
+  static constexpr int LPS = 1;   // cell layers per step
+  static constexpr int NPL = LPS + 1;  // lattice planes in LDS (ring)
+  static constexpr int WPE = 2;   // waves per SIMD (second __launch_bounds__ argument)
   // cell matrices [pair][lane]; once the row sums have read them, the finished
   // rows of the plane staged per x-line
   static constexpr int CELLS = 36 * 64 * static_cast<int>(sizeof(R));
   static constexpr int ROWS = 64 * 27 * static_cast<int>(sizeof(T));
   static constexpr int SLAB = CELLS > ROWS ? CELLS : ROWS;
+  static constexpr int LDS = SLAB + NPL * (kOwnTile + 1) * (kOwnTile + 1) * 3 * 8;  // bytes per wave
+  // resident waves per CU: registers allow 4 WPE, LDS (160 KB) may allow fewer
+  static constexpr int WPC = 4 * WPE < 160 * 1024 / LDS ? 4 * WPE : 160 * 1024 / LDS;
 };
 
 // FP32 form, strongly curved cell: FP64 geometry and quadrature from the FP64
@@ -435,11 +439,11 @@ static int launch_owner(const lor_sched* sched, int batch, const void* kappa, do
   if (tiles > INT32_MAX) LOR_FAIL(LOR_EOVERFLOW, "too many owner-computes tiles");
   // Split the z-march into segments (a segment above the bottom costs one
   // extra cell layer).  The waves run in rounds over the chip's wave slots
-  // (CUs x 4 SIMDs x waves per SIMD), so the launch takes about
+  // (CUs x resident waves per CU), so the launch takes about
   // ceil(waves / slots) x (layers per wave + 1) layer steps: pick the segment
   // length (at least 8 layers) that minimises it, so that the last round is
   // not left mostly idle.
-  const int64_t slots = static_cast<int64_t>(owner_num_cus()) * 4 * OwnCfg<T, R>::WPE;
+  const int64_t slots = static_cast<int64_t>(owner_num_cus()) * OwnCfg<T, R>::WPC;
   int64_t seglen = NZc, best = -1;
   for (int64_t len = std::min<int64_t>(8, NZc); len <= NZc; ++len) {
     const int64_t ns = ceil_div(NZc, len);
