@@ -50,17 +50,16 @@ constexpr int kOwnTile = 8;                  // cells per tile side (one wave: 8
 constexpr int kOwnStride = kOwnTile - 1;     // tiles overlap by one cell
 constexpr int kOwnPts = (kOwnTile + 1) * (kOwnTile + 1);  // lattice points of one tile plane
 
-// LDS slab of one wave and waves per SIMD.  Both forms ask for registers for
-// two waves per SIMD.  The FP64 form then spills a few registers (its
-// integration alone wants ~250, and the carry 36 more) and its 22 KB of LDS
-// per wave admit seven waves per CU; measured at the headline size that is
-// still 2% faster than one wave per SIMD without spills (0.777 against
-// 0.795 ms), where nothing hides the LDS round trips.
+// LDS slab of one wave and waves per SIMD.  The FP64 form runs one wave per
+// SIMD: its integration wants ~250 VGPRs and the carry 36 more.  At two waves
+// per SIMD it spills about 30 registers; measured at the headline size that
+// was within 2% in time but wrote 15% more to HBM (the spills).  The FP32
+// form runs two waves per SIMD.
 template <typename T, typename R>
 struct OwnCfg {
   static constexpr int LPS = 1;   // cell layers per step
   static constexpr int NPL = LPS + 1;  // lattice planes in LDS (ring)
-  static constexpr int WPE = 2;   // waves per SIMD (second __launch_bounds__ argument)
+  static constexpr int WPE = sizeof(R) == 8 ? 1 : 2;  // waves per SIMD (second __launch_bounds__ argument)
   // cell matrices [pair][lane]; once the row sums have read them, the finished
   // rows of the plane staged per x-line
   static constexpr int CELLS = 36 * 64 * static_cast<int>(sizeof(R));
@@ -69,8 +68,7 @@ struct OwnCfg {
   // one staged lattice plane (FP64 points), rounded to 16 bytes
   static constexpr int PLANE = ((kOwnTile + 1) * (kOwnTile + 1) * 3 * 8 + 15) / 16 * 16;
   // One buffer per wave: the slab at [0, SLAB), then the two planes (even Z,
-  // odd Z).  (Letting the FP64 slab overlap the older plane would fit eight
-  // waves per CU instead of seven; measured, that was 4% slower.)
+  // odd Z).
   static constexpr int LDS = SLAB + 2 * PLANE;  // bytes per wave
   // resident waves per CU: registers allow 4 WPE, LDS (160 KB) may allow fewer
   static constexpr int WPC = 4 * WPE < 160 * 1024 / LDS ? 4 * WPE : 160 * 1024 / LDS;
