@@ -142,6 +142,15 @@ __device__ __forceinline__ void own_st(float x, __amdgpu_buffer_rsrc_t r, uint32
   __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, x), r, static_cast<int>(off), 0, kOwnStoreNT);
 }
 
+// Bijection of [0, n): workgroup b (on XCD b mod 8) -> tile, the tiles of
+// one XCD consecutive.  With q = n / 8, r = n % 8, XCD x < r takes q + 1
+// tiles and the others q.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int own_xcd_tile(int b, int n) {
+  const int q = n / kXcds, r = n % kXcds, x = b % kXcds, k = b / kXcds;
+  return x < r ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
+}
+
 template <int P, typename T, typename R>
 __global__ __launch_bounds__(64, (OwnCfg<T, R>::WPE)) void k_h1_owner(
     int nex, int ney, int nez, int ntx, int seglen, const int32_t* __restrict__ elem3d,
@@ -159,7 +168,12 @@ __global__ __launch_bounds__(64, (OwnCfg<T, R>::WPE)) void k_h1_owner(
   const int NXc = nex * P, NYc = ney * P, NZc = nez * P;  // cells per axis
   const int LX = NXc + 1, LY = NYc + 1, LZ = NZc + 1;     // lattice points per axis
   const int lane = threadIdx.x;
-  const int ti = blockIdx.x % ntx, tj = blockIdx.x / ntx;
+  // Workgroups are dealt to the 8 XCDs in turn (workgroup b to XCD b mod 8),
+  // each with its own L2; tiles next to each other share a column or row of
+  // lattice points.  So XCD k gets a contiguous run of tiles (about an eighth
+  // of the tile rows) instead of every eighth tile.
+  const int tile = own_xcd_tile(static_cast<int>(blockIdx.x), static_cast<int>(gridDim.x));
+  const int ti = tile % ntx, tj = tile / ntx;
   const int x0 = kOwnStride * ti, y0 = kOwnStride * tj;
   const int zs = blockIdx.y * seglen;
   const int ze = zs + seglen < NZc ? zs + seglen : NZc;
