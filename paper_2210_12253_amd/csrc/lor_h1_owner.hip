@@ -105,6 +105,19 @@ __host__ __device__ constexpr int own_off(int u, int v) {
   return ((v & 1) - (u & 1) + 1) + 3 * (((v >> 1) & 1) - ((u >> 1) & 1) + 1) + 9 * ((v >> 2) - (u >> 2) + 1);
 }
 
+// Whether term v of cell k = a + 2 b (in the order b, a of the row sums;
+// lower corner k, or upper corner k + 4 if up) is the first term of its
+// offset.  Such a term is assigned instead of added to 0 (which is not a
+// no-op in IEEE arithmetic, so the compiler keeps it), except for the row
+// entries below the carry's 18, which start from the carry.
+__host__ __device__ constexpr bool own_first(int k, int v, int up) {
+  const int o = own_off(k + 4 * up, v);
+  for (int k2 = 0; k2 < k; ++k2)
+    for (int v2 = 0; v2 < 8; ++v2)
+      if (own_off(k2 + 4 * up, v2) == o) return false;
+  return up == 1 || o >= 18;
+}
+
 // Most entries of one x-line's span (8 rows of 2 or 3 x-offsets, times 3 x 3),
 // and the store instructions per lane that cover it.
 constexpr int kOwnSpanMax = (2 + 3 * (kOwnTile - 1)) * 9;
@@ -189,6 +202,13 @@ __global__ __launch_bounds__(64, (OwnCfg<T, R>::WPE)) void k_h1_owner(
   const bool cell_in = cX < NXc && cY < NYc;
   const bool row_in = cX <= NXc && cY <= NYc;           // row (cX, cY) exists in every plane
   const bool row_own = row_in && (lx > 0 || ti == 0) && (ly > 0 || tj == 0);
+  // An inner tile (most of them): all 64 of its cells exist and, on an inner
+  // plane (0 < Z < NZc), every row it owns (x, y in [1, 7]) has all 27
+  // neighbours.  Its steps on inner planes take a path without per-lane
+  // conditions: the row sums read all four cells (lanes x = 0 or y = 0 read
+  // clamped cells and own no row), each owned row is one 27-entry copy, and
+  // the seven owned lines of the plane are 7 rows x 27 entries each.
+  const bool tile_inner = ti > 0 && tj > 0 && x0 + kOwnTile <= NXc && y0 + kOwnTile <= NYc;
   // lattice points of a plane: slot j -> point lane + 64 j of the 9 x 9 grid
   auto pt_xy = [&](int j, int& X, int& Y) {
     const int pidx = lane + 64 * j;
@@ -347,7 +367,41 @@ __global__ __launch_bounds__(64, (OwnCfg<T, R>::WPE)) void k_h1_owner(
     for (int o = 0; o < 27; ++o) acc[o] = o < 18 ? carry[o] : 0.0;
 #pragma unroll
     for (int o = 0; o < 18; ++o) carry[o] = 0.0;
-    if (row_in && Z < NZc) {
+    const bool fast = tile_inner && Z > 0 && Z < NZc;  // the same for the whole wave
+    if (fast) {
+      // the 16 terms of two cells are read while the two before are summed
+      // (each term in the same order as on the general path)
+      R w[2][16];
+      auto fetch = [&](int k, R(&wk)[16]) {
+        const int a = k & 1, b = k >> 1;
+        const R* cm = sCell + (lx > a ? lx - a : 0) + 8 * (ly > b ? ly - b : 0);
+#pragma unroll
+        for (int v = 0; v < 8; ++v) {
+          wk[v] = cm[pair_index(k, v) * 64];
+          wk[8 + v] = cm[pair_index(k + 4, v) * 64];
+        }
+      };
+      auto sum = [&](int k, const R(&wk)[16]) {
+#pragma unroll
+        for (int v = 0; v < 8; ++v) {
+          double& ea = acc[own_off(k, v)];
+          double& ec = carry[own_off(k + 4, v)];
+          ea = own_first(k, v, 0) ? static_cast<double>(wk[v]) : ea + static_cast<double>(wk[v]);
+          ec = own_first(k, v, 1) ? static_cast<double>(wk[8 + v]) : ec + static_cast<double>(wk[8 + v]);
+        }
+      };
+      fetch(0, w[0]);
+      fetch(1, w[1]);
+      __builtin_amdgcn_sched_barrier(0);
+      sum(0, w[0]);
+      fetch(2, w[0]);
+      __builtin_amdgcn_sched_barrier(0);
+      sum(1, w[1]);
+      fetch(3, w[1]);
+      __builtin_amdgcn_sched_barrier(0);
+      sum(2, w[0]);
+      sum(3, w[1]);
+    } else if (row_in && Z < NZc) {
 #pragma unroll
       for (int b = 0; b < 2; ++b)
 #pragma unroll
@@ -375,7 +429,13 @@ __global__ __launch_bounds__(64, (OwnCfg<T, R>::WPE)) void k_h1_owner(
     const int xfirst = ti == 0 ? 0 : 1;  // first owned row of the tile's x-lines
     const int xa = x0 + xfirst;          // first owned row of the lines
     const int pxa = static_cast<int>(box_prefix(xa, LX));
-    if (row_own) {
+    if (fast) {
+      if (lx > 0 && ly > 0) {
+        T* row = sStg + 27 * 8 * ly + 27 * (lx - 1);
+#pragma unroll
+        for (int k = 0; k < 27; ++k) row[k] = static_cast<T>(acc[k]);
+      }
+    } else if (row_own) {
       const int xlo = cX > 0, xhi = cX < NXc, nx = 1 + xlo + xhi;
       // x-offset counts of the owned rows before this one in its line
       const int before = static_cast<int>(box_prefix(cX, LX)) - pxa;
@@ -397,9 +457,34 @@ __global__ __launch_bounds__(64, (OwnCfg<T, R>::WPE)) void k_h1_owner(
     // starts are below nnz < 2^31; line Y of plane Z starts at lb and its
     // rows from xa on at lb + cy cz box_prefix(xa), and line Y + 1 starts
     // SX cy cz later
+    const int SX = 3 * LX - 2;
+    if (fast) {
+      // lines 1..7: 7 rows x 27 entries, the owned rows of line y0 + l from
+      // box_row_start(0, y0, Z) + 9 (SX l + box_prefix(xa)); line 0 empty
+      const T* vb = values + (static_cast<int>(box_row_start(0, y0, Z, LX, LY, LZ)) + 9 * pxa);
+      const int dl = 9 * SX;
+      // all of the plane's staged values first, then the stores
+      T sv[8][kOwnSpanIters];
+#pragma unroll
+      for (int l = 0; l < 8; ++l)
+#pragma unroll
+        for (int it = 0; it < kOwnSpanIters; ++it) {
+          const int t = lane + 64 * it;
+          sv[l][it] = sStg[27 * 8 * l + (t < kOwnSpanMax ? t : kOwnSpanMax - 1)];
+        }
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int l = 0; l < 8; ++l) {
+        const auto rV = own_rsrc(vb + l * dl, l > 0 ? 7 * 27 * static_cast<uint32_t>(sizeof(T)) : 0u);
+#pragma unroll
+        for (int it = 0; it < kOwnSpanIters; ++it)
+          own_st(sv[l][it], rV, static_cast<uint32_t>((lane + 64 * it) * sizeof(T)));
+      }
+      continue;
+    }
     const int xlast = x0 + 7 < NXc ? x0 + 7 : NXc;  // last owned row of the lines
     const int span_x = static_cast<int>(box_prefix(xlast + 1, LX)) - pxa;
-    const int cz = 1 + zlo + zhi, SX = 3 * LX - 2;
+    const int cz = 1 + zlo + zhi;
     int lb = static_cast<int>(box_row_start(0, y0, Z, LX, LY, LZ));
 #pragma unroll
     for (int l = 0; l < 8; ++l) {
