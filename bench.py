@@ -933,15 +933,20 @@ def bench_2d(lor, meshgen, args, dev):
         ed = torch.from_numpy(m["elem_dofs"]).to(dev)
         x = torch.from_numpy(m["coords"]).to(dev)
         pat = lor.lor_pattern(lor.LOR_H1_2D, 6, ed, m["ndofs"])
-        res = {}
+        res = {"kernel": "owner" if pat.owner else "colored", "colored": {}}
         for name, dt in (("f64", torch.float64), ("f32", torch.float32)):
             k = m["kappa"].to(dev, dt)
             out = torch.empty(pat.nnz, dtype=dt, device=dev)
-            ms = time_it(lambda: lor.lor_assemble_h1_2d(pat, ed, x, k, m["beta"], dtype=dt, out=out),
+            fb = dt == torch.float32
+            ms = time_it(lambda: lor.lor_assemble_h1_2d(pat, ed, x, k, m["beta"], dtype=dt, fp64_fallback=fb, out=out),
                          args.steps, args.warmup)
             res[name] = {"ms": ms, "value": m["ndofs"] / (ms * 1e-3) / 1e6, "unit": "MDOF/s",
                          "roofline": roofline_of(algorithmic_bytes_2d(m["nel"], 6, m["ndofs"], pat.nnz, dt.itemsize),
                                                  ms)}
+            if pat.owner:  # the element-coloured kernel on the same mesh, for comparison
+                mc = time_it(lambda: lor.lor_assemble_h1_2d(pat, ed, x, k, m["beta"], dtype=dt, fp64_fallback=fb,
+                                                            out=out, kernel="colored"), args.steps, args.warmup)
+                res["colored"][name] = {"ms": mc, "owner_speedup": mc / ms}
         res["workload"] = "2D H1 LOR assembly, p=6, 512^2 curved quadrilaterals, kappa sigma=2, beta=1"
         res["rows"], res["nnz"], res["ncolors"] = m["ndofs"], pat.nnz, pat.ncolors
         return res

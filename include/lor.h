@@ -71,7 +71,7 @@ typedef enum { LOR_DIAG_ONE = 0, LOR_DIAG_KEEP = 1, LOR_DIAG_ZERO = 2 } lor_diag
  * det_ratio_thresh (or whose smallest corner Jacobian is <= 0) are integrated
  * with FP64 geometry instead of FP32. */
 #define LOR_FP64_FALLBACK 0x1u
-/* lor_assemble_h1: kernel choice.  By default the owner-computes kernel runs
+/* lor_assemble_h1 and lor_assemble_h1_2d: kernel choice.  By default the owner-computes kernel runs
  * when the schedule has it (sched->owner) and the coloured kernel otherwise;
  * LOR_COLORED forces the coloured kernel, LOR_OWNER the owner-computes one
  * (LOR_EUNSUPPORTED if the schedule has none).  Both give the same matrix up
@@ -116,7 +116,7 @@ typedef struct lor_sched {
   size_t off_st_ptr, off_st_col, off_ent_row, off_recipe;
   size_t off_zero;               /* 256 zero bytes (read in place of an old value that is absent) */
   size_t off_order_class;        /* class of order[i] (int32 per element, in colour order) */
-  /* Owner-computes schedule (LOR_H1 only; see lor_assemble_h1).  Present
+  /* Owner-computes schedule (LOR_H1 and LOR_H1_2D; see lor_assemble_h1).  Present
    * (owner == 1) when the mesh is a box lattice: the elements tile a box of
    * box[0] x box[1] x box[2] elements, each with its local axes along the box
    * axes, and the vertex at point (X, Y, Z) of the global lattice of
@@ -126,7 +126,9 @@ typedef struct lor_sched {
    * the box position) and rank tables in closed form.  owner == 0 otherwise,
    * and then only the colour schedule is used.  Phase 1 already sets owner
    * and box (a box lattice needs fewer schedule bytes); phase 2 fills the
-   * arrays. */
+   * arrays.  LOR_H1_2D: the same one dimension down (vertex X + LX Y,
+   * box[2] = 1, elem3d holds the element at (ex, ey)), found in phase 2 on
+   * top of the general schedule, which the coloured kernel keeps using. */
   size_t off_elem3d;             /* int32 [box[2]][box[1]][box[0]]: element at box position (ex, ey, ez) */
   size_t off_base;               /* int32 [LZ][LY]: vertex id of lattice point (0, Y, Z) */
   int32_t owner;                 /* 1 if the owner-computes schedule is valid */
@@ -255,7 +257,10 @@ int lor_assemble_rt(int p, int64_t nel, int64_t ndofs_h1, int64_t nfaces, int ba
  *   kappa      [batch][nel][p^2] in dtype, subelement i + p j.
  *   sched      from lor_pattern(LOR_H1_2D, p, elem_dofs).
  * Other arguments, the FP32 form and its fallback (corner-Jacobian ratio of
- * the 4 corners) as for lor_assemble_h1.
+ * the 4 corners) as for lor_assemble_h1.  Kernel choice (LOR_COLORED,
+ * LOR_OWNER) as for lor_assemble_h1: the owner-computes kernel runs by default
+ * when the mesh is a 2D box lattice (sched->owner, box[2] = 1; every row is
+ * then summed once in FP64 and stored once, in the FP32 form too).
  */
 int lor_assemble_h1_2d(int p, int64_t nel, int64_t ndofs, int batch, const int32_t* elem_dofs,
                        const double* coords, const void* kappa, double beta, const int32_t* row_ptr,

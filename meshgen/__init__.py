@@ -37,6 +37,7 @@ __all__ = [
     "gll_points",
     "cartesian_mesh",
     "cartesian_mesh_2d",
+    "box_mesh_2d",
     "affine_mesh",
     "nd_edge_map",
     "face_map",
@@ -199,6 +200,30 @@ def cartesian_mesh_2d(n: int, p: int, amp: float = 0.0) -> dict:
     g = (p * ex[:, None] + i[None, :]) + N * (p * ey[:, None] + j[None, :])
     return {"coords": np.stack([X, Y], axis=1).astype(np.float64), "elem_dofs": g.astype(np.int32),
             "n": n, "p": p, "N": N, "nel": n * n, "ndofs": N * N}
+
+
+def box_mesh_2d(nx: int, ny: int, p: int, amp: float = 0.0) -> dict:
+    """nx x ny quadrilaterals of degree p on [0, nx/m] x [0, ny/m] (m = max(nx, ny)),
+    numbered like cartesian_mesh_2d: element ex + nx*ey, lattice vertex X + LX*Y
+    with LX = nx*p + 1, local vertex i + (p+1)*j; every lattice vertex moved by
+    the map of cartesian_mesh_2d with A = amp / m.  box_mesh_2d(n, n, p, amp)
+    equals cartesian_mesh_2d(n, p, amp)."""
+    m = max(nx, ny)
+    q = p + 1
+    LX, LY = nx * p + 1, ny * p + 1
+    X, Y = np.meshgrid(_lattice_1d(nx, p) * (nx / m), _lattice_1d(ny, p) * (ny / m), indexing="xy")
+    X, Y = X.reshape(-1), Y.reshape(-1)
+    A = amp / m
+    if A != 0.0:
+        tp = 2.0 * math.pi
+        X, Y = X + A * np.sin(tp * Y), Y + A * np.sin(tp * X)
+    e = np.arange(nx * ny)
+    ex, ey = e % nx, e // nx
+    l = np.arange(q * q)
+    i, j = l % q, l // q
+    g = (p * ex[:, None] + i) + LX * (p * ey[:, None] + j)
+    return {"coords": np.stack([X, Y], axis=1).astype(np.float64), "elem_dofs": g.astype(np.int32), "p": p,
+            "box": (nx, ny), "nel": nx * ny, "ndofs": LX * LY}
 
 
 def affine_mesh(n: int, p: int, A: np.ndarray, t: np.ndarray) -> dict:

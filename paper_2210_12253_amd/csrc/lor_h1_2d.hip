@@ -12,11 +12,14 @@
 //            order (FP64), stored at row_ptr[row] + position-in-row (first
 //            contributor: store; later colours: add to the stored value).
 #include "lor_common.hpp"
-#include "lor_h1_math.hpp"
+#include "lor_h1_2d_math.hpp"
 
 namespace lor {
 
 int check_sched(const lor_sched* s, int space, int p, int64_t nel, int64_t nrows);
+template <typename T, typename R>
+int dispatch_2d_owner(int p, const lor_sched* s, int batch, const double* x, const void* k, double beta, void* v,
+                      unsigned f, double thr, int32_t* diag, hipStream_t st);
 
 template <int P, typename R>
 struct H12Cfg {
@@ -40,55 +43,6 @@ struct H12Cfg {
   static constexpr int WPC = WPC1 < 6 ? (WPC1 > 0 ? WPC1 : 1) : 6;  // resident workgroups per CU
   static_assert(E * NSUB <= THREADS, "one subelement per lane");
 };
-
-// Index of the unordered corner pair (u <= v) among the 10 pairs, u-major.
-__host__ __device__ constexpr int pair_index4(int u, int v) {
-  return u <= v ? 4 * u - (u * (u - 1)) / 2 + (v - u) : 4 * v - (v * (v - 1)) / 2 + (u - v);
-}
-
-// The 10 unique entries of kappa K + beta M on one bilinear quadrilateral with
-// corners X[v], v = a + 2b: e_b = X(1,b) - X(0,b), f_a = X(a,1) - X(a,0)
-// (formed in FP64 by the caller), J = [dx/dxi, dx/deta] at each Gauss point,
-// grad phi = J^-T g_hat, 2x2 Gauss, weight 1/4.  Returns false if det J <= 0.
-template <typename R>
-__device__ __forceinline__ bool q1_2d_entries(const R (&e)[2][2], const R (&f)[2][2], R kap, R bet, R (&out)[10]) {
-#pragma unroll
-  for (int k = 0; k < 10; ++k) out[k] = R(0);
-  bool ok = true;
-#pragma unroll
-  for (int q2 = 0; q2 < 2; ++q2)
-#pragma unroll
-    for (int q1 = 0; q1 < 2; ++q1) {
-      // dx/dxi at eta_q2 and dx/deta at xi_q1
-      R a[2], b[2];
-#pragma unroll
-      for (int d = 0; d < 2; ++d) {
-        a[d] = R(L1(0, q2)) * e[0][d] + R(L1(1, q2)) * e[1][d];
-        b[d] = R(L1(0, q1)) * f[0][d] + R(L1(1, q1)) * f[1][d];
-      }
-      const R det = a[0] * b[1] - a[1] * b[0];
-      ok = ok && det > R(0);
-      const R idet = rcp_refined(det);
-      const R wk = R(0.25) * kap * idet;
-      const R wm = R(0.25) * bet * det;
-      R gx[4], gy[4], ph[4];  // det * grad phi and phi at the point
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int va = v & 1, vb = v >> 1;
-        const R g0 = R(va ? 1.0 : -1.0) * R(L1(vb, q2));
-        const R g1 = R(L1(va, q1)) * R(vb ? 1.0 : -1.0);
-        gx[v] = b[1] * g0 - a[1] * g1;
-        gy[v] = -b[0] * g0 + a[0] * g1;
-        ph[v] = R(L1(va, q1)) * R(L1(vb, q2));
-      }
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int v = u; v < 4; ++v)
-          out[pair_index4(u, v)] += wk * (gx[u] * gx[v] + gy[u] * gy[v]) + wm * ph[u] * ph[v];
-    }
-  return ok;
-}
 
 template <int P, typename T, typename R>
 __global__ __launch_bounds__(256, (H12Cfg<P, R>::WPC)) void k_h1_2d_assemble(
@@ -316,7 +270,8 @@ extern "C" int lor_assemble_h1_2d(int p, int64_t nel, int64_t ndofs, int batch, 
   if (nel < 0 || ndofs < 1) LOR_FAIL(LOR_EINVAL, "nel < 0 or ndofs < 1");
   if (batch < 1 || batch > 65535) LOR_FAIL(LOR_EINVAL, "batch outside [1, 65535]");
   if (dtype != LOR_F64 && dtype != LOR_F32) LOR_FAIL(LOR_EINVAL, "dtype must be LOR_F64 or LOR_F32");
-  if (flags & ~LOR_FP64_FALLBACK) LOR_FAIL(LOR_EINVAL, "unknown flag bits 0x%x", flags);
+  if (flags & ~(LOR_FP64_FALLBACK | LOR_COLORED | LOR_OWNER)) LOR_FAIL(LOR_EINVAL, "unknown flag bits 0x%x", flags);
+  if ((flags & LOR_COLORED) && (flags & LOR_OWNER)) LOR_FAIL(LOR_EINVAL, "LOR_COLORED and LOR_OWNER both set");
   if ((flags & LOR_FP64_FALLBACK) && !(det_ratio_thresh >= 1.0))
     LOR_FAIL(LOR_EINVAL, "det_ratio_thresh must be >= 1");
   if (nel > 0 && (!elem_dofs || !coords || !kappa || !row_ptr || !values))
@@ -325,10 +280,19 @@ extern "C" int lor_assemble_h1_2d(int p, int64_t nel, int64_t ndofs, int batch, 
   if (rc) return rc;
   if (static_cast<int64_t>(batch) * sched->nnz >= (int64_t(1) << 40)) LOR_FAIL(LOR_EOVERFLOW, "batch * nnz too large");
   if (nel == 0) return LOR_OK;
+  if ((flags & LOR_OWNER) && !sched->owner)
+    LOR_FAIL(LOR_EUNSUPPORTED, "LOR_OWNER: the mesh is no 2D box lattice (no owner-computes schedule)");
   hipStream_t st = as_stream(stream);
+  // default: owner-computes wherever the schedule has it
+  const bool owner = sched->owner && !(flags & LOR_COLORED);
+  const unsigned fb = flags & LOR_FP64_FALLBACK;
   if (dtype == LOR_F64)
-    return dispatch_2d<double, double>(p, sched, batch, elem_dofs, coords, kappa, beta, row_ptr, values, 0u,
-                                       det_ratio_thresh, diag, st);
-  return dispatch_2d<float, float>(p, sched, batch, elem_dofs, coords, kappa, beta, row_ptr, values, flags,
-                                   det_ratio_thresh, diag, st);
+    return owner ? dispatch_2d_owner<double, double>(p, sched, batch, coords, kappa, beta, values, 0u,
+                                                     det_ratio_thresh, diag, st)
+                 : dispatch_2d<double, double>(p, sched, batch, elem_dofs, coords, kappa, beta, row_ptr, values, 0u,
+                                               det_ratio_thresh, diag, st);
+  return owner ? dispatch_2d_owner<float, float>(p, sched, batch, coords, kappa, beta, values, fb, det_ratio_thresh,
+                                                 diag, st)
+               : dispatch_2d<float, float>(p, sched, batch, elem_dofs, coords, kappa, beta, row_ptr, values, fb,
+                                           det_ratio_thresh, diag, st);
 }

@@ -999,6 +999,47 @@ __global__ void k_box_base(int64_t LX, int64_t nlines, int32_t* __restrict__ bas
   if (t < nlines) base[t] = static_cast<int32_t>(t * LX);
 }
 
+// 2D box lattices (quadrilateral H1 meshes): the same, one dimension down.
+// The vertex at lattice point (X, Y) of the LX x LY points has id X + LX Y;
+// the row of (X, Y) holds the in-box points of its 3 x 3 neighbourhood in
+// (dy, dx) order, so row starts are box_prefix(Y) (3 LX - 2) + box_count(Y)
+// box_prefix(X).  Element 0's vertices at local (0, 0), (1, 0), (0, 1) give
+// the strides.
+__global__ void k_box2d_probe(const int32_t* __restrict__ map, int p, int32_t* __restrict__ out) {
+  const int i = threadIdx.x;
+  if (i < 3) out[i] = map[i == 0 ? 0 : i == 1 ? 1 : p + 1];
+}
+
+template <int P>
+__global__ void k_box2d_place(const int32_t* __restrict__ map, int32_t nel, int32_t LX, int32_t LY, int nx,
+                              int32_t* __restrict__ elem2d, int32_t* __restrict__ flag) {
+  constexpr int Q = P + 1, NLOC = Q * Q;
+  const int32_t t = static_cast<int32_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= nel * NLOC) return;  // nel * NLOC < 2^31
+  const int32_t e = t / NLOC;
+  const int l = t - e * NLOC;
+  const int32_t v0 = map[e * NLOC];
+  bool bad = map[t] != v0 + (l % Q) + LX * (l / Q);
+  if (l == 0) {
+    const int32_t X0 = v0 % LX, Y0 = v0 / LX;
+    bad = bad || v0 < 0 || Y0 >= LY || X0 % P != 0 || Y0 % P != 0 || X0 + P >= LX || Y0 + P >= LY;
+    if (!bad) bad = atomicCAS(&elem2d[static_cast<int64_t>(Y0 / P) * nx + X0 / P], -1, e) != -1;
+  }
+  const uint64_t m = __ballot(bad);
+  if (m != 0 && (threadIdx.x & 63) == static_cast<unsigned>(__ffsll(static_cast<long long>(m)) - 1))
+    atomicOr(flag, 1);
+}
+
+// The caller's row pointer against the 2D lattice's closed form.
+__global__ void k_box2d_rows(const int32_t* __restrict__ row_ptr, int64_t LX, int64_t LY, int32_t* __restrict__ flag) {
+  const int64_t n = LX * LY;
+  const int64_t v = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (v > n) return;
+  const int64_t want = v == n ? (3 * LX - 2) * (3 * LY - 2)
+                              : box_prefix(v / LX, LY) * (3 * LX - 2) + box_count(v / LX, LY) * box_prefix(v % LX, LX);
+  if (row_ptr[v] != want) atomicOr(flag, 1);
+}
+
 // --------------------------------------------------------------- host side
 
 template <typename T>
@@ -1021,7 +1062,7 @@ static size_t layout(lor_sched* s, const RefElem& r) {
   s->tab_stride = (r.nent + 15) / 16 * 16;
   // one rank table per element at most; a box lattice (found in phase 1) has
   // at most kBoxKeys distinct ones
-  const int64_t ntab = s->owner ? std::min<int64_t>(s->nel, kBoxKeys) : s->nel;
+  const int64_t ntab = (s->owner && s->space == LOR_H1) ? std::min<int64_t>(s->nel, kBoxKeys) : s->nel;
   s->off_tables = take(static_cast<size_t>(ntab) * s->tab_stride);
   s->off_inc_ptr = take(sizeof(int32_t) * (s->nrows + 1));
   s->off_inc_list = take(sizeof(int32_t) * s->nel * r.nloc);
@@ -1175,6 +1216,67 @@ static int find_box(const int32_t* map, int p, int64_t nel, int64_t nrows, int32
   box->nx = static_cast<int>(nx);
   box->ny = static_cast<int>(ny);
   box->nz = static_cast<int>(nz);
+  *found = true;
+  return LOR_OK;
+}
+
+// 2D box-lattice detection of a quadrilateral H1 mesh, after its general
+// schedule: every element checked and placed in elem2d (nel int32, device),
+// and row_ptr checked against the lattice's closed form.  *found is false
+// when the mesh is no 2D box lattice.
+static int find_box_2d(const int32_t* map, int p, int64_t nel, int64_t nrows, const int32_t* row_ptr,
+                       int32_t* elem2d, Arena& a, hipStream_t st, BoxLattice* box, bool* found) {
+  *found = false;
+  if (nel == 0) return LOR_OK;
+  ArenaScope scope(a);
+  int32_t* probe;
+  LOR_TAKE(probe, a, int32_t, 5);
+  int rc;
+  k_box2d_probe<<<1, 64, 0, st>>>(map, p, probe);
+  LOR_LAUNCHED("k_box2d_probe");
+  int32_t h[3];
+  LOR_HIP(hipMemcpyAsync(h, probe, sizeof(h), hipMemcpyDeviceToHost, st));
+  LOR_HIP(hipStreamSynchronize(st));
+  const int64_t LX = static_cast<int64_t>(h[2]) - h[0];
+  if (static_cast<int64_t>(h[1]) - h[0] != 1 || LX < p + 1 || nrows % LX != 0) return LOR_OK;
+  const int64_t LY = nrows / LX;
+  if (LY < p + 1 || (LX - 1) % p != 0 || (LY - 1) % p != 0) return LOR_OK;
+  const int64_t nx = (LX - 1) / p, ny = (LY - 1) / p;
+  if (nx * ny != nel) return LOR_OK;
+  int32_t* flag = probe + 4;
+  LOR_HIP(hipMemsetAsync(flag, 0, sizeof(int32_t), st));
+  k_fill_i32<<<ceil_div(nel, 256), 256, 0, st>>>(elem2d, nel, -1);
+  LOR_LAUNCHED("k_fill_i32");
+  const int64_t q = p + 1, threads = nel * q * q;
+  const int32_t lx = static_cast<int32_t>(LX), ly = static_cast<int32_t>(LY), ne = static_cast<int32_t>(nel);
+  const int inx = static_cast<int>(nx);
+  switch (p) {
+#define LOR_BOX2D_PLACE(PP)                                                                                  \
+  case PP:                                                                                                   \
+    k_box2d_place<PP><<<ceil_div(threads, 256), 256, 0, st>>>(map, ne, lx, ly, inx, elem2d, flag);           \
+    break;
+    LOR_BOX2D_PLACE(1)
+    LOR_BOX2D_PLACE(2)
+    LOR_BOX2D_PLACE(3)
+    LOR_BOX2D_PLACE(4)
+    LOR_BOX2D_PLACE(5)
+    LOR_BOX2D_PLACE(6)
+#undef LOR_BOX2D_PLACE
+    default:
+      LOR_FAIL(LOR_EINVAL, "p = %d outside [1, %d]", p, LOR_MAX_P);
+  }
+  LOR_LAUNCHED("k_box2d_place");
+  k_box2d_rows<<<ceil_div(nrows + 1, 256), 256, 0, st>>>(row_ptr, LX, LY, flag);
+  LOR_LAUNCHED("k_box2d_rows");
+  int32_t hflag = 0;
+  if ((rc = read_err(flag, st, &hflag))) return rc;
+  if (hflag != 0) return LOR_OK;
+  box->LX = LX;
+  box->LY = LY;
+  box->LZ = 1;
+  box->nx = static_cast<int>(nx);
+  box->ny = static_cast<int>(ny);
+  box->nz = 1;
   *found = true;
   return LOR_OK;
 }
@@ -1564,7 +1666,7 @@ extern "C" int lor_pattern(int space, int p, int64_t nel, int64_t nrows, const i
   if ((rc = build_incidence(elem_map, nel, nloc, is_signed, nrows, dev_at<int32_t>(sched, sched->off_inc_ptr),
                             dev_at<int32_t>(sched, sched->off_inc_list), d_err, a, st)))
     return rc;
-  const bool box1 = sched->owner == 1;
+  const bool box1 = sched->owner == 1 && space == LOR_H1;  // (a 2D box lattice is found in phase 2)
   sched->owner = 0;
   sched->box[0] = sched->box[1] = sched->box[2] = 0;
   sched->max_row_nnz = 0;
@@ -1577,6 +1679,19 @@ extern "C" int lor_pattern(int space, int p, int64_t nel, int64_t nrows, const i
   else
     rc = general_schedule(sched, ref, is_signed, elem_map, row_ptr, col_idx, d_err, a, st);
   if (rc) return rc;
+  // a quadrilateral mesh keeps its general schedule (the coloured kernel) and
+  // gains the owner-computes one if it is a 2D box lattice
+  if (space == LOR_H1_2D) {
+    if ((rc = find_box_2d(elem_map, p, nel, nrows, row_ptr, dev_at<int32_t>(sched, sched->off_elem3d), a, st, &box,
+                          &is_box)))
+      return rc;
+    if (is_box) {
+      sched->box[0] = box.nx;
+      sched->box[1] = box.ny;
+      sched->box[2] = 1;
+      sched->owner = 1;
+    }
+  }
   LOR_HIP(hipStreamSynchronize(st));
   return LOR_OK;
 }

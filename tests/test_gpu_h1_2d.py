@@ -54,6 +54,58 @@ def test_h1_2d_small_parity(case):
     assert torch.equal(v64, v64[transpose_perm(rp, ci)])
 
 
+BOX2D = [(12, 5, 6, 0.1, True), (7, 9, 1, 0.15, False), (3, 4, 3, 0.1, True), (1, 1, 2, 0.0, False),
+         (70, 1, 1, 0.05, True)]
+
+
+@pytest.mark.parametrize("case", BOX2D, ids=[f"{c[0]}x{c[1]}p{c[2]}-perm{int(c[4])}" for c in BOX2D])
+def test_h1_2d_owner_parity(case):
+    """2D box lattices (also rectangular, with the elements in any order) get
+    the owner-computes schedule; both kernels in both forms against the
+    oracle, every row (row-relative 1e-12 FP64, 1e-6 FP32), the owner kernel
+    bitwise symmetric and deterministic.  12 x 5 at p = 6 spans two strips
+    of 64 cells (72 cells per line) and several segments along y; 70 x 1 at
+    p = 1 two strips with a short last one."""
+    nx, ny, p, amp, perm = case
+    _say("case", case)
+    m = meshgen.box_mesh_2d(nx, ny, p, amp)
+    kap = meshgen.kappa_field_2d(m["nel"], p, 1.0, seed=nx + ny + p)
+    if perm:
+        m, order = meshgen.permute_elements(m, seed=nx * ny)
+        kap = kap[torch.from_numpy(order)]
+    rp, ci, v = orc.h1_matrix_2d(m["coords"], m["elem_dofs"], p, kap, 0.6, m["ndofs"])
+    pat = lor.lor_pattern(lor.LOR_H1_2D, p, torch.from_numpy(m["elem_dofs"]).to(DEV), m["ndofs"])
+    assert pat.owner
+    assert torch.equal(pat.row_ptr.cpu().to(torch.int64), rp)
+    assert torch.equal(pat.col_idx.cpu().to(torch.int64), ci)
+    tp = transpose_perm(rp, ci)
+    for kern in ("owner", "colored"):
+        diag = torch.zeros(2, dtype=torch.int32, device=DEV)
+        v64 = _assemble(pat, m, kap, 0.6, kernel=kern, diag=diag)
+        v32 = _assemble(pat, m, kap.float(), 0.6, dtype=torch.float32, fp64_fallback=True, kernel=kern)
+        e64 = row_rel_err(rp, ci, v64, ci, v)
+        e32 = row_rel_err(rp, ci, v32, ci, v)
+        _say(f"  {kern}: fp64 {e64:.2e} fp32 {e32:.2e} diag {diag.cpu().tolist()}")
+        assert e64 <= 1e-12 and e32 <= 1e-6
+        assert diag.cpu().tolist() == [0, 0]
+        assert torch.equal(v64, v64[tp]) and torch.equal(v32, v32[tp])
+        if kern == "owner":
+            assert torch.equal(v64, _assemble(pat, m, kap, 0.6, kernel=kern))
+
+
+def test_h1_2d_owner_not_a_box():
+    """Renumbered vertices: no owner-computes schedule; asking for it fails
+    with LOR_EUNSUPPORTED and the default takes the coloured kernel."""
+    m = meshgen.cartesian_mesh_2d(3, 2, 0.1)
+    m, _ = meshgen.renumber_vertices(m, seed=4)
+    kap = meshgen.kappa_field_2d(m["nel"], 2, 1.0, seed=1)
+    pat = lor.lor_pattern(lor.LOR_H1_2D, 2, torch.from_numpy(m["elem_dofs"]).to(DEV), m["ndofs"])
+    assert not pat.owner
+    with pytest.raises(lor.LorError):
+        _assemble(pat, m, kap, 0.5, kernel="owner")
+    assert torch.equal(_assemble(pat, m, kap, 0.5), _assemble(pat, m, kap, 0.5, kernel="colored"))
+
+
 def test_h1_2d_closed_form_uniform():
     """Uniform square, kappa = 1, beta = 0: interior rows are the Q1 9-point
     stencil 8/3, -1/3 (printed form of the bilinear Laplacian)."""
@@ -91,8 +143,14 @@ def test_h1_2d_full_size_counts_and_sampled_rows():
     assert torch.equal(pat.col_idx.cpu().to(torch.int64)[idx], ci)
     e64 = row_rel_err(rp, ci, v64[idx], ci, v)
     e32 = row_rel_err(rp, ci, v32[idx], ci, v)
-    _say(f"sampled rows fp64 {e64:.2e} fp32 {e32:.2e}")
-    assert e64 <= 1e-12 and e32 <= 1e-6
+    assert pat.owner  # the default above is the owner-computes kernel; the coloured one too
+    c64 = _assemble(pat, m, m["kappa"], m["beta"], kernel="colored")
+    c32 = _assemble(pat, m, m["kappa"].float(), m["beta"], dtype=torch.float32, fp64_fallback=True, kernel="colored")
+    ec64 = row_rel_err(rp, ci, c64[idx], ci, v)
+    ec32 = row_rel_err(rp, ci, c32[idx], ci, v)
+    _say(f"sampled rows: owner fp64 {e64:.2e} fp32 {e32:.2e}; coloured fp64 {ec64:.2e} fp32 {ec32:.2e}")
+    assert e64 <= 1e-12 and e32 <= 1e-6 and ec64 <= 1e-12 and ec32 <= 1e-6
+    del c64, c32
     # the whole matrix: sorted rows, symmetric pattern, bitwise symmetric
     # values; and with zero diffusion row sums the entries add up to the area
     # of the mapped square, which is 1 (the boundary displacements A sin(2 pi t)

@@ -31,3 +31,33 @@ def test_box_mesh_incidence(box, p):
     # the perturbed lattice keeps the box corners where they were
     assert np.allclose(m["coords"][0], 0.0)
     assert np.allclose(m["coords"][-1], np.array(box) / max(box))
+
+
+@pytest.mark.parametrize("n,p", [(1, 1), (3, 2), (2, 5)])
+def test_box_mesh_2d_on_a_square_is_cartesian_mesh_2d(n, p):
+    a, b = meshgen.cartesian_mesh_2d(n, p, 0.1), meshgen.box_mesh_2d(n, n, p, 0.1)
+    assert np.array_equal(a["elem_dofs"], b["elem_dofs"])
+    assert np.array_equal(a["coords"], b["coords"])
+    assert a["ndofs"] == b["ndofs"] and a["nel"] == b["nel"]
+
+
+@pytest.mark.parametrize("box,p", [((3, 2), 2), ((1, 4), 3), ((5, 2), 1)])
+def test_box_mesh_2d_incidence(box, p):
+    m = meshgen.box_mesh_2d(*box, p)
+    L = [n * p + 1 for n in box]
+    counts = np.bincount(m["elem_dofs"].reshape(-1), minlength=m["ndofs"])
+    v = np.arange(m["ndofs"])
+    X, Y = v % L[0], v // L[0]
+
+    def per_axis(c, n):
+        return np.where((c % p == 0) & (c > 0) & (c < n * p), 2, 1)
+
+    assert np.array_equal(counts, per_axis(X, box[0]) * per_axis(Y, box[1]))
+    # local vertex i + (p+1) j of element (ex, ey) is lattice point (p ex + i, p ey + j)
+    e = box[0] + 0 if box[1] > 1 else 0
+    ex, ey = e % box[0], e // box[0]
+    q = p + 1
+    for l in range(q * q):
+        assert m["elem_dofs"][e][l] == (p * ex + l % q) + L[0] * (p * ey + l // q)
+    assert np.allclose(m["coords"][0], 0.0)
+    assert np.allclose(m["coords"][-1], np.array(box) / max(box))
