@@ -232,6 +232,12 @@ PROFILE_SETS = {
         "backward_f32": "k_h1_backward<4, float, float>",
         "gather_vertices": "k_gather_vertices",
     }, ("lor_backward.hip", "lor_h1_adjoint.hpp", "lor_h1_math.hpp", "lor_common.hpp")),
+    "h1_2d_p6_512sq": ({
+        "owner2d_f64": "k_h1_2d_owner<6, double, double>",
+        "owner2d_f32": "k_h1_2d_owner<6, float, float>",
+        "colored2d_f64": "k_h1_2d_assemble<6, double, double>",
+        "colored2d_f32": "k_h1_2d_assemble<6, float, float>",
+    }, ("lor_h1_2d_owner.hip", "lor_h1_2d.hip", "lor_h1_2d_math.hpp", "lor_h1_math.hpp", "lor_common.hpp")),
 }
 # VALU wave-instruction counters (one rocprofv3 --pmc pass holds all five)
 VALU_COUNTERS = ("SQ_INSTS_VALU_ADD_F64", "SQ_INSTS_VALU_MUL_F64", "SQ_INSTS_VALU_FMA_F64",
@@ -321,7 +327,8 @@ def summarize_profiles(stats_dir, fetch_dir, write_dir, command, name="h1_p6_32c
     --stats run; fetch_dir / write_dir: --pmc FETCH_SIZE and --pmc WRITE_SIZE
     runs (counters in KiB per dispatch), all of `bench.py --skip-extras` (the
     headline kernels on the headline mesh only) or of `bench.py
-    --backward-only` (name backward_p4_16cubed_b8)."""
+    --backward-only` (name backward_p4_16cubed_b8) or of `bench.py --h1-2d-only`
+    (name h1_2d_p6_512sq)."""
     kernels, sources = PROFILE_SETS[name]
     lines = [f"command: {command}", ""]
     stats = _read_csvs(stats_dir, "kernel_stats.csv")
@@ -455,6 +462,8 @@ def main():
     ap.add_argument("--skip-extras", action="store_true")
     ap.add_argument("--backward-only", action="store_true",
                     help="only the copy calibration and the backward leg (for profiling its kernels)")
+    ap.add_argument("--h1-2d-only", action="store_true",
+                    help="only the copy calibration and the 2D H1 leg (for profiling its kernels)")
     ap.add_argument("--pencil-small", action="store_true",
                     help="FP32 pencil eigenvalues on the 35,937-row mesh instead of the 274,625-row one")
     ap.add_argument("--summarize-profiles", nargs=3, metavar=("STATS_DIR", "FETCH_DIR", "WRITE_DIR"),
@@ -500,6 +509,12 @@ def main():
         calib = copy_calibration(torch, dev)
         log("backward")
         print(json.dumps({"backward": bench_backward(lor, meshgen, args, dev), "copy_calibration": calib}))
+        return
+    if args.h1_2d_only:
+        log("copy calibration")
+        calib = copy_calibration(torch, dev)
+        log("2D H1")
+        print(json.dumps({"h1_2d": bench_2d(lor, meshgen, args, dev), "copy_calibration": calib}))
         return
     log("building the headline inputs")
     m = meshgen.config_mesh("c3_h1_p6_curved")
@@ -940,9 +955,13 @@ def bench_2d(lor, meshgen, args, dev):
             fb = dt == torch.float32
             ms = time_it(lambda: lor.lor_assemble_h1_2d(pat, ed, x, k, m["beta"], dtype=dt, fp64_fallback=fb, out=out),
                          args.steps, args.warmup)
-            res[name] = {"ms": ms, "value": m["ndofs"] / (ms * 1e-3) / 1e6, "unit": "MDOF/s",
-                         "roofline": roofline_of(algorithmic_bytes_2d(m["nel"], 6, m["ndofs"], pat.nnz, dt.itemsize),
-                                                 ms)}
+            roof = roofline_of(algorithmic_bytes_2d(m["nel"], 6, m["ndofs"], pat.nnz, dt.itemsize), ms)
+            # HBM bytes of the kernel that ran, from the committed counter
+            # summary, if it is current
+            key = ("owner2d_" if pat.owner else "colored2d_") + name
+            tb, detail = load_traffic(key, "h1_2d_p6_512sq")
+            roof.update(traffic=tb, traffic_detail=detail)
+            res[name] = {"ms": ms, "value": m["ndofs"] / (ms * 1e-3) / 1e6, "unit": "MDOF/s", "roofline": roof}
             if pat.owner:  # the element-coloured kernel on the same mesh, for comparison
                 mc = time_it(lambda: lor.lor_assemble_h1_2d(pat, ed, x, k, m["beta"], dtype=dt, fp64_fallback=fb,
                                                             out=out, kernel="colored"), args.steps, args.warmup)
