@@ -981,16 +981,21 @@ def bench_rt(lor, meshgen, args, dev):
         fm = torch.from_numpy(m["elem_faces"]).to(dev)
         x = torch.from_numpy(m["coords"]).to(dev)
         pat = lor.lor_pattern(lor.LOR_RT, m["p"], fm, m["nfaces"])
-        res = {}
+        res = {"kernel": "owner" if pat.owner else "colored", "colored": {}}
         for name, dt in (("f64", torch.float64), ("f32", torch.float32)):
             k = m["kappa"].to(dev, dt)
             out = torch.empty(pat.nnz, dtype=dt, device=dev)
-            ms = time_it(lambda: lor.lor_assemble_rt(pat, ed, fm, x, k, 1.0, m["ndofs"], dtype=dt, out=out),
-                         args.steps, args.warmup)
+            fb = dt == torch.float32
+            ms = time_it(lambda: lor.lor_assemble_rt(pat, ed, fm, x, k, 1.0, m["ndofs"], dtype=dt, fp64_fallback=fb,
+                                                     out=out), args.steps, args.warmup)
             p = m["p"]
             res[name] = {"ms": ms, "value": m["nfaces"] / (ms * 1e-3) / 1e6, "unit": "MDOF/s",
                          "roofline": roofline_of(algorithmic_bytes_vec(m["nel"], p, m["nfaces"], m["ndofs"], pat.nnz,
                                                                        dt.itemsize, 3 * p * p * (p + 1)), ms)}
+            if pat.owner:  # the element-coloured kernel on the same mesh, for comparison
+                mc = time_it(lambda: lor.lor_assemble_rt(pat, ed, fm, x, k, 1.0, m["ndofs"], dtype=dt, fp64_fallback=fb,
+                                                         out=out, kernel="colored"), args.steps, args.warmup)
+                res["colored"][name] = {"ms": mc, "owner_speedup": mc / ms}
         res["workload"] = "H(div) LOR assembly, p=3, 24^3 curved hexes, kappa sigma=1, beta=1"
         res["rows"], res["nnz"], res["ncolors"] = m["nfaces"], pat.nnz, pat.ncolors
         return res

@@ -71,7 +71,7 @@ typedef enum { LOR_DIAG_ONE = 0, LOR_DIAG_KEEP = 1, LOR_DIAG_ZERO = 2 } lor_diag
  * det_ratio_thresh (or whose smallest corner Jacobian is <= 0) are integrated
  * with FP64 geometry instead of FP32. */
 #define LOR_FP64_FALLBACK 0x1u
-/* lor_assemble_h1 and lor_assemble_h1_2d: kernel choice.  By default the owner-computes kernel runs
+/* lor_assemble_h1, lor_assemble_h1_2d and lor_assemble_rt: kernel choice.  By default the owner-computes kernel runs
  * when the schedule has it (sched->owner) and the coloured kernel otherwise;
  * LOR_COLORED forces the coloured kernel, LOR_OWNER the owner-computes one
  * (LOR_EUNSUPPORTED if the schedule has none).  Both give the same matrix up
@@ -116,7 +116,7 @@ typedef struct lor_sched {
   size_t off_st_ptr, off_st_col, off_ent_row, off_recipe;
   size_t off_zero;               /* 256 zero bytes (read in place of an old value that is absent) */
   size_t off_order_class;        /* class of order[i] (int32 per element, in colour order) */
-  /* Owner-computes schedule (LOR_H1 and LOR_H1_2D; see lor_assemble_h1).  Present
+  /* Owner-computes schedule (LOR_H1, LOR_H1_2D, LOR_RT; see lor_assemble_h1).  Present
    * (owner == 1) when the mesh is a box lattice: the elements tile a box of
    * box[0] x box[1] x box[2] elements, each with its local axes along the box
    * axes, and the vertex at point (X, Y, Z) of the global lattice of
@@ -128,7 +128,8 @@ typedef struct lor_sched {
    * and box (a box lattice needs fewer schedule bytes); phase 2 fills the
    * arrays.  LOR_H1_2D: the same one dimension down (vertex X + LX Y,
    * box[2] = 1, elem3d holds the element at (ex, ey)), found in phase 2 on
-   * top of the general schedule, which the coloured kernel keeps using. */
+   * top of the general schedule, which the coloured kernel keeps using.
+   * LOR_RT: a face lattice (see lor_assemble_rt), also found in phase 2. */
   size_t off_elem3d;             /* int32 [box[2]][box[1]][box[0]]: element at box position (ex, ey, ez) */
   size_t off_base;               /* int32 [LZ][LY]: vertex id of lattice point (0, Y, Z) */
   int32_t owner;                 /* 1 if the owner-computes schedule is valid */
@@ -238,6 +239,13 @@ int lor_assemble_nd(int p, int64_t nel, int64_t ndofs_h1, int64_t nedges, int ba
  *   elem_faces  [nel][3p^2(p+1)] signed face map (the one given to lor_pattern
  *               with LOR_RT; layout as at lor_discrete_curl).
  *   nfaces      number of rows.  Other arguments as for lor_assemble_h1.
+ * Kernel choice (LOR_COLORED, LOR_OWNER) as for lor_assemble_h1: the
+ * owner-computes kernel runs by default when the face map is a face lattice
+ * (sched->owner: with (MX, MY, MZ) = (box[0] p, box[1] p, box[2] p) cells, the
+ * x-face at lattice x = X of cell row (Y, Z) has id X + (MX+1)(Y + MY Z), the
+ * y-faces and z-faces follow at OY = (MX+1) MY MZ and OZ = OY + MX (MY+1) MZ
+ * in the same way, any orientation signs, elements in any order, any vertex
+ * numbering); every row is then summed once in FP64 and stored once.
  */
 int lor_assemble_rt(int p, int64_t nel, int64_t ndofs_h1, int64_t nfaces, int batch,
                     const int32_t* elem_dofs, const int32_t* elem_faces, const double* coords,

@@ -41,6 +41,7 @@ __all__ = [
     "affine_mesh",
     "nd_edge_map",
     "face_map",
+    "face_map_box",
     "kappa_field",
     "kappa_field_2d",
     "cotangent",
@@ -303,6 +304,40 @@ def face_map(n: int, p: int) -> tuple[np.ndarray, int]:
                 X, Y, Z = p * ex + i, p * ey + j, p * ez + k
                 out[:, off + i + p * (j + p * k)] = 2 * N * M * M + X + M * (Y + M * Z)
     return out.astype(np.int32), 3 * N * M * M
+
+
+def face_map_box(nx: int, ny: int, nz: int, p: int) -> tuple[np.ndarray, int]:
+    """face_map for the nx x ny x nz elements of box_mesh: the same local
+    faces; global faces with cells (MX, MY, MZ) = (nx p, ny p, nz p) per axis:
+    x-faces X + (MX+1)*(Y + MY*Z); y-faces OY + X + MX*(Y + (MY+1)*Z) with
+    OY = (MX+1) MY MZ; z-faces OZ + X + MX*(Y + MY*Z) with OZ = OY + MX (MY+1) MZ.
+    face_map_box(n, n, n, p) equals face_map(n, p)."""
+    MX, MY, MZ = nx * p, ny * p, nz * p
+    q = p + 1
+    ne = nx * ny * nz
+    e = np.arange(ne)
+    ex, ey, ez = e % nx, (e // nx) % ny, e // (nx * ny)
+    OY = (MX + 1) * MY * MZ
+    OZ = OY + MX * (MY + 1) * MZ
+    out = np.empty((ne, 3 * p * p * q), dtype=np.int64)
+    for k in range(p):
+        for j in range(p):
+            for i in range(q):
+                X, Y, Z = p * ex + i, p * ey + j, p * ez + k
+                out[:, i + q * (j + p * k)] = X + (MX + 1) * (Y + MY * Z)
+    off = p * p * q
+    for k in range(p):
+        for j in range(q):
+            for i in range(p):
+                X, Y, Z = p * ex + i, p * ey + j, p * ez + k
+                out[:, off + i + p * (j + q * k)] = OY + X + MX * (Y + (MY + 1) * Z)
+    off = 2 * p * p * q
+    for k in range(q):
+        for j in range(p):
+            for i in range(p):
+                X, Y, Z = p * ex + i, p * ey + j, p * ez + k
+                out[:, off + i + p * (j + p * k)] = OZ + X + MX * (Y + MY * Z)
+    return out.astype(np.int32), OZ + MX * MY * (MZ + 1)
 
 
 def kappa_field(nel: int, p: int, sigma: float, seed: int = 0, batch: int | None = None,

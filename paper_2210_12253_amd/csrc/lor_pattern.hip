@@ -1030,6 +1030,84 @@ __global__ void k_box2d_place(const int32_t* __restrict__ map, int32_t nel, int3
     atomicOr(flag, 1);
 }
 
+// Face lattices (H(div) meshes): with (MX, MY, MZ) cells, the x-face at
+// lattice x = X of cell row (Y, Z) has id X + (MX + 1)(Y + MY Z), y-faces
+// OY + X + MX (Y + (MY + 1) Z) with OY = (MX + 1) MY MZ, z-faces
+// OZ + X + MX (Y + MY Z) with OZ = OY + MX (MY + 1) MZ.  Element 0's local
+// x-faces (0,0,0) and (1,0,0), y-faces (0,0,0) and (0,1,0), z-faces (0,0,0)
+// and (0,0,1) give the strides 1, MX and MX MY (signs dropped; these faces
+// exist at every p, also p = 1, where an element has one cell); one thread
+// per (element, local face) checks every id against the element's box
+// position, which its local x-face (0,0,0) gives.
+__device__ __forceinline__ int32_t face_id(int32_t v) { return v < 0 ? -1 - v : v; }
+
+__global__ void k_facebox_probe(const int32_t* __restrict__ map, int p, int32_t* __restrict__ out) {
+  const int q = p + 1, nx = p * p * q, i = threadIdx.x;
+  const int at[6] = {0, 1, nx, nx + p, 2 * nx, 2 * nx + p * p};
+  if (i < 6) out[i] = face_id(map[at[i]]);
+}
+
+template <int P>
+__global__ void k_facebox_place(const int32_t* __restrict__ map, int32_t nel, int32_t MX, int32_t MY, int32_t MZ,
+                                int nx, int ny, int32_t* __restrict__ elem3d, int32_t* __restrict__ flag) {
+  constexpr int Q = P + 1, NF = 3 * P * P * Q, NX = P * P * Q;
+  const int32_t t = static_cast<int32_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= nel * NF) return;  // nel * NF < 2^31
+  const int32_t e = t / NF;
+  const int l = t - e * NF;
+  const int64_t f0 = face_id(map[static_cast<int64_t>(e) * NF]);
+  const int64_t X0 = f0 % (MX + 1), Y0 = (f0 / (MX + 1)) % MY, Z0 = f0 / ((MX + 1) * static_cast<int64_t>(MY));
+  const int64_t OY = (MX + 1) * static_cast<int64_t>(MY) * MZ, OZ = OY + MX * static_cast<int64_t>(MY + 1) * MZ;
+  int64_t want;
+  if (l < NX) {
+    const int i = l % Q, j = (l / Q) % P, k = l / (Q * P);
+    want = (X0 + i) + (MX + 1) * ((Y0 + j) + MY * (Z0 + k));
+  } else if (l < 2 * NX) {
+    const int r = l - NX, i = r % P, j = (r / P) % Q, k = r / (P * Q);
+    want = OY + (X0 + i) + MX * ((Y0 + j) + (MY + 1) * (Z0 + k));
+  } else {
+    const int r = l - 2 * NX, i = r % P, j = (r / P) % P, k = r / (P * P);
+    want = OZ + (X0 + i) + MX * ((Y0 + j) + MY * (Z0 + k));
+  }
+  bool bad = face_id(map[t]) != want;
+  if (l == 0) {
+    bad = bad || Z0 >= MZ || X0 % P != 0 || Y0 % P != 0 || Z0 % P != 0 || X0 + P > MX || Y0 + P > MY ||
+          Z0 + P > MZ;
+    if (!bad) bad = atomicCAS(&elem3d[((Z0 / P) * ny + Y0 / P) * nx + X0 / P], -1, e) != -1;
+  }
+  const uint64_t m = __ballot(bad);
+  if (m != 0 && (threadIdx.x & 63) == static_cast<unsigned>(__ffsll(static_cast<long long>(m)) - 1))
+    atomicOr(flag, 1);
+}
+
+// The caller's row pointer against the face lattice's closed form: rows of
+// x-faces, then y-faces, then z-faces; 6 entries on the box boundary, 11
+// inside.
+__device__ __forceinline__ int64_t fl_prefix(int64_t X, int64_t M) {
+  return X <= 0 ? 0 : X <= M ? 6 + 11 * (X - 1) : 12 + 11 * (M - 1);
+}
+__global__ void k_facebox_rows(const int32_t* __restrict__ row_ptr, int64_t MX, int64_t MY, int64_t MZ,
+                               int32_t* __restrict__ flag) {
+  const int64_t OY = (MX + 1) * MY * MZ, OZ = OY + MX * (MY + 1) * MZ, n = OZ + MX * MY * (MZ + 1);
+  const int64_t f = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (f > n) return;
+  const int64_t nx = MY * MZ * fl_prefix(MX + 1, MX), ny = MZ * MX * fl_prefix(MY + 1, MY);
+  int64_t want;
+  if (f == n) {
+    want = nx + ny + MX * MY * fl_prefix(MZ + 1, MZ);
+  } else if (f < OY) {
+    const int64_t X = f % (MX + 1), YZ = f / (MX + 1);
+    want = YZ * fl_prefix(MX + 1, MX) + fl_prefix(X, MX);
+  } else if (f < OZ) {
+    const int64_t r = f - OY, X = r % MX, Y = (r / MX) % (MY + 1), Z = r / (MX * (MY + 1));
+    want = nx + Z * MX * fl_prefix(MY + 1, MY) + MX * fl_prefix(Y, MY) + X * ((Y == 0 || Y == MY) ? 6 : 11);
+  } else {
+    const int64_t r = f - OZ, XY = r % (MX * MY), Z = r / (MX * MY);
+    want = nx + ny + MX * MY * fl_prefix(Z, MZ) + XY * ((Z == 0 || Z == MZ) ? 6 : 11);
+  }
+  if (row_ptr[f] != want) atomicOr(flag, 1);
+}
+
 // The caller's row pointer against the 2D lattice's closed form.
 __global__ void k_box2d_rows(const int32_t* __restrict__ row_ptr, int64_t LX, int64_t LY, int32_t* __restrict__ flag) {
   const int64_t n = LX * LY;
@@ -1277,6 +1355,73 @@ static int find_box_2d(const int32_t* map, int p, int64_t nel, int64_t nrows, co
   box->nx = static_cast<int>(nx);
   box->ny = static_cast<int>(ny);
   box->nz = 1;
+  *found = true;
+  return LOR_OK;
+}
+
+// Face-lattice detection of an H(div) mesh, after its general schedule:
+// every element checked and placed in elem3d, row_ptr checked against the
+// closed form.  *found is false when the face map is no face lattice.
+static int find_face_box(const int32_t* map, int p, int64_t nel, int64_t nrows, const int32_t* row_ptr,
+                         int32_t* elem3d, Arena& a, hipStream_t st, BoxLattice* box, bool* found) {
+  *found = false;
+  if (nel == 0) return LOR_OK;
+  ArenaScope scope(a);
+  int32_t* probe;
+  LOR_TAKE(probe, a, int32_t, 7);
+  int rc;
+  k_facebox_probe<<<1, 64, 0, st>>>(map, p, probe);
+  LOR_LAUNCHED("k_facebox_probe");
+  int32_t h[6];
+  LOR_HIP(hipMemcpyAsync(h, probe, sizeof(h), hipMemcpyDeviceToHost, st));
+  LOR_HIP(hipStreamSynchronize(st));
+  const int64_t MX = static_cast<int64_t>(h[3]) - h[2];
+  if (static_cast<int64_t>(h[1]) - h[0] != 1 || MX < p || MX % p != 0) return LOR_OK;
+  const int64_t dz = static_cast<int64_t>(h[5]) - h[4];
+  if (dz <= 0 || dz % MX != 0) return LOR_OK;
+  const int64_t MY = dz / MX;
+  // nrows = (MX + 1) MY MZ + MX (MY + 1) MZ + MX MY (MZ + 1)
+  const int64_t per_z = (MX + 1) * MY + MX * (MY + 1) + MX * MY;
+  if (MY < p || MY % p != 0 || nrows < MX * MY || (nrows - MX * MY) % per_z != 0) return LOR_OK;
+  const int64_t MZ = (nrows - MX * MY) / per_z;
+  if (MZ < p || MZ % p != 0) return LOR_OK;
+  const int64_t nx = MX / p, ny = MY / p, nz = MZ / p;
+  if (nx * ny * nz != nel) return LOR_OK;
+  int32_t* flag = probe + 6;
+  LOR_HIP(hipMemsetAsync(flag, 0, sizeof(int32_t), st));
+  k_fill_i32<<<ceil_div(nel, 256), 256, 0, st>>>(elem3d, nel, -1);
+  LOR_LAUNCHED("k_fill_i32");
+  const int64_t threads = nel * 3 * p * p * (p + 1);
+  const int32_t mx = static_cast<int32_t>(MX), my = static_cast<int32_t>(MY), mz = static_cast<int32_t>(MZ);
+  const int32_t ne = static_cast<int32_t>(nel);
+  const int inx = static_cast<int>(nx), iny = static_cast<int>(ny);
+  switch (p) {
+#define LOR_FACEBOX_PLACE(PP)                                                                                    \
+  case PP:                                                                                                       \
+    k_facebox_place<PP><<<ceil_div(threads, 256), 256, 0, st>>>(map, ne, mx, my, mz, inx, iny, elem3d, flag);    \
+    break;
+    LOR_FACEBOX_PLACE(1)
+    LOR_FACEBOX_PLACE(2)
+    LOR_FACEBOX_PLACE(3)
+    LOR_FACEBOX_PLACE(4)
+    LOR_FACEBOX_PLACE(5)
+    LOR_FACEBOX_PLACE(6)
+#undef LOR_FACEBOX_PLACE
+    default:
+      LOR_FAIL(LOR_EINVAL, "p = %d outside [1, %d]", p, LOR_MAX_P);
+  }
+  LOR_LAUNCHED("k_facebox_place");
+  k_facebox_rows<<<ceil_div(nrows + 1, 256), 256, 0, st>>>(row_ptr, MX, MY, MZ, flag);
+  LOR_LAUNCHED("k_facebox_rows");
+  int32_t hflag = 0;
+  if ((rc = read_err(flag, st, &hflag))) return rc;
+  if (hflag != 0) return LOR_OK;
+  box->LX = MX;
+  box->LY = MY;
+  box->LZ = MZ;
+  box->nx = static_cast<int>(nx);
+  box->ny = static_cast<int>(ny);
+  box->nz = static_cast<int>(nz);
   *found = true;
   return LOR_OK;
 }
@@ -1576,7 +1721,7 @@ extern "C" int lor_pattern(int space, int p, int64_t nel, int64_t nrows, const i
   }
 
   // temporaries of this call, in one allocation
-  const size_t box_ws = arena_bytes<int32_t>(1) + arena_bytes<int32_t>(5) + arena_bytes<int32_t>(nel);
+  const size_t box_ws = arena_bytes<int32_t>(1) + arena_bytes<int32_t>(8) + arena_bytes<int32_t>(nel);
   Arena a;
   int32_t* d_err;
   int32_t herr = 0;
@@ -1680,7 +1825,19 @@ extern "C" int lor_pattern(int space, int p, int64_t nel, int64_t nrows, const i
     rc = general_schedule(sched, ref, is_signed, elem_map, row_ptr, col_idx, d_err, a, st);
   if (rc) return rc;
   // a quadrilateral mesh keeps its general schedule (the coloured kernel) and
-  // gains the owner-computes one if it is a 2D box lattice
+  // gains the owner-computes one if it is a 2D box lattice; an H(div) mesh
+  // if its face map is a face lattice
+  if (space == LOR_RT) {
+    if ((rc = find_face_box(elem_map, p, nel, nrows, row_ptr, dev_at<int32_t>(sched, sched->off_elem3d), a, st, &box,
+                            &is_box)))
+      return rc;
+    if (is_box) {
+      sched->box[0] = box.nx;
+      sched->box[1] = box.ny;
+      sched->box[2] = box.nz;
+      sched->owner = 1;
+    }
+  }
   if (space == LOR_H1_2D) {
     if ((rc = find_box_2d(elem_map, p, nel, nrows, row_ptr, dev_at<int32_t>(sched, sched->off_elem3d), a, st, &box,
                           &is_box)))

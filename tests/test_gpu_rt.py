@@ -70,6 +70,70 @@ def test_rt_small_parity(case):
     assert torch.equal(v64, v64[t])  # bitwise symmetric
 
 
+BOXRT = [(3, 3, 3, 1, 0.1, True, False, False), (2, 3, 1, 3, 0.12, False, True, True),
+         (5, 1, 2, 3, 0.1, True, True, False), (1, 1, 1, 6, 0.1, False, False, True),
+         (2, 2, 2, 4, 0.1, True, False, True)]
+
+
+@pytest.mark.parametrize("case", BOXRT, ids=[f"{c[0]}x{c[1]}x{c[2]}p{c[3]}-f{int(c[5])}r{int(c[6])}e{int(c[7])}"
+                                             for c in BOXRT])
+def test_rt_owner_parity(case):
+    """Face lattices (also rectangular boxes, flipped face orientations,
+    renumbered vertices, elements in any order) get the owner-computes
+    schedule; both kernels in both forms against the oracle, every row, the
+    owner kernel bitwise symmetric and deterministic.  5 x 1 x 2 at p = 3
+    spans three tiles of 8 cells along x (15 cells), 2 x 2 x 2 at p = 4 two
+    along each of x and y."""
+    nx, ny, nz, p, amp, flip, renumber, perm = case
+    _say("case", case)
+    m = meshgen.box_mesh(nx, ny, nz, p, amp)
+    fm, nf = meshgen.face_map_box(nx, ny, nz, p)
+    kap = meshgen.kappa_field(m["nel"], p, 1.0, seed=nx + ny + nz + p)
+    if flip:
+        fm, _ = meshgen.flip_edge_signs(fm, nf, seed=p)
+    if renumber:
+        m, _ = meshgen.renumber_vertices(m, seed=p + 1)
+    if perm:
+        m, order = meshgen.permute_elements(m, seed=nx * ny * nz)
+        fm = np.ascontiguousarray(fm[order])
+        kap = kap[torch.from_numpy(order)]
+    rp, ci, v = orc.rt_matrix(m["coords"], m["elem_dofs"], fm, p, kap, 0.8, nf)
+    pat = lor.lor_pattern(lor.LOR_RT, p, torch.from_numpy(fm).to(DEV), nf)
+    assert pat.owner
+    assert torch.equal(pat.row_ptr.cpu().to(torch.int64), rp)
+    assert torch.equal(pat.col_idx.cpu().to(torch.int64), ci)
+    tp = transpose_perm(rp, ci)
+    for kern in ("owner", "colored"):
+        diag = torch.zeros(2, dtype=torch.int32, device=DEV)
+        v64 = _assemble(pat, m, fm, kap, 0.8, kernel=kern, diag=diag)
+        v32 = _assemble(pat, m, fm, kap.float(), 0.8, dtype=torch.float32, fp64_fallback=True, kernel=kern)
+        e64 = row_rel_err(rp, ci, v64, ci, v)
+        e32 = row_rel_err(rp, ci, v32, ci, v)
+        _say(f"  {kern}: fp64 {e64:.2e} fp32 {e32:.2e} diag {diag.cpu().tolist()}")
+        assert e64 <= 1e-12 and e32 <= 1e-6
+        assert diag.cpu().tolist() == [0, 0]
+        assert torch.equal(v64, v64[tp]) and torch.equal(v32, v32[tp])
+        if kern == "owner":
+            assert torch.equal(v64, _assemble(pat, m, fm, kap, 0.8, kernel=kern))
+
+
+def test_rt_owner_not_a_face_lattice():
+    """Reoriented elements: no face lattice, LOR_OWNER fails with
+    LOR_EUNSUPPORTED, the default takes the coloured kernel."""
+    m = meshgen.cartesian_mesh(2, 2, 0.1)
+    fm, nf = meshgen.face_map(2, 2)
+    kap = meshgen.kappa_field(m["nel"], 2, 1.0, seed=3)
+    m2, kap2, _ = meshgen.reorient_elements(m, seed=5, kappa=kap)
+    fm2, nf2 = meshgen.face_map_from_vertices(m2["elem_dofs"], 2)
+    assert nf2 == nf
+    pat = lor.lor_pattern(lor.LOR_RT, 2, torch.from_numpy(fm2).to(DEV), nf)
+    assert not pat.owner
+    with pytest.raises(lor.LorError):
+        _assemble(pat, m2, fm2, kap2, 0.5, kernel="owner")
+    rp, ci, v = orc.rt_matrix(m2["coords"], m2["elem_dofs"], fm2, 2, kap2, 0.5, nf)
+    assert row_rel_err(rp, ci, _assemble(pat, m2, fm2, kap2, 0.5), ci, v) <= 1e-12
+
+
 def test_rt_batch_matches_single_and_is_deterministic():
     m, fm, nf, _ = _setup(2, 3, 0.1, 1.0, seed=1)
     kb = meshgen.kappa_field(m["nel"], 3, 1.0, seed=4, batch=3)

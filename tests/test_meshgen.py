@@ -61,3 +61,32 @@ def test_box_mesh_2d_incidence(box, p):
         assert m["elem_dofs"][e][l] == (p * ex + l % q) + L[0] * (p * ey + l // q)
     assert np.allclose(m["coords"][0], 0.0)
     assert np.allclose(m["coords"][-1], np.array(box) / max(box))
+
+
+@pytest.mark.parametrize("n,p", [(1, 2), (2, 3), (3, 1)])
+def test_face_map_box_on_a_cube_is_face_map(n, p):
+    a, na = meshgen.face_map(n, p)
+    b, nb = meshgen.face_map_box(n, n, n, p)
+    assert na == nb and np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("box,p", [((3, 2, 1), 2), ((1, 2, 3), 1)])
+def test_face_map_box_matches_vertices(box, p):
+    """Every face once per macro element holding it (2 on the faces between
+    two elements, 1 elsewhere), and the same faces as derived from the vertex
+    map alone."""
+    m = meshgen.box_mesh(*box, p)
+    fm, nf = meshgen.face_map_box(*box, p)
+    counts = np.bincount(fm.reshape(-1), minlength=nf)
+    M = [n * p for n in box]
+    nshared = (box[0] - 1) * M[1] * M[2] + (box[1] - 1) * M[0] * M[2] + (box[2] - 1) * M[0] * M[1]
+    assert nf == (M[0] + 1) * M[1] * M[2] + M[0] * (M[1] + 1) * M[2] + M[0] * M[1] * (M[2] + 1)
+    assert np.sort(counts).tolist() == [1] * (nf - nshared) + [2] * nshared
+    fv, nfv = meshgen.face_map_from_vertices(m["elem_dofs"], p)
+    assert nfv == nf
+    # the two numberings differ by a relabelling of the faces: the same
+    # partition of (element, local face) slots into faces
+    pairs = {}
+    for a, b in zip(np.abs(fm).reshape(-1).tolist(), (np.where(fv < 0, -1 - fv, fv)).reshape(-1).tolist()):
+        assert pairs.setdefault(a, b) == b
+    assert len(set(pairs.values())) == nf
