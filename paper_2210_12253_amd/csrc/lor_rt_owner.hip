@@ -26,6 +26,8 @@
 // two cells in a fixed order.  All sums are FP64, in the FP32 form too.  The
 // cell corners are gathered through the vertex map (the vertex numbering can
 // be anything), the element and its coefficient through the element grid.
+#include <algorithm>
+
 #include "lor_common.hpp"
 #include "lor_rt_math.hpp"
 
@@ -75,6 +77,36 @@ __host__ __device__ constexpr int rt_pos(int axis, int hi, int v) {
   return P[axis][hi][v];
 }
 
+// FP32 form, strongly distorted cell: the FP64 integration from the FP64
+// corners (gathered again through the vertex map; lv0 is the local vertex of
+// corner 0), entries signed by negmask (bit u: face u reversed) and rounded
+// to FP32 into the slab (64 = distance between two entries of a cell).
+template <int P>
+__device__ __noinline__ bool rt_owner_fp64_fallback(const int32_t* __restrict__ elem_dofs,
+                                                    const double* __restrict__ coords, int32_t el, int lv0, double kap,
+                                                    double bet, unsigned negmask, float* out) {
+  constexpr int Q = P + 1, NLOCV = Q * Q * Q;
+  double X[8][3];
+#pragma unroll
+  for (int v = 0; v < 8; ++v) {
+    const int64_t g = elem_dofs[static_cast<int64_t>(el) * NLOCV + lv0 + (v & 1) + Q * (((v >> 1) & 1) + Q * (v >> 2))];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) X[v][d] = coords[3 * g + d];
+  }
+  double ex[2][2][3], ey[2][2][3], ez[2][2][3];
+  h1_edges<double>(X, ex, ey, ez);
+  RTFactors<double> F;
+  const bool ok = rt_factors<double>(ex, ey, ez, kap, bet, F);
+#pragma unroll
+  for (int u = 0; u < 6; ++u)
+#pragma unroll
+    for (int v = u; v < 6; ++v) {
+      const float e = static_cast<float>(rt_entry<double>(F, u, v));
+      out[pair_index6(u, v) * 64] = (((negmask >> u) ^ (negmask >> v)) & 1u) ? -e : e;
+    }
+  return ok;
+}
+
 template <int P, typename T, typename R>
 __global__ __launch_bounds__(64) void k_rt_owner(int nex, int ney, int nez, int ntx, int seglen,
                                                 const int32_t* __restrict__ elem3d,
@@ -116,31 +148,91 @@ __global__ __launch_bounds__(64) void k_rt_owner(int nex, int ney, int nez, int 
 #pragma unroll
   for (int v = 0; v < 6; ++v) carry[v] = 0.0;
 
+  // Loads of the cell column, layer Zl clamped to the mesh (a lane without a
+  // cell reads the last one and never uses it).
+  const int sx = Xc % P, sy = Yc % P;
+  auto elem_of = [&](int Zl) {
+    const int zc = Zl < MZ ? Zl : MZ - 1;
+    return elem3d[(static_cast<int64_t>(zc / P) * ney + Yc / P) * nex + Xc / P];
+  };
+  // vertex ids of the 4 corners of the cell of layer Zl on its lower (c = 0)
+  // or upper (c = 1) face, corner a + 2 b
+  auto corner_ids = [&](int32_t el, int Zl, int c, int32_t(&ids)[4]) {
+    const int sz = (Zl < MZ ? Zl : MZ - 1) % P + c;
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+      ids[v] = elem_dofs[static_cast<int64_t>(el) * NLOCV + (sx + (v & 1)) + Q * ((sy + (v >> 1)) + Q * sz)];
+  };
+  auto corner_xyz = [&](const int32_t(&ids)[4], double(&c)[4][3]) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+#pragma unroll
+      for (int d = 0; d < 3; ++d) c[v][d] = coords[3 * static_cast<int64_t>(ids[v]) + d];
+  };
+  // the face-map words of the cell's faces x-, x+, y-, y+, z-, z+ (local face
+  // numbering of the element: x-faces i + q (j + p k), y-faces
+  // p^2 q + i + p (j + q k), z-faces 2 p^2 q + i + p (j + p k)); their signs
+  // are the orientations
+  auto face_words = [&](int32_t el, int Zl, int32_t(&fw)[6]) {
+    const int sz = (Zl < MZ ? Zl : MZ - 1) % P;
+    const int32_t* fm = elem_faces + static_cast<int64_t>(el) * NLOCF;
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      fw[0 + t] = fm[(sx + t) + Q * (sy + P * sz)];
+      fw[2 + t] = fm[P * P * Q + sx + P * ((sy + t) + Q * sz)];
+      fw[4 + t] = fm[2 * P * P * Q + sx + P * (sy + P * (sz + t))];
+    }
+  };
+  auto kap_of = [&](int32_t el, int Zl) {
+    const int sz = (Zl < MZ ? Zl : MZ - 1) % P;
+    return kappa[static_cast<int64_t>(el) * NSUB + sx + P * (sy + P * sz)];
+  };
+
+  // Pipeline: the step of layer Z holds the corners of its cell (lower =
+  // upper of the cell below), its face words and coefficient, the element
+  // of layer Z + 1 and the upper-corner ids of the cell of layer Z + 1.  It
+  // loads, before its integration, the face words and coefficient of the next
+  // cell and the element two layers up, and after it the next cell's upper
+  // corners and the upper-corner ids of the cell after that, so that no step
+  // waits on a chain of dependent loads (and the integration, the register
+  // peak, holds no prefetched corners).
+  double lo[4][3], hi[4][3];
+  int32_t fw[6], idn[4];
+  T kq;
+  int32_t el1, elc;  // elements of layers Z + 1 and Z
+  {
+    const int32_t el0 = elem_of(zfirst);
+    elc = el0;
+    int32_t ids[4];
+    corner_ids(el0, zfirst, 0, ids);
+    corner_xyz(ids, lo);
+    corner_ids(el0, zfirst, 1, ids);
+    corner_xyz(ids, hi);
+    face_words(el0, zfirst, fw);
+    kq = kap_of(el0, zfirst);
+    el1 = elem_of(zfirst + 1);
+    corner_ids(el1, zfirst + 1, 1, idn);
+  }
+
   for (int Z = zfirst; Z < zend; ++Z) {
     const bool cell = cell_col && Z < MZ;
+    int32_t fwn[6];
+    face_words(el1, Z + 1, fwn);
+    const T kn = kap_of(el1, Z + 1);
+    const int32_t el2 = elem_of(Z + 2);
     if (cell) {
-      const int32_t el = elem3d[(static_cast<int64_t>(Z / P) * ney + Yc / P) * nex + Xc / P];
-      const int sx = Xc % P, sy = Yc % P, sz = Z % P;
-      const R kap = static_cast<R>(kappa[static_cast<int64_t>(el) * NSUB + sx + P * (sy + P * sz)]);
+      const R kap = static_cast<R>(kq);
       double Xv[8][3];
 #pragma unroll
-      for (int v = 0; v < 8; ++v) {
-        const int lv = (sx + (v & 1)) + Q * ((sy + ((v >> 1) & 1)) + Q * (sz + (v >> 2)));
-        const int64_t g = elem_dofs[static_cast<int64_t>(el) * NLOCV + lv];
+      for (int v = 0; v < 4; ++v)
 #pragma unroll
-        for (int d = 0; d < 3; ++d) Xv[v][d] = coords[3 * g + d];
-      }
-      // orientation signs of the cell's faces x-, x+, y-, y+, z-, z+ (local
-      // face numbering of the element: x-faces i + q (j + p k), y-faces
-      // p^2 q + i + p (j + q k), z-faces 2 p^2 q + i + p (j + p k))
+        for (int d = 0; d < 3; ++d) {
+          Xv[v][d] = lo[v][d];
+          Xv[4 + v][d] = hi[v][d];
+        }
       bool neg[6];
-      const int32_t* fm = elem_faces + static_cast<int64_t>(el) * NLOCF;
 #pragma unroll
-      for (int t = 0; t < 2; ++t) {
-        neg[0 + t] = fm[(sx + t) + Q * (sy + P * sz)] < 0;
-        neg[2 + t] = fm[P * P * Q + sx + P * ((sy + t) + Q * sz)] < 0;
-        neg[4 + t] = fm[2 * P * P * Q + sx + P * (sy + P * (sz + t))] < 0;
-      }
+      for (int u = 0; u < 6; ++u) neg[u] = fw[u] < 0;
       // counted once: a cell in a tile's last column (row) is the first of
       // the next tile, which counts it
       const bool own = Z >= zs && lx < kRtStride && ly < kRtStride;
@@ -154,7 +246,6 @@ __global__ __launch_bounds__(64) void k_rt_owner(int nex, int ney, int nez, int 
           fallback = !(dmin > R(0)) || dmax > det_thresh * dmin;
         }
       }
-      R ent[21];
       if (!fallback) {
         R ex[2][2][3], ey[2][2][3], ez[2][2][3];
         h1_edges<R>(Xv, ex, ey, ez);
@@ -163,30 +254,32 @@ __global__ __launch_bounds__(64) void k_rt_owner(int nex, int ney, int nez, int 
 #pragma unroll
         for (int u = 0; u < 6; ++u)
 #pragma unroll
-          for (int v = u; v < 6; ++v) ent[pair_index6(u, v)] = rt_entry<R>(F, u, v);
+          for (int v = u; v < 6; ++v) {
+            const R e = rt_entry<R>(F, u, v);
+            sCell[pair_index6(u, v) * 64 + lane] = (neg[u] != neg[v]) ? -e : e;
+          }
         if (!ok && own && diag) atomicAdd(&diag[1], 1);
       } else {
-        double ex[2][2][3], ey[2][2][3], ez[2][2][3];
-        h1_edges<double>(Xv, ex, ey, ez);
-        RTFactors<double> F;
-        const bool ok = rt_factors<double>(ex, ey, ez, static_cast<double>(kap), static_cast<double>(beta), F);
+        // FP32 only, rare: FP64 geometry and quadrature out of line (inlined,
+        // its FP64 registers would be reserved for the whole kernel)
+        unsigned negmask = 0;
 #pragma unroll
-        for (int u = 0; u < 6; ++u)
-#pragma unroll
-          for (int v = u; v < 6; ++v) ent[pair_index6(u, v)] = static_cast<R>(rt_entry<double>(F, u, v));
+        for (int u = 0; u < 6; ++u) negmask |= neg[u] ? 1u << u : 0u;
+        const bool ok = rt_owner_fp64_fallback<P>(elem_dofs, coords, elc, sx + Q * (sy + Q * (Z % P)),
+                                               static_cast<double>(kap), static_cast<double>(beta), negmask,
+                                               reinterpret_cast<float*>(sCell) + lane);
         if (own && diag) {
           atomicAdd(&diag[0], 1);
           if (!ok) atomicAdd(&diag[1], 1);
         }
       }
-#pragma unroll
-      for (int u = 0; u < 6; ++u)
-#pragma unroll
-        for (int v = u; v < 6; ++v) {
-          const R e = ent[pair_index6(u, v)];
-          sCell[pair_index6(u, v) * 64 + lane] = (neg[u] != neg[v]) ? -e : e;
-        }
     }
+    // the next cell's upper corners (their ids arrived during the
+    // integration) and the ids of the one after it
+    double hin[4][3];
+    corner_xyz(idn, hin);
+    int32_t idn2[4];
+    corner_ids(el2, Z + 2, 1, idn2);
     __syncthreads();
 
     // the three rows of this lane, each at the interior positions; the terms
@@ -232,6 +325,21 @@ __global__ __launch_bounds__(64) void k_rt_owner(int nex, int ney, int nez, int 
       }
     }
     __syncthreads();
+    // the next layer's cell: its lower corners are this cell's upper ones
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        lo[v][d] = hi[v][d];
+        hi[v][d] = hin[v][d];
+      }
+#pragma unroll
+    for (int u = 0; u < 6; ++u) fw[u] = fwn[u];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) idn[v] = idn2[v];
+    kq = kn;
+    elc = el1;
+    el1 = el2;
     if (Z < zs) continue;  // the layer below the segment: carry only
 
     // stage and store one row type at a time: line l of the tile holds the
@@ -334,15 +442,34 @@ static int launch_rt_owner(const lor_sched* s, int batch, const int32_t* elem_do
   const int MX = nex * P, MY = ney * P, MZ = nez * P;
   // tiles so that the last one reaches the last face: 7 (ntx - 1) + 7 >= MX
   const int ntx = static_cast<int>(ceil_div(MX, kRtStride)), nty = static_cast<int>(ceil_div(MY, kRtStride));
-  // segments along z: about 4 waves per SIMD, at least 4 layers each (a
-  // segment integrates one extra layer to build its carry)
-  const int64_t target = int64_t(4) * 4 * num_cus_rt();
-  int seglen = static_cast<int>(ceil_div(static_cast<int64_t>(MZ) * ntx * nty * batch, target));
-  if (seglen < 4) seglen = 4;
-  if (seglen > MZ) seglen = MZ;
+  // Segments along z (a segment above the bottom integrates one extra layer
+  // to build its carry).  The waves run in rounds over the chip's wave slots
+  // (CUs x resident waves per CU, from the kernel's register use), so the
+  // launch takes about ceil(waves / slots) x (layers per wave + 1) layer
+  // steps: pick the segment length that minimises it.
+  static int wpc[64] = {};
+  int dev = 0;
+  LOR_HIP(hipGetDevice(&dev));
+  if (dev >= 0 && dev < 64 && wpc[dev] == 0) {
+    int n = 0;
+    LOR_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_rt_owner<P, T, R>, 64, 0));
+    wpc[dev] = n > 0 ? n : 1;
+  }
+  const int64_t slots = static_cast<int64_t>(num_cus_rt()) * ((dev >= 0 && dev < 64) ? wpc[dev] : 1);
+  const int64_t tiles = static_cast<int64_t>(ntx) * nty;
+  int64_t seglen = MZ, best = -1;
+  for (int64_t len = std::min<int64_t>(2, MZ); len <= MZ; ++len) {
+    const int64_t ns = ceil_div(MZ, len);
+    if (ns > 1 && ceil_div(MZ, ns) != len) continue;  // same split as a shorter length
+    const int64_t cost = ceil_div(tiles * ns * batch, slots) * (len + (ns > 1));
+    if (best < 0 || cost < best) {
+      best = cost;
+      seglen = len;
+    }
+  }
   const int nseg = static_cast<int>(ceil_div(MZ, seglen));
   dim3 grid(static_cast<unsigned>(ntx * nty), static_cast<unsigned>(nseg), static_cast<unsigned>(batch));
-  k_rt_owner<P, T, R><<<grid, 64, 0, st>>>(nex, ney, nez, ntx, seglen, dev_at<int32_t>(s, s->off_elem3d), elem_dofs,
+  k_rt_owner<P, T, R><<<grid, 64, 0, st>>>(nex, ney, nez, ntx, static_cast<int>(seglen), dev_at<int32_t>(s, s->off_elem3d), elem_dofs,
                                           elem_faces, coords, static_cast<const T*>(kappa), static_cast<T>(beta),
                                           s->nel, s->nnz, static_cast<T*>(values), flags, static_cast<R>(thr), diag);
   LOR_LAUNCHED("k_rt_owner");
