@@ -40,6 +40,7 @@ __all__ = [
     "box_mesh_2d",
     "affine_mesh",
     "nd_edge_map",
+    "nd_edge_map_box",
     "face_map",
     "face_map_box",
     "kappa_field",
@@ -266,6 +267,41 @@ def nd_edge_map(n: int, p: int) -> tuple[np.ndarray, int]:
                 X, Y, Z = p * ex + i, p * ey + j, p * ez + k
                 out[:, ll] = 2 * M * N * N + X + N * (Y + N * Z)
     return out.astype(np.int32), 3 * M * N * N
+
+
+def nd_edge_map_box(nx: int, ny: int, nz: int, p: int) -> tuple[np.ndarray, int]:
+    """nd_edge_map for the nx x ny x nz elements of box_mesh: the same local
+    edges; global edges with cells (MX, MY, MZ) = (nx p, ny p, nz p) per axis:
+    x-edges X + MX*(Y + (MY+1)*Z); y-edges OY + X + (MX+1)*(Y + MY*Z) with
+    OY = MX (MY+1) (MZ+1); z-edges OZ + X + (MX+1)*(Y + (MY+1)*Z) with
+    OZ = OY + (MX+1) MY (MZ+1).  nd_edge_map_box(n, n, n, p) equals
+    nd_edge_map(n, p)."""
+    MX, MY, MZ = nx * p, ny * p, nz * p
+    q = p + 1
+    ne = nx * ny * nz
+    e = np.arange(ne)
+    ex, ey, ez = e % nx, (e // nx) % ny, e // (nx * ny)
+    OY = MX * (MY + 1) * (MZ + 1)
+    OZ = OY + (MX + 1) * MY * (MZ + 1)
+    out = np.empty((ne, 3 * p * q * q), dtype=np.int64)
+    for k in range(q):
+        for j in range(q):
+            for i in range(p):
+                X, Y, Z = p * ex + i, p * ey + j, p * ez + k
+                out[:, i + p * (j + q * k)] = X + MX * (Y + (MY + 1) * Z)
+    off = p * q * q
+    for k in range(q):
+        for j in range(p):
+            for i in range(q):
+                X, Y, Z = p * ex + i, p * ey + j, p * ez + k
+                out[:, off + i + q * (j + p * k)] = OY + X + (MX + 1) * (Y + MY * Z)
+    off = 2 * p * q * q
+    for k in range(p):
+        for j in range(q):
+            for i in range(q):
+                X, Y, Z = p * ex + i, p * ey + j, p * ez + k
+                out[:, off + i + q * (j + q * k)] = OZ + X + (MX + 1) * (Y + (MY + 1) * Z)
+    return out.astype(np.int32), OZ + (MX + 1) * (MY + 1) * MZ
 
 
 def face_map(n: int, p: int) -> tuple[np.ndarray, int]:

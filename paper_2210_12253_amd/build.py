@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "liblor.so")
-SOURCES = ["lor_common.hip", "lor_pattern.hip", "lor_h1.hip", "lor_h1_owner.hip", "lor_nd.hip", "lor_rt.hip", "lor_rt_owner.hip", "lor_h1_2d.hip", "lor_h1_2d_owner.hip", "lor_backward.hip", "lor_elim.hip", "lor_aux.hip", "lor_unstructured.hip"]
+SOURCES = ["lor_common.hip", "lor_pattern.hip", "lor_h1.hip", "lor_h1_owner.hip", "lor_nd.hip", "lor_nd_owner.hip", "lor_rt.hip", "lor_rt_owner.hip", "lor_h1_2d.hip", "lor_h1_2d_owner.hip", "lor_backward.hip", "lor_elim.hip", "lor_aux.hip", "lor_unstructured.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

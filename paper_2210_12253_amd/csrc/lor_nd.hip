@@ -23,6 +23,10 @@
 namespace lor {
 
 int check_sched(const lor_sched* s, int space, int p, int64_t nel, int64_t nrows);
+template <typename T, typename R>
+int dispatch_nd_owner(int p, const lor_sched* s, int batch, const int32_t* ed, const int32_t* em, const double* x,
+                      const void* k, double beta, const int32_t* rp, void* v, unsigned f, double thr, int32_t* diag,
+                      hipStream_t st);
 
 template <int P, typename R>
 struct NDCfg {
@@ -454,7 +458,8 @@ extern "C" int lor_assemble_nd(int p, int64_t nel, int64_t ndofs_h1, int64_t ned
   if (nel < 0 || ndofs_h1 < 1 || nedges < 1) LOR_FAIL(LOR_EINVAL, "nel < 0, ndofs_h1 < 1 or nedges < 1");
   if (batch < 1 || batch > 65535) LOR_FAIL(LOR_EINVAL, "batch outside [1, 65535]");
   if (dtype != LOR_F64 && dtype != LOR_F32) LOR_FAIL(LOR_EINVAL, "dtype must be LOR_F64 or LOR_F32");
-  if (flags & ~LOR_FP64_FALLBACK) LOR_FAIL(LOR_EINVAL, "unknown flag bits 0x%x", flags);
+  if (flags & ~(LOR_FP64_FALLBACK | LOR_COLORED | LOR_OWNER)) LOR_FAIL(LOR_EINVAL, "unknown flag bits 0x%x", flags);
+  if ((flags & LOR_COLORED) && (flags & LOR_OWNER)) LOR_FAIL(LOR_EINVAL, "LOR_COLORED and LOR_OWNER both set");
   if ((flags & LOR_FP64_FALLBACK) && !(det_ratio_thresh >= 1.0))
     LOR_FAIL(LOR_EINVAL, "det_ratio_thresh must be >= 1");
   if (nel > 0 && (!elem_dofs || !elem_edges || !coords || !kappa || !row_ptr || !values))
@@ -463,10 +468,20 @@ extern "C" int lor_assemble_nd(int p, int64_t nel, int64_t ndofs_h1, int64_t ned
   if (rc) return rc;
   if (static_cast<int64_t>(batch) * sched->nnz >= (int64_t(1) << 40)) LOR_FAIL(LOR_EOVERFLOW, "batch * nnz too large");
   if (nel == 0) return LOR_OK;
+  if ((flags & LOR_OWNER) && !sched->owner)
+    LOR_FAIL(LOR_EUNSUPPORTED, "LOR_OWNER: the edge map is no edge lattice (no owner-computes schedule)");
   hipStream_t st = as_stream(stream);
+  // default: owner-computes wherever the schedule has it (also at p = 6,
+  // which the coloured kernel does not take)
+  const bool owner = sched->owner && !(flags & LOR_COLORED);
+  const unsigned fb = flags & LOR_FP64_FALLBACK;
   if (dtype == LOR_F64)
-    return dispatch_nd<double, double>(p, sched, batch, elem_dofs, elem_edges, coords, kappa, beta, row_ptr, values,
-                                       0u, det_ratio_thresh, diag, st);
-  return dispatch_nd<float, float>(p, sched, batch, elem_dofs, elem_edges, coords, kappa, beta, row_ptr, values,
-                                   flags, det_ratio_thresh, diag, st);
+    return owner ? dispatch_nd_owner<double, double>(p, sched, batch, elem_dofs, elem_edges, coords, kappa, beta,
+                                                     row_ptr, values, 0u, det_ratio_thresh, diag, st)
+                 : dispatch_nd<double, double>(p, sched, batch, elem_dofs, elem_edges, coords, kappa, beta, row_ptr,
+                                               values, 0u, det_ratio_thresh, diag, st);
+  return owner ? dispatch_nd_owner<float, float>(p, sched, batch, elem_dofs, elem_edges, coords, kappa, beta, row_ptr,
+                                                 values, fb, det_ratio_thresh, diag, st)
+               : dispatch_nd<float, float>(p, sched, batch, elem_dofs, elem_edges, coords, kappa, beta, row_ptr,
+                                           values, fb, det_ratio_thresh, diag, st);
 }

@@ -1108,6 +1108,112 @@ __global__ void k_facebox_rows(const int32_t* __restrict__ row_ptr, int64_t MX, 
   if (row_ptr[f] != want) atomicOr(flag, 1);
 }
 
+// Edge lattices (H(curl) meshes): with (MX, MY, MZ) cells, the x-edge from
+// lattice point (X, Y, Z) has id X + MX (Y + (MY + 1) Z), y-edges
+// OY + X + (MX + 1)(Y + MY Z) with OY = MX (MY + 1)(MZ + 1), z-edges
+// OZ + X + (MX + 1)(Y + (MY + 1) Z) with OZ = OY + (MX + 1) MY (MZ + 1).
+// Element 0's local x-edges (0,0,0), (0,1,0) and y-edges (0,0,0), (1,0,0),
+// (0,0,1) give the strides 1, MX and (MX + 1) MY (they exist at every p).
+__global__ void k_edgebox_probe(const int32_t* __restrict__ map, int p, int32_t* __restrict__ out) {
+  const int q = p + 1, ny = p * q * q, i = threadIdx.x;
+  const int at[5] = {0, p, ny, ny + 1, ny + q * p};
+  if (i < 5) out[i] = face_id(map[at[i]]);
+}
+
+template <int P>
+__global__ void k_edgebox_place(const int32_t* __restrict__ map, int32_t nel, int32_t MX, int32_t MY, int32_t MZ,
+                                int nx, int ny, int32_t* __restrict__ elem3d, int32_t* __restrict__ flag) {
+  constexpr int Q = P + 1, NE = 3 * P * Q * Q, NX = P * Q * Q;
+  const int32_t t = static_cast<int32_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= nel * NE) return;  // nel * NE < 2^31
+  const int32_t e = t / NE;
+  const int l = t - e * NE;
+  const int64_t f0 = face_id(map[static_cast<int64_t>(e) * NE]);
+  const int64_t X0 = f0 % MX, Y0 = (f0 / MX) % (MY + 1), Z0 = f0 / (MX * static_cast<int64_t>(MY + 1));
+  const int64_t OY = MX * static_cast<int64_t>(MY + 1) * (MZ + 1), OZ = OY + (MX + 1) * static_cast<int64_t>(MY) * (MZ + 1);
+  int64_t want;
+  if (l < NX) {
+    const int i = l % P, j = (l / P) % Q, k = l / (P * Q);
+    want = (X0 + i) + MX * ((Y0 + j) + (MY + 1) * (Z0 + k));
+  } else if (l < 2 * NX) {
+    const int r = l - NX, i = r % Q, j = (r / Q) % P, k = r / (Q * P);
+    want = OY + (X0 + i) + (MX + 1) * ((Y0 + j) + MY * (Z0 + k));
+  } else {
+    const int r = l - 2 * NX, i = r % Q, j = (r / Q) % Q, k = r / (Q * Q);
+    want = OZ + (X0 + i) + (MX + 1) * ((Y0 + j) + (MY + 1) * (Z0 + k));
+  }
+  bool bad = face_id(map[t]) != want;
+  if (l == 0) {
+    bad = bad || Z0 > MZ || X0 % P != 0 || Y0 % P != 0 || Z0 % P != 0 || X0 + P > MX || Y0 + P > MY ||
+          Z0 + P > MZ;
+    if (!bad) bad = atomicCAS(&elem3d[((Z0 / P) * ny + Y0 / P) * nx + X0 / P], -1, e) != -1;
+  }
+  const uint64_t m = __ballot(bad);
+  if (m != 0 && (threadIdx.x & 63) == static_cast<unsigned>(__ffsll(static_cast<long long>(m)) - 1))
+    atomicOr(flag, 1);
+}
+
+// The caller's CSR pattern against the edge lattice's closed form: the row
+// of an edge along m holds the edges of the <= 4 cells around it, sorted:
+// x-edges, y-edges, z-edges, each group in (z, y, x) order over per-axis
+// ranges (along m: the edge's cell for its own group, the 2 end nodes for
+// the others; along another axis d: the cells d - 1, d for the group along
+// d, the nodes d - 1 .. d + 1 for the others, as far as they exist).
+__global__ void k_edgebox_rows(const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col_idx, int64_t MX,
+                               int64_t MY, int64_t MZ, int32_t* __restrict__ flag) {
+  const int64_t L[3] = {MX, MY, MZ};
+  const int64_t OY = MX * (MY + 1) * (MZ + 1), OZ = OY + (MX + 1) * MY * (MZ + 1);
+  const int64_t n = OZ + (MX + 1) * (MY + 1) * MZ;
+  const int64_t f = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (f >= n) return;
+  int m;
+  int64_t c[3];
+  if (f < OY) {
+    m = 0;
+    c[0] = f % MX;
+    c[1] = (f / MX) % (MY + 1);
+    c[2] = f / (MX * (MY + 1));
+  } else if (f < OZ) {
+    const int64_t r = f - OY;
+    m = 1;
+    c[0] = r % (MX + 1);
+    c[1] = (r / (MX + 1)) % MY;
+    c[2] = r / ((MX + 1) * MY);
+  } else {
+    const int64_t r = f - OZ;
+    m = 2;
+    c[0] = r % (MX + 1);
+    c[1] = (r / (MX + 1)) % (MY + 1);
+    c[2] = r / ((MX + 1) * (MY + 1));
+  }
+  int64_t start = row_ptr[f], pos = 0;
+  bool bad = false;
+  for (int g = 0; g < 3; ++g) {
+    int64_t lo[3], cnt[3];
+    for (int d = 0; d < 3; ++d) {
+      if (d == m) {
+        lo[d] = c[d];
+        cnt[d] = g == m ? 1 : 2;
+      } else {
+        lo[d] = c[d] - (c[d] > 0);
+        cnt[d] = (g == d ? 0 : 1) + (c[d] > 0) + (c[d] < L[d]);
+      }
+    }
+    for (int64_t iz = 0; iz < cnt[2]; ++iz)
+      for (int64_t iy = 0; iy < cnt[1]; ++iy)
+        for (int64_t ix = 0; ix < cnt[0]; ++ix) {
+          const int64_t x = lo[0] + ix, y = lo[1] + iy, z = lo[2] + iz;
+          const int64_t want = g == 0   ? x + MX * (y + (MY + 1) * z)
+                               : g == 1 ? OY + x + (MX + 1) * (y + MY * z)
+                                        : OZ + x + (MX + 1) * (y + (MY + 1) * z);
+          if (start + pos >= row_ptr[f + 1] || col_idx[start + pos] != want) bad = true;
+          ++pos;
+        }
+  }
+  if (start + pos != row_ptr[f + 1]) bad = true;
+  if (bad) atomicOr(flag, 1);
+}
+
 // The caller's row pointer against the 2D lattice's closed form.
 __global__ void k_box2d_rows(const int32_t* __restrict__ row_ptr, int64_t LX, int64_t LY, int32_t* __restrict__ flag) {
   const int64_t n = LX * LY;
@@ -1413,6 +1519,75 @@ static int find_face_box(const int32_t* map, int p, int64_t nel, int64_t nrows, 
   LOR_LAUNCHED("k_facebox_place");
   k_facebox_rows<<<ceil_div(nrows + 1, 256), 256, 0, st>>>(row_ptr, MX, MY, MZ, flag);
   LOR_LAUNCHED("k_facebox_rows");
+  int32_t hflag = 0;
+  if ((rc = read_err(flag, st, &hflag))) return rc;
+  if (hflag != 0) return LOR_OK;
+  box->LX = MX;
+  box->LY = MY;
+  box->LZ = MZ;
+  box->nx = static_cast<int>(nx);
+  box->ny = static_cast<int>(ny);
+  box->nz = static_cast<int>(nz);
+  *found = true;
+  return LOR_OK;
+}
+
+// Edge-lattice detection of an H(curl) mesh, after its general schedule:
+// every element checked and placed in elem3d, the CSR pattern checked
+// against the closed form.  *found is false when the edge map is no edge
+// lattice.
+static int find_edge_box(const int32_t* map, int p, int64_t nel, int64_t nrows, const int32_t* row_ptr,
+                         const int32_t* col_idx, int32_t* elem3d, Arena& a, hipStream_t st, BoxLattice* box,
+                         bool* found) {
+  *found = false;
+  if (nel == 0) return LOR_OK;
+  ArenaScope scope(a);
+  int32_t* probe;
+  LOR_TAKE(probe, a, int32_t, 7);
+  int rc;
+  k_edgebox_probe<<<1, 64, 0, st>>>(map, p, probe);
+  LOR_LAUNCHED("k_edgebox_probe");
+  int32_t h[5];
+  LOR_HIP(hipMemcpyAsync(h, probe, sizeof(h), hipMemcpyDeviceToHost, st));
+  LOR_HIP(hipStreamSynchronize(st));
+  const int64_t MX = static_cast<int64_t>(h[1]) - h[0];
+  if (static_cast<int64_t>(h[3]) - h[2] != 1 || MX < p || MX % p != 0) return LOR_OK;
+  const int64_t dz = static_cast<int64_t>(h[4]) - h[2];
+  if (dz <= 0 || dz % (MX + 1) != 0) return LOR_OK;
+  const int64_t MY = dz / (MX + 1);
+  // nrows = MX (MY + 1)(MZ + 1) + (MX + 1) MY (MZ + 1) + (MX + 1)(MY + 1) MZ
+  const int64_t base = MX * (MY + 1) + (MX + 1) * MY, per_z = base + (MX + 1) * (MY + 1);
+  if (MY < p || MY % p != 0 || nrows < base || (nrows - base) % per_z != 0) return LOR_OK;
+  const int64_t MZ = (nrows - base) / per_z;
+  if (MZ < p || MZ % p != 0) return LOR_OK;
+  const int64_t nx = MX / p, ny = MY / p, nz = MZ / p;
+  if (nx * ny * nz != nel) return LOR_OK;
+  int32_t* flag = probe + 6;
+  LOR_HIP(hipMemsetAsync(flag, 0, sizeof(int32_t), st));
+  k_fill_i32<<<ceil_div(nel, 256), 256, 0, st>>>(elem3d, nel, -1);
+  LOR_LAUNCHED("k_fill_i32");
+  const int64_t threads = nel * 3 * p * (p + 1) * (p + 1);
+  const int32_t mx = static_cast<int32_t>(MX), my = static_cast<int32_t>(MY), mz = static_cast<int32_t>(MZ);
+  const int32_t ne = static_cast<int32_t>(nel);
+  const int inx = static_cast<int>(nx), iny = static_cast<int>(ny);
+  switch (p) {
+#define LOR_EDGEBOX_PLACE(PP)                                                                                    \
+  case PP:                                                                                                       \
+    k_edgebox_place<PP><<<ceil_div(threads, 256), 256, 0, st>>>(map, ne, mx, my, mz, inx, iny, elem3d, flag);    \
+    break;
+    LOR_EDGEBOX_PLACE(1)
+    LOR_EDGEBOX_PLACE(2)
+    LOR_EDGEBOX_PLACE(3)
+    LOR_EDGEBOX_PLACE(4)
+    LOR_EDGEBOX_PLACE(5)
+    LOR_EDGEBOX_PLACE(6)
+#undef LOR_EDGEBOX_PLACE
+    default:
+      LOR_FAIL(LOR_EINVAL, "p = %d outside [1, %d]", p, LOR_MAX_P);
+  }
+  LOR_LAUNCHED("k_edgebox_place");
+  k_edgebox_rows<<<ceil_div(nrows, 256), 256, 0, st>>>(row_ptr, col_idx, MX, MY, MZ, flag);
+  LOR_LAUNCHED("k_edgebox_rows");
   int32_t hflag = 0;
   if ((rc = read_err(flag, st, &hflag))) return rc;
   if (hflag != 0) return LOR_OK;
@@ -1827,6 +2002,17 @@ extern "C" int lor_pattern(int space, int p, int64_t nel, int64_t nrows, const i
   // a quadrilateral mesh keeps its general schedule (the coloured kernel) and
   // gains the owner-computes one if it is a 2D box lattice; an H(div) mesh
   // if its face map is a face lattice
+  if (space == LOR_ND) {
+    if ((rc = find_edge_box(elem_map, p, nel, nrows, row_ptr, col_idx, dev_at<int32_t>(sched, sched->off_elem3d), a,
+                            st, &box, &is_box)))
+      return rc;
+    if (is_box) {
+      sched->box[0] = box.nx;
+      sched->box[1] = box.ny;
+      sched->box[2] = box.nz;
+      sched->owner = 1;
+    }
+  }
   if (space == LOR_RT) {
     if ((rc = find_face_box(elem_map, p, nel, nrows, row_ptr, dev_at<int32_t>(sched, sched->off_elem3d), a, st, &box,
                             &is_box)))

@@ -239,7 +239,7 @@ class Pattern:
     @property
     def owner(self) -> bool:
         """True if the mesh has the owner-computes schedule (an H1 box lattice,
-        3D or 2D, or an H(div) face lattice)."""
+        3D or 2D, an H(curl) edge lattice or an H(div) face lattice)."""
         return bool(self.sched.owner)
 
 
@@ -301,8 +301,13 @@ def lor_assemble_h1(pat: Pattern, elem_dofs, coords, kappa, beta: float, dtype=t
 
 def lor_assemble_nd(pat: Pattern, elem_dofs, elem_edges, coords, kappa, beta: float, ndofs_h1: int,
                     dtype=torch.float64, fp64_fallback: bool = False, det_ratio_thresh: float = 10.0,
-                    diag: torch.Tensor | None = None, out: torch.Tensor | None = None) -> torch.Tensor:
-    """Values of the H(curl) LOR matrix, [nnz] (or [batch, nnz])."""
+                    diag: torch.Tensor | None = None, out: torch.Tensor | None = None,
+                    kernel: str = "auto") -> torch.Tensor:
+    """Values of the H(curl) LOR matrix, [nnz] (or [batch, nnz]).  kernel:
+    "auto" (owner-computes when the edge map is an edge lattice, else
+    coloured), "owner" or "colored"."""
+    if kernel not in _KERNEL_FLAGS:
+        raise ValueError("kernel must be 'auto', 'owner' or 'colored'")
     lib = load_library()
     dev = pat.row_ptr.device
     ed = _dev_tensor(elem_dofs, torch.int32, "elem_dofs", dev)
@@ -318,7 +323,7 @@ def lor_assemble_nd(pat: Pattern, elem_dofs, elem_edges, coords, kappa, beta: fl
     _need(k, batch * pat.nel * p ** 3, "kappa")
     diag = _diag(diag, 2, dev)
     out = _out(out, (batch, pat.nnz) if batched else (pat.nnz,), dtype, dev)
-    flags = LOR_FP64_FALLBACK if fp64_fallback else 0
+    flags = (LOR_FP64_FALLBACK if fp64_fallback else 0) | _KERNEL_FLAGS[kernel]
     _check(lib.lor_assemble_nd(pat.p, pat.nel, ndofs_h1, pat.nrows, batch, _ptr(ed), _ptr(ee), _ptr(x), _ptr(k),
                                float(beta), _ptr(pat.row_ptr), ctypes.byref(pat.sched), _ptr(out),
                                _dtype_code(dtype), flags, float(det_ratio_thresh), _ptr(diag), _stream()))

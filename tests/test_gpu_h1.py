@@ -319,9 +319,9 @@ def test_pattern_workspace_bounds_phase1_bytes(space):
         sp = lor.LOR_RT
     pat = lor.lor_pattern(sp, p, torch.from_numpy(emap).to(DEV), nrows)
     ws = lib.lor_pattern_workspace(sp, p, emap.shape[0], nrows)
-    # box lattices (H1 3D and 2D) and face lattices (H(div)) have the
-    # owner-computes schedule; it does not change the 2D and H(div) sizes
-    assert pat.owner == (space in ("h1", "h1_box", "rt", "h1_2d"))
+    # box lattices (H1 3D and 2D), face lattices (H(div)) and edge lattices (H(curl))
+    # have the owner-computes schedule; it does not change the 2D, H(div) and H(curl) sizes
+    assert pat.owner == (space in ("h1", "h1_box", "rt", "h1_2d", "nd"))
     if space == "h1_box":
         assert int(pat.sched.dev_bytes) < ws
     else:

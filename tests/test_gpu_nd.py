@@ -110,3 +110,81 @@ def test_nd_exact_sequence_on_gpu_values():
     G = orc.csr_to_scipy(grp, gci, gv, m["ndofs"])
     KG = (K @ G).toarray()
     assert np.abs(KG).max() <= 1e-13 * abs(K).max()
+
+
+BOXND = [(3, 3, 3, 1, 0.1, True, False, False), (2, 3, 1, 3, 0.12, False, True, True),
+         (5, 1, 2, 3, 0.1, True, True, False), (1, 1, 1, 6, 0.1, False, False, True),
+         (2, 2, 2, 4, 0.1, True, False, True), (1, 2, 1, 5, 0.12, True, True, True),
+         (2, 1, 1, 6, 0.1, True, False, False)]
+
+
+@pytest.mark.parametrize("case", BOXND, ids=[f"{c[0]}x{c[1]}x{c[2]}p{c[3]}-f{int(c[5])}r{int(c[6])}e{int(c[7])}"
+                                             for c in BOXND])
+def test_nd_owner_parity(case):
+    """Edge lattices (also rectangular boxes, flipped edge orientations,
+    renumbered vertices, elements in any order) get the owner-computes
+    schedule; both kernels in both forms against the oracle, every row, the
+    owner kernel bitwise symmetric and deterministic.  5 x 1 x 2 at p = 3
+    spans two tiles of 8 edges along y and z (15 cells along x), 2 x 2 x 2
+    at p = 4 two tiles on every axis; p = 6 is taken by the owner kernel
+    only (the coloured kernel stops at p = 5)."""
+    nx, ny, nz, p, amp, flip, renumber, perm = case
+    _say("case", case)
+    m = meshgen.box_mesh(nx, ny, nz, p, amp)
+    ee, ned = meshgen.nd_edge_map_box(nx, ny, nz, p)
+    kap = meshgen.kappa_field(m["nel"], p, 1.0, seed=nx + ny + nz + p)
+    if flip:
+        ee, _ = meshgen.flip_edge_signs(ee, ned, seed=p)
+    if renumber:
+        m, _ = meshgen.renumber_vertices(m, seed=p + 1)
+    if perm:
+        m, order = meshgen.permute_elements(m, seed=nx * ny * nz)
+        ee = np.ascontiguousarray(ee[order])
+        kap = kap[torch.from_numpy(order)]
+    rp, ci, v = orc.nd_matrix(m["coords"], m["elem_dofs"], ee, p, kap, 0.7, ned)
+    pat = lor.lor_pattern(lor.LOR_ND, p, torch.from_numpy(ee).to(DEV), ned)
+    assert pat.owner
+    assert torch.equal(pat.row_ptr.cpu().to(torch.int64), rp)
+    assert torch.equal(pat.col_idx.cpu().to(torch.int64), ci)
+    tp = torch.from_numpy(transpose_perm(rp, ci))
+    for kern in ("owner", "colored") if p <= 5 else ("owner",):
+        diag = torch.zeros(2, dtype=torch.int32, device=DEV)
+        v64 = _assemble(pat, m, ee, kap, 0.7, kernel=kern, diag=diag)
+        v32 = _assemble(pat, m, ee, kap.float(), 0.7, dtype=torch.float32, fp64_fallback=True, kernel=kern)
+        e64 = row_rel_err(rp, ci, v64, ci, v)
+        e32 = row_rel_err(rp, ci, v32, ci, v)
+        _say(f"  {kern}: fp64 {e64:.2e} fp32 {e32:.2e} diag {diag.cpu().tolist()}")
+        assert e64 <= 1e-12 and e32 <= 1e-6
+        assert diag.cpu().tolist() == [0, 0]
+        assert torch.equal(v64, v64[tp]) and torch.equal(v32, v32[tp])
+        if kern == "owner":
+            assert torch.equal(v64, _assemble(pat, m, ee, kap, 0.7, kernel=kern))
+    if p == 6:
+        with pytest.raises(lor.LorError):
+            _assemble(pat, m, ee, kap, 0.7, kernel="colored")
+
+
+def test_nd_owner_batch_matches_single():
+    """A batch of coefficients through the owner kernel equals the single
+    calls, row for row, in both forms."""
+    m = meshgen.box_mesh(3, 2, 2, 2, 0.1)
+    ee, ned = meshgen.nd_edge_map_box(3, 2, 2, 2)
+    kb = meshgen.kappa_field(m["nel"], 2, 1.0, seed=4, batch=3)
+    pat = lor.lor_pattern(lor.LOR_ND, 2, torch.from_numpy(ee).to(DEV), ned)
+    assert pat.owner
+    for dt in (torch.float64, torch.float32):
+        vb = _assemble(pat, m, ee, kb.to(dt), 0.5, dtype=dt, kernel="owner")
+        for b in range(3):
+            assert torch.equal(vb[b], _assemble(pat, m, ee, kb[b].to(dt), 0.5, dtype=dt, kernel="owner"))
+
+
+def test_nd_owner_not_an_edge_lattice():
+    """Reoriented elements: no edge lattice, LOR_OWNER fails with
+    LOR_EUNSUPPORTED, the default takes the coloured kernel."""
+    m, ee, ned, kap = _setup(2, 2, 0.1, 1.0, seed=3, reorient=True)
+    pat = lor.lor_pattern(lor.LOR_ND, 2, torch.from_numpy(ee).to(DEV), ned)
+    assert not pat.owner
+    with pytest.raises(lor.LorError):
+        _assemble(pat, m, ee, kap, 0.5, kernel="owner")
+    rp, ci, v = orc.nd_matrix(m["coords"], m["elem_dofs"], ee, 2, kap, 0.5, ned)
+    assert row_rel_err(rp, ci, _assemble(pat, m, ee, kap, 0.5), ci, v) <= 1e-12
