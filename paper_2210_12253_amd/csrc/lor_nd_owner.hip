@@ -137,7 +137,7 @@ __host__ __device__ __forceinline__ int64_t nd_edge_id(int e, int64_t x, int64_t
 // edges along m (local r0 + a + 2 b) signed by negmask (bit v: edge v
 // reversed) and rounded to FP32 into the slab ([row][col][lane]).
 template <int P>
-__device__ __noinline__ bool nd_owner_fp64_fallback(const int32_t* __restrict__ elem_dofs,
+__device__ __forceinline__ bool nd_owner_fp64_fallback(const int32_t* __restrict__ elem_dofs,
                                                     const double* __restrict__ coords, int32_t el, int lv0, int r0,
                                                     double kap, double bet, unsigned negmask, float* out) {
   constexpr int Q = P + 1, NLOCV = Q * Q * Q;
@@ -164,8 +164,10 @@ __device__ __noinline__ bool nd_owner_fp64_fallback(const int32_t* __restrict__ 
   return ok;
 }
 
+// Two waves per SIMD at most registers: the FP32 form's FP64 fallback is
+// inlined (a call would make the kernel reserve the callee's registers too).
 template <int P, typename T, typename R, int M>
-__global__ __launch_bounds__(64) void k_nd_owner(int nex, int ney, int nez, int nt1, int seglen,
+__global__ __launch_bounds__(64, 2) void k_nd_owner(int nex, int ney, int nez, int nt1, int seglen,
                                                 const int32_t* __restrict__ elem3d,
                                                 const int32_t* __restrict__ elem_dofs,
                                                 const int32_t* __restrict__ elem_edges,
