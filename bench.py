@@ -1011,18 +1011,23 @@ def bench_nd(lor, meshgen, args, dev):
         ee = torch.from_numpy(m["elem_edges"]).to(dev)
         x = torch.from_numpy(m["coords"]).to(dev)
         pat = lor.lor_pattern(lor.LOR_ND, m["p"], ee, m["nedges"])
-        res = {}
+        res = {"kernel": "owner" if pat.owner else "colored", "colored": {}}
         for name, dt in (("f64", torch.float64), ("f32", torch.float32)):
             k = m["kappa"].to(dev, dt)
             out = torch.empty(pat.nnz, dtype=dt, device=dev)
-            ms = time_it(lambda: lor.lor_assemble_nd(pat, ed, ee, x, k, 1.0, m["ndofs"], dtype=dt, out=out),
-                         args.steps, args.warmup)
+            fb = dt == torch.float32
+            ms = time_it(lambda: lor.lor_assemble_nd(pat, ed, ee, x, k, 1.0, m["ndofs"], dtype=dt, fp64_fallback=fb,
+                                                     out=out), args.steps, args.warmup)
             p = m["p"]
             res[name] = {"ms": ms, "value": m["nedges"] / (ms * 1e-3) / 1e6, "unit": "MDOF/s",
                          "roofline": roofline_of(algorithmic_bytes_vec(m["nel"], p, m["nedges"], m["ndofs"], pat.nnz,
                                                                        dt.itemsize, 3 * p * (p + 1) ** 2), ms)}
+            if pat.owner:  # the element-coloured kernel on the same mesh, for comparison
+                mc = time_it(lambda: lor.lor_assemble_nd(pat, ed, ee, x, k, 1.0, m["ndofs"], dtype=dt, fp64_fallback=fb,
+                                                         out=out, kernel="colored"), args.steps, args.warmup)
+                res["colored"][name] = {"ms": mc, "owner_speedup": mc / ms}
         res["workload"] = "H(curl) LOR assembly, p=3, 24^3 curved hexes, kappa sigma=1, beta=1"
-        res["rows"], res["nnz"] = m["nedges"], pat.nnz
+        res["rows"], res["nnz"], res["ncolors"] = m["nedges"], pat.nnz, pat.ncolors
         return res
     except lor.LorError as e:
         return {"error": str(e)}

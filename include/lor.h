@@ -71,11 +71,12 @@ typedef enum { LOR_DIAG_ONE = 0, LOR_DIAG_KEEP = 1, LOR_DIAG_ZERO = 2 } lor_diag
  * det_ratio_thresh (or whose smallest corner Jacobian is <= 0) are integrated
  * with FP64 geometry instead of FP32. */
 #define LOR_FP64_FALLBACK 0x1u
-/* lor_assemble_h1, lor_assemble_h1_2d and lor_assemble_rt: kernel choice.  By default the owner-computes kernel runs
- * when the schedule has it (sched->owner) and the coloured kernel otherwise;
- * LOR_COLORED forces the coloured kernel, LOR_OWNER the owner-computes one
- * (LOR_EUNSUPPORTED if the schedule has none).  Both give the same matrix up
- * to the order of the floating-point sums. */
+/* lor_assemble_h1, lor_assemble_h1_2d, lor_assemble_rt and lor_assemble_nd:
+ * kernel choice.  By default the owner-computes kernel runs when the schedule
+ * has it (sched->owner) and the coloured kernel otherwise; LOR_COLORED forces
+ * the coloured kernel, LOR_OWNER the owner-computes one (LOR_EUNSUPPORTED if
+ * the schedule has none).  Both give the same matrix up to the order of the
+ * floating-point sums. */
 #define LOR_COLORED 0x2u
 #define LOR_OWNER 0x4u
 
@@ -116,7 +117,7 @@ typedef struct lor_sched {
   size_t off_st_ptr, off_st_col, off_ent_row, off_recipe;
   size_t off_zero;               /* 256 zero bytes (read in place of an old value that is absent) */
   size_t off_order_class;        /* class of order[i] (int32 per element, in colour order) */
-  /* Owner-computes schedule (LOR_H1, LOR_H1_2D, LOR_RT; see lor_assemble_h1).  Present
+  /* Owner-computes schedule (LOR_H1, LOR_H1_2D, LOR_RT, LOR_ND; see lor_assemble_h1).  Present
    * (owner == 1) when the mesh is a box lattice: the elements tile a box of
    * box[0] x box[1] x box[2] elements, each with its local axes along the box
    * axes, and the vertex at point (X, Y, Z) of the global lattice of
@@ -129,7 +130,8 @@ typedef struct lor_sched {
    * arrays.  LOR_H1_2D: the same one dimension down (vertex X + LX Y,
    * box[2] = 1, elem3d holds the element at (ex, ey)), found in phase 2 on
    * top of the general schedule, which the coloured kernel keeps using.
-   * LOR_RT: a face lattice (see lor_assemble_rt), also found in phase 2. */
+   * LOR_RT: a face lattice (see lor_assemble_rt), LOR_ND: an edge lattice
+   * (see lor_assemble_nd), both also found in phase 2. */
   size_t off_elem3d;             /* int32 [box[2]][box[1]][box[0]]: element at box position (ex, ey, ez) */
   size_t off_base;               /* int32 [LZ][LY]: vertex id of lattice point (0, Y, Z) */
   int32_t owner;                 /* 1 if the owner-computes schedule is valid */
@@ -220,6 +222,16 @@ int lor_assemble_h1(int p, int64_t nel, int64_t ndofs, int batch, const int32_t*
  *   elem_dofs   [nel][(p+1)^3] vertex map (geometry).
  *   elem_edges  [nel][3p(p+1)^2] signed edge map (the one given to lor_pattern).
  *   nedges      number of rows.  Other arguments as for lor_assemble_h1.
+ * Kernel choice (LOR_COLORED, LOR_OWNER) as for lor_assemble_h1: the
+ * owner-computes kernel runs by default when the edge map is an edge lattice
+ * (sched->owner: with (MX, MY, MZ) = (box[0] p, box[1] p, box[2] p) cells, the
+ * x-edge from lattice point (X, Y, Z) has id X + MX (Y + (MY+1) Z), the
+ * y-edges and z-edges follow at OY = MX (MY+1)(MZ+1) and
+ * OZ = OY + (MX+1) MY (MZ+1) in the same way, any orientation signs, elements
+ * in any order, any vertex numbering); every row is then summed once in FP64
+ * and stored once.  The coloured kernel takes p <= 5 (LOR_EUNSUPPORTED
+ * above: a macro element's 78 entries per subelement no longer fit in LDS at
+ * p = 6); the owner-computes kernel takes every p up to LOR_MAX_P.
  */
 int lor_assemble_nd(int p, int64_t nel, int64_t ndofs_h1, int64_t nedges, int batch,
                     const int32_t* elem_dofs, const int32_t* elem_edges, const double* coords,
