@@ -16,10 +16,12 @@
 //     in a layer need only that layer's cells, so the steps carry nothing;
 //   * lane (i, j) integrates its cell (the 4 rows of its edges along m, 12
 //     columns each, times the orientation signs from its element's edge map)
-//     into the wave's LDS slab, then sums the row of the edge along m at its
-//     tile node from the cells at lanes (i - a, j - b), a, b in {0, 1}, in
-//     one fixed order of the cells (increasing z, then y, then x) that every
-//     direction's launch shares, so the matrix is bitwise symmetric;
+//     into the wave's LDS slab (FP64: 2 rows at a time, in two passes, so
+//     that LDS does not limit the waves per CU), then sums the row of the
+//     edge along m at its tile node from the cells at lanes (i - a, j - b),
+//     a, b in {0, 1}, in one fixed order of the cells (increasing z, then y,
+//     then x) that every direction's launch shares, so the matrix is bitwise
+//     symmetric;
 //   * a row's columns are sorted by id: the x-edges, then the y-edges, then
 //     the z-edges, each group in (z, y, x) order over per-axis ranges (a
 //     node axis has 3 values inside the box and 2 on its faces, a cell axis
@@ -178,7 +180,12 @@ __global__ __launch_bounds__(64, 2) void k_nd_owner(int nex, int ney, int nez, i
   constexpr int Q = P + 1, NSUB = P * P * P, NLOCV = Q * Q * Q, NLOCE = 3 * P * Q * Q;
   constexpr int T1 = M == 0 ? 1 : 0, T2 = M == 2 ? 1 : 2;  // the tile axes
   constexpr int RBASE = 4 * M;                              // first local edge along M
-  constexpr int SLAB = 48 * 64 * static_cast<int>(sizeof(R));
+  // FP64: the cell's 4 rows go through the slab in two passes (b = 1, then
+  // b = 0), so that the slab takes half the LDS and does not limit the waves
+  // per CU
+  constexpr int NH = sizeof(R) == 8 ? 2 : 1;
+  constexpr int RPP = 4 / NH;  // rows per pass
+  constexpr int SLAB = RPP * 12 * 64 * static_cast<int>(sizeof(R));
   constexpr int STG = 64 * kNdRow * static_cast<int>(sizeof(T));
   __shared__ __align__(16) unsigned char sBuf[SLAB > STG ? SLAB : STG];
   __shared__ int64_t sStart[64];
@@ -207,92 +214,184 @@ __global__ __launch_bounds__(64, 2) void k_nd_owner(int nex, int ney, int nez, i
   // first; only the x-edge launch counts
   const bool count = M == 0 && l1 < kNdStride && l2 < kNdStride;
 
+  // the cell's rows RBASE + jb .. RBASE + jb + RPP - 1 into the slab, signed
+  auto write_rows = [&](const H1Factors<R>& F, const NDCurl<R>& W, unsigned negmask, int jb) {
+#pragma unroll
+    for (int jj = 0; jj < RPP; ++jj) {
+      const int r = RBASE + jb + jj;
+#pragma unroll
+      for (int v = 0; v < 12; ++v) {
+        const R e = nd_entry<R>(F, W, r < v ? r : v, r < v ? v : r);
+        sCell[(jj * 12 + v) * 64 + lane] = (((negmask >> r) ^ (negmask >> v)) & 1u) ? -e : e;
+      }
+    }
+  };
+  // the cell's element, coefficient, corners and edge orientations (bit v of
+  // negmask: local edge v reversed; local edges of the element: x-edges
+  // i + p (j + q k), y-edges p q^2 + i + q (j + p k), z-edges
+  // 2 p q^2 + i + q (j + q k))
+  auto load_cell = [&](const int (&C)[3], int32_t& el, int& lv0, R& kap, double (&Xv)[8][3], unsigned& negmask) {
+    el = elem3d[(static_cast<int64_t>(C[2] / P) * ney + C[1] / P) * nex + C[0] / P];
+    const int sx = C[0] % P, sy = C[1] % P, sz = C[2] % P;
+    lv0 = sx + Q * (sy + Q * sz);
+    kap = static_cast<R>(kappa[static_cast<int64_t>(el) * NSUB + sx + P * (sy + P * sz)]);
+#pragma unroll
+    for (int v = 0; v < 8; ++v) {
+      const int64_t g = elem_dofs[static_cast<int64_t>(el) * NLOCV + (sx + (v & 1)) +
+                                  Q * ((sy + ((v >> 1) & 1)) + Q * (sz + (v >> 2)))];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) Xv[v][d] = coords[3 * g + d];
+    }
+    const int32_t* em = elem_edges + static_cast<int64_t>(el) * NLOCE;
+    negmask = 0;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int lo = s & 1, hi = s >> 1;
+      negmask |= (em[sx + P * ((sy + lo) + Q * (sz + hi))] < 0 ? 1u : 0u) << s;
+      negmask |= (em[P * Q * Q + (sx + lo) + Q * (sy + P * (sz + hi))] < 0 ? 1u : 0u) << (4 + s);
+      negmask |= (em[2 * P * Q * Q + (sx + lo) + Q * ((sy + hi) + Q * sz)] < 0 ? 1u : 0u) << (8 + s);
+    }
+  };
+  // add the slab's rows of the cells at lanes (l1 - a, l2 - b), b in
+  // [b_hi, b_lo] downwards and a = 1 before a = 0, to the row of the edge
+  // along M at this lane's node (the edge is the cell's local edge
+  // RBASE + a + 2b; the slab holds rows from RBASE + jb)
+  auto sum_rows = [&](double (&acc)[kNdRow], int b_hi, int b_lo, int jb) {
+#pragma unroll
+    for (int b = 1; b >= 0; --b) {
+      if (b > b_hi || b < b_lo) continue;
+#pragma unroll
+      for (int a = 1; a >= 0; --a) {
+        if ((a == 0 || lo1) && (b == 0 || lo2) && (a == 1 || hi1) && (b == 1 || hi2)) {
+          const R* cm_ = sCell + (lane - a - 8 * b) + (a + 2 * b - jb) * 12 * 64;
+#pragma unroll
+          for (int v = 0; v < 12; ++v) acc[nd_slot(M, a, b, v)] += static_cast<double>(cm_[v * 64]);
+        }
+      }
+    }
+  };
+
   for (int cm = ms; cm < me; ++cm) {
-    int C[3];
-    C[M] = cm;
-    C[T1] = c1c;
-    C[T2] = c2c;
-    if (cell_col) {
-      const int32_t el = elem3d[(static_cast<int64_t>(C[2] / P) * ney + C[1] / P) * nex + C[0] / P];
-      const int sx = C[0] % P, sy = C[1] % P, sz = C[2] % P;
-      const R kap = static_cast<R>(kappa[static_cast<int64_t>(el) * NSUB + sx + P * (sy + P * sz)]);
-      double Xv[8][3];
+    double acc[kNdRow];
+    if constexpr (NH == 1) {
+      // all 4 rows through the slab at once; in the FP32 form strongly
+      // distorted cells take the FP64 fallback (the gathers written out here:
+      // through load_cell this form compiles to a slower schedule)
+      int C[3];
+      C[M] = cm;
+      C[T1] = c1c;
+      C[T2] = c2c;
+      if (cell_col) {
+        const int32_t el = elem3d[(static_cast<int64_t>(C[2] / P) * ney + C[1] / P) * nex + C[0] / P];
+        const int sx = C[0] % P, sy = C[1] % P, sz = C[2] % P;
+        const R kap = static_cast<R>(kappa[static_cast<int64_t>(el) * NSUB + sx + P * (sy + P * sz)]);
+        double Xv[8][3];
 #pragma unroll
-      for (int v = 0; v < 8; ++v) {
-        const int64_t g = elem_dofs[static_cast<int64_t>(el) * NLOCV + (sx + (v & 1)) +
-                                    Q * ((sy + ((v >> 1) & 1)) + Q * (sz + (v >> 2)))];
+        for (int v = 0; v < 8; ++v) {
+          const int64_t g = elem_dofs[static_cast<int64_t>(el) * NLOCV + (sx + (v & 1)) +
+                                      Q * ((sy + ((v >> 1) & 1)) + Q * (sz + (v >> 2)))];
 #pragma unroll
-        for (int d = 0; d < 3; ++d) Xv[v][d] = coords[3 * g + d];
-      }
-      // orientation of the cell's 12 edges in its element's edge map (local
-      // edges: x-edges i + p (j + q k), y-edges p q^2 + i + q (j + p k),
-      // z-edges 2 p q^2 + i + q (j + q k))
-      unsigned negmask = 0;
-      const int32_t* em = elem_edges + static_cast<int64_t>(el) * NLOCE;
+          for (int d = 0; d < 3; ++d) Xv[v][d] = coords[3 * g + d];
+        }
+        // orientation of the cell's 12 edges in its element's edge map (local
+        // edges: x-edges i + p (j + q k), y-edges p q^2 + i + q (j + p k),
+        // z-edges 2 p q^2 + i + q (j + q k))
+        unsigned negmask = 0;
+        const int32_t* em = elem_edges + static_cast<int64_t>(el) * NLOCE;
 #pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        const int lo = s & 1, hi = s >> 1;
-        negmask |= (em[sx + P * ((sy + lo) + Q * (sz + hi))] < 0 ? 1u : 0u) << s;
-        negmask |= (em[P * Q * Q + (sx + lo) + Q * (sy + P * (sz + hi))] < 0 ? 1u : 0u) << (4 + s);
-        negmask |= (em[2 * P * Q * Q + (sx + lo) + Q * ((sy + hi) + Q * sz)] < 0 ? 1u : 0u) << (8 + s);
-      }
-      bool fallback = false;
-      if constexpr (!std::is_same<R, double>::value) {
-        if (flags & LOR_FP64_FALLBACK) {
+        for (int s = 0; s < 4; ++s) {
+          const int lo = s & 1, hi = s >> 1;
+          negmask |= (em[sx + P * ((sy + lo) + Q * (sz + hi))] < 0 ? 1u : 0u) << s;
+          negmask |= (em[P * Q * Q + (sx + lo) + Q * (sy + P * (sz + hi))] < 0 ? 1u : 0u) << (4 + s);
+          negmask |= (em[2 * P * Q * Q + (sx + lo) + Q * ((sy + hi) + Q * sz)] < 0 ? 1u : 0u) << (8 + s);
+        }
+        bool fallback = false;
+        if constexpr (!std::is_same<R, double>::value) {
+          if (flags & LOR_FP64_FALLBACK) {
+            R ex[2][2][3], ey[2][2][3], ez[2][2][3];
+            h1_edges<R>(Xv, ex, ey, ez);
+            R dmin, dmax;
+            h1_corner_det_range<R>(ex, ey, ez, dmin, dmax);
+            fallback = !(dmin > R(0)) || dmax > det_thresh * dmin;
+          }
+        }
+        if (!fallback) {
           R ex[2][2][3], ey[2][2][3], ez[2][2][3];
           h1_edges<R>(Xv, ex, ey, ez);
-          R dmin, dmax;
-          h1_corner_det_range<R>(ex, ey, ez, dmin, dmax);
-          fallback = !(dmin > R(0)) || dmax > det_thresh * dmin;
+          H1Factors<R> F;
+          NDCurl<R> W;
+          const bool ok = nd_factors<R>(ex, ey, ez, kap, static_cast<R>(beta), F, W);
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const int r = RBASE + j;
+#pragma unroll
+            for (int v = 0; v < 12; ++v) {
+              const R e = nd_entry<R>(F, W, r < v ? r : v, r < v ? v : r);
+              sCell[(j * 12 + v) * 64 + lane] = (((negmask >> r) ^ (negmask >> v)) & 1u) ? -e : e;
+            }
+          }
+          if (!ok && count && diag) atomicAdd(&diag[1], 1);
+        } else {
+          const bool ok = nd_owner_fp64_fallback<P>(elem_dofs, coords, el, sx + Q * (sy + Q * sz), RBASE,
+                                                    static_cast<double>(kap), static_cast<double>(beta), negmask,
+                                                    reinterpret_cast<float*>(sCell) + lane);
+          if (count && diag) {
+            atomicAdd(&diag[0], 1);
+            if (!ok) atomicAdd(&diag[1], 1);
+          }
         }
       }
-      if (!fallback) {
+      __syncthreads();
+
+      // the row of the edge along M at (cm, c1, c2): the cells at lanes
+      // (l1 - a, l2 - b) in increasing (z, y, x), i.e. b = 1 before b = 0 and a
+      // = 1 before a = 0 (the edge is the cell's local edge RBASE + a + 2b)
+#pragma unroll
+      for (int k = 0; k < kNdRow; ++k) acc[k] = 0.0;
+      if (row_own) {
+#pragma unroll
+        for (int b = 1; b >= 0; --b)
+#pragma unroll
+          for (int a = 1; a >= 0; --a) {
+            if ((a == 0 || lo1) && (b == 0 || lo2) && (a == 1 || hi1) && (b == 1 || hi2)) {
+              const R* cm_ = sCell + (lane - a - 8 * b) + (a + 2 * b) * 12 * 64;
+#pragma unroll
+              for (int v = 0; v < 12; ++v) acc[nd_slot(M, a, b, v)] += static_cast<double>(cm_[v * 64]);
+            }
+          }
+      }
+      __syncthreads();  // the staging area is the slab
+    } else {
+      // FP64 form: the rows of b = 1 (local edges RBASE + 2, + 3), then those
+      // of b = 0, each pass through the half-size slab
+      int C[3];
+      C[M] = cm;
+      C[T1] = c1c;
+      C[T2] = c2c;
+      H1Factors<R> F;
+      NDCurl<R> W;
+      unsigned negmask = 0;
+      if (cell_col) {
+        int32_t el;
+        int lv0;
+        R kap;
+        double Xv[8][3];
+        load_cell(C, el, lv0, kap, Xv, negmask);
         R ex[2][2][3], ey[2][2][3], ez[2][2][3];
         h1_edges<R>(Xv, ex, ey, ez);
-        H1Factors<R> F;
-        NDCurl<R> W;
         const bool ok = nd_factors<R>(ex, ey, ez, kap, static_cast<R>(beta), F, W);
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const int r = RBASE + j;
-#pragma unroll
-          for (int v = 0; v < 12; ++v) {
-            const R e = nd_entry<R>(F, W, r < v ? r : v, r < v ? v : r);
-            sCell[(j * 12 + v) * 64 + lane] = (((negmask >> r) ^ (negmask >> v)) & 1u) ? -e : e;
-          }
-        }
         if (!ok && count && diag) atomicAdd(&diag[1], 1);
-      } else {
-        const bool ok = nd_owner_fp64_fallback<P>(elem_dofs, coords, el, sx + Q * (sy + Q * sz), RBASE,
-                                                  static_cast<double>(kap), static_cast<double>(beta), negmask,
-                                                  reinterpret_cast<float*>(sCell) + lane);
-        if (count && diag) {
-          atomicAdd(&diag[0], 1);
-          if (!ok) atomicAdd(&diag[1], 1);
-        }
+      }
+#pragma unroll
+      for (int k = 0; k < kNdRow; ++k) acc[k] = 0.0;
+#pragma unroll
+      for (int b = 1; b >= 0; --b) {
+        if (cell_col) write_rows(F, W, negmask, 2 * b);
+        __syncthreads();
+        if (row_own) sum_rows(acc, b, b, 2 * b);
+        __syncthreads();  // the slab is written again, or is the staging area
       }
     }
-    __syncthreads();
-
-    // the row of the edge along M at (cm, c1, c2): the cells at lanes
-    // (l1 - a, l2 - b) in increasing (z, y, x), i.e. b = 1 before b = 0 and a
-    // = 1 before a = 0 (the edge is the cell's local edge RBASE + a + 2b)
-    double acc[kNdRow];
-#pragma unroll
-    for (int k = 0; k < kNdRow; ++k) acc[k] = 0.0;
-    if (row_own) {
-#pragma unroll
-      for (int b = 1; b >= 0; --b)
-#pragma unroll
-        for (int a = 1; a >= 0; --a) {
-          if ((a == 0 || lo1) && (b == 0 || lo2) && (a == 1 || hi1) && (b == 1 || hi2)) {
-            const R* cm_ = sCell + (lane - a - 8 * b) + (a + 2 * b) * 12 * 64;
-#pragma unroll
-            for (int v = 0; v < 12; ++v) acc[nd_slot(M, a, b, v)] += static_cast<double>(cm_[v * 64]);
-          }
-        }
-    }
-    __syncthreads();  // the staging area is the slab
 
     // stage the row, compacted on the box faces, and its start and length
     if (row_own) {
