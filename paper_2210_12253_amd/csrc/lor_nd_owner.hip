@@ -195,10 +195,19 @@ __global__ __launch_bounds__(64, 2) void k_nd_owner(int nex, int ney, int nez, i
 
   const int L[3] = {nex * P, ney * P, nez * P};
   const int lane = threadIdx.x;
-  const int i1 = blockIdx.x % nt1, i2 = blockIdx.x / nt1;
+  // XCD-aware order: workgroups go to the 8 XCDs round-robin by linear id, so
+  // linear id g runs (tile, segment) number (g mod 8) * (n / 8) + g / 8 of
+  // the tile-fastest order: each XCD walks a contiguous run of layers, tile
+  // after tile, and finds the corners and edge words its neighbours loaded
+  // in its own L2 (the last n mod 8 ids keep their place)
+  const int64_t ntile = gridDim.x, nlin = ntile * gridDim.y;
+  const int64_t glin = blockIdx.x + ntile * blockIdx.y, gfull = nlin & ~int64_t(7);
+  const int64_t hlin = glin < gfull ? (glin & 7) * (gfull >> 3) + (glin >> 3) : glin;
+  const int tile = static_cast<int>(hlin % ntile), seg = static_cast<int>(hlin / ntile);
+  const int i1 = tile % nt1, i2 = tile / nt1;
   const int l1 = lane & 7, l2 = lane >> 3;
   const int c1 = kNdStride * i1 + l1, c2 = kNdStride * i2 + l2;  // this lane's cell / node along T1, T2
-  const int ms = blockIdx.y * seglen;
+  const int ms = seg * seglen;
   const int me = ms + seglen < L[M] ? ms + seglen : L[M];
   kappa += static_cast<int64_t>(blockIdx.z) * nel * NSUB;
   values += static_cast<int64_t>(blockIdx.z) * nnz;
