@@ -73,11 +73,16 @@ def test_nd_p3_24cubed_every_row():
     m = meshgen.config_mesh("c4_nd_p3_curved")
     ed, ee, x = torch.from_numpy(m["elem_dofs"]), torch.from_numpy(m["elem_edges"]), torch.from_numpy(m["coords"])
     pat = lor.lor_pattern(lor.LOR_ND, 3, ee.to(DEV), m["nedges"])
-    v64 = lor.lor_assemble_nd(pat, ed, ee, x, m["kappa"], 1.0, m["ndofs"])
-    v32 = lor.lor_assemble_nd(pat, ed, ee, x, m["kappa"].float(), 1.0, m["ndofs"], dtype=torch.float32,
-                              fp64_fallback=True)
-    torch.cuda.synchronize()
-    values = {"fp64": (v64.cpu(), 1e-12), "fp32": (v32.cpu(), 1e-6)}
+    assert pat.owner
+    values = {}
+    for kern in ("owner", "colored"):
+        v64 = lor.lor_assemble_nd(pat, ed, ee, x, m["kappa"], 1.0, m["ndofs"], kernel=kern)
+        v32 = lor.lor_assemble_nd(pat, ed, ee, x, m["kappa"].float(), 1.0, m["ndofs"], dtype=torch.float32,
+                                  fp64_fallback=True, kernel=kern)
+        torch.cuda.synchronize()
+        values[f"{kern} fp64"] = (v64.cpu(), 1e-12)
+        values[f"{kern} fp32"] = (v32.cpu(), 1e-6)
+        del v64, v32
     grp = pat.row_ptr.cpu().to(torch.int64)
     gci = pat.col_idx.cpu().to(torch.int64)
     ned = m["nedges"]
