@@ -90,3 +90,29 @@ def test_face_map_box_matches_vertices(box, p):
     for a, b in zip(np.abs(fm).reshape(-1).tolist(), (np.where(fv < 0, -1 - fv, fv)).reshape(-1).tolist()):
         assert pairs.setdefault(a, b) == b
     assert len(set(pairs.values())) == nf
+
+
+@pytest.mark.parametrize("n,p", [(1, 2), (2, 3), (3, 1)])
+def test_nd_edge_map_box_on_a_cube_is_nd_edge_map(n, p):
+    a, na = meshgen.nd_edge_map(n, p)
+    b, nb = meshgen.nd_edge_map_box(n, n, n, p)
+    assert na == nb and np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("box,p", [((3, 2, 1), 2), ((1, 2, 3), 1), ((2, 1, 2), 3)])
+def test_nd_edge_map_box_matches_vertices(box, p):
+    """The edge count of the box's lattice, every edge along its axis (no
+    reversed entries), and the same edges as derived from the vertex map
+    alone: the same partition of (element, local edge) slots into edges, and
+    the same orientation (box vertex ids grow along every axis)."""
+    m = meshgen.box_mesh(*box, p)
+    em, ne = meshgen.nd_edge_map_box(*box, p)
+    M = [n * p for n in box]
+    assert ne == M[0] * (M[1] + 1) * (M[2] + 1) + (M[0] + 1) * M[1] * (M[2] + 1) + (M[0] + 1) * (M[1] + 1) * M[2]
+    assert em.min() >= 0 and set(np.unique(em).tolist()) == set(range(ne))
+    ev, nev = meshgen.edge_map_from_vertices(m["elem_dofs"], p)
+    assert nev == ne and ev.min() >= 0
+    pairs = {}
+    for a, b in zip(em.reshape(-1).tolist(), ev.reshape(-1).tolist()):
+        assert pairs.setdefault(a, b) == b
+    assert len(set(pairs.values())) == ne
