@@ -44,7 +44,7 @@ namespace lor {
 constexpr int kNdTile = 8;               // cells per tile side (one wave: 8 x 8)
 constexpr int kNdStride = kNdTile - 1;   // tiles overlap by one cell
 constexpr int kNdRow = 33;               // entries of an inside row
-constexpr int kNdStoreIters = 64 * kNdRow / 64;  // store trips: 64 staged rows, 64 lanes a trip
+constexpr int kNdStoreIters = 64 * kNdRow / 64;
 
 // Local edge v of a cell (numbering of the ND integration): its direction
 // and its offset from the cell's lowest corner.
