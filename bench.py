@@ -413,6 +413,39 @@ def summarize_valu(pmc_dir, command):
     return "\n".join(lines) + "\n", rec
 
 
+WAVE_COUNTERS = (("SQ_WAVES", "SQ_WAVE_CYCLES", "SQ_BUSY_CYCLES", "SQ_WAIT_INST_LDS", "SQ_LDS_BANK_CONFLICT",
+                  "SQ_ACTIVE_INST_VALU", "SQ_WAIT_ANY", "SQ_WAIT_INST_ANY"),
+                 ("SQ_INSTS_VALU", "SQ_INSTS_LDS", "SQ_INSTS_VMEM", "SQ_ACTIVE_INST_LDS", "SQ_ACTIVE_INST_VMEM",
+                  "SQ_INST_LEVEL_VMEM", "SQ_INSTS_SALU", "SQ_ACTIVE_INST_ANY"))
+
+
+def summarize_waves(pmc_dirs, command, name):
+    """Wave-state summary of the profiled kernels from two rocprofv3 --pmc runs
+    of WAVE_COUNTERS (one pass each): per dispatch, the counters and the
+    shares of the summed wave cycles spent issuing VALU, LDS and any
+    instruction, waiting on memory or LDS counters, and waiting for an
+    instruction to issue."""
+    kernels = PROFILE_SETS[name][0]
+    per = {}
+    for d in pmc_dirs:
+        for r in _read_csvs(d, "counter_collection.csv"):
+            for key, needle in kernels.items():
+                if needle in r["Kernel_Name"]:
+                    per.setdefault(key, {}).setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    lines = [f"command: {command}", ""]
+    for key, cs in per.items():
+        avg = {c: sum(v) / len(v) for c, v in cs.items()}
+        lines.append(f"{kernels[key]}: {len(cs.get('SQ_WAVES', []))} dispatches, per dispatch")
+        lines += [f"  {c:24s} {avg[c]:16.0f}" for c in sorted(avg)]
+        wc = avg.get("SQ_WAVE_CYCLES")
+        if wc:
+            shares = [(c, avg[c] / wc) for c in ("SQ_ACTIVE_INST_VALU", "SQ_ACTIVE_INST_LDS", "SQ_ACTIVE_INST_ANY",
+                                                 "SQ_WAIT_ANY", "SQ_WAIT_INST_ANY", "SQ_WAIT_INST_LDS") if c in avg]
+            lines.append("  share of SQ_WAVE_CYCLES: " + ", ".join(f"{c[3:]} {v:.3f}" for c, v in shares))
+        lines.append("")
+    return "\n".join(lines)
+
+
 def valu_bound(key, avg_launch_us):
     """Arithmetic bound of one launch from its counted wave instructions: the
     issue time if every VALU wave instruction ran back to back on the chip's
@@ -478,6 +511,8 @@ def main():
                     help="summarise rocprofv3 CSV output of this script (no GPU use)")
     ap.add_argument("--summarize-valu", metavar="PMC_DIR",
                     help="summarise a rocprofv3 --pmc run of the VALU counters (no GPU use)")
+    ap.add_argument("--summarize-waves", nargs=2, metavar=("PMC_DIR_A", "PMC_DIR_B"),
+                    help="summarise two rocprofv3 --pmc runs of the wave-state counters (no GPU use)")
     ap.add_argument("--profile-command", default="", help="command recorded in the summary")
     ap.add_argument("--profile-name", default="h1_p6_32cubed")
     args = ap.parse_args()
@@ -489,6 +524,13 @@ def main():
         if rec is not None:
             with open(os.path.join(ROOT, "profiles", VALU_FILE), "w") as f:
                 json.dump(rec, f, indent=1)
+        print(text)
+        return
+    if args.summarize_waves:
+        text = summarize_waves(args.summarize_waves, args.profile_command, args.profile_name)
+        os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
+        with open(os.path.join(ROOT, "profiles", args.profile_name + "_waves.txt"), "w") as f:
+            f.write(text)
         print(text)
         return
     if args.summarize_profiles:
