@@ -43,8 +43,12 @@ __host__ __device__ __forceinline__ int64_t box2d_row_start(int64_t X, int64_t Y
   return box_prefix(Y, LY) * (3 * LX - 2) + box_count(Y, LY) * box_prefix(X, LX);
 }
 
+// Registers for four waves per SIMD (128 VGPRs): the FP64 form needs 126;
+// the FP32 form would take 146 (three waves) with its FP64 fallback inlined,
+// and at 128 keeps a few loop-invariant values in scratch (stored once,
+// reloaded per step), which costs less than the fourth wave gains.
 template <int P, typename T, typename R>
-__global__ __launch_bounds__(64) void k_h1_2d_owner(int nex, int ney, int seglen, const int32_t* __restrict__ elem2d,
+__global__ __launch_bounds__(64, 4) void k_h1_2d_owner(int nex, int ney, int seglen, const int32_t* __restrict__ elem2d,
                                                    const double* __restrict__ coords, const T* __restrict__ kappa,
                                                    T beta, int64_t nel, int64_t nnz, T* __restrict__ values,
                                                    unsigned flags, R det_thresh, int32_t* __restrict__ diag) {
